@@ -1,0 +1,317 @@
+/*
+ * CPU oracle for levelized static timing analysis.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg load this library.  It shares no code, header, table or helper
+ * with the HIP implementation; both read the same seeded input arrays.
+ *
+ * What it computes.  The paper (Heteroflow, Section IV-A, "VLSI Timing Analysis")
+ * runs a timer over a 1.5M-gate design for many views (corner x mode) but prints no
+ * timing formula and no timing value, so no pin below comes from the paper itself:
+ * every function is pinned against mathematics instead (closed forms, brute force on
+ * tiny graphs, an independent O(n^2) moment definition, invariants), as listed in the
+ * test suite.  The definitions follow the textbook method:
+ *   step 1  levelize: Kahn's algorithm; level(PI) = 0, level(g) = 1 + max level of the
+ *           drivers of g's inputs; a cycle is an error;
+ *   step 2  RC delay calculation per net in FP64: lumped load, Elmore first moment m1,
+ *           second moment m2 (Rubinstein-Penfield-Horowitz / PERI), imp2 = 2 m2 - m1^2;
+ *   step 3  NLDM 7x7 bilinear lookup in FP32, each operation rounded separately,
+ *           linear extrapolation from the end segment (no clamp);
+ *   step 4  net slew: S_sink = sqrt(S_drv^2 + imp2)  (PERI quadrature);
+ *   step 5  forward propagation in FP32: AT_out = max (late) / min (early) over cell arcs
+ *           of (AT_in + d), smallest arc index wins ties; slew = worst arc slew;
+ *   step 6  backward required times in FP32 and slack = RAT - AT (late) or AT - RAT
+ *           (early).  WNS/TNS are formed by the Python wrapper from the endpoint slacks.
+ *
+ * Build: gcc -O2 -ffp-contract=off (x86-64 SSE arithmetic: every float/double
+ * operation is a single IEEE-754 round-to-nearest-even operation).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG (-1)
+#define ORC_E_RANGE (-2)
+#define ORC_E_CYCLE (-3)
+
+/* ---- step 1: levelization --------------------------------------------------- */
+
+/* Kahn's algorithm on the gate graph.  level[d] for every driver d (PIs 0, gate
+ * output n_pi+g gets its gate's level), topo[] receives the gates in the order Kahn's
+ * queue released them.  Returns ORC_E_CYCLE if some gate never becomes ready. */
+int orc_levelize(int n_pi, int n_gates, const int32_t* gate_arc_ptr, const int32_t* arc_drv,
+                 int32_t* level, int32_t* topo)
+{
+    int D = n_pi + n_gates;
+    int A = gate_arc_ptr[n_gates];
+    int32_t* indeg = (int32_t*)calloc((size_t)n_gates + 1, sizeof(int32_t));
+    int32_t* fo_cnt = (int32_t*)calloc((size_t)D + 1, sizeof(int32_t));
+    int32_t* fo_ptr = (int32_t*)calloc((size_t)D + 1, sizeof(int32_t));
+    int32_t* fo_gate = (int32_t*)malloc(((size_t)A + 1) * sizeof(int32_t));
+    int32_t* queue = (int32_t*)malloc(((size_t)n_gates + 1) * sizeof(int32_t));
+    int rc = ORC_OK;
+    if (!indeg || !fo_cnt || !fo_ptr || !fo_gate || !queue) { rc = ORC_E_ARG; goto done; }
+
+    for (int g = 0; g < n_gates; ++g)
+        for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
+            int d = arc_drv[a];
+            if (d < 0 || d >= D) { rc = ORC_E_RANGE; goto done; }
+            fo_cnt[d]++;
+            if (d >= n_pi) indeg[g]++;
+        }
+    for (int d = 0; d < D; ++d) fo_ptr[d + 1] = fo_ptr[d] + fo_cnt[d];
+    memset(fo_cnt, 0, sizeof(int32_t) * (size_t)D);
+    for (int g = 0; g < n_gates; ++g)
+        for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
+            int d = arc_drv[a];
+            fo_gate[fo_ptr[d] + fo_cnt[d]++] = g;
+        }
+
+    for (int d = 0; d < n_pi; ++d) level[d] = 0;
+    int head = 0, tail = 0;
+    for (int g = 0; g < n_gates; ++g)
+        if (indeg[g] == 0) queue[tail++] = g;
+    while (head < tail) {
+        int g = queue[head++];
+        int lv = 0;
+        for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
+            int l = level[arc_drv[a]];
+            if (l > lv) lv = l;
+        }
+        level[n_pi + g] = lv + 1;
+        int o = n_pi + g;
+        for (int i = fo_ptr[o]; i < fo_ptr[o + 1]; ++i) {
+            int c = fo_gate[i];
+            if (--indeg[c] == 0) queue[tail++] = c;
+        }
+    }
+    if (tail != n_gates) { rc = ORC_E_CYCLE; goto done; }
+    if (topo) memcpy(topo, queue, sizeof(int32_t) * (size_t)n_gates);
+done:
+    free(indeg); free(fo_cnt); free(fo_ptr); free(fo_gate); free(queue);
+    return rc;
+}
+
+/* ---- step 2: RC delay calculation (FP64) ------------------------------------ */
+
+/* For every net (driver d), nodes k = 0..M-1 local, parent[k] < k for k >= 1.
+ *   C[k]  = wire cap + pin caps of the sinks tapped at k (sinks in ascending arc id)
+ *   Cd    = C; for k = M-1..1: Cd[parent[k]] += Cd[k]          (downstream cap)
+ *   load  = Cd[0]
+ *   m1[0] = 0; m1[k] = m1[parent[k]] + (R[k] * Cd[k]) * 1e-3     (ohm*fF -> ps)
+ *   W     = C * m1; for k = M-1..1: W[parent[k]] += W[k]
+ *   m2[0] = 0; m2[k] = m2[parent[k]] + (R[k] * W[k]) * 1e-3
+ *   imp2  = max(0, 2*m2 - m1*m1)
+ * Per sink arc: net_delay = fl32(m1[tap]), net_imp2 = fl32(imp2[tap]); load[d] = fl32(load).
+ * node_m1/node_m2/node_cd (FP64, per global node) are optional outputs for the tests. */
+int orc_delay_calc(int n_drv, const int32_t* net_node_ptr, const int32_t* node_parent,
+                   const float* node_R, const float* node_C,
+                   int n_arcs, const int32_t* arc_drv, const int32_t* arc_tap, const float* arc_pincap,
+                   float* load, float* net_delay, float* net_imp2,
+                   double* node_m1, double* node_m2, double* node_cd)
+{
+    int M = net_node_ptr[n_drv];
+    double* C = (double*)malloc(((size_t)M + 1) * sizeof(double));
+    double* Cd = (double*)malloc(((size_t)M + 1) * sizeof(double));
+    double* m1 = (double*)malloc(((size_t)M + 1) * sizeof(double));
+    double* W = (double*)malloc(((size_t)M + 1) * sizeof(double));
+    double* m2 = (double*)malloc(((size_t)M + 1) * sizeof(double));
+    int rc = ORC_OK;
+    if (!C || !Cd || !m1 || !W || !m2) { rc = ORC_E_ARG; goto done; }
+
+    for (int k = 0; k < M; ++k) C[k] = (double)node_C[k];
+    for (int a = 0; a < n_arcs; ++a) {
+        int d = arc_drv[a];
+        if (d < 0 || d >= n_drv) { rc = ORC_E_RANGE; goto done; }
+        int n0 = net_node_ptr[d], nm = net_node_ptr[d + 1] - n0;
+        if (arc_tap[a] < 0 || arc_tap[a] >= nm) { rc = ORC_E_RANGE; goto done; }
+        C[n0 + arc_tap[a]] += (double)arc_pincap[a];
+    }
+    for (int d = 0; d < n_drv; ++d) {
+        int n0 = net_node_ptr[d], nm = net_node_ptr[d + 1] - n0;
+        const int32_t* par = node_parent + n0;
+        for (int k = 1; k < nm; ++k)
+            if (par[k] < 0 || par[k] >= k) { rc = ORC_E_RANGE; goto done; }
+        for (int k = 0; k < nm; ++k) Cd[n0 + k] = C[n0 + k];
+        for (int k = nm - 1; k >= 1; --k) Cd[n0 + par[k]] += Cd[n0 + k];
+        load[d] = (float)Cd[n0];
+        m1[n0] = 0.0;
+        for (int k = 1; k < nm; ++k)
+            m1[n0 + k] = m1[n0 + par[k]] + ((double)node_R[n0 + k] * Cd[n0 + k]) * 1e-3;
+        for (int k = 0; k < nm; ++k) W[n0 + k] = C[n0 + k] * m1[n0 + k];
+        for (int k = nm - 1; k >= 1; --k) W[n0 + par[k]] += W[n0 + k];
+        m2[n0] = 0.0;
+        for (int k = 1; k < nm; ++k)
+            m2[n0 + k] = m2[n0 + par[k]] + ((double)node_R[n0 + k] * W[n0 + k]) * 1e-3;
+    }
+    for (int a = 0; a < n_arcs; ++a) {
+        int k = net_node_ptr[arc_drv[a]] + arc_tap[a];
+        double imp2 = 2.0 * m2[k] - m1[k] * m1[k];
+        if (imp2 < 0.0) imp2 = 0.0;
+        net_delay[a] = (float)m1[k];
+        net_imp2[a] = (float)imp2;
+    }
+    if (node_m1) memcpy(node_m1, m1, sizeof(double) * (size_t)M);
+    if (node_m2) memcpy(node_m2, m2, sizeof(double) * (size_t)M);
+    if (node_cd) memcpy(node_cd, Cd, sizeof(double) * (size_t)M);
+done:
+    free(C); free(Cd); free(m1); free(W); free(m2);
+    return rc;
+}
+
+/* ---- step 3: NLDM bilinear lookup (FP32) ------------------------------------ */
+
+/* largest i in 0..5 with axis[i] <= v; 0 when v < axis[0] */
+static int seg7(const float* axis, float v)
+{
+    int i = 0;
+    for (int t = 1; t <= 5; ++t)
+        if (axis[t] <= v) i = t;
+    return i;
+}
+
+/* T is one 7x7 table, row-major T[i*7+j] at (x[i], y[j]).  Every -, *, + and / below is
+ * a separately rounded FP32 operation (no contraction). */
+float orc_bilerp(const float* x, const float* y, const float* T, float s, float l)
+{
+    int i = seg7(x, s);
+    int j = seg7(y, l);
+    float tx = (s - x[i]) / (x[i + 1] - x[i]);
+    float ty = (l - y[j]) / (y[j + 1] - y[j]);
+    float t00 = T[i * 7 + j], t10 = T[(i + 1) * 7 + j];
+    float t01 = T[i * 7 + j + 1], t11 = T[(i + 1) * 7 + j + 1];
+    float p = t00 + tx * (t10 - t00);
+    float q = t01 + tx * (t11 - t01);
+    return p + ty * (q - p);
+}
+
+void orc_bilerp_many(const float* x, const float* y, const float* T, int n,
+                     const float* s, const float* l, float* out)
+{
+    for (int k = 0; k < n; ++k) out[k] = orc_bilerp(x, y, T, s[k], l[k]);
+}
+
+/* ---- steps 4-5: forward propagation (FP32) ----------------------------------- */
+
+/* mode 0 = late (max), 1 = early (min).  lib_tab holds n_tables pairs, each 2x49 floats:
+ * [t][0] delay table, [t][1] slew table.  Gates are evaluated in a topological order
+ * (Kahn's), which fixes every operand, so the result does not depend on that order. */
+int orc_propagate(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr,
+                  const int32_t* arc_drv, const int32_t* arc_tbl, int n_tables,
+                  const float* lib_x, const float* lib_y, const float* lib_tab,
+                  const float* load, const float* net_delay, const float* net_imp2,
+                  const float* pi_at, const float* pi_slew,
+                  float* at_drv, float* slew_drv, float* at_in, float* slew_in,
+                  float* arc_delay, int32_t* argmax)
+{
+    int D = n_pi + n_gates;
+    int32_t* level = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    int32_t* topo = (int32_t*)malloc(((size_t)n_gates + 1) * sizeof(int32_t));
+    int rc = ORC_OK;
+    if (!level || !topo) { rc = ORC_E_ARG; goto done; }
+    rc = orc_levelize(n_pi, n_gates, gate_arc_ptr, arc_drv, level, topo);
+    if (rc != ORC_OK) goto done;
+
+    for (int d = 0; d < n_pi; ++d) { at_drv[d] = pi_at[d]; slew_drv[d] = pi_slew[d]; }
+    for (int t = 0; t < n_gates; ++t) {
+        int g = topo[t];
+        int o = n_pi + g;
+        float best_at = 0.0f, best_slew = 0.0f;
+        int best_k = -1;
+        for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
+            int u = arc_drv[a];
+            int tb = arc_tbl[a];
+            if (tb < 0 || tb >= n_tables) { rc = ORC_E_RANGE; goto done; }
+            float ai = at_drv[u] + net_delay[a];
+            float su2 = slew_drv[u] * slew_drv[u];
+            float si = sqrtf(su2 + net_imp2[a]);
+            at_in[a] = ai;
+            slew_in[a] = si;
+            float d = orc_bilerp(lib_x, lib_y, lib_tab + (size_t)tb * 98, si, load[o]);
+            float s = orc_bilerp(lib_x, lib_y, lib_tab + (size_t)tb * 98 + 49, si, load[o]);
+            arc_delay[a] = d;
+            float cand = ai + d;
+            int k = a - gate_arc_ptr[g];
+            if (best_k < 0) {
+                best_at = cand; best_slew = s; best_k = k;
+            } else if (mode == 0) {
+                if (cand > best_at) { best_at = cand; best_k = k; }
+                if (s > best_slew) best_slew = s;
+            } else {
+                if (cand < best_at) { best_at = cand; best_k = k; }
+                if (s < best_slew) best_slew = s;
+            }
+        }
+        at_drv[o] = best_at;
+        slew_drv[o] = best_slew;
+        argmax[g] = best_k;
+    }
+done:
+    free(level); free(topo);
+    return rc;
+}
+
+/* ---- step 6: required times and slack (FP32) --------------------------------- */
+
+/* Endpoints are drivers without sinks; ep_rat[r] is the required time of the r-th
+ * endpoint in ascending driver id.  Late: RAT_drv = min over its sink arcs of
+ * (RAT_in - net_delay), RAT_in = RAT_out - arc_delay, slack = RAT - AT.
+ * Early: max instead of min, slack = AT - RAT.  Gates are visited in reverse
+ * topological order so that every sink's RAT_in exists before its driver needs it. */
+int orc_slack(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr, const int32_t* arc_drv,
+              const float* net_delay, const float* arc_delay,
+              const float* at_drv, const float* at_in, const float* ep_rat,
+              float* rat_drv, float* rat_in, float* slack_drv, float* slack_in)
+{
+    int D = n_pi + n_gates;
+    int A = gate_arc_ptr[n_gates];
+    int32_t* level = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    int32_t* topo = (int32_t*)malloc(((size_t)n_gates + 1) * sizeof(int32_t));
+    int32_t* fo_ptr = (int32_t*)calloc((size_t)D + 2, sizeof(int32_t));
+    int32_t* fo_arc = (int32_t*)malloc(((size_t)A + 1) * sizeof(int32_t));
+    int32_t* ep_rank = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    int rc = ORC_OK;
+    if (!level || !topo || !fo_ptr || !fo_arc || !ep_rank) { rc = ORC_E_ARG; goto done; }
+    rc = orc_levelize(n_pi, n_gates, gate_arc_ptr, arc_drv, level, topo);
+    if (rc != ORC_OK) goto done;
+
+    for (int a = 0; a < A; ++a) fo_ptr[arc_drv[a] + 2]++;
+    for (int d = 0; d < D; ++d) fo_ptr[d + 2] += fo_ptr[d + 1];
+    for (int a = 0; a < A; ++a) fo_arc[fo_ptr[arc_drv[a] + 1]++] = a;
+    {
+        int r = 0;
+        for (int d = 0; d < D; ++d) ep_rank[d] = (fo_ptr[d + 1] == fo_ptr[d]) ? r++ : -1;
+    }
+
+    for (int t = n_gates - 1; t >= -n_pi; --t) {
+        /* t >= 0: gate topo[t]; t < 0: primary input -t-1 */
+        int o = (t >= 0) ? n_pi + topo[t] : -t - 1;
+        float r;
+        if (ep_rank[o] >= 0) {
+            r = ep_rat[ep_rank[o]];
+        } else {
+            r = 0.0f;
+            for (int i = fo_ptr[o]; i < fo_ptr[o + 1]; ++i) {
+                int a = fo_arc[i];
+                float v = rat_in[a] - net_delay[a];
+                if (i == fo_ptr[o]) r = v;
+                else if (mode == 0) { if (v < r) r = v; }
+                else { if (v > r) r = v; }
+            }
+        }
+        rat_drv[o] = r;
+        slack_drv[o] = (mode == 0) ? (r - at_drv[o]) : (at_drv[o] - r);
+        if (t >= 0) {
+            int g = topo[t];
+            for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
+                rat_in[a] = r - arc_delay[a];
+                slack_in[a] = (mode == 0) ? (rat_in[a] - at_in[a]) : (at_in[a] - rat_in[a]);
+            }
+        }
+    }
+done:
+    free(level); free(topo); free(fo_ptr); free(fo_arc); free(ep_rank);
+    return rc;
+}
