@@ -1,0 +1,213 @@
+"""Benchmark: levelized STA of the 1M-pin design on one MI355X.
+
+A step is one pass of the whole timing path over the resident design: RC delay
+calculation (FP64 moments), forward propagation of the late and early views, and the
+backward required-time/slack pass with WNS/TNS.  The graph build (levelization and
+layout, host code, once per design) and the upload are outside the timed region and
+reported separately.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pin-updates/s at 1M pins (bit-exact) + %HBM roofline; surrogate vs exact speedup"
+HBM_PEAK_GBS = 8000.0
+
+
+def fwd_bytes_per_pass(G, A, n_views):
+    """Algorithmic bytes of the forward pass: per gate 20 B for the first view (arc
+    pointer, load, arrival+slew out, argmax) and 12 B for each further view; per arc 34 B
+    for the first view (driver id, gathered arrival+slew, net delay+spread, table id,
+    input-pin arrival+slew, arc delay) and 20 B for each further view."""
+    return (20 + 12 * (n_views - 1)) * G + (34 + 20 * (n_views - 1)) * A
+
+
+def bwd_bytes_per_pass(D, A, n_views):
+    """Per sink arc: its id 4, gathered RAT of the gate output 4, arc delay 4, net delay 4,
+    input-pin arrival 4, required time and slack out 8 (28 B); per driver: arrival 4,
+    required time and slack out 8, sink pointer 4 (16 B), plus 8 B per further view and arc."""
+    return (28 + 16 * (n_views - 1)) * A + (16 + 12 * (n_views - 1)) * D
+
+
+def dc_bytes(D, A, M):
+    """Per driver: node pointer, sink pointer, load (12 B); per node R, C, parent (10 B);
+    per sink: arc id, tap, pin cap, net delay, spread (17 B)."""
+    return 12 * D + 10 * M + 17 * A
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (one design on one GPU); "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_08395_amd import gen, sta
+
+    name = args.workload
+    cfg = gen.CONFIGS[name]
+    t0 = time.perf_counter()
+    d = gen.make_design(**cfg)
+    lib = gen.make_library()
+    pa, ps = gen.make_pi(d)
+    late, early = gen.make_rat(d, cfg["n_levels"], **gen.RAT_PARAMS[name])
+    t_gen = time.perf_counter() - t0
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    g = sta.Graph(d, n_tables=lib.n_tables)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g.upload(dev)
+    torch.cuda.synchronize()
+    t_upload = time.perf_counter() - t0
+    s = g.sizes
+    D, A, G, M, E, L = (s[k] for k in ("n_drivers", "n_arcs", "n_gates", "n_nodes", "n_endpoints", "n_levels"))
+    modes = [sta.STA_LATE, sta.STA_EARLY]
+    V = len(modes)
+    L_lib = sta.make_library(lib.x, lib.y, torch.from_numpy(lib.tab).to(dev))
+    views = sta.make_views(modes)
+    pi = np.zeros((d.n_pi, V, 2), np.float32)
+    pi[:, :, 0] = pa[:, None]
+    pi[:, :, 1] = ps[:, None]
+    pi_t = torch.from_numpy(pi).to(dev)
+    rat = np.stack([late, early], axis=1).astype(np.float32)
+    rat_t = torch.from_numpy(rat).to(dev)
+    nd = {"load": torch.empty(D, dtype=torch.float32, device=dev),
+          "net_delay": torch.empty(A, dtype=torch.float32, device=dev),
+          "net_imp2": torch.empty(A, dtype=torch.float32, device=dev)}
+    tm = sta.alloc_timing(g, V)
+    sl = sta.alloc_slack(g, V)
+
+    def step():
+        sta.delay_calc(g, sta.STA_DC_FP64, out=nd)
+        sta.propagate(g, L_lib, views, pi_t, nd, out=tm)
+        sta.slack(g, views, nd, tm, rat_t, out=sl)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+
+    # propagate-only rate (same buffers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sta.propagate(g, L_lib, views, pi_t, nd, out=tm)
+    torch.cuda.synchronize()
+    ms_prop = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    # per-kernel durations from HIP events bracketing every launch, same stream and shapes
+    sta.profile_begin()
+    for _ in range(args.steps):
+        step()
+    kstats = sta.profile_end()
+    torch.cuda.synchronize()
+
+    updates = (s["n_pins"] - d.n_pi) * V
+    value = updates / (ms_step * 1e-3)
+    fwd_launch_bytes = fwd_bytes_per_pass(G, A, V) / L
+    k_fwd = kstats.get("k_forward", (1, float("nan")))
+    fwd_avg_ms = k_fwd[1] / k_fwd[0]
+    achieved = fwd_launch_bytes / (fwd_avg_ms * 1e-3) / 1e9
+    kernels = {k: {"launches": n // args.steps, "avg_us": 1e3 * ms / n, "ms_per_step": ms / args.steps}
+               for k, (n, ms) in kstats.items()}
+    dcb = dc_bytes(D, A, M)
+    if "k_delay_calc" in kstats:
+        n, ms = kstats["k_delay_calc"]
+        kernels["k_delay_calc"]["GB_s"] = dcb / (ms / n * 1e-3) / 1e9
+    bwb = bwd_bytes_per_pass(D, A, V)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pin-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{name}: seeded levelized DAG, {s['n_pins']} pins, {L} levels, "
+                               f"geometric fanin (mean 2.5, max 16), 16 fanout-64 nets, RC chains 2-8 nodes, "
+                               f"128 NLDM 7x7 table pairs, late+early views; FP32 propagation, FP64 RC moments",
+                   "pins": s["n_pins"], "primary_inputs": d.n_pi, "gates": G, "arcs": A, "rc_nodes": M,
+                   "levels": L, "endpoints": E, "views": ["late", "early"],
+                   "step": "delay_calc + propagate(late,early) + slack(late,early)"},
+        "roofline": {"bound": "hbm", "kernel": "k_forward", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": fwd_launch_bytes, "avg_launch_us": fwd_avg_ms * 1e3,
+                     "launches_per_step": int(k_fwd[0] // args.steps)},
+        "propagate_ms": ms_prop,
+        "propagate_pin_updates_per_s": updates / (ms_prop * 1e-3),
+        "kernels": kernels,
+        "algorithmic_bytes_per_step": {"delay_calc": dcb, "forward": fwd_bytes_per_pass(G, A, V),
+                                       "backward": bwb},
+        "pass_GB_s": (dcb + fwd_bytes_per_pass(G, A, V) + bwb) / (ms_step * 1e-3) / 1e9,
+        "host": {"generate_s": t_gen, "build_graph_s": t_build, "upload_s": t_upload,
+                 "graph_bytes": s["graph_bytes"]},
+    }
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(d, lib, pa, ps, late, early, updates, args.cpu_seconds, g, nd, tm, sl)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(d, lib, pa, ps, late, early, updates, budget_s, g, nd, tm, sl):
+    """The oracle as it stands, single-threaded on a host core, over whole passes of the
+    same workload; its last results are also compared bit for bit with the GPU's."""
+    import oracle
+    t_pass = []
+    res = None
+    t_all = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        res = oracle.run(d, lib, pa, ps, late, early, modes=(oracle.LATE, oracle.EARLY))
+        t_pass.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_all > budget_s or len(t_pass) >= 200:
+            break
+    sec = float(np.median(t_pass))
+    D, A = d.n_drivers, d.n_arcs
+    same = True
+    h = {k: v.cpu().numpy() for k, v in list(nd.items()) + list(tm.items()) + list(sl.items()) if k != "scratch"}
+    chk = [(g.drv_to_input(h["load"][:D]), res["load"]), (g.arc_to_input(h["net_delay"][:A]), res["net_delay"])]
+    for v, m in enumerate(("late", "early")):
+        r = res[m]
+        chk += [(g.drv_to_input(h["drv_ts"][:D, v, 0]), r["at_drv"]), (g.drv_to_input(h["drv_ts"][:D, v, 1]), r["slew_drv"]),
+                (g.arc_to_input(h["arc_ts"][:A, v, 0]), r["at_in"]), (g.arc_to_input(h["arc_delay"][:A, v]), r["arc_delay"]),
+                (g.drv_to_input(h["drv_slack"][:D, v]), r["slack_drv"]), (g.arc_to_input(h["arc_slack"][:A, v]), r["slack_in"]),
+                (np.array([h["tns"][v]]), np.array([r["tns"]]))]
+    for got, want in chk:
+        same = same and np.array_equal(np.ascontiguousarray(got).view(np.uint8), np.ascontiguousarray(want).view(np.uint8))
+    return {"value": updates / sec, "unit": "pin-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(t_pass)} whole passes of the same workload (delay calc + late/early propagate + slack), "
+                      f"median {sec * 1e3:.1f} ms per pass, single-threaded C (gcc -O2)",
+            "gpu_bitwise_equal": bool(same)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,432 @@
+// Host side of the library: design validation, levelization, the level-sorted CSR and
+// the wave-sized work tiles, the device image and its upload.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sta_internal.h"
+
+namespace sta {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+sta_status fail(sta_status st, const std::string& msg) {
+    set_error(msg);
+    return st;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+DevGraph dev_graph(const sta_graph* g) {
+    DevGraph d{};
+    const DevLayout& L = g->lay;
+    uint8_t* b = g->dev;
+    d.net_node_ptr = reinterpret_cast<const int32_t*>(b + L.net_node_ptr);
+    d.node_parent = reinterpret_cast<const int16_t*>(b + L.node_parent);
+    d.node_R = reinterpret_cast<const float*>(b + L.node_R);
+    d.node_C = reinterpret_cast<const float*>(b + L.node_C);
+    d.fo_ptr = reinterpret_cast<const int32_t*>(b + L.fo_ptr);
+    d.fo_arc = reinterpret_cast<const int32_t*>(b + L.fo_arc);
+    d.fo_tap = reinterpret_cast<const uint8_t*>(b + L.fo_tap);
+    d.fo_cap = reinterpret_cast<const float*>(b + L.fo_cap);
+    d.arc_src = reinterpret_cast<const int32_t*>(b + L.arc_src);
+    d.arc_meta = reinterpret_cast<const uint32_t*>(b + L.arc_meta);
+    d.ftile_arc = reinterpret_cast<const int32_t*>(b + L.ftile_arc);
+    d.ftile_gate = reinterpret_cast<const int32_t*>(b + L.ftile_gate);
+    d.btile_drv = reinterpret_cast<const int32_t*>(b + L.btile_drv);
+    d.btile_slot = reinterpret_cast<const int32_t*>(b + L.btile_slot);
+    d.bslot_arc = reinterpret_cast<const int32_t*>(b + L.bslot_arc);
+    d.bslot_out = reinterpret_cast<const int32_t*>(b + L.bslot_out);
+    d.ep_drv = reinterpret_cast<const int32_t*>(b + L.ep_drv);
+    d.n_pi = g->n_pi;
+    d.n_gates = g->n_gates;
+    d.n_drivers = static_cast<int32_t>(g->D);
+    d.n_arcs = static_cast<int32_t>(g->A);
+    return d;
+}
+
+static bool finite_nonneg(float v) { return std::isfinite(v) && v >= 0.0f; }
+
+static sta_status build(const sta_design_desc* d, sta_graph* g) {
+    if (!d) return fail(STA_E_ARG, "sta_build_graph: null design");
+    if (d->n_pi < 0 || d->n_gates < 0) return fail(STA_E_ARG, "sta_build_graph: negative n_pi or n_gates");
+    if (d->n_tables < 1 || d->n_tables > STA_MAX_TABLES)
+        return fail(STA_E_ARG, "sta_build_graph: n_tables must be in 1..65535");
+    const int64_t G = d->n_gates, P = d->n_pi, D = P + G;
+    if (D > INT32_MAX / 2) return fail(STA_E_ARG, "sta_build_graph: too many drivers");
+    if (!d->gate_arc_ptr || !d->net_node_ptr) return fail(STA_E_ARG, "sta_build_graph: null gate_arc_ptr or net_node_ptr");
+    if (d->gate_arc_ptr[0] != 0) return fail(STA_E_ARG, "sta_build_graph: gate_arc_ptr[0] != 0");
+    int max_fanin = 0;
+    for (int64_t q = 0; q < G; ++q) {
+        int64_t k = int64_t(d->gate_arc_ptr[q + 1]) - d->gate_arc_ptr[q];
+        if (k < 1 || k > STA_MAX_FANIN)
+            return fail(STA_E_ARG, "sta_build_graph: gate " + std::to_string(q) + " has " + std::to_string(k) +
+                                       " arcs (allowed 1.." + std::to_string(STA_MAX_FANIN) + ")");
+        max_fanin = std::max<int>(max_fanin, int(k));
+    }
+    const int64_t A = d->gate_arc_ptr[G];
+    if (A > INT32_MAX / 2) return fail(STA_E_ARG, "sta_build_graph: too many arcs");
+    if (A > 0 && (!d->arc_drv || !d->arc_tbl || !d->arc_tap || !d->arc_pincap))
+        return fail(STA_E_ARG, "sta_build_graph: null arc array");
+    if (d->net_node_ptr[0] != 0) return fail(STA_E_ARG, "sta_build_graph: net_node_ptr[0] != 0");
+    int max_nodes = 0;
+    for (int64_t u = 0; u < D; ++u) {
+        int64_t m = int64_t(d->net_node_ptr[u + 1]) - d->net_node_ptr[u];
+        if (m < 1 || m > STA_MAX_NET_NODES)
+            return fail(STA_E_ARG, "sta_build_graph: net of driver " + std::to_string(u) + " has " +
+                                       std::to_string(m) + " nodes (allowed 1.." + std::to_string(STA_MAX_NET_NODES) + ")");
+        max_nodes = std::max<int>(max_nodes, int(m));
+    }
+    const int64_t M = d->net_node_ptr[D];
+    if (M > 0 && (!d->node_parent || !d->node_R || !d->node_C)) return fail(STA_E_ARG, "sta_build_graph: null node array");
+    for (int64_t u = 0; u < D; ++u) {
+        int64_t n0 = d->net_node_ptr[u], m = d->net_node_ptr[u + 1] - n0;
+        if (d->node_parent[n0] != -1) return fail(STA_E_RANGE, "sta_build_graph: node 0 of net " + std::to_string(u) + " has a parent");
+        for (int64_t k = 1; k < m; ++k) {
+            int32_t p = d->node_parent[n0 + k];
+            if (p < 0 || p >= k)
+                return fail(STA_E_RANGE, "sta_build_graph: net " + std::to_string(u) + " node " + std::to_string(k) +
+                                             " has parent " + std::to_string(p) + " (must be in 0..node-1)");
+        }
+    }
+    for (int64_t k = 0; k < M; ++k) {
+        if (!finite_nonneg(d->node_C[k])) return fail(STA_E_NONFINITE, "sta_build_graph: node_C[" + std::to_string(k) + "] is not finite and >= 0");
+        if (!finite_nonneg(d->node_R[k])) return fail(STA_E_NONFINITE, "sta_build_graph: node_R[" + std::to_string(k) + "] is not finite and >= 0");
+    }
+    for (int64_t a = 0; a < A; ++a) {
+        int32_t u = d->arc_drv[a];
+        if (u < 0 || u >= D) return fail(STA_E_RANGE, "sta_build_graph: arc " + std::to_string(a) + " driver " + std::to_string(u) + " out of range");
+        if (d->arc_tbl[a] < 0 || d->arc_tbl[a] >= d->n_tables)
+            return fail(STA_E_RANGE, "sta_build_graph: arc " + std::to_string(a) + " table out of range");
+        int32_t m = d->net_node_ptr[u + 1] - d->net_node_ptr[u];
+        if (d->arc_tap[a] < 0 || d->arc_tap[a] >= m)
+            return fail(STA_E_RANGE, "sta_build_graph: arc " + std::to_string(a) + " taps node " + std::to_string(d->arc_tap[a]) +
+                                         " of a " + std::to_string(m) + "-node net");
+        if (!finite_nonneg(d->arc_pincap[a])) return fail(STA_E_NONFINITE, "sta_build_graph: arc_pincap[" + std::to_string(a) + "] is not finite and >= 0");
+    }
+
+    // ---- levelize (Kahn) -------------------------------------------------------------
+    std::vector<int32_t> fo_cnt(D + 1, 0), fo_ptr_in(D + 1, 0), fo_in(A);
+    for (int64_t a = 0; a < A; ++a) fo_cnt[d->arc_drv[a]]++;
+    for (int64_t u = 0; u < D; ++u) fo_ptr_in[u + 1] = fo_ptr_in[u] + fo_cnt[u];
+    {
+        std::vector<int32_t> fill(fo_ptr_in.begin(), fo_ptr_in.end() - 1);
+        for (int64_t a = 0; a < A; ++a) fo_in[fill[d->arc_drv[a]]++] = int32_t(a);   // ascending input arc id
+    }
+    std::vector<int32_t> gate_of_arc(A);
+    for (int64_t q = 0; q < G; ++q)
+        for (int32_t a = d->gate_arc_ptr[q]; a < d->gate_arc_ptr[q + 1]; ++a) gate_of_arc[a] = int32_t(q);
+    std::vector<int32_t> indeg(G, 0), lev(D, 0), queue;
+    queue.reserve(G);
+    for (int64_t a = 0; a < A; ++a)
+        if (d->arc_drv[a] >= P) indeg[gate_of_arc[a]]++;
+    for (int64_t q = 0; q < G; ++q)
+        if (indeg[q] == 0) queue.push_back(int32_t(q));
+    for (size_t h = 0; h < queue.size(); ++h) {
+        int32_t q = queue[h];
+        int32_t lv = 0;
+        for (int32_t a = d->gate_arc_ptr[q]; a < d->gate_arc_ptr[q + 1]; ++a) lv = std::max(lv, lev[d->arc_drv[a]]);
+        lev[P + q] = lv + 1;
+        int64_t o = P + q;
+        for (int32_t i = fo_ptr_in[o]; i < fo_ptr_in[o + 1]; ++i) {
+            int32_t c = gate_of_arc[fo_in[i]];
+            if (--indeg[c] == 0) queue.push_back(c);
+        }
+    }
+    if (int64_t(queue.size()) != G)
+        return fail(STA_E_CYCLE, "sta_build_graph: combinational cycle through " + std::to_string(G - queue.size()) + " gates");
+    int32_t Lmax = 0;
+    for (int64_t u = 0; u < D; ++u) Lmax = std::max(Lmax, lev[u]);
+
+    // ---- internal numbering: gates by (level, input id) ------------------------------
+    std::vector<int32_t> lvl_cnt(Lmax + 2, 0);
+    for (int64_t q = 0; q < G; ++q) lvl_cnt[lev[P + q]]++;
+    std::vector<int32_t> lvl_gate_ptr(Lmax + 2, 0);   // gates of level l: [ptr[l-1], ptr[l]) with ptr[0] = 0
+    for (int32_t l = 1; l <= Lmax; ++l) lvl_gate_ptr[l] = lvl_gate_ptr[l - 1] + lvl_cnt[l];
+    std::vector<int32_t> gate_int(G), gate_in(G);
+    {
+        std::vector<int32_t> fill(Lmax + 1, 0);
+        for (int32_t l = 1; l <= Lmax; ++l) fill[l] = lvl_gate_ptr[l - 1];
+        for (int64_t q = 0; q < G; ++q) {
+            int32_t i = fill[lev[P + q]]++;
+            gate_int[q] = i;
+            gate_in[i] = int32_t(q);
+        }
+    }
+    auto drv_int = [&](int64_t u) -> int32_t { return u < P ? int32_t(u) : int32_t(P + gate_int[u - P]); };
+    g->drv_input.resize(D);
+    g->level.resize(D);
+    for (int64_t u = 0; u < D; ++u) {
+        int32_t i = drv_int(u);
+        g->drv_input[i] = int32_t(u);
+        g->level[i] = lev[u];
+    }
+    g->gate_input = gate_in;
+    std::vector<int32_t> arc_int(A), gate_arc_ptr_int(G + 1, 0);
+    g->arc_input.resize(A);
+    for (int64_t i = 0; i < G; ++i) {
+        int32_t q = gate_in[i];
+        int32_t k = d->gate_arc_ptr[q + 1] - d->gate_arc_ptr[q];
+        gate_arc_ptr_int[i + 1] = gate_arc_ptr_int[i] + k;
+        for (int32_t j = 0; j < k; ++j) {
+            int32_t a = d->gate_arc_ptr[q] + j;
+            arc_int[a] = gate_arc_ptr_int[i] + j;
+            g->arc_input[gate_arc_ptr_int[i] + j] = a;
+        }
+    }
+
+    // ---- endpoints -------------------------------------------------------------------
+    std::vector<int32_t> ep_rank_in(D, -1);
+    int64_t E = 0;
+    for (int64_t u = 0; u < D; ++u)
+        if (fo_cnt[u] == 0) ep_rank_in[u] = int32_t(E++);
+    g->ep_driver.resize(E);
+    for (int64_t u = 0; u < D; ++u)
+        if (ep_rank_in[u] >= 0) g->ep_driver[ep_rank_in[u]] = drv_int(u);
+
+    int max_fanout = 0;
+    for (int64_t u = 0; u < D; ++u) max_fanout = std::max(max_fanout, fo_cnt[u]);
+
+    // ---- forward tiles: consecutive whole gates of one level, <= 64 arcs -------------
+    std::vector<int32_t> ftile_arc, ftile_gate;
+    g->fwd_tile_ptr.assign(Lmax + 2, 0);
+    for (int32_t l = 1; l <= Lmax; ++l) {
+        g->fwd_tile_ptr[l] = int32_t(ftile_arc.size());
+        int32_t q0 = lvl_gate_ptr[l - 1], q1 = lvl_gate_ptr[l];
+        int32_t q = q0;
+        while (q < q1) {
+            ftile_arc.push_back(gate_arc_ptr_int[q]);
+            ftile_gate.push_back(q);
+            int32_t used = 0;
+            while (q < q1 && used + (gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q]) <= kTileSlots) {
+                used += gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q];
+                ++q;
+            }
+        }
+    }
+    g->fwd_tile_ptr[Lmax + 1] = int32_t(ftile_arc.size());
+    const int64_t NF = int64_t(ftile_arc.size());
+    ftile_arc.push_back(int32_t(A));
+    ftile_gate.push_back(int32_t(G));
+
+    // ---- internal sink lists and backward slots --------------------------------------
+    // driver i's slots: one per sink (ascending input arc id), or one endpoint slot
+    std::vector<int32_t> fo_ptr(D + 1, 0), fo_arc(A);
+    std::vector<uint8_t> fo_tap(A);
+    std::vector<float> fo_cap(A);
+    for (int64_t i = 0; i < D; ++i) fo_ptr[i + 1] = fo_ptr[i] + fo_cnt[g->drv_input[i]];
+    for (int64_t i = 0; i < D; ++i) {
+        int32_t u = g->drv_input[i];
+        for (int32_t j = 0; j < fo_cnt[u]; ++j) {
+            int32_t a = fo_in[fo_ptr_in[u] + j];
+            fo_arc[fo_ptr[i] + j] = arc_int[a];
+            fo_tap[fo_ptr[i] + j] = uint8_t(d->arc_tap[a]);
+            fo_cap[fo_ptr[i] + j] = d->arc_pincap[a];
+        }
+    }
+    std::vector<int32_t> slot_ptr(D + 1, 0);
+    for (int64_t i = 0; i < D; ++i) slot_ptr[i + 1] = slot_ptr[i] + std::max(1, fo_ptr[i + 1] - fo_ptr[i]);
+    const int64_t S = slot_ptr[D];
+    std::vector<int32_t> bslot_arc(S), bslot_out(S);
+    std::vector<int32_t> int_gate_of_arc(A);
+    for (int64_t i = 0; i < G; ++i)
+        for (int32_t a = gate_arc_ptr_int[i]; a < gate_arc_ptr_int[i + 1]; ++a) int_gate_of_arc[a] = int32_t(i);
+    for (int64_t i = 0; i < D; ++i) {
+        int32_t nfo = fo_ptr[i + 1] - fo_ptr[i];
+        if (nfo == 0) {
+            bslot_arc[slot_ptr[i]] = -1;
+            bslot_out[slot_ptr[i]] = int32_t(uint32_t(ep_rank_in[g->drv_input[i]]) | kHeadBit);
+        } else {
+            for (int32_t j = 0; j < nfo; ++j) {
+                int32_t a = fo_arc[fo_ptr[i] + j];
+                bslot_arc[slot_ptr[i] + j] = a;
+                uint32_t o = uint32_t(P + int_gate_of_arc[a]);
+                bslot_out[slot_ptr[i] + j] = int32_t(o | (j == 0 ? kHeadBit : 0u));
+            }
+        }
+    }
+    // backward tiles: consecutive drivers of one level, <= 64 slots, or one large driver
+    std::vector<int32_t> btile_drv, btile_slot;
+    g->bwd_tile_ptr.assign(Lmax + 2, 0);
+    for (int32_t l = 0; l <= Lmax; ++l) {
+        g->bwd_tile_ptr[l] = int32_t(btile_drv.size());
+        int64_t i0 = (l == 0) ? 0 : P + lvl_gate_ptr[l - 1];
+        int64_t i1 = (l == 0) ? P : P + lvl_gate_ptr[l];
+        int64_t i = i0;
+        while (i < i1) {
+            btile_drv.push_back(int32_t(i));
+            btile_slot.push_back(slot_ptr[i]);
+            int32_t first = slot_ptr[i + 1] - slot_ptr[i];
+            if (first > kTileSlots) { ++i; continue; }
+            int32_t used = 0;
+            while (i < i1 && slot_ptr[i + 1] - slot_ptr[i] <= kTileSlots && used + (slot_ptr[i + 1] - slot_ptr[i]) <= kTileSlots) {
+                used += slot_ptr[i + 1] - slot_ptr[i];
+                ++i;
+            }
+        }
+    }
+    g->bwd_tile_ptr[Lmax + 1] = int32_t(btile_drv.size());
+    const int64_t NB = int64_t(btile_drv.size());
+    btile_drv.push_back(int32_t(D));
+    btile_slot.push_back(int32_t(S));
+
+    // ---- internal arcs and nets --------------------------------------------------------
+    std::vector<int32_t> arc_src(A);
+    std::vector<uint32_t> arc_meta(A);
+    for (int64_t i = 0; i < A; ++i) {
+        int32_t a = g->arc_input[i];
+        arc_src[i] = drv_int(d->arc_drv[a]);
+        uint32_t kpos = uint32_t(i - gate_arc_ptr_int[int_gate_of_arc[i]]);
+        arc_meta[i] = uint32_t(d->arc_tbl[a]) | (kpos << 16);
+    }
+    std::vector<int32_t> net_ptr(D + 1, 0);
+    for (int64_t i = 0; i < D; ++i) {
+        int32_t u = g->drv_input[i];
+        net_ptr[i + 1] = net_ptr[i] + (d->net_node_ptr[u + 1] - d->net_node_ptr[u]);
+    }
+    std::vector<int16_t> node_parent(M);
+    std::vector<float> node_R(M), node_C(M);
+    for (int64_t i = 0; i < D; ++i) {
+        int32_t u = g->drv_input[i];
+        int32_t s0 = d->net_node_ptr[u], m = d->net_node_ptr[u + 1] - s0;
+        for (int32_t k = 0; k < m; ++k) {
+            node_parent[net_ptr[i] + k] = int16_t(d->node_parent[s0 + k]);
+            node_R[net_ptr[i] + k] = d->node_R[s0 + k];
+            node_C[net_ptr[i] + k] = d->node_C[s0 + k];
+        }
+    }
+
+    // ---- device image --------------------------------------------------------------------
+    DevLayout& lay = g->lay;
+    size_t off = 0;
+    auto place = [&](size_t bytes) { size_t o = off; off = align256(off + std::max<size_t>(bytes, 1)); return o; };
+    lay.net_node_ptr = place((D + 1) * 4);
+    lay.node_parent = place(M * 2);
+    lay.node_R = place(M * 4);
+    lay.node_C = place(M * 4);
+    lay.fo_ptr = place((D + 1) * 4);
+    lay.fo_arc = place(A * 4);
+    lay.fo_tap = place(A);
+    lay.fo_cap = place(A * 4);
+    lay.arc_src = place(A * 4);
+    lay.arc_meta = place(A * 4);
+    lay.ftile_arc = place((NF + 1) * 4);
+    lay.ftile_gate = place((NF + 1) * 4);
+    lay.btile_drv = place((NB + 1) * 4);
+    lay.btile_slot = place((NB + 1) * 4);
+    lay.bslot_arc = place(S * 4);
+    lay.bslot_out = place(S * 4);
+    lay.ep_drv = place(E * 4);
+    lay.total = off;
+    g->image.assign(off, 0);
+    auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) std::memcpy(g->image.data() + o, src, bytes); };
+    put(lay.net_node_ptr, net_ptr.data(), (D + 1) * 4);
+    put(lay.node_parent, node_parent.data(), M * 2);
+    put(lay.node_R, node_R.data(), M * 4);
+    put(lay.node_C, node_C.data(), M * 4);
+    put(lay.fo_ptr, fo_ptr.data(), (D + 1) * 4);
+    put(lay.fo_arc, fo_arc.data(), A * 4);
+    put(lay.fo_tap, fo_tap.data(), A);
+    put(lay.fo_cap, fo_cap.data(), A * 4);
+    put(lay.arc_src, arc_src.data(), A * 4);
+    put(lay.arc_meta, arc_meta.data(), A * 4);
+    put(lay.ftile_arc, ftile_arc.data(), (NF + 1) * 4);
+    put(lay.ftile_gate, ftile_gate.data(), (NF + 1) * 4);
+    put(lay.btile_drv, btile_drv.data(), (NB + 1) * 4);
+    put(lay.btile_slot, btile_slot.data(), (NB + 1) * 4);
+    put(lay.bslot_arc, bslot_arc.data(), S * 4);
+    put(lay.bslot_out, bslot_out.data(), S * 4);
+    put(lay.ep_drv, g->ep_driver.data(), E * 4);
+
+    g->n_pi = int32_t(P);
+    g->n_gates = int32_t(G);
+    g->n_tables = d->n_tables;
+    g->D = D; g->A = A; g->M = M; g->L = Lmax; g->E = E; g->S = S;
+    g->max_fanin = max_fanin;
+    g->max_fanout = max_fanout;
+    g->max_net_nodes = max_nodes;
+    g->n_ftiles = NF;
+    g->n_btiles = NB;
+    return STA_OK;
+}
+
+}  // namespace sta
+
+extern "C" {
+
+const char* sta_last_error(void) { return sta::g_last_error.c_str(); }
+
+sta_status sta_build_graph(const sta_design_desc* d, sta_graph** out) {
+    if (!out) return sta::fail(STA_E_ARG, "sta_build_graph: null out");
+    sta_graph* g = nullptr;
+    try {
+        g = new sta_graph();
+        sta_status st = sta::build(d, g);
+        if (st != STA_OK) { delete g; return st; }
+    } catch (const std::bad_alloc&) {
+        delete g;
+        return sta::fail(STA_E_ALLOC, "sta_build_graph: out of host memory");
+    } catch (...) {
+        delete g;
+        return sta::fail(STA_E_ARG, "sta_build_graph: unexpected failure");
+    }
+    *out = g;
+    return STA_OK;
+}
+
+sta_status sta_graph_sizes(const sta_graph* g, sta_sizes* s) {
+    if (!g || !s) return sta::fail(STA_E_ARG, "sta_graph_sizes: null argument");
+    s->n_pi = g->n_pi;
+    s->n_gates = g->n_gates;
+    s->n_drivers = g->D;
+    s->n_arcs = g->A;
+    s->n_nodes = g->M;
+    s->n_pins = g->D + g->A;
+    s->n_levels = g->L;
+    s->n_endpoints = g->E;
+    s->max_fanin = g->max_fanin;
+    s->max_fanout = g->max_fanout;
+    s->max_net_nodes = g->max_net_nodes;
+    s->n_fwd_tiles = g->n_ftiles;
+    s->n_bwd_tiles = g->n_btiles;
+    s->graph_bytes = g->lay.total;
+    s->scratch_bytes = sta::scratch_bytes();
+    return STA_OK;
+}
+
+sta_status sta_graph_perm(const sta_graph* g, int32_t* drv_input, int32_t* arc_input, int32_t* gate_input,
+                          int32_t* level, int32_t* ep_driver) {
+    if (!g) return sta::fail(STA_E_ARG, "sta_graph_perm: null graph");
+    auto cp = [](int32_t* dst, const std::vector<int32_t>& v) { if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * 4); };
+    cp(drv_input, g->drv_input);
+    cp(arc_input, g->arc_input);
+    cp(gate_input, g->gate_input);
+    cp(level, g->level);
+    cp(ep_driver, g->ep_driver);
+    return STA_OK;
+}
+
+sta_status sta_graph_upload(sta_graph* g, void* dev_buf, size_t bytes, void* stream) {
+    if (!g || !dev_buf) return sta::fail(STA_E_ARG, "sta_graph_upload: null argument");
+    if (bytes < g->lay.total) return sta::fail(STA_E_ARG, "sta_graph_upload: buffer smaller than graph_bytes");
+    if (reinterpret_cast<uintptr_t>(dev_buf) % 256 != 0) return sta::fail(STA_E_ARG, "sta_graph_upload: buffer not 256-byte aligned");
+    hipError_t e = hipMemcpyAsync(dev_buf, g->image.data(), g->lay.total, hipMemcpyHostToDevice,
+                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return sta::fail(STA_E_HIP, std::string("sta_graph_upload: hipMemcpyAsync: ") + hipGetErrorString(e));
+    e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return sta::fail(STA_E_HIP, std::string("sta_graph_upload: hipStreamSynchronize: ") + hipGetErrorString(e));
+    g->dev = static_cast<uint8_t*>(dev_buf);
+    return STA_OK;
+}
+
+void sta_graph_free(sta_graph* g) { delete g; }
+
+}  // extern "C"

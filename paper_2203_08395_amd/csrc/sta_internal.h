@@ -1,0 +1,69 @@
+// Internal layout of an sta_graph: host-side maps and the device array offsets.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sta.h"
+
+namespace sta {
+
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kTileSlots = 64;      // one work tile = one wavefront of arcs / fanout slots
+constexpr uint32_t kHeadBit = 0x80000000u;
+
+// Device arrays of a graph (offsets in bytes into the one device buffer).
+struct DevLayout {
+    size_t net_node_ptr, node_parent, node_R, node_C;
+    size_t fo_ptr, fo_arc, fo_tap, fo_cap;
+    size_t arc_src, arc_meta;
+    size_t ftile_arc, ftile_gate;
+    size_t btile_drv, btile_slot, bslot_arc, bslot_out;
+    size_t ep_drv;
+    size_t total;
+};
+
+// Device pointers handed to the kernels by value.
+struct DevGraph {
+    const int32_t* net_node_ptr;   // [D+1]
+    const int16_t* node_parent;    // [M] local parent, -1 at node 0
+    const float* node_R;           // [M]
+    const float* node_C;           // [M]
+    const int32_t* fo_ptr;         // [D+1] sink list of every driver
+    const int32_t* fo_arc;         // [A]   internal arc of each sink, ascending input arc id
+    const uint8_t* fo_tap;         // [A]   RC node tapped by that sink
+    const float* fo_cap;           // [A]   its pin capacitance
+    const int32_t* arc_src;        // [A]   internal driver of the net feeding the arc
+    const uint32_t* arc_meta;      // [A]   table id | (position in gate) << 16
+    const int32_t* ftile_arc;      // [NF+1] forward tile -> first arc
+    const int32_t* ftile_gate;     // [NF+1] forward tile -> first gate
+    const int32_t* btile_drv;      // [NB+1] backward tile -> first driver
+    const int32_t* btile_slot;     // [NB+1] backward tile -> first slot
+    const int32_t* bslot_arc;      // [S]   sink arc of the slot, -1 for an endpoint slot
+    const int32_t* bslot_out;      // [S]   driver of the sink's gate (or endpoint rank) | head bit
+    const int32_t* ep_drv;         // [E]   internal driver of each endpoint rank
+    int32_t n_pi, n_gates, n_drivers, n_arcs;
+};
+
+}  // namespace sta
+
+struct sta_graph {
+    int32_t n_pi = 0, n_gates = 0, n_tables = 0;
+    int64_t D = 0, A = 0, M = 0, L = 0, E = 0, S = 0;
+    int32_t max_fanin = 0, max_fanout = 0, max_net_nodes = 0;
+    std::vector<int32_t> drv_input, arc_input, gate_input, level, ep_driver;
+    std::vector<int32_t> fwd_tile_ptr;   // [L+2]: tiles of gate level l are [p[l], p[l+1])
+    std::vector<int32_t> bwd_tile_ptr;   // [L+2]: tiles of driver level l are [p[l], p[l+1])
+    int64_t n_ftiles = 0, n_btiles = 0;
+    sta::DevLayout lay{};
+    std::vector<uint8_t> image;          // host image of the device buffer
+    uint8_t* dev = nullptr;              // caller's device buffer after upload
+};
+
+namespace sta {
+void set_error(const std::string& msg);
+sta_status fail(sta_status st, const std::string& msg);
+DevGraph dev_graph(const sta_graph* g);
+size_t scratch_bytes();            // device scratch sta_slack needs (fixed size)
+}  // namespace sta

@@ -1,0 +1,301 @@
+"""Python binding of libsta.so: argument marshalling only.
+
+Every step of the timing path runs in the library's HIP kernels; this module allocates
+the device buffers with torch (device memory and the current stream are all torch
+provides), fills the C structs and raises ``StaError`` on a non-OK status.  There is no
+CPU fallback: without the built library (``python -m paper_2203_08395_amd.build``) every
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsta.so")
+
+STA_LATE, STA_EARLY = 0, 1
+STA_DC_FP64, STA_DC_FP32 = 0, 1
+MAX_VIEWS = 8
+_STATUS = {0: "OK", -1: "E_ARG", -2: "E_RANGE", -3: "E_CYCLE", -4: "E_NONFINITE", -5: "E_ALLOC", -6: "E_HIP"}
+
+_P = ctypes.c_void_p
+
+
+class StaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+class DesignDesc(ctypes.Structure):
+    _fields_ = [("n_pi", ctypes.c_int32), ("n_gates", ctypes.c_int32), ("n_tables", ctypes.c_int32),
+                ("gate_arc_ptr", _P), ("arc_drv", _P), ("arc_tbl", _P), ("arc_tap", _P), ("arc_pincap", _P),
+                ("net_node_ptr", _P), ("node_parent", _P), ("node_R", _P), ("node_C", _P)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("n_pi", "n_gates", "n_drivers", "n_arcs", "n_nodes", "n_pins", "n_levels", "n_endpoints",
+                 "max_fanin", "max_fanout", "max_net_nodes", "n_fwd_tiles", "n_bwd_tiles")] + \
+               [("graph_bytes", ctypes.c_size_t), ("scratch_bytes", ctypes.c_size_t)]
+
+
+class LibraryC(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_float * 7), ("y", ctypes.c_float * 7), ("tables", _P),
+                ("n_sets", ctypes.c_int32), ("n_tables", ctypes.c_int32)]
+
+
+class ViewsC(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int32), ("mode", ctypes.c_int32 * MAX_VIEWS),
+                ("table_set", ctypes.c_int32 * MAX_VIEWS)]
+
+
+class NetOut(ctypes.Structure):
+    _fields_ = [("load", _P), ("net_delay", _P), ("net_imp2", _P)]
+
+
+class TimingOut(ctypes.Structure):
+    _fields_ = [("drv_ts", _P), ("arc_ts", _P), ("arc_delay", _P), ("argmax", _P)]
+
+
+class SlackOut(ctypes.Structure):
+    _fields_ = [("drv_rat", _P), ("arc_rat", _P), ("drv_slack", _P), ("arc_slack", _P), ("tns", _P), ("wns", _P)]
+
+
+_lib = None
+
+EXPORTS = ("sta_last_error", "sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload",
+           "sta_graph_free", "sta_delay_calc", "sta_propagate", "sta_slack", "sta_profile_begin",
+           "sta_profile_end")
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+def load_library():
+    """Load libsta.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2203_08395_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.sta_last_error.restype = ctypes.c_char_p
+    lib.sta_last_error.argtypes = []
+    lib.sta_build_graph.argtypes = [ctypes.POINTER(DesignDesc), ctypes.POINTER(_P)]
+    lib.sta_graph_sizes.argtypes = [_P, ctypes.POINTER(Sizes)]
+    lib.sta_graph_perm.argtypes = [_P, _P, _P, _P, _P, _P]
+    lib.sta_graph_upload.argtypes = [_P, _P, ctypes.c_size_t, _P]
+    lib.sta_graph_free.argtypes = [_P]
+    lib.sta_graph_free.restype = None
+    lib.sta_delay_calc.argtypes = [_P, ctypes.c_int, ctypes.POINTER(NetOut), _P]
+    lib.sta_propagate.argtypes = [_P, ctypes.POINTER(LibraryC), ctypes.POINTER(ViewsC), _P,
+                                  ctypes.POINTER(NetOut), ctypes.POINTER(TimingOut), _P]
+    lib.sta_slack.argtypes = [_P, ctypes.POINTER(ViewsC), ctypes.POINTER(NetOut), ctypes.POINTER(TimingOut), _P,
+                              ctypes.POINTER(SlackOut), _P, ctypes.c_size_t, _P]
+    lib.sta_profile_begin.argtypes = []
+    lib.sta_profile_end.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    for f in ("sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload", "sta_delay_calc",
+              "sta_propagate", "sta_slack", "sta_profile_begin", "sta_profile_end"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st, what):
+    if st != 0:
+        msg = load_library().sta_last_error().decode(errors="replace")
+        raise StaError(st, msg or what)
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _ptr(t):
+    return None if t is None else _P(t.data_ptr())
+
+
+def _stream(torch, device):
+    return _P(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Graph:
+    """A levelized design (host side built by sta_build_graph); ``upload`` places it on a GPU."""
+
+    def __init__(self, design, n_tables=None):
+        lib = load_library()
+        self._keep = [_np(design.gate_arc_ptr, np.int32), _np(design.arc_drv, np.int32),
+                      _np(design.arc_tbl, np.int32), _np(design.arc_tap, np.int32),
+                      _np(design.arc_pincap, np.float32), _np(design.net_node_ptr, np.int32),
+                      _np(design.node_parent, np.int32), _np(design.node_R, np.float32),
+                      _np(design.node_C, np.float32)]
+        if n_tables is None:
+            n_tables = int(self._keep[2].max()) + 1 if self._keep[2].size else 1
+        d = DesignDesc(int(design.n_pi), int(design.n_gates), n_tables,
+                       *[_P(a.ctypes.data) for a in self._keep])
+        h = _P()
+        _check(lib.sta_build_graph(ctypes.byref(d), ctypes.byref(h)), "sta_build_graph")
+        self._h = h
+        self._keep = None
+        s = Sizes()
+        _check(lib.sta_graph_sizes(h, ctypes.byref(s)), "sta_graph_sizes")
+        self.sizes = {f: int(getattr(s, f)) for f, _ in Sizes._fields_}
+        D, A, G, E = (self.sizes[k] for k in ("n_drivers", "n_arcs", "n_gates", "n_endpoints"))
+        self.drv_input = np.zeros(D, np.int32)
+        self.arc_input = np.zeros(A, np.int32)
+        self.gate_input = np.zeros(G, np.int32)
+        self.level = np.zeros(D, np.int32)
+        self.ep_driver = np.zeros(E, np.int32)
+        _check(lib.sta_graph_perm(h, *[_P(a.ctypes.data) if a.size else None for a in
+                                       (self.drv_input, self.arc_input, self.gate_input, self.level,
+                                        self.ep_driver)]), "sta_graph_perm")
+        self.dev = None
+        self.device = None
+
+    def upload(self, device="cuda"):
+        import torch
+        lib = load_library()
+        nb = max(self.sizes["graph_bytes"], 256)
+        self.dev = torch.empty(nb, dtype=torch.uint8, device=device)
+        self.device = self.dev.device
+        _check(lib.sta_graph_upload(self._h, _P(self.dev.data_ptr()), nb, _stream(torch, self.device)),
+               "sta_graph_upload")
+        return self
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.sta_graph_free(h)
+            self._h = None
+
+    # maps from internal (level) order to input order
+    def drv_to_input(self, x):
+        out = np.empty_like(x)
+        out[self.drv_input] = x
+        return out
+
+    def arc_to_input(self, x):
+        out = np.empty_like(x)
+        out[self.arc_input] = x
+        return out
+
+    def gate_to_input(self, x):
+        out = np.empty_like(x)
+        out[self.gate_input] = x
+        return out
+
+
+def make_views(modes, table_sets=None):
+    v = ViewsC()
+    v.n_views = len(modes)
+    for i, m in enumerate(modes):
+        v.mode[i] = int(m)
+        v.table_set[i] = int(table_sets[i]) if table_sets is not None else 0
+    return v
+
+
+def make_library(x, y, tables):
+    """tables: device tensor [n_sets, K, 2, 7, 7] (or [K, 2, 7, 7]) float32."""
+    L = LibraryC()
+    for i in range(7):
+        L.x[i] = float(np.float32(x[i]))
+        L.y[i] = float(np.float32(y[i]))
+    if tables.dim() == 4:
+        tables = tables.unsqueeze(0)
+    L.tables = _P(tables.data_ptr())
+    L.n_sets = int(tables.shape[0])
+    L.n_tables = int(tables.shape[1])
+    L._tensor = tables
+    return L
+
+
+def delay_calc(g: Graph, precision=STA_DC_FP64, out=None):
+    import torch
+    D, A = g.sizes["n_drivers"], g.sizes["n_arcs"]
+    if out is None:
+        out = {"load": torch.empty(max(D, 1), dtype=torch.float32, device=g.device),
+               "net_delay": torch.empty(max(A, 1), dtype=torch.float32, device=g.device),
+               "net_imp2": torch.empty(max(A, 1), dtype=torch.float32, device=g.device)}
+    no = NetOut(_ptr(out["load"]), _ptr(out["net_delay"]), _ptr(out["net_imp2"]))
+    _check(load_library().sta_delay_calc(g.handle, int(precision), ctypes.byref(no), _stream(torch, g.device)),
+           "sta_delay_calc")
+    return out
+
+
+def _netout(nd):
+    return NetOut(_ptr(nd["load"]), _ptr(nd["net_delay"]), _ptr(nd["net_imp2"]))
+
+
+def alloc_timing(g: Graph, n_views):
+    import torch
+    D, A, G = g.sizes["n_drivers"], g.sizes["n_arcs"], g.sizes["n_gates"]
+    dev = g.device
+    return {"drv_ts": torch.empty((max(D, 1), n_views, 2), dtype=torch.float32, device=dev),
+            "arc_ts": torch.empty((max(A, 1), n_views, 2), dtype=torch.float32, device=dev),
+            "arc_delay": torch.empty((max(A, 1), n_views), dtype=torch.float32, device=dev),
+            "argmax": torch.empty((max(G, 1), n_views), dtype=torch.uint8, device=dev)}
+
+
+def propagate(g: Graph, lib: LibraryC, views: ViewsC, pi_ts, nd, out=None):
+    """pi_ts: device [n_pi, V, 2] float32 (arrival, slew) of the primary inputs."""
+    import torch
+    if out is None:
+        out = alloc_timing(g, views.n_views)
+    to = TimingOut(_ptr(out["drv_ts"]), _ptr(out["arc_ts"]), _ptr(out["arc_delay"]), _ptr(out["argmax"]))
+    no = _netout(nd)
+    _check(load_library().sta_propagate(g.handle, ctypes.byref(lib), ctypes.byref(views), _ptr(pi_ts),
+                                        ctypes.byref(no), ctypes.byref(to), _stream(torch, g.device)),
+           "sta_propagate")
+    return out
+
+
+def alloc_slack(g: Graph, n_views):
+    import torch
+    D, A = g.sizes["n_drivers"], g.sizes["n_arcs"]
+    dev = g.device
+    return {"drv_rat": torch.empty((max(D, 1), n_views), dtype=torch.float32, device=dev),
+            "arc_rat": torch.empty((max(A, 1), n_views), dtype=torch.float32, device=dev),
+            "drv_slack": torch.empty((max(D, 1), n_views), dtype=torch.float32, device=dev),
+            "arc_slack": torch.empty((max(A, 1), n_views), dtype=torch.float32, device=dev),
+            "tns": torch.empty(n_views, dtype=torch.float64, device=dev),
+            "wns": torch.empty(n_views, dtype=torch.float32, device=dev),
+            "scratch": torch.empty(g.sizes["scratch_bytes"], dtype=torch.uint8, device=dev)}
+
+
+def slack(g: Graph, views: ViewsC, nd, timing, ep_rat, out=None):
+    """ep_rat: device [E, V] float32 required time of each endpoint (rank order)."""
+    import torch
+    if out is None:
+        out = alloc_slack(g, views.n_views)
+    to = TimingOut(_ptr(timing["drv_ts"]), _ptr(timing["arc_ts"]), _ptr(timing["arc_delay"]),
+                   _ptr(timing["argmax"]))
+    so = SlackOut(_ptr(out["drv_rat"]), _ptr(out["arc_rat"]), _ptr(out["drv_slack"]), _ptr(out["arc_slack"]),
+                  _ptr(out["tns"]), _ptr(out["wns"]))
+    no = _netout(nd)
+    _check(load_library().sta_slack(g.handle, ctypes.byref(views), ctypes.byref(no), ctypes.byref(to),
+                                    _ptr(ep_rat), ctypes.byref(so), _ptr(out["scratch"]),
+                                    out["scratch"].numel(), _stream(torch, g.device)), "sta_slack")
+    return out
+
+
+def profile_begin():
+    _check(load_library().sta_profile_begin(), "sta_profile_begin")
+
+
+def profile_end():
+    """{kernel name: (launches, total ms)} of the launches since profile_begin (HIP events)."""
+    cap = 32
+    arr = (KernelStat * cap)()
+    n = ctypes.c_int32(0)
+    _check(load_library().sta_profile_end(arr, cap, ctypes.byref(n)), "sta_profile_end")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, cap))}

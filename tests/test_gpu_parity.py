@@ -1,0 +1,125 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, bit for bit: RC delay
+calculation (FP64 mode), forward arrival/slew/arc delay/argmax, backward required times,
+slacks, WNS and TNS, in every view."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_08395_amd import gen, sta
+from tests import tiny
+from tests.gpu_common import EARLY, LATE, assert_bitwise, compare_all, gpu_run, say, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def test_c1_late_and_early():
+    d, lib, pa, ps, late, early = workload("c1")
+    compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label="c1 10k pins")
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_tiny_designs(seed):
+    from tests.test_oracle_graph import _random_tiny
+    d, lib, pa, ps = _random_tiny(seed)
+    ep = oracle.endpoints(d)
+    rng = np.random.default_rng(seed)
+    rat = [rng.uniform(0, 2000, ep.size).astype(np.float32) for _ in range(2)]
+    compare_all(d, lib, pa, ps, rat, [LATE, EARLY], label=f"tiny seed {seed}")
+
+
+@pytest.mark.parametrize("nv", [1, 4, 8])
+def test_view_counts_and_corners(nv):
+    d = gen.make_design(n_pins=30000, n_levels=40, fanin="geom", seed=21, n_fanout64=2)
+    lib = gen.make_library(kappas=gen.CORNER_KAPPAS)
+    pa, ps = gen.make_pi(d, seed=5)
+    late, early = gen.make_rat(d, 40, late_per_level=70.0, hold=120.0)
+    modes = [LATE if v % 2 == 0 else EARLY for v in range(nv)]
+    sets = [(v // 2) % 4 for v in range(nv)]
+    rats = [late if m == LATE else early for m in modes]
+    compare_all(d, lib, pa, ps, rats, modes, sets, label=f"{nv} views over corners")
+
+
+def test_ragged_tiles_and_extremes():
+    # fanin 64 (a full wavefront), a 200-sink net (a backward tile of several passes),
+    # a 256-node RC tree and a one-gate level between wide ones
+    rng = np.random.default_rng(3)
+    n_pi = 70
+    gates = [list(range(64))]                                   # gate 0: fanin 64
+    gates += [[int(x)] for x in rng.integers(0, n_pi, 200)]     # gates 1..200
+    gates += [[0] + [n_pi + 1 + i for i in range(3)]]           # one deeper gate
+    gates += [[n_pi] * 1 for _ in range(200)]                   # 200 sinks on gate 0's output
+    nets = []
+    for u in range(n_pi + len(gates)):
+        m = 256 if u == 5 else int(rng.integers(2, 9))
+        parent = [-1] + [int(rng.integers(0, k)) for k in range(1, m)]
+        nets.append((parent, [0.0] + list(rng.uniform(10, 500, m - 1)), list(rng.uniform(0.1, 5, m))))
+    A = sum(len(x) for x in gates)
+    taps = []
+    sizes = [len(n[0]) for n in nets]
+    for ins in gates:
+        for u in ins:
+            taps.append(int(rng.integers(0, sizes[u])))
+    d = tiny.design(n_pi, gates, nets, pincaps=list(rng.uniform(1, 4, A)), tables=list(rng.integers(0, 128, A)),
+                    taps=taps)
+    lib = gen.make_library()
+    pa = rng.uniform(0, 50, n_pi).astype(np.float32)
+    ps = rng.uniform(5, 50, n_pi).astype(np.float32)
+    ep = oracle.endpoints(d)
+    rat = [rng.uniform(100, 900, ep.size).astype(np.float32) for _ in range(2)]
+    compare_all(d, lib, pa, ps, rat, [LATE, EARLY], label="ragged tiles and extremes")
+
+
+def test_ties_on_gpu():
+    same = tiny.chain_net([100.0, 50.0], [0.5, 0.5, 0.5])
+    one = ([-1], [0.0], [0.4])
+    # every primary input drives one sink through the same net: all candidates are equal
+    d = tiny.design(8, [[4, 3, 2, 1, 0], [5, 6, 7]], [same] * 8 + [one, one],
+                    pincaps=[2.0] * 8, tables=[1] * 8)
+    lib = gen.make_library(n_tables=2, seed=3)
+    g, h = compare_all(d, lib, np.full(8, 20.0, np.float32), np.full(8, 30.0, np.float32),
+                       [np.full(2, 500.0, np.float32)] * 2, [LATE, EARLY], label="equal candidates")
+    assert np.all(h["argmax"][:2] == 0)
+
+
+def test_pi_only_and_empty_designs():
+    d = tiny.design(3, [], [tiny.chain_net([5.0], [1.0, 1.0])] * 3)
+    lib = gen.make_library(n_tables=1, seed=1)
+    compare_all(d, lib, np.array([1, 2, 3], np.float32), np.array([5, 6, 7], np.float32),
+                [np.array([10, -1, 2.5], np.float32)] * 2, [LATE, EARLY], label="primary inputs only")
+    say("[gpu case] empty design")
+    d = tiny.design(0, [], [])
+    g, h = gpu_run(d, lib, np.zeros(0, np.float32), np.zeros(0, np.float32), [np.zeros(0, np.float32)],
+                   [LATE])
+    assert h["tns"][0] == 0.0 and np.isinf(h["wns"][0])
+
+
+def test_fp32_delay_calc_within_1e5():
+    d, lib, pa, ps, late, early = workload("c1")
+    say("[gpu case] fp32 delay calc c1")
+    import torch
+    g = sta.Graph(d, n_tables=128).upload("cuda")
+    nd = sta.delay_calc(g, sta.STA_DC_FP32)
+    torch.cuda.synchronize()
+    load, m1, imp2 = oracle.delay_calc(d)
+    gl = g.drv_to_input(nd["load"].cpu().numpy()[: d.n_drivers])
+    gm = g.arc_to_input(nd["net_delay"].cpu().numpy()[: d.n_arcs])
+    gi = g.arc_to_input(nd["net_imp2"].cpu().numpy()[: d.n_arcs])
+    assert np.all(np.abs(gl - load) <= 1e-5 * load)
+    assert np.all(np.abs(gm - m1) <= 1e-5 * m1)
+    scale = np.maximum(imp2, m1.astype(np.float64) ** 2)
+    assert np.all(np.abs(gi.astype(np.float64) - imp2) <= 1e-5 * scale)
+
+
+def test_deterministic_reruns():
+    d, lib, pa, ps, late, early = workload("c1")
+    say("[gpu case] determinism c1")
+    _, h1 = gpu_run(d, lib, pa, ps, [late, early], [LATE, EARLY])
+    _, h2 = gpu_run(d, lib, pa, ps, [late, early], [LATE, EARLY])
+    for k in h1:
+        assert_bitwise("rerun " + k, h1[k].reshape(-1), h2[k].reshape(-1))
+
+
+def test_c2_full_size_bitwise():
+    # the 1M-pin workload in the launch configuration the benchmark times
+    d, lib, pa, ps, late, early = workload("c2")
+    compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label="c2 1M pins")
