@@ -206,6 +206,17 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
                      const sta_timing_out* t, const float* ep_rat, const sta_slack_out* out,
                      void* scratch, size_t scratch_bytes, void* stream);
 
+/* Schedule of sta_propagate and sta_slack on graph g.  The view schedule (one workgroup
+ * per view walks every level, a workgroup barrier between levels) is used when the
+ * design's mean cell arcs per level is at most view_max_arcs_per_level (and the level
+ * data fits in LDS), the level schedule (one launch per level, all views per launch)
+ * otherwise.  0 forces the level schedule; a negative value restores the default (512).
+ * use_graphs != 0 (the default) lets the level schedule capture its launch sequence in a
+ * hipGraph on first use and replay it while the call's arguments stay the same (the
+ * capture is per graph and per call kind; a change of any pointer or view re-captures).
+ * Every choice gives identical results. */
+sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32_t use_graphs);
+
 /* Per-kernel timing record of the instrumentation calls below. */
 typedef struct {
     char name[48];        /* kernel name (template arguments dropped)      */

@@ -325,6 +325,8 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     lay.bslot_arc = place(S * 4);
     lay.bslot_out = place(S * 4);
     lay.ep_drv = place(E * 4);
+    lay.fwd_lvl = place((Lmax + 2) * 12);
+    lay.bwd_lvl = place((Lmax + 2) * 12);
     lay.total = off;
     g->image.assign(off, 0);
     auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) std::memcpy(g->image.data() + o, src, bytes); };
@@ -345,6 +347,31 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     put(lay.bslot_arc, bslot_arc.data(), S * 4);
     put(lay.bslot_out, bslot_out.data(), S * 4);
     put(lay.ep_drv, g->ep_driver.data(), E * 4);
+    // level tables: forward level l (1..L) owns tiles [f[l].t, f[l+1].t), arcs and gates from
+    // f[l].a and f[l].g on; backward level l (0..L) likewise with slots and drivers
+    std::vector<int32_t> flvl((Lmax + 2) * 3), blvl((Lmax + 2) * 3);
+    for (int32_t l = 0; l <= Lmax + 1; ++l) {
+        const int32_t ft = g->fwd_tile_ptr[l];
+        flvl[l * 3 + 0] = ft;
+        flvl[l * 3 + 1] = ftile_arc[ft];
+        flvl[l * 3 + 2] = ftile_gate[ft];
+        const int32_t bt = g->bwd_tile_ptr[l];
+        blvl[l * 3 + 0] = bt;
+        blvl[l * 3 + 1] = btile_slot[bt];
+        blvl[l * 3 + 2] = btile_drv[bt];
+    }
+    for (int32_t l = 0; l <= Lmax; ++l) {
+        if (l >= 1) {
+            g->max_ft = std::max(g->max_ft, flvl[(l + 1) * 3] - flvl[l * 3]);
+            g->max_fa = std::max(g->max_fa, flvl[(l + 1) * 3 + 1] - flvl[l * 3 + 1]);
+            g->max_fg = std::max(g->max_fg, flvl[(l + 1) * 3 + 2] - flvl[l * 3 + 2]);
+        }
+        g->max_bt = std::max(g->max_bt, blvl[(l + 1) * 3] - blvl[l * 3]);
+        g->max_bs = std::max(g->max_bs, blvl[(l + 1) * 3 + 1] - blvl[l * 3 + 1]);
+        g->max_bd = std::max(g->max_bd, blvl[(l + 1) * 3 + 2] - blvl[l * 3 + 2]);
+    }
+    put(lay.fwd_lvl, flvl.data(), flvl.size() * 4);
+    put(lay.bwd_lvl, blvl.data(), blvl.size() * 4);
 
     g->n_pi = int32_t(P);
     g->n_gates = int32_t(G);
@@ -355,6 +382,10 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     g->max_net_nodes = max_nodes;
     g->n_ftiles = NF;
     g->n_btiles = NB;
+    g->ftile_arc_h = ftile_arc;
+    g->ftile_gate_h = ftile_gate;
+    g->btile_slot_h = btile_slot;
+    g->btile_drv_h = btile_drv;
     return STA_OK;
 }
 
@@ -427,6 +458,13 @@ sta_status sta_graph_upload(sta_graph* g, void* dev_buf, size_t bytes, void* str
     return STA_OK;
 }
 
-void sta_graph_free(sta_graph* g) { delete g; }
+void sta_graph_free(sta_graph* g) {
+    if (!g) return;
+    for (sta::LaunchCache* c : {&g->fwd_cache, &g->bwd_cache}) {
+        if (c->exec) (void)hipGraphExecDestroy(c->exec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+    }
+    delete g;
+}
 
 }  // extern "C"

@@ -1,7 +1,10 @@
 // Internal layout of an sta_graph: host-side maps and the device array offsets.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -12,6 +15,8 @@ namespace sta {
 constexpr int kWave = 64;           // CDNA wavefront width
 constexpr int kTileSlots = 64;      // one work tile = one wavefront of arcs / fanout slots
 constexpr uint32_t kHeadBit = 0x80000000u;
+constexpr int32_t kDefaultViewSchedMaxArcs = 512;    // mean cell arcs per level
+constexpr size_t kViewTableLdsMax = 65536;            // LDS bytes for tables + axes
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
 struct DevLayout {
@@ -21,6 +26,7 @@ struct DevLayout {
     size_t ftile_arc, ftile_gate;
     size_t btile_drv, btile_slot, bslot_arc, bslot_out;
     size_t ep_drv;
+    size_t fwd_lvl, bwd_lvl;       // per level (first tile, first arc|slot, first gate|driver)
     size_t total;
 };
 
@@ -46,6 +52,13 @@ struct DevGraph {
     int32_t n_pi, n_gates, n_drivers, n_arcs;
 };
 
+// A captured launch sequence (hipGraph) reused while its arguments stay the same.
+struct LaunchCache {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 }  // namespace sta
 
 struct sta_graph {
@@ -54,8 +67,15 @@ struct sta_graph {
     int32_t max_fanin = 0, max_fanout = 0, max_net_nodes = 0;
     std::vector<int32_t> drv_input, arc_input, gate_input, level, ep_driver;
     std::vector<int32_t> fwd_tile_ptr;   // [L+2]: tiles of gate level l are [p[l], p[l+1])
+    std::vector<int32_t> ftile_arc_h, ftile_gate_h, btile_slot_h, btile_drv_h;   // host copies of the tiles
     std::vector<int32_t> bwd_tile_ptr;   // [L+2]: tiles of driver level l are [p[l], p[l+1])
     int64_t n_ftiles = 0, n_btiles = 0;
+    // per-level maxima: forward tiles/arcs/gates, backward tiles/slots/drivers
+    int32_t max_ft = 0, max_fa = 0, max_fg = 0, max_bt = 0, max_bs = 0, max_bd = 0;
+    int32_t view_sched_max_arcs = sta::kDefaultViewSchedMaxArcs;
+    bool use_graphs = true;              // replay level-schedule launch sequences from hipGraphs
+    mutable std::mutex cache_mu;
+    mutable sta::LaunchCache fwd_cache, bwd_cache;
     sta::DevLayout lay{};
     std::vector<uint8_t> image;          // host image of the device buffer
     uint8_t* dev = nullptr;              // caller's device buffer after upload

@@ -5,17 +5,21 @@
 // below is the same single rounded operation as in the operation order the header
 // documents, so results equal the CPU definition bit for bit.
 //
-// Work decomposition (one design, all views of a call at once):
-//   K1 k_delay_calc   one lane per net, level-free, node temporaries in LDS.
-//   K2 k_forward      one launch per gate level; a wavefront owns a tile of <= 64 cell
-//                     arcs of consecutive whole gates; per-gate max/argmax by a
-//                     segmented shuffle reduction inside the wavefront.
-//   K3 k_backward     one launch per driver level, highest first; a wavefront owns
-//                     <= 64 sink slots of consecutive drivers (or one large driver).
-//   K4 k_endpoint_*   WNS by min, TNS by exact integer (fixed-point) accumulation of
-//                     the negative endpoint slacks, rounded once to FP64.
+// Work decomposition.  The unit of work is a tile: one wavefront over <= 64 cell arcs of
+// consecutive whole gates of one level (forward), or over <= 64 sink slots of
+// consecutive drivers of one level (backward; a driver with more sinks gets a tile of
+// its own whose lanes take contiguous runs of its sinks).  Two schedules run the tiles:
+//   level schedule  one launch per level; every launch covers all views of the call.
+//                   For wide levels (the whole chip works on one level).
+//   view schedule   one 1024-lane workgroup per view walks every level itself, with only
+//                   a workgroup barrier between levels and the NLDM tables in LDS; the
+//                   views run on separate compute units.  For the usual narrow levels,
+//                   where a device-wide step (a launch or a grid barrier, >= 2 us on
+//                   MI355X) costs more than the level's own work on one compute unit.
+// K1 (RC delay calculation) is level-free: one lane per net.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -78,12 +82,11 @@ __global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict
 }
 
 // ---------------------------------------------------------------------------------
-// NLDM lookup helpers (shared by all views)
+// NLDM lookup helpers
 // ---------------------------------------------------------------------------------
 
 struct KLib {
-    float x[7], y[7];
-    float dx[6], dy[6];          // fl32(x[i+1]-x[i]), fl32(y[j+1]-y[j])
+    float ax[26];                // x[7], y[7], dx[6] = fl32(x[i+1]-x[i]), dy[6]
     const float* tables;         // [sets][K][2][49]
     int32_t n_tables;
 };
@@ -101,7 +104,7 @@ __device__ __forceinline__ int seg6(const float* ax, float v) {
     return i;
 }
 
-__device__ __forceinline__ float bilerp(const float* __restrict__ T, int i, int j, float tx, float ty) {
+__device__ __forceinline__ float bilerp(const float* T, int i, int j, float tx, float ty) {
     const float t00 = T[i * 7 + j], t01 = T[i * 7 + j + 1];
     const float t10 = T[(i + 1) * 7 + j], t11 = T[(i + 1) * 7 + j + 1];
     const float p = t00 + tx * (t10 - t00);
@@ -113,138 +116,109 @@ __device__ __forceinline__ uint64_t lanes_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }
 
+__device__ __forceinline__ void load_axes(float* s_ax, const KLib& lib) {
+    for (int i = threadIdx.x; i < 26; i += blockDim.x) s_ax[i] = lib.ax[i];
+}
+
 // ---------------------------------------------------------------------------------
-// K2: forward propagation of one gate level
+// forward tile: views v0 .. v0+NW-1 of an NV-view interleaved layout
 // ---------------------------------------------------------------------------------
 
-template <int NV>
-__global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
-                                                 const float* __restrict__ load,
-                                                 const float* __restrict__ nd,
-                                                 const float* __restrict__ ni,
-                                                 float* __restrict__ drv_ts, float* __restrict__ arc_ts,
-                                                 float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
-    __shared__ float s_ax[7 + 7 + 6 + 6];
-    if (threadIdx.x < 7) s_ax[threadIdx.x] = lib.x[threadIdx.x];
-    else if (threadIdx.x < 14) s_ax[threadIdx.x] = lib.y[threadIdx.x - 7];
-    else if (threadIdx.x < 20) s_ax[threadIdx.x] = lib.dx[threadIdx.x - 14];
-    else if (threadIdx.x < 26) s_ax[threadIdx.x] = lib.dy[threadIdx.x - 20];
-    __syncthreads();
+// one lane's cell arc in a tile (inputs gathered by the caller)
+struct FwdLane {
+    int a, g, gi, kpos, tb, seg_end;
+    bool active, head;
+    float nd, ni, Lo;
+};
+
+// gate heads, the lane's gate within the tile and its gate's end lane (wave-uniform call)
+__device__ __forceinline__ void fwd_lane_setup(FwdLane& x, bool act, uint32_t meta, int n, int lane) {
+    x.active = act;
+    x.kpos = int((meta >> 16) & 0xffu);
+    x.tb = int(meta & 0xffffu);
+    x.head = act && x.kpos == 0;
+    const uint64_t heads = __ballot(x.head);
+    const uint64_t le = lanes_le(lane);
+    x.gi = __popcll(heads & le) - 1;
+    const uint64_t after = heads & ~le;
+    x.seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : n;
+}
+
+// arc arithmetic, per-gate max/argmax (min for early views) and the writes
+template <int NW>
+__device__ __forceinline__ void fwd_finish(const FwdLane& x, const float2* ts, const float* s_ax,
+                                           const float* const* tab, const bool* early, int NV, int v0, int n_pi,
+                                           float* __restrict__ drv_ts, float* __restrict__ arc_ts,
+                                           float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
     const float* X = s_ax;
     const float* Y = s_ax + 7;
     const float* DX = s_ax + 14;
     const float* DY = s_ax + 20;
-
     const int lane = threadIdx.x & 63;
-    const int t = tile0 + blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= tile1) return;                      // uniform per wavefront
-    const int a0 = G.ftile_arc[t];
-    const int n = G.ftile_arc[t + 1] - a0;
-    const int g0 = G.ftile_gate[t];
-    const bool active = lane < n;
-    const int a = a0 + lane;
-    const uint32_t meta = active ? G.arc_meta[a] : 0u;
-    const int kpos = int((meta >> 16) & 0xffu);
-    const bool head = active && kpos == 0;
-    const uint64_t heads = __ballot(head);
-    const uint64_t le = lanes_le(lane);
-    const int gi = __popcll(heads & le) - 1;
-    const uint64_t after = heads & ~le;
-    const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : n;
-    const int g = g0 + gi;
-    const int o = G.n_pi + g;
-
-    float cand[NV], slw[NV];
-    int best_k[NV];
-    if (active) {
-        const int u = G.arc_src[a];
-        const float ndv = nd[a];
-        const float niv = ni[a];
-        const int tb = int(meta & 0xffffu);
-        const float Lo = load[o];
-        const int j = seg6(Y, Lo);
-        const float ty = (Lo - Y[j]) / DY[j];
-        float in_at[NV], in_sl[NV];
-        const float2* src = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV;
+    float cand[NW], slw[NW];
+    int best_k[NW];
+    if (x.active) {
+        const int j = seg6(Y, x.Lo);
+        const float ty = (x.Lo - Y[j]) / DY[j];
+        float2* dst = reinterpret_cast<float2*>(arc_ts) + size_t(x.a) * NV + v0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const float2 ts = src[v];
-            in_at[v] = ts.x;
-            in_sl[v] = ts.y;
-        }
-        float2* dst = reinterpret_cast<float2*>(arc_ts) + size_t(a) * NV;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const float ai = in_at[v] + ndv;
-            const float su2 = in_sl[v] * in_sl[v];
-            const float si = sqrtf(su2 + niv);
+        for (int w = 0; w < NW; ++w) {
+            const float ai = ts[w].x + x.nd;
+            const float su2 = ts[w].y * ts[w].y;
+            const float si = sqrtf(su2 + x.ni);
             const int i = seg6(X, si);
             const float tx = (si - X[i]) / DX[i];
-            const float* T = lib.tables + (size_t(V.set[v]) * lib.n_tables + tb) * 98;
+            const float* T = tab[w] + size_t(x.tb) * 98;
             const float dl = bilerp(T, i, j, tx, ty);
             const float sl = bilerp(T + 49, i, j, tx, ty);
-            dst[v] = make_float2(ai, si);
-            arc_delay[size_t(a) * NV + v] = dl;
-            cand[v] = ai + dl;
-            slw[v] = sl;
-            best_k[v] = kpos;
+            dst[w] = make_float2(ai, si);
+            arc_delay[size_t(x.a) * NV + v0 + w] = dl;
+            cand[w] = ai + dl;
+            slw[w] = sl;
+            best_k[w] = x.kpos;
         }
     } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) { cand[v] = 0.0f; slw[v] = 0.0f; best_k[v] = 0; }
+        for (int w = 0; w < NW; ++w) { cand[w] = 0.0f; slw[w] = 0.0f; best_k[w] = 0; }
     }
     // segmented reduction toward each gate's first lane; the left operand covers the
     // lower arc positions, so keeping it on ties keeps the smallest arc index
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const bool take = (lane + off) < seg_end;
+        const bool take = (lane + off) < x.seg_end;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const float c2 = __shfl_down(cand[v], off, 64);
-            const float s2 = __shfl_down(slw[v], off, 64);
-            const int k2 = __shfl_down(best_k[v], off, 64);
+        for (int w = 0; w < NW; ++w) {
+            const float c2 = __shfl_down(cand[w], off, 64);
+            const float s2 = __shfl_down(slw[w], off, 64);
+            const int k2 = __shfl_down(best_k[w], off, 64);
             if (take) {
-                const bool late = V.mode[v] == STA_LATE;
-                if (late ? (c2 > cand[v]) : (c2 < cand[v])) { cand[v] = c2; best_k[v] = k2; }
-                if (late ? (s2 > slw[v]) : (s2 < slw[v])) slw[v] = s2;
+                if (early[w] ? (c2 < cand[w]) : (c2 > cand[w])) { cand[w] = c2; best_k[w] = k2; }
+                if (early[w] ? (s2 < slw[w]) : (s2 > slw[w])) slw[w] = s2;
             }
         }
     }
-    if (head) {
-        float2* out = reinterpret_cast<float2*>(drv_ts) + size_t(o) * NV;
+    if (x.head) {
+        float2* out = reinterpret_cast<float2*>(drv_ts) + size_t(n_pi + x.g) * NV + v0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            out[v] = make_float2(cand[v], slw[v]);
-            argmax[size_t(g) * NV + v] = uint8_t(best_k[v]);
+        for (int w = 0; w < NW; ++w) {
+            out[w] = make_float2(cand[w], slw[w]);
+            argmax[size_t(x.g) * NV + v0 + w] = uint8_t(best_k[w]);
         }
     }
 }
 
-// primary inputs: copy (arrival, slew) of every view
-__global__ void k_copy_pi(const float* __restrict__ pi_ts, float* __restrict__ drv_ts, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) drv_ts[i] = pi_ts[i];
-}
-
 // ---------------------------------------------------------------------------------
-// K3: backward required times of one driver level
+// backward tile
 // ---------------------------------------------------------------------------------
 
-template <int NV>
-__global__ __launch_bounds__(256) void k_backward(DevGraph G, KViews V, int tile0, int tile1,
-                                                  const float* __restrict__ nd,
-                                                  const float* __restrict__ drv_ts,
-                                                  const float* __restrict__ arc_ts,
-                                                  const float* __restrict__ arc_delay,
-                                                  const float* __restrict__ ep_rat,
-                                                  float* __restrict__ drv_rat, float* __restrict__ arc_rat,
-                                                  float* __restrict__ drv_slack, float* __restrict__ arc_slack) {
+template <int NW>
+__device__ __forceinline__ void bwd_tile(const DevGraph& G, const bool* early, int NV, int v0, int s0, int n, int d0,
+                                         const float* __restrict__ nd, const float* __restrict__ drv_ts,
+                                         const float* __restrict__ arc_ts, const float* __restrict__ arc_delay,
+                                         const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
+                                         float* __restrict__ arc_rat, float* __restrict__ drv_slack,
+                                         float* __restrict__ arc_slack) {
     const int lane = threadIdx.x & 63;
-    const int t = tile0 + blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= tile1) return;
-    const int d0 = G.btile_drv[t];
-    const int s0 = G.btile_slot[t];
-    const int n = G.btile_slot[t + 1] - s0;
     // n <= 64, or one driver owning every slot; lane owns the contiguous slots
     // [lane*c, min(n, (lane+1)*c)) so lower lanes always hold lower sink positions
     const int c = (n + 63) >> 6;
@@ -253,37 +227,35 @@ __global__ __launch_bounds__(256) void k_backward(DevGraph G, KViews V, int tile
     bool head;
     if (c > 1) head = (lane == 0);
     else head = (sb < n) && (uint32_t(G.bslot_out[s0 + sb]) & kHeadBit) != 0u;
-    float best[NV];
+    float best[NW];
     bool have = false;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) best[v] = 0.0f;
+    for (int w = 0; w < NW; ++w) best[w] = 0.0f;
     for (int s = sb; s < se; ++s) {
         const int slot = s0 + s;
         const int sa = G.bslot_arc[slot];
         const int so = G.bslot_out[slot] & 0x7fffffff;
-        float val[NV];
+        float val[NW];
         if (sa >= 0) {
             const float ndv = nd[sa];
-            const float* ro = drv_rat + size_t(so) * NV;
-            const float* dl = arc_delay + size_t(sa) * NV;
-            const float2* ts = reinterpret_cast<const float2*>(arc_ts) + size_t(sa) * NV;
+            const float* ro = drv_rat + size_t(so) * NV + v0;
+            const float* dl = arc_delay + size_t(sa) * NV + v0;
+            const float2* ts = reinterpret_cast<const float2*>(arc_ts) + size_t(sa) * NV + v0;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const float rin = ro[v] - dl[v];
-                const float ati = ts[v].x;
-                arc_rat[size_t(sa) * NV + v] = rin;
-                arc_slack[size_t(sa) * NV + v] = (V.mode[v] == STA_LATE) ? (rin - ati) : (ati - rin);
-                val[v] = rin - ndv;
+            for (int w = 0; w < NW; ++w) {
+                const float rin = ro[w] - dl[w];
+                const float ati = ts[w].x;
+                arc_rat[size_t(sa) * NV + v0 + w] = rin;
+                arc_slack[size_t(sa) * NV + v0 + w] = early[w] ? (ati - rin) : (rin - ati);
+                val[w] = rin - ndv;
             }
         } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) val[v] = ep_rat[size_t(so) * NV + v];
+            for (int w = 0; w < NW; ++w) val[w] = ep_rat[size_t(so) * NV + v0 + w];
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const bool late = V.mode[v] == STA_LATE;
-            if (!have || (late ? (val[v] < best[v]) : (val[v] > best[v]))) best[v] = val[v];
-        }
+        for (int w = 0; w < NW; ++w)
+            if (!have || (early[w] ? (val[w] > best[w]) : (val[w] < best[w]))) best[w] = val[w];
         have = true;
     }
     // segment = lanes of one driver: heads from the slot flags (c == 1) or lane 0 (c > 1)
@@ -297,40 +269,210 @@ __global__ __launch_bounds__(256) void k_backward(DevGraph G, KViews V, int tile
     for (int off = 1; off < 64; off <<= 1) {
         const bool take = (lane + off) < seg_end;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const float b2 = __shfl_down(best[v], off, 64);
-            if (take) {
-                const bool late = V.mode[v] == STA_LATE;
-                if (late ? (b2 < best[v]) : (b2 > best[v])) best[v] = b2;
-            }
+        for (int w = 0; w < NW; ++w) {
+            const float b2 = __shfl_down(best[w], off, 64);
+            if (take && (early[w] ? (b2 > best[w]) : (b2 < best[w]))) best[w] = b2;
         }
     }
     if (head) {
         const int u = d0 + gi;
-        const float2* ts = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV;
+        const float2* ts = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV + v0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const float r = best[v];
-            const float at = ts[v].x;
-            drv_rat[size_t(u) * NV + v] = r;
-            drv_slack[size_t(u) * NV + v] = (V.mode[v] == STA_LATE) ? (r - at) : (at - r);
+        for (int w = 0; w < NW; ++w) {
+            const float r = best[w];
+            const float at = ts[w].x;
+            drv_rat[size_t(u) * NV + v0 + w] = r;
+            drv_slack[size_t(u) * NV + v0 + w] = early[w] ? (at - r) : (r - at);
         }
     }
 }
 
 // ---------------------------------------------------------------------------------
-// K4: endpoint summaries
+// exact endpoint TNS: fixed-point digits
 // ---------------------------------------------------------------------------------
 
 // |x| of a finite FP32 value is m * 2^(sh - 149) with m < 2^24 and 0 <= sh <= 253.
 // It is added exactly into a 320-bit fixed-point number held as ten 32-bit digits in
-// 64-bit words (the upper halves absorb carries; 2^32 additions cannot overflow).
+// 64-bit words (the upper halves absorb carries; 2^31 additions cannot overflow).
 constexpr int kLimbs = 10;
 constexpr int kK4Blocks = 256;
 constexpr int kK4Threads = 256;
 
 size_t scratch_bytes() {
     return size_t(kK4Blocks) * STA_MAX_VIEWS * kLimbs * 8 + size_t(kK4Blocks) * STA_MAX_VIEWS * 4;
+}
+
+__device__ __forceinline__ void add_neg_slack(unsigned long long (&l)[kLimbs], float s) {
+    if (!(s < 0.0f)) return;
+    const uint32_t bits = __float_as_uint(s) & 0x7fffffffu;
+    const uint32_t ex = bits >> 23;
+    uint64_t m = bits & 0x7fffffu;
+    if (ex) m |= 0x800000u;
+    const int sh = ex ? int(ex) - 1 : 0;
+    const int li = sh >> 5;
+    const uint64_t x = m << (sh & 31);
+    const uint64_t lo = x & 0xffffffffull, hi = x >> 32;
+#pragma unroll
+    for (int i = 0; i < kLimbs; ++i) {
+        l[i] += (i == li) ? lo : 0ull;
+        l[i] += (i == li + 1) ? hi : 0ull;
+    }
+}
+
+// carries propagated, then sum(L[i] 2^(32 i)) * 2^-149 rounded to nearest-even FP64
+__device__ double digits_to_double(const unsigned long long* S) {
+    uint64_t L[kLimbs];
+    uint64_t carry = 0;
+#pragma unroll
+    for (int i = 0; i < kLimbs; ++i) {
+        const uint64_t x = S[i] + carry;            // < 2^63 + 2^32
+        L[i] = x & 0xffffffffull;
+        carry = x >> 32;
+    }
+    int t = -1;
+#pragma unroll
+    for (int i = 0; i < kLimbs; ++i)
+        if (L[i]) t = i;
+    if (t < 0) return 0.0;
+    // 128-bit window of digits t..t-3 (missing digits are 0); the rest is sticky
+    uint64_t d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+    bool sticky = false;
+#pragma unroll
+    for (int i = 0; i < kLimbs; ++i) {
+        if (i == t) d0 = L[i];
+        else if (i == t - 1) d1 = L[i];
+        else if (i == t - 2) d2 = L[i];
+        else if (i == t - 3) d3 = L[i];
+        else if (i < t - 3) sticky = sticky || (L[i] != 0ull);
+    }
+    const uint64_t hi = (d0 << 32) | d1;
+    const uint64_t lo = (d2 << 32) | d3;
+    const int s = __clzll(hi);                     // 0..31: hi's top digit is nonzero
+    const uint64_t whi = s ? ((hi << s) | (lo >> (64 - s))) : hi;
+    const uint64_t wlo = lo << s;
+    const int msb = 32 * t + 31 - s;               // bit index of the leading one
+    uint64_t mant = whi >> 11;                     // 53 bits
+    const uint64_t rb = whi & 0x7ffull;
+    sticky = sticky || (wlo != 0ull);
+    int e = msb - 52;
+    if (rb > 0x400ull || (rb == 0x400ull && (sticky || (mant & 1ull)))) mant += 1ull;
+    if (mant == (1ull << 53)) { mant >>= 1; e += 1; }
+    return ldexp(double(mant), e - 149);
+}
+
+// ---------------------------------------------------------------------------------
+// level schedule kernels
+// ---------------------------------------------------------------------------------
+
+// Tile bounds of one level passed by value in the kernel arguments (read with scalar
+// loads at wave start, no dependent memory round trip); wider levels read them from
+// the graph's tile arrays.
+constexpr int kArgTiles = 160;
+struct KTiles {
+    int32_t inl;                 // 1: bounds below are valid
+    int32_t first[kArgTiles + 1];  // first arc (forward) or slot (backward) of each tile, + end
+    int32_t base[kArgTiles];       // first gate (forward) or driver (backward) of each tile
+};
+
+// Level schedule, forward: 4 tiles per 256-lane block.  The block first issues its
+// tiles' arc loads, then copies the view tables into LDS (TAB_LDS: every view reads the
+// same table set), then gathers the drivers' results and computes.
+template <int NV, bool TAB_LDS>
+__global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V, int tile0, int tile1, KTiles kt,
+                                                 const float* __restrict__ load, const float* __restrict__ nd,
+                                                 const float* __restrict__ ni, float* __restrict__ drv_ts,
+                                                 float* __restrict__ arc_ts, float* __restrict__ arc_delay,
+                                                 uint8_t* __restrict__ argmax) {
+    extern __shared__ float s_dyn[];
+    __shared__ float s_ax[26];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = tile0 + blockIdx.x * 4 + wave;
+    const bool valid = t < tile1;
+    int a0 = 0, n = 0, g0 = 0;
+    if (valid) {
+        if (kt.inl) {
+            a0 = kt.first[t - tile0];
+            n = kt.first[t - tile0 + 1] - a0;
+            g0 = kt.base[t - tile0];
+        } else {
+            a0 = G.ftile_arc[t];
+            n = G.ftile_arc[t + 1] - a0;
+            g0 = G.ftile_gate[t];
+        }
+    }
+    const bool act = lane < n;
+    const int a = a0 + lane;
+    const uint32_t meta = act ? G.arc_meta[a] : 0u;
+    const int u = act ? G.arc_src[a] : 0;
+    FwdLane x;
+    x.nd = act ? nd[a] : 0.0f;
+    x.ni = act ? ni[a] : 0.0f;
+    load_axes(s_ax, lib);
+    if (TAB_LDS) {
+        const float* gt = lib.tables + size_t(V.set[0]) * lib.n_tables * 98;
+        const int nt = lib.n_tables * 98;
+        int done = 0;
+        if ((reinterpret_cast<uintptr_t>(gt) & 15u) == 0) {
+            const float4* src = reinterpret_cast<const float4*>(gt);
+            float4* dst = reinterpret_cast<float4*>(s_dyn);
+            done = (nt / 4) * 4;
+            for (int i = threadIdx.x; i < nt / 4; i += 256) dst[i] = src[i];
+        }
+        for (int i = done + threadIdx.x; i < nt; i += 256) s_dyn[i] = gt[i];
+    }
+    __syncthreads();
+    if (!valid) return;
+    fwd_lane_setup(x, act, meta, n, lane);
+    x.a = a;
+    x.g = g0 + x.gi;
+    x.Lo = act ? load[G.n_pi + x.g] : 0.0f;
+    float2 ts[NV];
+    const float2* srcp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ts[v] = act ? srcp[v] : make_float2(0.0f, 0.0f);
+    const float* tab[NV];
+    bool early[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        tab[v] = TAB_LDS ? s_dyn : lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
+        early[v] = V.mode[v] == STA_EARLY;
+    }
+    fwd_finish<NV>(x, ts, s_ax, tab, early, NV, 0, G.n_pi, drv_ts, arc_ts, arc_delay, argmax);
+}
+
+// primary inputs: copy (arrival, slew) of every view
+__global__ void k_copy_pi(const float* __restrict__ pi_ts, float* __restrict__ drv_ts, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) drv_ts[i] = pi_ts[i];
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_backward(DevGraph G, KViews V, int tile0, int tile1, KTiles kt,
+                                                  const float* __restrict__ nd, const float* __restrict__ drv_ts,
+                                                  const float* __restrict__ arc_ts,
+                                                  const float* __restrict__ arc_delay,
+                                                  const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
+                                                  float* __restrict__ arc_rat, float* __restrict__ drv_slack,
+                                                  float* __restrict__ arc_slack) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = tile0 + blockIdx.x * 4 + wave;
+    if (t >= tile1) return;
+    bool early[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
+    int s0, n, d0;
+    if (kt.inl) {
+        s0 = kt.first[t - tile0];
+        n = kt.first[t - tile0 + 1] - s0;
+        d0 = kt.base[t - tile0];
+    } else {
+        s0 = G.btile_slot[t];
+        n = G.btile_slot[t + 1] - s0;
+        d0 = G.btile_drv[t];
+    }
+    bwd_tile<NV>(G, early, NV, 0, s0, n, d0, nd, drv_ts, arc_ts, arc_delay, ep_rat, drv_rat, arc_rat, drv_slack,
+                 arc_slack);
 }
 
 template <int NV>
@@ -352,21 +494,7 @@ __global__ __launch_bounds__(kK4Threads) void k_endpoint_partial(const int32_t* 
         for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
             const float s = drv_slack[size_t(ep_drv[e]) * NV + v];
             mn = (s < mn) ? s : mn;
-            if (s < 0.0f) {
-                const uint32_t bits = __float_as_uint(s) & 0x7fffffffu;
-                const uint32_t ex = bits >> 23;
-                uint64_t m = bits & 0x7fffffu;
-                if (ex) m |= 0x800000u;
-                const int sh = ex ? int(ex) - 1 : 0;
-                const int li = sh >> 5;
-                const uint64_t x = m << (sh & 31);
-                const uint64_t lo = x & 0xffffffffull, hi = x >> 32;
-#pragma unroll
-                for (int i = 0; i < kLimbs; ++i) {
-                    l[i] += (i == li) ? lo : 0ull;
-                    l[i] += (i == li + 1) ? hi : 0ull;
-                }
-            }
+            add_neg_slack(l, s);
         }
 #pragma unroll
         for (int i = 0; i < kLimbs; ++i)
@@ -387,59 +515,395 @@ __global__ __launch_bounds__(kK4Threads) void k_endpoint_partial(const int32_t* 
     }
 }
 
-// bit p of the normalized digit string (0 outside it)
-__device__ inline uint32_t big_bit(const uint64_t* L, int p) {
-    if (p < 0 || p >= 32 * kLimbs) return 0u;
-    return uint32_t(L[p >> 5] >> (p & 31)) & 1u;
-}
-
-// round the non-negative integer sum(L[i] 2^(32 i)) * 2^-149 to nearest-even FP64
-__device__ double big_to_double(const uint64_t* L) {
-    int top = -1;
-    for (int i = kLimbs - 1; i >= 0; --i)
-        if (L[i]) { top = i; break; }
-    if (top < 0) return 0.0;
-    const int msb = top * 32 + (31 - __clz(uint32_t(L[top])));
-    uint64_t w = 0;
-    for (int q = 0; q < 64; ++q) w |= uint64_t(big_bit(L, msb - 63 + q)) << q;
-    bool sticky = false;
-    for (int p = 0; p < msb - 63; ++p) sticky = sticky || big_bit(L, p);
-    uint64_t mant = w >> 11;
-    const uint32_t rb = uint32_t(w & 0x7ffu);
-    int e = msb - 52;
-    if (rb > 0x400u || (rb == 0x400u && (sticky || (mant & 1ull)))) mant += 1ull;
-    if (mant == (1ull << 53)) { mant >>= 1; e += 1; }
-    return ldexp(double(mant), e - 149);
-}
-
 template <int NV>
-__global__ void k_endpoint_final(int nblk, const unsigned long long* __restrict__ part_limbs,
-                                 const float* __restrict__ part_wns, double* __restrict__ tns,
-                                 float* __restrict__ wns) {
+__global__ __launch_bounds__(256) void k_endpoint_final(int nblk, const unsigned long long* __restrict__ part_limbs,
+                                                        const float* __restrict__ part_wns, double* __restrict__ tns,
+                                                        float* __restrict__ wns) {
     __shared__ unsigned long long s_sum[NV * kLimbs];
-    for (int i = threadIdx.x; i < NV * kLimbs; i += blockDim.x) {
-        unsigned long long acc = 0ull;
-        for (int b = 0; b < nblk; ++b) acc += part_limbs[size_t(b) * NV * kLimbs + i];
-        s_sum[i] = acc;
+    __shared__ float s_min[NV][4];
+    for (int i = threadIdx.x; i < NV * kLimbs; i += blockDim.x) s_sum[i] = 0ull;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nblk * NV * kLimbs; i += blockDim.x) {
+        const unsigned long long x = part_limbs[i];
+        if (x) atomicAdd(&s_sum[i % (NV * kLimbs)], x);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        float mn = __builtin_inff();
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+            const float x = part_wns[size_t(b) * NV + v];
+            mn = (x < mn) ? x : mn;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float o2 = __shfl_xor(mn, off, 64);
+            mn = (o2 < mn) ? o2 : mn;
+        }
+        if (lane == 0) s_min[v][w] = mn;
     }
     __syncthreads();
     if (threadIdx.x < NV) {
         const int v = threadIdx.x;
-        uint64_t L[kLimbs];
-        uint64_t carry = 0;
-        for (int i = 0; i < kLimbs; ++i) {
-            const uint64_t x = s_sum[v * kLimbs + i] + carry;   // < 2^63 + 2^32
-            L[i] = x & 0xffffffffull;
-            carry = x >> 32;
-        }
-        const double mag = big_to_double(L);
+        const double mag = digits_to_double(&s_sum[v * kLimbs]);
         tns[v] = (mag == 0.0) ? 0.0 : -mag;
-        float mn = __builtin_inff();
-        for (int b = 0; b < nblk; ++b) {
-            const float x = part_wns[size_t(b) * NV + v];
-            mn = (x < mn) ? x : mn;
-        }
+        float mn = s_min[v][0];
+        for (int i = 1; i < 4; ++i) mn = (s_min[v][i] < mn) ? s_min[v][i] : mn;
         wns[v] = mn;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// view schedule kernels: one 1024-lane workgroup per view walks every level
+// ---------------------------------------------------------------------------------
+//
+// Each level's static data (tile bounds, arc records, gate loads; for the backward
+// pass sink slots and driver arrival times) is staged in LDS.  The loads for level
+// l+1 are issued as coalesced 4-byte loads before level l computes and are written to
+// LDS after it, so a level costs one dependent round trip (the gather of the drivers'
+// results) plus its arithmetic.  A wave owns tiles wave, wave+16, ... of a level and
+// issues the gathers of all of them before computing any.
+
+constexpr int kViewThreads = 1024;
+constexpr int kViewWaves = kViewThreads / 64;
+
+// LDS layout of k_forward_view (in 4-byte words)
+struct FwdLds {
+    int ax, tab, lvl, taoff, tgoff, src, meta, nd, ni, ld, total;
+};
+
+__host__ __device__ inline FwdLds fwd_lds(int n_tables, int L, int capT, int capA, int capG) {
+    FwdLds o{};
+    o.ax = 0;
+    o.tab = 32;
+    o.lvl = o.tab + n_tables * 98;
+    o.taoff = o.lvl + (L + 2) * 3;
+    o.tgoff = o.taoff + capT + 1;
+    o.src = o.tgoff + capT;
+    o.meta = o.src + capA;
+    o.nd = o.meta + capA;
+    o.ni = o.nd + capA;
+    o.ld = o.ni + capA;
+    o.total = o.ld + capG;
+    return o;
+}
+
+template <int RW>
+__global__ __launch_bounds__(kViewThreads) void k_forward_view(DevGraph G, KLib lib, KViews V, int NV, int L,
+                                                               const int32_t* __restrict__ lvl_g, int capT, int capA,
+                                                               int capG, const float* __restrict__ pi_ts,
+                                                               const float* __restrict__ load,
+                                                               const float* __restrict__ nd,
+                                                               const float* __restrict__ ni,
+                                                               float* __restrict__ drv_ts, float* __restrict__ arc_ts,
+                                                               float* __restrict__ arc_delay,
+                                                               uint8_t* __restrict__ argmax) {
+    extern __shared__ float s_mem[];
+    const FwdLds lo = fwd_lds(lib.n_tables, L, capT, capA, capG);
+    float* s_ax = s_mem + lo.ax;
+    float* s_tab = s_mem + lo.tab;
+    int* s_lvl = reinterpret_cast<int*>(s_mem + lo.lvl);
+    int* s_taoff = reinterpret_cast<int*>(s_mem + lo.taoff);
+    int* s_tgoff = reinterpret_cast<int*>(s_mem + lo.tgoff);
+    int* s_src = reinterpret_cast<int*>(s_mem + lo.src);
+    uint32_t* s_meta = reinterpret_cast<uint32_t*>(s_mem + lo.meta);
+    float* s_nd = s_mem + lo.nd;
+    float* s_ni = s_mem + lo.ni;
+    float* s_ld = s_mem + lo.ld;
+    const int v = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const float* gtab = lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
+    load_axes(s_ax, lib);
+    for (int i = tid; i < lib.n_tables * 98; i += kViewThreads) s_tab[i] = gtab[i];
+    for (int i = tid; i < (L + 2) * 3; i += kViewThreads) s_lvl[i] = lvl_g[i];
+    for (int i = tid; i < G.n_pi; i += kViewThreads)
+        reinterpret_cast<float2*>(drv_ts)[size_t(i) * NV + v] = reinterpret_cast<const float2*>(pi_ts)[size_t(i) * NV + v];
+    const bool early[1] = {V.mode[v] == STA_EARLY};
+    const float* tab[1] = {s_tab};
+    __syncthreads();
+
+    // static data of level l into registers (coalesced), then into LDS
+    int p_src[RW], p_ld_n = 0;
+    uint32_t p_meta[RW];
+    float p_nd[RW], p_ni[RW], p_ld[RW];
+    int p_ta = 0, p_tg = 0;
+    auto fetch = [&](int l) {
+        const int t0 = s_lvl[l * 3], t1 = s_lvl[(l + 1) * 3];
+        const int al = s_lvl[l * 3 + 1], ah = s_lvl[(l + 1) * 3 + 1];
+        const int gl = s_lvl[l * 3 + 2], gh = s_lvl[(l + 1) * 3 + 2];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int i = tid + k * kViewThreads;
+            const bool ok = i < ah - al;
+            p_src[k] = ok ? G.arc_src[al + i] : 0;
+            p_meta[k] = ok ? G.arc_meta[al + i] : 0u;
+            p_nd[k] = ok ? nd[al + i] : 0.0f;
+            p_ni[k] = ok ? ni[al + i] : 0.0f;
+            p_ld[k] = (i < gh - gl) ? load[G.n_pi + gl + i] : 0.0f;
+        }
+        p_ta = (tid <= t1 - t0) ? G.ftile_arc[t0 + tid] - al : 0;
+        p_tg = (tid < t1 - t0) ? G.ftile_gate[t0 + tid] - gl : 0;
+        p_ld_n = 0;
+    };
+    auto stash = [&](int l) {
+        const int t0 = s_lvl[l * 3], t1 = s_lvl[(l + 1) * 3];
+        const int al = s_lvl[l * 3 + 1], ah = s_lvl[(l + 1) * 3 + 1];
+        const int gl = s_lvl[l * 3 + 2], gh = s_lvl[(l + 1) * 3 + 2];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int i = tid + k * kViewThreads;
+            if (i < ah - al) { s_src[i] = p_src[k]; s_meta[i] = p_meta[k]; s_nd[i] = p_nd[k]; s_ni[i] = p_ni[k]; }
+            if (i < gh - gl) s_ld[i] = p_ld[k];
+        }
+        if (tid <= t1 - t0) s_taoff[tid] = p_ta;
+        if (tid < t1 - t0) s_tgoff[tid] = p_tg;
+    };
+    if (L >= 1) {
+        fetch(1);
+        stash(1);
+    }
+    (void)p_ld_n;
+    __syncthreads();
+
+    for (int l = 1; l <= L; ++l) {
+        const int T = s_lvl[(l + 1) * 3] - s_lvl[l * 3];
+        const int al = s_lvl[l * 3 + 1], gl = s_lvl[l * 3 + 2];
+        // this wave's tiles: LDS reads, then every gather
+        FwdLane x[RW];
+        float2 ts[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int tl = wave + r * kViewWaves;
+            const bool valid = tl < T;
+            const int a_off = valid ? s_taoff[tl] : 0;
+            const int n = valid ? s_taoff[tl + 1] - a_off : 0;
+            const int g_off = valid ? s_tgoff[tl] : 0;
+            const bool act = lane < n;
+            const int ai = a_off + lane;
+            const uint32_t meta = act ? s_meta[ai] : 0u;
+            fwd_lane_setup(x[r], act, meta, n, lane);
+            x[r].a = al + ai;
+            x[r].g = gl + g_off + x[r].gi;
+            x[r].nd = act ? s_nd[ai] : 0.0f;
+            x[r].ni = act ? s_ni[ai] : 0.0f;
+            x[r].Lo = act ? s_ld[g_off + x[r].gi] : 0.0f;
+            const int u = act ? s_src[ai] : 0;
+            ts[r] = act ? reinterpret_cast<const float2*>(drv_ts)[size_t(u) * NV + v] : make_float2(0.0f, 0.0f);
+        }
+        if (l < L) fetch(l + 1);
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+            fwd_finish<1>(x[r], &ts[r], s_ax, tab, early, NV, v, G.n_pi, drv_ts, arc_ts, arc_delay, argmax);
+        __syncthreads();
+        if (l < L) stash(l + 1);
+        __syncthreads();
+    }
+}
+
+// LDS layout of k_backward_view (in 4-byte words)
+struct BwdLds {
+    int lvl, tsoff, tdoff, sa, so, at, lim, mn, total;
+};
+
+__host__ __device__ inline BwdLds bwd_lds(int L, int capT, int capS, int capD) {
+    BwdLds o{};
+    o.lvl = 0;
+    o.tsoff = o.lvl + (L + 2) * 3;
+    o.tdoff = o.tsoff + capT + 1;
+    o.sa = o.tdoff + capT;
+    o.so = o.sa + capS;
+    o.at = o.so + capS;
+    o.lim = ((o.at + capD) + 1) & ~1;              // 8-byte aligned digits
+    o.mn = o.lim + 2 * kLimbs;
+    o.total = o.mn + kViewWaves;
+    return o;
+}
+
+template <int RW>
+__global__ __launch_bounds__(kViewThreads) void k_backward_view(DevGraph G, KViews V, int NV, int L, int E,
+                                                                const int32_t* __restrict__ lvl_g, int capT, int capS,
+                                                                int capD, const float* __restrict__ nd,
+                                                                const float* __restrict__ drv_ts,
+                                                                const float* __restrict__ arc_ts,
+                                                                const float* __restrict__ arc_delay,
+                                                                const float* __restrict__ ep_rat,
+                                                                float* __restrict__ drv_rat,
+                                                                float* __restrict__ arc_rat,
+                                                                float* __restrict__ drv_slack,
+                                                                float* __restrict__ arc_slack,
+                                                                double* __restrict__ tns, float* __restrict__ wns) {
+    extern __shared__ float s_mem[];
+    const BwdLds lo = bwd_lds(L, capT, capS, capD);
+    int* s_lvl = reinterpret_cast<int*>(s_mem + lo.lvl);
+    int* s_tsoff = reinterpret_cast<int*>(s_mem + lo.tsoff);
+    int* s_tdoff = reinterpret_cast<int*>(s_mem + lo.tdoff);
+    int* s_sa = reinterpret_cast<int*>(s_mem + lo.sa);
+    int* s_so = reinterpret_cast<int*>(s_mem + lo.so);
+    float* s_at = s_mem + lo.at;
+    unsigned long long* s_l = reinterpret_cast<unsigned long long*>(s_mem + lo.lim);
+    float* s_min = s_mem + lo.mn;
+    const int v = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const bool early = V.mode[v] == STA_EARLY;
+    for (int i = tid; i < (L + 2) * 3; i += kViewThreads) s_lvl[i] = lvl_g[i];
+    if (tid < kLimbs) s_l[tid] = 0ull;
+    __syncthreads();
+
+    int p_sa[RW], p_so[RW];
+    float p_at[RW];
+    int p_ts = 0, p_td = 0;
+    auto fetch = [&](int l) {
+        const int t0 = s_lvl[l * 3], t1 = s_lvl[(l + 1) * 3];
+        const int sl = s_lvl[l * 3 + 1], sh = s_lvl[(l + 1) * 3 + 1];
+        const int dl = s_lvl[l * 3 + 2], dh = s_lvl[(l + 1) * 3 + 2];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int i = tid + k * kViewThreads;
+            const bool ok = i < sh - sl;
+            p_sa[k] = ok ? G.bslot_arc[sl + i] : 0;
+            p_so[k] = ok ? G.bslot_out[sl + i] : 0;
+            p_at[k] = (i < dh - dl) ? drv_ts[(size_t(dl + i) * NV + v) * 2] : 0.0f;
+        }
+        p_ts = (tid <= t1 - t0) ? G.btile_slot[t0 + tid] - sl : 0;
+        p_td = (tid < t1 - t0) ? G.btile_drv[t0 + tid] - dl : 0;
+    };
+    auto stash = [&](int l) {
+        const int t0 = s_lvl[l * 3], t1 = s_lvl[(l + 1) * 3];
+        const int sl = s_lvl[l * 3 + 1], sh = s_lvl[(l + 1) * 3 + 1];
+        const int dl = s_lvl[l * 3 + 2], dh = s_lvl[(l + 1) * 3 + 2];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int i = tid + k * kViewThreads;
+            if (i < sh - sl) { s_sa[i] = p_sa[k]; s_so[i] = p_so[k]; }
+            if (i < dh - dl) s_at[i] = p_at[k];
+        }
+        if (tid <= t1 - t0) s_tsoff[tid] = p_ts;
+        if (tid < t1 - t0) s_tdoff[tid] = p_td;
+    };
+    fetch(L);
+    stash(L);
+    __syncthreads();
+
+    for (int l = L; l >= 0; --l) {
+        const int T = s_lvl[(l + 1) * 3] - s_lvl[l * 3];
+        const int dl = s_lvl[l * 3 + 2];
+        // one-slot-per-lane tiles: every gather first
+        float ro[RW], dlv[RW], ati[RW], ndv[RW], epr[RW];
+        int sa_r[RW];
+        bool big[RW], act[RW], head[RW];
+        int s0r[RW], nr[RW], doff[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int tl = wave + r * kViewWaves;
+            const bool valid = tl < T;
+            s0r[r] = valid ? s_tsoff[tl] : 0;
+            nr[r] = valid ? s_tsoff[tl + 1] - s0r[r] : 0;
+            doff[r] = valid ? s_tdoff[tl] : 0;
+            big[r] = nr[r] > 64;
+            act[r] = !big[r] && lane < nr[r];
+            const int si = s0r[r] + lane;
+            const int sa = act[r] ? s_sa[si] : -1;
+            const int so = act[r] ? s_so[si] : 0;
+            head[r] = act[r] && (uint32_t(so) & kHeadBit) != 0u;
+            const int o = so & 0x7fffffff;
+            sa_r[r] = sa;
+            ro[r] = (sa >= 0) ? drv_rat[size_t(o) * NV + v] : 0.0f;
+            dlv[r] = (sa >= 0) ? arc_delay[size_t(sa) * NV + v] : 0.0f;
+            ati[r] = (sa >= 0) ? arc_ts[(size_t(sa) * NV + v) * 2] : 0.0f;
+            ndv[r] = (sa >= 0) ? nd[sa] : 0.0f;
+            epr[r] = (act[r] && sa < 0) ? ep_rat[size_t(o) * NV + v] : 0.0f;
+        }
+        if (l > 0) fetch(l - 1);
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            if (big[r]) {
+                // one driver with more than 64 sinks: lanes take contiguous runs of them
+                const int n = nr[r], c = (n + 63) >> 6, sb = lane * c, se = min(n, sb + c);
+                float best = 0.0f;
+                bool have = false;
+                for (int s = sb; s < se; ++s) {
+                    const int sa = s_sa[s0r[r] + s];
+                    const int o = s_so[s0r[r] + s] & 0x7fffffff;
+                    const float rin = drv_rat[size_t(o) * NV + v] - arc_delay[size_t(sa) * NV + v];
+                    const float at_i = arc_ts[(size_t(sa) * NV + v) * 2];
+                    arc_rat[size_t(sa) * NV + v] = rin;
+                    arc_slack[size_t(sa) * NV + v] = early ? (at_i - rin) : (rin - at_i);
+                    const float val = rin - nd[sa];
+                    if (!have || (early ? (val > best) : (val < best))) best = val;
+                    have = true;
+                }
+                const int nl = (n + c - 1) / c;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const float b2 = __shfl_down(best, off, 64);
+                    if ((lane + off) < nl && (early ? (b2 > best) : (b2 < best))) best = b2;
+                }
+                if (lane == 0) {
+                    const int u = dl + doff[r];
+                    const float at = s_at[doff[r]];
+                    drv_rat[size_t(u) * NV + v] = best;
+                    drv_slack[size_t(u) * NV + v] = early ? (at - best) : (best - at);
+                }
+                continue;
+            }
+            float val = 0.0f;
+            if (sa_r[r] >= 0) {
+                const int sa = sa_r[r];
+                const float rin = ro[r] - dlv[r];
+                arc_rat[size_t(sa) * NV + v] = rin;
+                arc_slack[size_t(sa) * NV + v] = early ? (ati[r] - rin) : (rin - ati[r]);
+                val = rin - ndv[r];
+            } else if (act[r]) {
+                val = epr[r];
+            }
+            const uint64_t heads = __ballot(head[r]);
+            const uint64_t le = lanes_le(lane);
+            const int gi = __popcll(heads & le) - 1;
+            const uint64_t after = heads & ~le;
+            const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : nr[r];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const float b2 = __shfl_down(val, off, 64);
+                if ((lane + off) < seg_end && (early ? (b2 > val) : (b2 < val))) val = b2;
+            }
+            if (head[r]) {
+                const int dloc = doff[r] + gi;
+                const int u = dl + dloc;
+                const float at = s_at[dloc];
+                drv_rat[size_t(u) * NV + v] = val;
+                drv_slack[size_t(u) * NV + v] = early ? (at - val) : (val - at);
+            }
+        }
+        __syncthreads();
+        if (l > 0) stash(l - 1);
+        __syncthreads();
+    }
+    // endpoint summaries of this view
+    unsigned long long lim[kLimbs];
+#pragma unroll
+    for (int i = 0; i < kLimbs; ++i) lim[i] = 0ull;
+    float mn = __builtin_inff();
+    for (int e = tid; e < E; e += kViewThreads) {
+        const float s = drv_slack[size_t(G.ep_drv[e]) * NV + v];
+        mn = (s < mn) ? s : mn;
+        add_neg_slack(lim, s);
+    }
+#pragma unroll
+    for (int i = 0; i < kLimbs; ++i)
+        if (lim[i]) atomicAdd(&s_l[i], lim[i]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float o2 = __shfl_xor(mn, off, 64);
+        mn = (o2 < mn) ? o2 : mn;
+    }
+    if (lane == 0) s_min[wave] = mn;
+    __syncthreads();
+    if (tid == 0) {
+        const double mag = digits_to_double(s_l);
+        tns[v] = (mag == 0.0) ? 0.0 : -mag;
+        float m = s_min[0];
+        for (int i = 1; i < kViewWaves; ++i) m = (s_min[i] < m) ? s_min[i] : m;
+        wns[v] = m;
     }
 }
 
@@ -526,11 +990,114 @@ static KViews kviews(const sta_views* v) {
     return k;
 }
 
-template <int NV>
-static void run_forward(const sta_graph* g, const KLib& lib, const KViews& kv, const float* pi_ts,
-                        const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
+// Per-wave tile count of the view schedule (1, 2, 4 or 8; 0 = does not fit), from the
+// widest level: 16 waves, <= 64 arcs or slots per tile and per staged lane load.
+static int view_rw(int max_tiles, int max_items) {
+    const int need = std::max((max_tiles + kViewWaves - 1) / kViewWaves, (max_items + kViewThreads - 1) / kViewThreads);
+    for (int rw = 1; rw <= 8; rw *= 2)
+        if (need <= rw) return rw;
+    return 0;
+}
+
+static size_t lds_limit() {
+    static size_t lim = 0;
+    if (!lim) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && v > 0)
+            lim = size_t(v);
+        else
+            lim = 65536;
+    }
+    return lim;
+}
+
+// The view schedule runs while one compute unit finishes an average level faster than
+// a device-wide step does (a few thousand cell arcs per level) and the level's staged
+// data and the view's tables fit in LDS.
+static bool use_view_forward(const sta_graph* g, int n_tables, int* rw, size_t* lds) {
+    if (g->L == 0 || double(g->A) / double(g->L) > double(g->view_sched_max_arcs)) return false;
+    *rw = view_rw(g->max_ft, std::max(g->max_fa, g->max_fg));
+    if (!*rw) return false;
+    *lds = size_t(fwd_lds(n_tables, int(g->L), g->max_ft, g->max_fa, g->max_fg).total) * 4;
+    return *lds <= lds_limit();
+}
+
+static bool use_view_backward(const sta_graph* g, int* rw, size_t* lds) {
+    if (g->L == 0 || double(g->A) / double(g->L) > double(g->view_sched_max_arcs)) return false;
+    *rw = view_rw(g->max_bt, std::max(g->max_bs, g->max_bd));
+    if (!*rw) return false;
+    *lds = size_t(bwd_lds(int(g->L), g->max_bt, g->max_bs, g->max_bd).total) * 4;
+    return *lds <= lds_limit();
+}
+
+template <typename K>
+static void set_lds(K kernel, size_t lds) {
+    if (lds > 65536) hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+}
+
+static KTiles ktiles(const std::vector<int32_t>& first, const std::vector<int32_t>& base, int t0, int t1) {
+    KTiles k;
+    std::memset(&k, 0, sizeof(k));
+    k.inl = (t1 - t0) <= kArgTiles ? 1 : 0;
+    if (k.inl) {
+        for (int t = t0; t <= t1; ++t) k.first[t - t0] = first[t];
+        for (int t = t0; t < t1; ++t) k.base[t - t0] = base[t];
+    }
+    return k;
+}
+
+// Runs enqueue(stream) directly, or replays it from the cached hipGraph of this call
+// kind (capturing it first when the key differs).  Profiling always runs it directly.
+template <typename F>
+static sta_status run_sequence(const sta_graph* g, LaunchCache& c, std::vector<uint64_t> key, hipStream_t s,
+                               F&& enqueue) {
+    if (!g->use_graphs || g_prof.on) {
+        enqueue(s);
+        return STA_OK;
+    }
+    std::lock_guard<std::mutex> lock(g->cache_mu);
+    if (!c.exec || c.key != key) {
+        if (c.exec) { (void)hipGraphExecDestroy(c.exec); c.exec = nullptr; }
+        if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
+        c.key.clear();
+        hipStream_t cap = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return fail(STA_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            return fail(STA_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+        }
+        enqueue(cap);
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(cap, &gr);
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) return fail(STA_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            return fail(STA_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        c.graph = gr;
+        c.exec = ex;
+        c.key = std::move(key);
+    }
+    hipError_t e = hipGraphLaunch(c.exec, s);
+    if (e != hipSuccess) return fail(STA_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    return STA_OK;
+}
+
+static uint64_t pk(const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); }
+
+template <int NV, bool TAB_LDS>
+static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KViews& kv, const float* pi_ts,
+                                   const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
     const DevGraph dg = dev_graph(g);
     const int npi = int(g->n_pi) * NV * 2;
+    const size_t lds = TAB_LDS ? size_t(lib.n_tables) * 98 * 4 : 0;
+    if (TAB_LDS) set_lds(k_forward<NV, TAB_LDS>, lds);
     if (npi > 0)
         prof_launch("k_copy_pi", s, [&] {
             hipLaunchKernelGGL(k_copy_pi, dim3((npi + 255) / 256), dim3(256), 0, s, pi_ts, o->drv_ts, npi);
@@ -538,22 +1105,69 @@ static void run_forward(const sta_graph* g, const KLib& lib, const KViews& kv, c
     for (int64_t l = 1; l <= g->L; ++l) {
         const int t0 = g->fwd_tile_ptr[l], t1 = g->fwd_tile_ptr[l + 1];
         if (t1 <= t0) continue;
+        const KTiles kt = ktiles(g->ftile_arc_h, g->ftile_gate_h, t0, t1);
         prof_launch("k_forward", s, [&] {
-            hipLaunchKernelGGL((k_forward<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, lib, kv, t0, t1,
-                               nd->load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts, o->arc_delay, o->argmax);
+            hipLaunchKernelGGL((k_forward<NV, TAB_LDS>), dim3((t1 - t0 + 3) / 4), dim3(256), lds, s, dg, lib, kv, t0,
+                               t1, kt, nd->load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts, o->arc_delay,
+                               o->argmax);
         });
     }
 }
 
 template <int NV>
-static void run_backward(const sta_graph* g, const KViews& kv, const sta_net_out* nd, const sta_timing_out* t,
-                         const float* ep_rat, const sta_slack_out* o, void* scratch, hipStream_t s) {
+static sta_status run_forward_levels(const sta_graph* g, const KLib& lib, const KViews& kv, const float* pi_ts,
+                                     const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
+    bool same_set = true;
+    for (int v = 1; v < NV; ++v) same_set = same_set && kv.set[v] == kv.set[0];
+    // Copying the tables into every block's LDS costs more than the L2-resident global
+    // reads it replaces (one level is ~10 blocks that each use a few hundred entries).
+    const bool tab_lds = false;
+    (void)same_set;
+    std::vector<uint64_t> key = {uint64_t(NV), pk(lib.tables), uint64_t(lib.n_tables), pk(pi_ts), pk(nd->load),
+                                 pk(nd->net_delay), pk(nd->net_imp2), pk(o->drv_ts), pk(o->arc_ts), pk(o->arc_delay),
+                                 pk(o->argmax), uint64_t(tab_lds)};
+    for (int i = 0; i < 26; ++i) { uint32_t b; std::memcpy(&b, &lib.ax[i], 4); key.push_back(b); }
+    for (int v = 0; v < NV; ++v) key.push_back((uint64_t(kv.mode[v]) << 32) | uint32_t(kv.set[v]));
+    return run_sequence(g, g->fwd_cache, std::move(key), s, [&](hipStream_t q) {
+        if (tab_lds) enqueue_forward_levels<NV, true>(g, lib, kv, pi_ts, nd, o, q);
+        else enqueue_forward_levels<NV, false>(g, lib, kv, pi_ts, nd, o, q);
+    });
+}
+
+template <int RW>
+static void launch_forward_view(const sta_graph* g, int NV, const KLib& lib, const KViews& kv, const float* pi_ts,
+                                const sta_net_out* nd, const sta_timing_out* o, size_t lds, hipStream_t s) {
+    const DevGraph dg = dev_graph(g);
+    const int32_t* lv = reinterpret_cast<const int32_t*>(g->dev + g->lay.fwd_lvl);
+    set_lds(k_forward_view<RW>, lds);
+    prof_launch("k_forward_view", s, [&] {
+        hipLaunchKernelGGL((k_forward_view<RW>), dim3(NV), dim3(kViewThreads), lds, s, dg, lib, kv, NV, int(g->L), lv,
+                           g->max_ft, g->max_fa, g->max_fg, pi_ts, nd->load, nd->net_delay, nd->net_imp2, o->drv_ts,
+                           o->arc_ts, o->arc_delay, o->argmax);
+    });
+}
+
+static void run_forward_views(const sta_graph* g, int rw, size_t lds, int NV, const KLib& lib, const KViews& kv,
+                              const float* pi_ts, const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
+    switch (rw) {
+        case 1: launch_forward_view<1>(g, NV, lib, kv, pi_ts, nd, o, lds, s); break;
+        case 2: launch_forward_view<2>(g, NV, lib, kv, pi_ts, nd, o, lds, s); break;
+        case 4: launch_forward_view<4>(g, NV, lib, kv, pi_ts, nd, o, lds, s); break;
+        default: launch_forward_view<8>(g, NV, lib, kv, pi_ts, nd, o, lds, s); break;
+    }
+}
+
+template <int NV>
+static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const sta_net_out* nd,
+                                    const sta_timing_out* t, const float* ep_rat, const sta_slack_out* o,
+                                    void* scratch, hipStream_t s) {
     const DevGraph dg = dev_graph(g);
     for (int64_t l = g->L; l >= 0; --l) {
         const int t0 = g->bwd_tile_ptr[l], t1 = g->bwd_tile_ptr[l + 1];
         if (t1 <= t0) continue;
+        const KTiles kt = ktiles(g->btile_slot_h, g->btile_drv_h, t0, t1);
         prof_launch("k_backward", s, [&] {
-            hipLaunchKernelGGL((k_backward<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, kv, t0, t1,
+            hipLaunchKernelGGL((k_backward<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, kv, t0, t1, kt,
                                nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat, o->arc_rat,
                                o->drv_slack, o->arc_slack);
         });
@@ -567,8 +1181,45 @@ static void run_backward(const sta_graph* g, const KViews& kv, const sta_net_out
                            o->drv_slack, limbs, pw);
     });
     prof_launch("k_endpoint_final", s, [&] {
-        hipLaunchKernelGGL((k_endpoint_final<NV>), dim3(1), dim3(64), 0, s, nblk, limbs, pw, o->tns, o->wns);
+        hipLaunchKernelGGL((k_endpoint_final<NV>), dim3(1), dim3(256), 0, s, nblk, limbs, pw, o->tns, o->wns);
     });
+}
+
+template <int NV>
+static sta_status run_backward_levels(const sta_graph* g, const KViews& kv, const sta_net_out* nd,
+                                      const sta_timing_out* t, const float* ep_rat, const sta_slack_out* o,
+                                      void* scratch, hipStream_t s) {
+    std::vector<uint64_t> key = {uint64_t(NV), pk(nd->net_delay), pk(t->drv_ts), pk(t->arc_ts), pk(t->arc_delay),
+                                 pk(ep_rat), pk(o->drv_rat), pk(o->arc_rat), pk(o->drv_slack), pk(o->arc_slack),
+                                 pk(o->tns), pk(o->wns), pk(scratch)};
+    for (int v = 0; v < NV; ++v) key.push_back(uint64_t(kv.mode[v]));
+    return run_sequence(g, g->bwd_cache, std::move(key), s, [&](hipStream_t q) {
+        enqueue_backward_levels<NV>(g, kv, nd, t, ep_rat, o, scratch, q);
+    });
+}
+
+template <int RW>
+static void launch_backward_view(const sta_graph* g, int NV, const KViews& kv, const sta_net_out* nd,
+                                 const sta_timing_out* t, const float* ep_rat, const sta_slack_out* o, size_t lds,
+                                 hipStream_t s) {
+    const DevGraph dg = dev_graph(g);
+    const int32_t* lv = reinterpret_cast<const int32_t*>(g->dev + g->lay.bwd_lvl);
+    set_lds(k_backward_view<RW>, lds);
+    prof_launch("k_backward_view", s, [&] {
+        hipLaunchKernelGGL((k_backward_view<RW>), dim3(NV), dim3(kViewThreads), lds, s, dg, kv, NV, int(g->L),
+                           int(g->E), lv, g->max_bt, g->max_bs, g->max_bd, nd->net_delay, t->drv_ts, t->arc_ts,
+                           t->arc_delay, ep_rat, o->drv_rat, o->arc_rat, o->drv_slack, o->arc_slack, o->tns, o->wns);
+    });
+}
+
+static void run_backward_views(const sta_graph* g, int rw, size_t lds, int NV, const KViews& kv, const sta_net_out* nd,
+                               const sta_timing_out* t, const float* ep_rat, const sta_slack_out* o, hipStream_t s) {
+    switch (rw) {
+        case 1: launch_backward_view<1>(g, NV, kv, nd, t, ep_rat, o, lds, s); break;
+        case 2: launch_backward_view<2>(g, NV, kv, nd, t, ep_rat, o, lds, s); break;
+        case 4: launch_backward_view<4>(g, NV, kv, nd, t, ep_rat, o, lds, s); break;
+        default: launch_backward_view<8>(g, NV, kv, nd, t, ep_rat, o, lds, s); break;
+    }
 }
 
 }  // namespace sta
@@ -580,13 +1231,13 @@ extern "C" {
 sta_status sta_delay_calc(const sta_graph* g, sta_dc_precision prec, const sta_net_out* out, void* stream) {
     if (!g || !out) return fail(STA_E_ARG, "sta_delay_calc: null argument");
     if (!g->dev) return fail(STA_E_ARG, "sta_delay_calc: graph not uploaded");
+    if (prec != STA_DC_FP64 && prec != STA_DC_FP32) return fail(STA_E_ARG, "sta_delay_calc: unknown precision");
     if (g->D == 0) return STA_OK;
     if (!out->load || (g->A > 0 && (!out->net_delay || !out->net_imp2)))
         return fail(STA_E_ARG, "sta_delay_calc: null output buffer");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (prec == STA_DC_FP64) dispatch_dc<double>(g, out, s);
-    else if (prec == STA_DC_FP32) dispatch_dc<float>(g, out, s);
-    else return fail(STA_E_ARG, "sta_delay_calc: unknown precision");
+    else dispatch_dc<float>(g, out, s);
     return launch_check("sta_delay_calc");
 }
 
@@ -605,21 +1256,30 @@ sta_status sta_propagate(const sta_graph* g, const sta_library* lib, const sta_v
         if (!(lib->x[i] < lib->x[i + 1]) || !(lib->y[i] < lib->y[i + 1]))
             return fail(STA_E_ARG, "sta_propagate: library axes must strictly increase");
     if (g->D == 0) return STA_OK;
-    if ((g->n_pi > 0 && !pi_ts) || !out->drv_ts || (g->A > 0 && (!out->arc_ts || !out->arc_delay || !out->argmax ||
-                                                                  !nd->net_delay || !nd->net_imp2)) || !nd->load)
+    if ((g->n_pi > 0 && !pi_ts) || !out->drv_ts ||
+        (g->A > 0 && (!out->arc_ts || !out->arc_delay || !out->argmax || !nd->net_delay || !nd->net_imp2)) ||
+        !nd->load)
         return fail(STA_E_ARG, "sta_propagate: null buffer");
     KLib kl{};
-    for (int i = 0; i < 7; ++i) { kl.x[i] = lib->x[i]; kl.y[i] = lib->y[i]; }
-    for (int i = 0; i < 6; ++i) { kl.dx[i] = lib->x[i + 1] - lib->x[i]; kl.dy[i] = lib->y[i + 1] - lib->y[i]; }
+    for (int i = 0; i < 7; ++i) { kl.ax[i] = lib->x[i]; kl.ax[7 + i] = lib->y[i]; }
+    for (int i = 0; i < 6; ++i) { kl.ax[14 + i] = lib->x[i + 1] - lib->x[i]; kl.ax[20 + i] = lib->y[i + 1] - lib->y[i]; }
     kl.tables = lib->tables;
     kl.n_tables = lib->n_tables;
     const KViews kv = kviews(views);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    switch (views->n_views) {
-        case 1: run_forward<1>(g, kl, kv, pi_ts, nd, out, s); break;
-        case 2: run_forward<2>(g, kl, kv, pi_ts, nd, out, s); break;
-        case 4: run_forward<4>(g, kl, kv, pi_ts, nd, out, s); break;
-        default: run_forward<8>(g, kl, kv, pi_ts, nd, out, s); break;
+    int rw = 0;
+    size_t lds = 0;
+    if (use_view_forward(g, lib->n_tables, &rw, &lds)) {
+        run_forward_views(g, rw, lds, views->n_views, kl, kv, pi_ts, nd, out, s);
+    } else {
+        sta_status st;
+        switch (views->n_views) {
+            case 1: st = run_forward_levels<1>(g, kl, kv, pi_ts, nd, out, s); break;
+            case 2: st = run_forward_levels<2>(g, kl, kv, pi_ts, nd, out, s); break;
+            case 4: st = run_forward_levels<4>(g, kl, kv, pi_ts, nd, out, s); break;
+            default: st = run_forward_levels<8>(g, kl, kv, pi_ts, nd, out, s); break;
+        }
+        if (st != STA_OK) return st;
     }
     return launch_check("sta_propagate");
 }
@@ -637,11 +1297,19 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
         return fail(STA_E_ARG, "sta_slack: null buffer");
     const KViews kv = kviews(views);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    switch (views->n_views) {
-        case 1: run_backward<1>(g, kv, nd, t, ep_rat, out, scratch, s); break;
-        case 2: run_backward<2>(g, kv, nd, t, ep_rat, out, scratch, s); break;
-        case 4: run_backward<4>(g, kv, nd, t, ep_rat, out, scratch, s); break;
-        default: run_backward<8>(g, kv, nd, t, ep_rat, out, scratch, s); break;
+    int rw = 0;
+    size_t lds = 0;
+    if (use_view_backward(g, &rw, &lds)) {
+        run_backward_views(g, rw, lds, views->n_views, kv, nd, t, ep_rat, out, s);
+    } else {
+        sta_status st;
+        switch (views->n_views) {
+            case 1: st = run_backward_levels<1>(g, kv, nd, t, ep_rat, out, scratch, s); break;
+            case 2: st = run_backward_levels<2>(g, kv, nd, t, ep_rat, out, scratch, s); break;
+            case 4: st = run_backward_levels<4>(g, kv, nd, t, ep_rat, out, scratch, s); break;
+            default: st = run_backward_levels<8>(g, kv, nd, t, ep_rat, out, scratch, s); break;
+        }
+        if (st != STA_OK) return st;
     }
     return launch_check("sta_slack");
 }
@@ -685,6 +1353,13 @@ sta_status sta_profile_end(sta_kernel_stat* stats, int32_t cap, int32_t* n) {
     }
     *n = k;
     return st;
+}
+
+sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32_t use_graphs) {
+    if (!g) return fail(STA_E_ARG, "sta_set_schedule: null graph");
+    g->view_sched_max_arcs = view_max_arcs_per_level < 0 ? kDefaultViewSchedMaxArcs : view_max_arcs_per_level;
+    g->use_graphs = use_graphs != 0;
+    return STA_OK;
 }
 
 }  // extern "C"

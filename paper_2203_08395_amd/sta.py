@@ -69,8 +69,8 @@ class SlackOut(ctypes.Structure):
 _lib = None
 
 EXPORTS = ("sta_last_error", "sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload",
-           "sta_graph_free", "sta_delay_calc", "sta_propagate", "sta_slack", "sta_profile_begin",
-           "sta_profile_end")
+           "sta_graph_free", "sta_delay_calc", "sta_propagate", "sta_slack", "sta_set_schedule",
+           "sta_profile_begin", "sta_profile_end")
 
 
 class KernelStat(ctypes.Structure):
@@ -84,6 +84,9 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2203_08395_amd.build`")
+    # torch first, so that libsta binds to the HIP runtime torch already uses (one runtime
+    # per process: device pointers and streams from torch are then valid in libsta)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     lib.sta_last_error.restype = ctypes.c_char_p
     lib.sta_last_error.argtypes = []
@@ -98,10 +101,11 @@ def load_library():
                                   ctypes.POINTER(NetOut), ctypes.POINTER(TimingOut), _P]
     lib.sta_slack.argtypes = [_P, ctypes.POINTER(ViewsC), ctypes.POINTER(NetOut), ctypes.POINTER(TimingOut), _P,
                               ctypes.POINTER(SlackOut), _P, ctypes.c_size_t, _P]
+    lib.sta_set_schedule.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
     lib.sta_profile_begin.argtypes = []
     lib.sta_profile_end.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     for f in ("sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload", "sta_delay_calc",
-              "sta_propagate", "sta_slack", "sta_profile_begin", "sta_profile_end"):
+              "sta_propagate", "sta_slack", "sta_set_schedule", "sta_profile_begin", "sta_profile_end"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -166,6 +170,13 @@ class Graph:
         self.device = self.dev.device
         _check(lib.sta_graph_upload(self._h, _P(self.dev.data_ptr()), nb, _stream(torch, self.device)),
                "sta_graph_upload")
+        return self
+
+    def set_schedule(self, view_max_arcs_per_level, use_graphs=True):
+        """0: one launch per level; -1: default choice; n: view schedule up to n arcs per
+        level.  use_graphs: replay the level schedule's launches from a captured hipGraph."""
+        _check(load_library().sta_set_schedule(self._h, int(view_max_arcs_per_level), int(bool(use_graphs))),
+               "sta_set_schedule")
         return self
 
     @property

@@ -33,11 +33,19 @@ def assert_bitwise(name, got, want):
         raise AssertionError(f"{name}: {bad.size} of {got.size} differ; first at {i}: got {got[i]!r} want {want[i]!r}")
 
 
-def gpu_run(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, precision=sta.STA_DC_FP64, device="cuda"):
-    """ep_rats[v]: endpoint required times of view v (rank order)."""
+# name: (view-schedule threshold in arcs per level, replay from hipGraphs)
+SCHEDULES = {"level": (0, True), "level_plain": (0, False), "view": (1 << 30, True)}
+
+
+def gpu_run(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, precision=sta.STA_DC_FP64, device="cuda",
+            schedule=None):
+    """ep_rats[v]: endpoint required times of view v (rank order); schedule: None (the
+    library's choice), "level" or "view"."""
     import torch
     V = len(modes)
     g = sta.Graph(d, n_tables=lib.tab.shape[-4]).upload(device)
+    if schedule is not None:
+        g.set_schedule(*SCHEDULES[schedule])
     tables = torch.from_numpy(np.ascontiguousarray(lib.tab)).to(device)
     L = sta.make_library(lib.x, lib.y, tables)
     views = sta.make_views(modes, table_sets)
@@ -47,22 +55,30 @@ def gpu_run(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, precision=s
         pi[: d.n_pi, v, 0] = pi_at
         pi[: d.n_pi, v, 1] = pi_slew
     pi_t = torch.from_numpy(pi).to(device)
-    t = sta.propagate(g, L, views, pi_t, nd)
     E = g.sizes["n_endpoints"]
     rat = np.zeros((max(E, 1), V), np.float32)
     for v in range(V):
         rat[:E, v] = ep_rats[v]
     rat_t = torch.from_numpy(rat).to(device)
-    s = sta.slack(g, views, nd, t, rat_t)
     torch.cuda.synchronize()
+    sta.profile_begin()
+    t = sta.propagate(g, L, views, pi_t, nd)
+    s = sta.slack(g, views, nd, t, rat_t)
+    ran = sta.profile_end()
+    torch.cuda.synchronize()
+    if schedule == "view" and g.sizes["n_levels"] > 0:
+        # wide levels may not fit a workgroup's LDS: then that pass runs per level
+        assert "k_forward_view" in ran or "k_backward_view" in ran, ran
+    if schedule in ("level", "level_plain") and g.sizes["n_levels"] > 0:
+        assert "k_forward" in ran and "k_backward" in ran, ran
     host = {k: v.cpu().numpy() for k, v in list(nd.items()) + list(t.items()) + list(s.items()) if k != "scratch"}
     return g, host
 
 
-def compare_all(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, label=""):
+def compare_all(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, label="", schedule=None):
     """HIP path vs oracle, bit for bit, every output of every view."""
-    say(f"[gpu case] {label}: pins={d.n_pins} views={list(modes)} sets={table_sets}")
-    g, h = gpu_run(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets)
+    say(f"[gpu case] {label}: pins={d.n_pins} views={list(modes)} sets={table_sets} schedule={schedule}")
+    g, h = gpu_run(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets, schedule=schedule)
     D, A, G = d.n_drivers, d.n_arcs, d.n_gates
     load, nd, ni = oracle.delay_calc(d)
     assert_bitwise("load", g.drv_to_input(h["load"][:D]), load)

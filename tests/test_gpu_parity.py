@@ -11,24 +11,29 @@ from tests.gpu_common import EARLY, LATE, assert_bitwise, compare_all, gpu_run, 
 
 pytestmark = pytest.mark.gpu
 
+SCHED = pytest.mark.parametrize("schedule", ["level", "level_plain", "view"])
 
-def test_c1_late_and_early():
+
+@SCHED
+def test_c1_late_and_early(schedule):
     d, lib, pa, ps, late, early = workload("c1")
-    compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label="c1 10k pins")
+    compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label="c1 10k pins", schedule=schedule)
 
 
+@SCHED
 @pytest.mark.parametrize("seed", range(12))
-def test_random_tiny_designs(seed):
+def test_random_tiny_designs(seed, schedule):
     from tests.test_oracle_graph import _random_tiny
     d, lib, pa, ps = _random_tiny(seed)
     ep = oracle.endpoints(d)
     rng = np.random.default_rng(seed)
     rat = [rng.uniform(0, 2000, ep.size).astype(np.float32) for _ in range(2)]
-    compare_all(d, lib, pa, ps, rat, [LATE, EARLY], label=f"tiny seed {seed}")
+    compare_all(d, lib, pa, ps, rat, [LATE, EARLY], label=f"tiny seed {seed}", schedule=schedule)
 
 
+@SCHED
 @pytest.mark.parametrize("nv", [1, 4, 8])
-def test_view_counts_and_corners(nv):
+def test_view_counts_and_corners(nv, schedule):
     d = gen.make_design(n_pins=30000, n_levels=40, fanin="geom", seed=21, n_fanout64=2)
     lib = gen.make_library(kappas=gen.CORNER_KAPPAS)
     pa, ps = gen.make_pi(d, seed=5)
@@ -36,10 +41,11 @@ def test_view_counts_and_corners(nv):
     modes = [LATE if v % 2 == 0 else EARLY for v in range(nv)]
     sets = [(v // 2) % 4 for v in range(nv)]
     rats = [late if m == LATE else early for m in modes]
-    compare_all(d, lib, pa, ps, rats, modes, sets, label=f"{nv} views over corners")
+    compare_all(d, lib, pa, ps, rats, modes, sets, label=f"{nv} views over corners", schedule=schedule)
 
 
-def test_ragged_tiles_and_extremes():
+@SCHED
+def test_ragged_tiles_and_extremes(schedule):
     # fanin 64 (a full wavefront), a 200-sink net (a backward tile of several passes),
     # a 256-node RC tree and a one-gate level between wide ones
     rng = np.random.default_rng(3)
@@ -66,10 +72,11 @@ def test_ragged_tiles_and_extremes():
     ps = rng.uniform(5, 50, n_pi).astype(np.float32)
     ep = oracle.endpoints(d)
     rat = [rng.uniform(100, 900, ep.size).astype(np.float32) for _ in range(2)]
-    compare_all(d, lib, pa, ps, rat, [LATE, EARLY], label="ragged tiles and extremes")
+    compare_all(d, lib, pa, ps, rat, [LATE, EARLY], label="ragged tiles and extremes", schedule=schedule)
 
 
-def test_ties_on_gpu():
+@SCHED
+def test_ties_on_gpu(schedule):
     same = tiny.chain_net([100.0, 50.0], [0.5, 0.5, 0.5])
     one = ([-1], [0.0], [0.4])
     # every primary input drives one sink through the same net: all candidates are equal
@@ -77,19 +84,22 @@ def test_ties_on_gpu():
                     pincaps=[2.0] * 8, tables=[1] * 8)
     lib = gen.make_library(n_tables=2, seed=3)
     g, h = compare_all(d, lib, np.full(8, 20.0, np.float32), np.full(8, 30.0, np.float32),
-                       [np.full(2, 500.0, np.float32)] * 2, [LATE, EARLY], label="equal candidates")
+                       [np.full(2, 500.0, np.float32)] * 2, [LATE, EARLY], label="equal candidates",
+                       schedule=schedule)
     assert np.all(h["argmax"][:2] == 0)
 
 
-def test_pi_only_and_empty_designs():
+@SCHED
+def test_pi_only_and_empty_designs(schedule):
     d = tiny.design(3, [], [tiny.chain_net([5.0], [1.0, 1.0])] * 3)
     lib = gen.make_library(n_tables=1, seed=1)
     compare_all(d, lib, np.array([1, 2, 3], np.float32), np.array([5, 6, 7], np.float32),
-                [np.array([10, -1, 2.5], np.float32)] * 2, [LATE, EARLY], label="primary inputs only")
+                [np.array([10, -1, 2.5], np.float32)] * 2, [LATE, EARLY], label="primary inputs only",
+                schedule=schedule)
     say("[gpu case] empty design")
     d = tiny.design(0, [], [])
     g, h = gpu_run(d, lib, np.zeros(0, np.float32), np.zeros(0, np.float32), [np.zeros(0, np.float32)],
-                   [LATE])
+                   [LATE], schedule=schedule)
     assert h["tns"][0] == 0.0 and np.isinf(h["wns"][0])
 
 
@@ -110,16 +120,52 @@ def test_fp32_delay_calc_within_1e5():
     assert np.all(np.abs(gi.astype(np.float64) - imp2) <= 1e-5 * scale)
 
 
-def test_deterministic_reruns():
+@SCHED
+def test_deterministic_reruns(schedule):
     d, lib, pa, ps, late, early = workload("c1")
-    say("[gpu case] determinism c1")
-    _, h1 = gpu_run(d, lib, pa, ps, [late, early], [LATE, EARLY])
-    _, h2 = gpu_run(d, lib, pa, ps, [late, early], [LATE, EARLY])
+    say(f"[gpu case] determinism c1 {schedule}")
+    _, h1 = gpu_run(d, lib, pa, ps, [late, early], [LATE, EARLY], schedule=schedule)
+    _, h2 = gpu_run(d, lib, pa, ps, [late, early], [LATE, EARLY], schedule=schedule)
     for k in h1:
         assert_bitwise("rerun " + k, h1[k].reshape(-1), h2[k].reshape(-1))
 
 
-def test_c2_full_size_bitwise():
-    # the 1M-pin workload in the launch configuration the benchmark times
+@pytest.mark.parametrize("schedule", [None, "level_plain", "view"])
+def test_c2_full_size_bitwise(schedule):
+    # the 1M-pin workload; schedule None is the library's own choice, which the
+    # benchmark times
     d, lib, pa, ps, late, early = workload("c2")
-    compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label="c2 1M pins")
+    compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label="c2 1M pins", schedule=schedule)
+
+
+def test_graph_replays_match_plain_launches():
+    # the level schedule replays a captured hipGraph; replay it several times with torch's
+    # own work (zeroing every output) and synchronizations in between, and compare every
+    # replay with a plain-launch run
+    import torch
+    d, lib, pa, ps, late, early = workload("c1")
+    say("[gpu case] graph replays c1")
+    _, ref = gpu_run(d, lib, pa, ps, [late, early], [LATE, EARLY], schedule="level_plain")
+    g = sta.Graph(d, n_tables=lib.n_tables).upload("cuda")
+    g.set_schedule(0, True)
+    Lb = sta.make_library(lib.x, lib.y, torch.from_numpy(lib.tab).cuda())
+    views = sta.make_views([LATE, EARLY])
+    pi = np.zeros((d.n_pi, 2, 2), np.float32)
+    pi[:, :, 0] = pa[:, None]
+    pi[:, :, 1] = ps[:, None]
+    pit = torch.from_numpy(pi).cuda()
+    rat = torch.from_numpy(np.stack([late, early], 1).astype(np.float32)).cuda()
+    nd = sta.delay_calc(g)
+    tm = sta.alloc_timing(g, 2)
+    sl = sta.alloc_slack(g, 2)
+    for rep in range(4):
+        for tsr in list(tm.values()) + [v for k, v in sl.items() if k != "scratch"]:
+            tsr.zero_()
+        torch.cuda.synchronize()
+        sta.propagate(g, Lb, views, pit, nd, out=tm)
+        sta.slack(g, views, nd, tm, rat, out=sl)
+        torch.cuda.synchronize()
+        for k, v in list(tm.items()) + list(sl.items()):
+            if k == "scratch":
+                continue
+            assert_bitwise(f"replay {rep} {k}", v.cpu().numpy().reshape(-1), ref[k].reshape(-1))
