@@ -46,6 +46,9 @@ DevGraph dev_graph(const sta_graph* g) {
     d.bslot_arc = reinterpret_cast<const int32_t*>(b + L.bslot_arc);
     d.bslot_out = reinterpret_cast<const int32_t*>(b + L.bslot_out);
     d.ep_drv = reinterpret_cast<const int32_t*>(b + L.ep_drv);
+    d.ftile_maxk = reinterpret_cast<const int32_t*>(b + L.ftile_maxk);
+    d.fwd_chunk = reinterpret_cast<const int32_t*>(b + L.fwd_chunk);
+    d.bwd_chunk = reinterpret_cast<const int32_t*>(b + L.bwd_chunk);
     d.n_pi = g->n_pi;
     d.n_gates = g->n_gates;
     d.n_drivers = static_cast<int32_t>(g->D);
@@ -216,6 +219,26 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     const int64_t NF = int64_t(ftile_arc.size());
     ftile_arc.push_back(int32_t(A));
     ftile_gate.push_back(int32_t(G));
+    std::vector<int32_t> ftile_maxk(std::max<int64_t>(NF, 1), 0);
+    for (int64_t t = 0; t < NF; ++t)
+        for (int32_t q = ftile_gate[t]; q < ftile_gate[t + 1]; ++q)
+            ftile_maxk[t] = std::max(ftile_maxk[t], gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q]);
+    // forward chunks: consecutive whole tiles of one level within the staging bounds
+    std::vector<int32_t> fchunk;   // 4 ints per chunk: first tile, first arc, first gate, level
+    for (int32_t l = 1; l <= Lmax; ++l) {
+        int32_t t = g->fwd_tile_ptr[l];
+        const int32_t t1 = g->fwd_tile_ptr[l + 1];
+        while (t < t1) {
+            const int32_t c0 = t;
+            while (t < t1 && (t - c0) < kFwdCapT && ftile_arc[t + 1] - ftile_arc[c0] <= kFwdCapA &&
+                   ftile_gate[t + 1] - ftile_gate[c0] <= kFwdCapG)
+                ++t;
+            if (t == c0) ++t;   // a single tile always fits (<= 64 arcs and gates)
+            fchunk.insert(fchunk.end(), {c0, ftile_arc[c0], ftile_gate[c0], l});
+        }
+    }
+    g->n_fchunks = int32_t(fchunk.size() / 4);
+    fchunk.insert(fchunk.end(), {int32_t(NF), int32_t(A), int32_t(G), int32_t(Lmax + 1)});
 
     // ---- internal sink lists and backward slots --------------------------------------
     // driver i's slots: one per sink (ascending input arc id), or one endpoint slot
@@ -277,6 +300,27 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     const int64_t NB = int64_t(btile_drv.size());
     btile_drv.push_back(int32_t(D));
     btile_slot.push_back(int32_t(S));
+    // backward chunks, in processing order (levels L..0, tiles ascending): each entry is
+    // (first tile, tile end, first slot, slot end, first driver, driver end, level, 0).
+    // No chunk is made when a single tile exceeds the bounds (then only the level
+    // schedule runs the backward pass).
+    std::vector<int32_t> bchunk;
+    bool bwd_chunkable = true;
+    for (int32_t l = Lmax; l >= 0 && bwd_chunkable; --l) {
+        int32_t t = g->bwd_tile_ptr[l];
+        const int32_t t1 = g->bwd_tile_ptr[l + 1];
+        while (t < t1) {
+            const int32_t c0 = t;
+            while (t < t1 && (t - c0) < kBwdCapT && btile_slot[t + 1] - btile_slot[c0] <= kBwdCapS &&
+                   btile_drv[t + 1] - btile_drv[c0] <= kBwdCapD)
+                ++t;
+            if (t == c0) { bwd_chunkable = false; break; }
+            bchunk.insert(bchunk.end(), {c0, t, btile_slot[c0], btile_slot[t], btile_drv[c0], btile_drv[t], l, 0});
+        }
+    }
+    if (!bwd_chunkable) bchunk.clear();
+    g->n_bchunks = int32_t(bchunk.size() / 8);
+    bchunk.insert(bchunk.end(), {0, 0, 0, 0, 0, 0, -1, 0});
 
     // ---- internal arcs and nets --------------------------------------------------------
     std::vector<int32_t> arc_src(A);
@@ -326,6 +370,9 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     lay.bslot_out = place(S * 4);
     lay.ep_drv = place(E * 4);
     lay.fwd_lvl = place((Lmax + 2) * 12);
+    lay.ftile_maxk = place(ftile_maxk.size() * 4);
+    lay.fwd_chunk = place(fchunk.size() * 4);
+    lay.bwd_chunk = place(bchunk.size() * 4);
     lay.bwd_lvl = place((Lmax + 2) * 12);
     lay.total = off;
     g->image.assign(off, 0);
@@ -371,6 +418,9 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
         g->max_bd = std::max(g->max_bd, blvl[(l + 1) * 3 + 2] - blvl[l * 3 + 2]);
     }
     put(lay.fwd_lvl, flvl.data(), flvl.size() * 4);
+    put(lay.ftile_maxk, ftile_maxk.data(), ftile_maxk.size() * 4);
+    put(lay.fwd_chunk, fchunk.data(), fchunk.size() * 4);
+    put(lay.bwd_chunk, bchunk.data(), bchunk.size() * 4);
     put(lay.bwd_lvl, blvl.data(), blvl.size() * 4);
 
     g->n_pi = int32_t(P);

@@ -16,6 +16,10 @@ constexpr int kWave = 64;           // CDNA wavefront width
 constexpr int kTileSlots = 64;      // one work tile = one wavefront of arcs / fanout slots
 constexpr uint32_t kHeadBit = 0x80000000u;
 constexpr int32_t kDefaultViewSchedMaxArcs = 512;    // mean cell arcs per level
+// view-schedule forward chunks: whole tiles of one level, bounded for LDS staging
+constexpr int kFwdCapA = 2816, kFwdCapG = 1152, kFwdCapT = 96;
+// view-schedule backward chunks: whole tiles of one driver level
+constexpr int kBwdCapS = 4096, kBwdCapD = 2048, kBwdCapT = 128;
 constexpr size_t kViewTableLdsMax = 65536;            // LDS bytes for tables + axes
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
@@ -27,6 +31,9 @@ struct DevLayout {
     size_t btile_drv, btile_slot, bslot_arc, bslot_out;
     size_t ep_drv;
     size_t fwd_lvl, bwd_lvl;       // per level (first tile, first arc|slot, first gate|driver)
+    size_t ftile_maxk;             // per forward tile: the largest gate fanin in it
+    size_t fwd_chunk;              // per forward chunk (first tile, first arc, first gate, level)
+    size_t bwd_chunk;              // per backward chunk (first tile, first slot, first driver, level)
     size_t total;
 };
 
@@ -49,6 +56,9 @@ struct DevGraph {
     const int32_t* bslot_arc;      // [S]   sink arc of the slot, -1 for an endpoint slot
     const int32_t* bslot_out;      // [S]   driver of the sink's gate (or endpoint rank) | head bit
     const int32_t* ep_drv;         // [E]   internal driver of each endpoint rank
+    const int32_t* ftile_maxk;     // [NF]  largest gate fanin of each forward tile
+    const int32_t* fwd_chunk;      // [NC+1][4] forward chunks
+    const int32_t* bwd_chunk;      // [NB+1][4] backward chunks in processing order (+ 4 ints of bounds)
     int32_t n_pi, n_gates, n_drivers, n_arcs;
 };
 
@@ -72,6 +82,7 @@ struct sta_graph {
     int64_t n_ftiles = 0, n_btiles = 0;
     // per-level maxima: forward tiles/arcs/gates, backward tiles/slots/drivers
     int32_t max_ft = 0, max_fa = 0, max_fg = 0, max_bt = 0, max_bs = 0, max_bd = 0;
+    int32_t n_fchunks = 0, n_bchunks = 0;
     int32_t view_sched_max_arcs = sta::kDefaultViewSchedMaxArcs;
     bool use_graphs = true;              // replay level-schedule launch sequences from hipGraphs
     mutable std::mutex cache_mu;

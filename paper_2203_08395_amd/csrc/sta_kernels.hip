@@ -144,22 +144,29 @@ __device__ __forceinline__ void fwd_lane_setup(FwdLane& x, bool act, uint32_t me
     x.seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : n;
 }
 
-// arc arithmetic, per-gate max/argmax (min for early views) and the writes
-template <int NW>
-__device__ __forceinline__ void fwd_finish(const FwdLane& x, const float2* ts, const float* s_ax,
-                                           const float* const* tab, const bool* early, int NV, int v0, int n_pi,
-                                           float* __restrict__ drv_ts, float* __restrict__ arc_ts,
-                                           float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
-    const float* X = s_ax;
+// the load segment and fraction of a gate output (shared by the gate's arcs)
+__device__ __forceinline__ void gate_jty(const float* s_ax, float Lo, int& j, float& ty) {
     const float* Y = s_ax + 7;
-    const float* DX = s_ax + 14;
     const float* DY = s_ax + 20;
+    j = seg6(Y, Lo);
+    ty = (Lo - Y[j]) / DY[j];
+}
+
+// arc arithmetic, per-gate max/argmax (min for early views) and the writes.  span: the
+// largest gate fanin in the tile (the reduction needs ceil(log2(span)) steps).
+// fresh_out (optional, LDS): the gate outputs of the first view, by gate index - gbase.
+template <int NW>
+__device__ __forceinline__ void fwd_finish(const FwdLane& x, const float2* ts, int j, float ty, int span,
+                                           const float* s_ax, const float* const* tab, const bool* early, int NV,
+                                           int v0, int n_pi, float* __restrict__ drv_ts, float* __restrict__ arc_ts,
+                                           float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
+                                           float2* fresh_out = nullptr, int gbase = 0) {
+    const float* X = s_ax;
+    const float* DX = s_ax + 14;
     const int lane = threadIdx.x & 63;
     float cand[NW], slw[NW];
     int best_k[NW];
     if (x.active) {
-        const int j = seg6(Y, x.Lo);
-        const float ty = (x.Lo - Y[j]) / DY[j];
         float2* dst = reinterpret_cast<float2*>(arc_ts) + size_t(x.a) * NV + v0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
@@ -183,8 +190,7 @@ __device__ __forceinline__ void fwd_finish(const FwdLane& x, const float2* ts, c
     }
     // segmented reduction toward each gate's first lane; the left operand covers the
     // lower arc positions, so keeping it on ties keeps the smallest arc index
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
+    for (int off = 1; off < span; off <<= 1) {
         const bool take = (lane + off) < x.seg_end;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
@@ -204,6 +210,7 @@ __device__ __forceinline__ void fwd_finish(const FwdLane& x, const float2* ts, c
             out[w] = make_float2(cand[w], slw[w]);
             argmax[size_t(x.g) * NV + v0 + w] = uint8_t(best_k[w]);
         }
+        if (fresh_out) fresh_out[x.g - gbase] = make_float2(cand[0], slw[0]);
     }
 }
 
@@ -427,6 +434,9 @@ __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V,
     x.a = a;
     x.g = g0 + x.gi;
     x.Lo = act ? load[G.n_pi + x.g] : 0.0f;
+    int j = 0;
+    float ty = 0.0f;
+    gate_jty(s_ax, x.Lo, j, ty);
     float2 ts[NV];
     const float2* srcp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV;
 #pragma unroll
@@ -438,7 +448,7 @@ __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V,
         tab[v] = TAB_LDS ? s_dyn : lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
         early[v] = V.mode[v] == STA_EARLY;
     }
-    fwd_finish<NV>(x, ts, s_ax, tab, early, NV, 0, G.n_pi, drv_ts, arc_ts, arc_delay, argmax);
+    fwd_finish<NV>(x, ts, j, ty, 64, s_ax, tab, early, NV, 0, G.n_pi, drv_ts, arc_ts, arc_delay, argmax);
 }
 
 // primary inputs: copy (arrival, slew) of every view
@@ -567,31 +577,44 @@ __global__ __launch_bounds__(256) void k_endpoint_final(int nblk, const unsigned
 constexpr int kViewThreads = 1024;
 constexpr int kViewWaves = kViewThreads / 64;
 
-// LDS layout of k_forward_view (in 4-byte words)
+// k_forward_view: the levels are cut into chunks (whole tiles of one level, at most
+// kFwdCapA arcs / kFwdCapG gates).  While chunk c computes, the workgroup issues the
+// global loads of chunk c+1's arc records and gate loads, of chunk c+2's driver ids, and
+// the gathers of chunk c+1's inputs whose drivers are final (earlier chunks).  Inputs
+// produced by chunk c itself are handed to chunk c+1 through LDS.  The compute phase
+// reads LDS only.
 struct FwdLds {
-    int ax, tab, lvl, taoff, tgoff, src, meta, nd, ni, ld, total;
+    int ax, tab, meta, nd, ni, src, in_at, in_sl, flag, gj, gty, f0, f1, taoff, tgoff, tmaxk, total;
 };
 
-__host__ __device__ inline FwdLds fwd_lds(int n_tables, int L, int capT, int capA, int capG) {
+__host__ __device__ inline FwdLds fwd_lds(int n_tables) {
     FwdLds o{};
     o.ax = 0;
     o.tab = 32;
-    o.lvl = o.tab + n_tables * 98;
-    o.taoff = o.lvl + (L + 2) * 3;
-    o.tgoff = o.taoff + capT + 1;
-    o.src = o.tgoff + capT;
-    o.meta = o.src + capA;
-    o.nd = o.meta + capA;
-    o.ni = o.nd + capA;
-    o.ld = o.ni + capA;
-    o.total = o.ld + capG;
+    o.meta = o.tab + n_tables * 98;
+    o.nd = o.meta + kFwdCapA;
+    o.ni = o.nd + kFwdCapA;
+    o.src = o.ni + kFwdCapA;
+    o.in_at = o.src + kFwdCapA;
+    o.in_sl = o.in_at + kFwdCapA;
+    o.flag = o.in_sl + kFwdCapA;                  // bytes
+    o.gj = o.flag + kFwdCapA / 4;
+    o.gty = o.gj + kFwdCapG;
+    o.f0 = ((o.gty + kFwdCapG) + 1) & ~1;         // float2, 8-byte aligned
+    o.f1 = o.f0 + 2 * kFwdCapG;
+    o.taoff = o.f1 + 2 * kFwdCapG;
+    o.tgoff = o.taoff + kFwdCapT + 1;
+    o.tmaxk = o.tgoff + kFwdCapT;
+    o.total = o.tmaxk + kFwdCapT;
     return o;
 }
 
-template <int RW>
-__global__ __launch_bounds__(kViewThreads) void k_forward_view(DevGraph G, KLib lib, KViews V, int NV, int L,
-                                                               const int32_t* __restrict__ lvl_g, int capT, int capA,
-                                                               int capG, const float* __restrict__ pi_ts,
+constexpr int kFwdRA = (kFwdCapA + kViewThreads - 1) / kViewThreads;   // arcs per lane when staging
+constexpr int kFwdRG = (kFwdCapG + kViewThreads - 1) / kViewThreads;   // gates per lane when staging
+constexpr int kFwdRT = (kFwdCapT + kViewWaves - 1) / kViewWaves;       // tiles per wave
+
+__global__ __launch_bounds__(kViewThreads) void k_forward_view(DevGraph G, KLib lib, KViews V, int NV, int NC,
+                                                               const float* __restrict__ pi_ts,
                                                                const float* __restrict__ load,
                                                                const float* __restrict__ nd,
                                                                const float* __restrict__ ni,
@@ -599,130 +622,240 @@ __global__ __launch_bounds__(kViewThreads) void k_forward_view(DevGraph G, KLib 
                                                                float* __restrict__ arc_delay,
                                                                uint8_t* __restrict__ argmax) {
     extern __shared__ float s_mem[];
-    const FwdLds lo = fwd_lds(lib.n_tables, L, capT, capA, capG);
+    const FwdLds lo = fwd_lds(lib.n_tables);
     float* s_ax = s_mem + lo.ax;
     float* s_tab = s_mem + lo.tab;
-    int* s_lvl = reinterpret_cast<int*>(s_mem + lo.lvl);
-    int* s_taoff = reinterpret_cast<int*>(s_mem + lo.taoff);
-    int* s_tgoff = reinterpret_cast<int*>(s_mem + lo.tgoff);
-    int* s_src = reinterpret_cast<int*>(s_mem + lo.src);
     uint32_t* s_meta = reinterpret_cast<uint32_t*>(s_mem + lo.meta);
     float* s_nd = s_mem + lo.nd;
     float* s_ni = s_mem + lo.ni;
-    float* s_ld = s_mem + lo.ld;
+    int* s_src = reinterpret_cast<int*>(s_mem + lo.src);
+    float* s_in_at = s_mem + lo.in_at;
+    float* s_in_sl = s_mem + lo.in_sl;
+    uint8_t* s_flag = reinterpret_cast<uint8_t*>(s_mem + lo.flag);
+    int* s_gj = reinterpret_cast<int*>(s_mem + lo.gj);
+    float* s_gty = s_mem + lo.gty;
+    // the two fresh-output buffers are addressed by offset from the LDS base (an array
+    // of pointers would lose the LDS address space and turn the accesses into flat ones)
+    float2* s_f0 = reinterpret_cast<float2*>(s_mem + lo.f0);
+    int* s_taoff = reinterpret_cast<int*>(s_mem + lo.taoff);
+    int* s_tgoff = reinterpret_cast<int*>(s_mem + lo.tgoff);
+    int* s_tmaxk = reinterpret_cast<int*>(s_mem + lo.tmaxk);
     const int v = blockIdx.x;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const float* gtab = lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
+    const int* CH = G.fwd_chunk;
     load_axes(s_ax, lib);
     for (int i = tid; i < lib.n_tables * 98; i += kViewThreads) s_tab[i] = gtab[i];
-    for (int i = tid; i < (L + 2) * 3; i += kViewThreads) s_lvl[i] = lvl_g[i];
     for (int i = tid; i < G.n_pi; i += kViewThreads)
         reinterpret_cast<float2*>(drv_ts)[size_t(i) * NV + v] = reinterpret_cast<const float2*>(pi_ts)[size_t(i) * NV + v];
     const bool early[1] = {V.mode[v] == STA_EARLY};
     const float* tab[1] = {s_tab};
     __syncthreads();
 
-    // static data of level l into registers (coalesced), then into LDS
-    int p_src[RW], p_ld_n = 0;
-    uint32_t p_meta[RW];
-    float p_nd[RW], p_ni[RW], p_ld[RW];
-    int p_ta = 0, p_tg = 0;
-    auto fetch = [&](int l) {
-        const int t0 = s_lvl[l * 3], t1 = s_lvl[(l + 1) * 3];
-        const int al = s_lvl[l * 3 + 1], ah = s_lvl[(l + 1) * 3 + 1];
-        const int gl = s_lvl[l * 3 + 2], gh = s_lvl[(l + 1) * 3 + 2];
+    // staging registers
+    uint32_t p_meta[kFwdRA];
+    float p_nd[kFwdRA], p_ni[kFwdRA], p_ld[kFwdRG];
+    int p_src2[kFwdRA];
+    float p_at[kFwdRA], p_sl[kFwdRA];
+    bool p_fresh[kFwdRA];
+    int p_ta = 0, p_tg = 0, p_tk = 0;
+
+    // static records of chunk c (arc records, gate loads, tile bounds) into registers
+    auto fetch_static = [&](int c) {
+        const int t0 = CH[c * 4], t1 = CH[c * 4 + 4];
+        const int al = CH[c * 4 + 1], ah = CH[c * 4 + 5];
+        const int gl = CH[c * 4 + 2], gh = CH[c * 4 + 6];
+        // loads are unconditional, from clamped (always valid) indices, so that no
+        // branch forces an early wait for them; the values are selected afterwards
 #pragma unroll
-        for (int k = 0; k < RW; ++k) {
+        for (int k = 0; k < kFwdRA; ++k) {
             const int i = tid + k * kViewThreads;
-            const bool ok = i < ah - al;
-            p_src[k] = ok ? G.arc_src[al + i] : 0;
-            p_meta[k] = ok ? G.arc_meta[al + i] : 0u;
-            p_nd[k] = ok ? nd[al + i] : 0.0f;
-            p_ni[k] = ok ? ni[al + i] : 0.0f;
-            p_ld[k] = (i < gh - gl) ? load[G.n_pi + gl + i] : 0.0f;
+            const int ia = (i < ah - al) ? al + i : 0;
+            p_meta[k] = G.arc_meta[ia];
+            p_nd[k] = nd[ia];
+            p_ni[k] = ni[ia];
         }
-        p_ta = (tid <= t1 - t0) ? G.ftile_arc[t0 + tid] - al : 0;
-        p_tg = (tid < t1 - t0) ? G.ftile_gate[t0 + tid] - gl : 0;
-        p_ld_n = 0;
-    };
-    auto stash = [&](int l) {
-        const int t0 = s_lvl[l * 3], t1 = s_lvl[(l + 1) * 3];
-        const int al = s_lvl[l * 3 + 1], ah = s_lvl[(l + 1) * 3 + 1];
-        const int gl = s_lvl[l * 3 + 2], gh = s_lvl[(l + 1) * 3 + 2];
 #pragma unroll
-        for (int k = 0; k < RW; ++k) {
+        for (int k = 0; k < kFwdRG; ++k) {
             const int i = tid + k * kViewThreads;
-            if (i < ah - al) { s_src[i] = p_src[k]; s_meta[i] = p_meta[k]; s_nd[i] = p_nd[k]; s_ni[i] = p_ni[k]; }
-            if (i < gh - gl) s_ld[i] = p_ld[k];
+            p_ld[k] = load[(i < gh - gl) ? G.n_pi + gl + i : 0];
+        }
+        p_ta = G.ftile_arc[(tid <= t1 - t0) ? t0 + tid : 0] - al;
+        const int it = (tid < t1 - t0) ? t0 + tid : 0;
+        p_tg = G.ftile_gate[it] - gl;
+        p_tk = G.ftile_maxk[it];
+    };
+    auto stash_static = [&](int c) {
+        const int t0 = CH[c * 4], t1 = CH[c * 4 + 4];
+        const int al = CH[c * 4 + 1], ah = CH[c * 4 + 5];
+        const int gl = CH[c * 4 + 2], gh = CH[c * 4 + 6];
+#pragma unroll
+        for (int k = 0; k < kFwdRA; ++k) {
+            const int i = tid + k * kViewThreads;
+            if (i < ah - al) { s_meta[i] = p_meta[k]; s_nd[i] = p_nd[k]; s_ni[i] = p_ni[k]; }
+        }
+#pragma unroll
+        for (int k = 0; k < kFwdRG; ++k) {
+            const int i = tid + k * kViewThreads;
+            if (i < gh - gl) {
+                int j;
+                float ty;
+                gate_jty(s_ax, p_ld[k], j, ty);
+                s_gj[i] = j;
+                s_gty[i] = ty;
+            }
         }
         if (tid <= t1 - t0) s_taoff[tid] = p_ta;
-        if (tid < t1 - t0) s_tgoff[tid] = p_tg;
+        if (tid < t1 - t0) { s_tgoff[tid] = p_tg; s_tmaxk[tid] = p_tk; }
     };
-    if (L >= 1) {
-        fetch(1);
-        stash(1);
-    }
-    (void)p_ld_n;
-    __syncthreads();
-
-    for (int l = 1; l <= L; ++l) {
-        const int T = s_lvl[(l + 1) * 3] - s_lvl[l * 3];
-        const int al = s_lvl[l * 3 + 1], gl = s_lvl[l * 3 + 2];
-        // this wave's tiles: LDS reads, then every gather
-        FwdLane x[RW];
-        float2 ts[RW];
+    // driver ids of chunk c
+    auto fetch_src = [&](int c) {
+        const int al = CH[c * 4 + 1], ah = CH[c * 4 + 5];
 #pragma unroll
-        for (int r = 0; r < RW; ++r) {
+        for (int k = 0; k < kFwdRA; ++k) {
+            const int i = tid + k * kViewThreads;
+            p_src2[k] = G.arc_src[(i < ah - al) ? al + i : 0];
+        }
+    };
+    auto stash_src = [&](int c) {
+        const int al = CH[c * 4 + 1], ah = CH[c * 4 + 5];
+#pragma unroll
+        for (int k = 0; k < kFwdRA; ++k) {
+            const int i = tid + k * kViewThreads;
+            if (i < ah - al) s_src[i] = p_src2[k];
+        }
+    };
+    // inputs of chunk c (driver ids in s_src): gathered when the driver is below
+    // `done` (final), else an index into the outputs of the gates from `fresh_base`
+    auto fetch_inputs = [&](int c, int done, int fresh_base) {
+        const int al = CH[c * 4 + 1], ah = CH[c * 4 + 5];
+#pragma unroll
+        for (int k = 0; k < kFwdRA; ++k) {
+            const int i = tid + k * kViewThreads;
+            const int u = (i < ah - al) ? s_src[i] : 0;
+            p_fresh[k] = u >= done;
+            const int ug = p_fresh[k] ? 0 : u;       // driver 0 stands in for fresh inputs
+            const float2 tsv = reinterpret_cast<const float2*>(drv_ts)[size_t(ug) * NV + v];
+            p_at[k] = p_fresh[k] ? __int_as_float(u - fresh_base) : tsv.x;
+            p_sl[k] = tsv.y;
+        }
+    };
+    auto stash_inputs = [&](int c) {
+        const int al = CH[c * 4 + 1], ah = CH[c * 4 + 5];
+#pragma unroll
+        for (int k = 0; k < kFwdRA; ++k) {
+            const int i = tid + k * kViewThreads;
+            if (i < ah - al) { s_in_at[i] = p_at[k]; s_in_sl[i] = p_sl[k]; s_flag[i] = p_fresh[k] ? 1 : 0; }
+        }
+    };
+
+    if (NC > 0) {
+        // prologue: chunk 0 (its drivers are primary inputs, final) and chunk 1's driver ids
+        fetch_static(0);
+        fetch_src(0);
+        stash_static(0);
+        stash_src(0);
+        __syncthreads();
+        fetch_inputs(0, G.n_drivers, 0);
+        if (NC > 1) fetch_src(1);
+        __syncthreads();
+        stash_inputs(0);
+        if (NC > 1) stash_src(1);
+        __syncthreads();
+    }
+
+    for (int c = 0; c < NC; ++c) {
+        const int t0 = CH[c * 4], T = CH[c * 4 + 4] - t0;
+        const int al = CH[c * 4 + 1], gl = CH[c * 4 + 2];
+        const int gdone = G.n_pi + gl;          // drivers below are final once chunk c is done... minus chunk c
+        // 1. issue the next chunks' global loads
+        if (c + 1 < NC) {
+            fetch_static(c + 1);
+            fetch_inputs(c + 1, gdone, gdone);
+        }
+        if (c + 2 < NC) fetch_src(c + 2);
+        // 2. compute chunk c from LDS
+        const float2* fresh_in = s_f0 + ((c + 1) & 1) * kFwdCapG;
+        float2* fresh_out = s_f0 + (c & 1) * kFwdCapG;
+        for (int r = 0; r < kFwdRT; ++r) {
             const int tl = wave + r * kViewWaves;
-            const bool valid = tl < T;
-            const int a_off = valid ? s_taoff[tl] : 0;
-            const int n = valid ? s_taoff[tl + 1] - a_off : 0;
-            const int g_off = valid ? s_tgoff[tl] : 0;
+            if (tl >= T) break;                 // uniform per wave
+            const int a_off = s_taoff[tl];
+            const int n = s_taoff[tl + 1] - a_off;
+            const int g_off = s_tgoff[tl];
+            const int span = s_tmaxk[tl];
             const bool act = lane < n;
             const int ai = a_off + lane;
+            FwdLane x;
             const uint32_t meta = act ? s_meta[ai] : 0u;
-            fwd_lane_setup(x[r], act, meta, n, lane);
-            x[r].a = al + ai;
-            x[r].g = gl + g_off + x[r].gi;
-            x[r].nd = act ? s_nd[ai] : 0.0f;
-            x[r].ni = act ? s_ni[ai] : 0.0f;
-            x[r].Lo = act ? s_ld[g_off + x[r].gi] : 0.0f;
-            const int u = act ? s_src[ai] : 0;
-            ts[r] = act ? reinterpret_cast<const float2*>(drv_ts)[size_t(u) * NV + v] : make_float2(0.0f, 0.0f);
+            fwd_lane_setup(x, act, meta, n, lane);
+            x.a = al + ai;
+            x.g = gl + g_off + x.gi;
+            x.nd = act ? s_nd[ai] : 0.0f;
+            x.ni = act ? s_ni[ai] : 0.0f;
+            x.Lo = 0.0f;
+            const int gidx = g_off + x.gi;
+            const int j = act ? s_gj[gidx] : 0;
+            const float ty = act ? s_gty[gidx] : 0.0f;
+            float2 ts[1];
+            if (act) {
+                const float a_in = s_in_at[ai];
+                ts[0] = s_flag[ai] ? fresh_in[__float_as_int(a_in)] : make_float2(a_in, s_in_sl[ai]);
+            } else {
+                ts[0] = make_float2(0.0f, 0.0f);
+            }
+            fwd_finish<1>(x, ts, j, ty, span, s_ax, tab, early, NV, v, G.n_pi, drv_ts, arc_ts, arc_delay, argmax,
+                          fresh_out, gl);
         }
-        if (l < L) fetch(l + 1);
-#pragma unroll
-        for (int r = 0; r < RW; ++r)
-            fwd_finish<1>(x[r], &ts[r], s_ax, tab, early, NV, v, G.n_pi, drv_ts, arc_ts, arc_delay, argmax);
         __syncthreads();
-        if (l < L) stash(l + 1);
+        // 3. stage chunk c+1 (and chunk c+2's driver ids)
+        if (c + 1 < NC) {
+            stash_static(c + 1);
+            stash_inputs(c + 1);
+        }
+        if (c + 2 < NC) stash_src(c + 2);
         __syncthreads();
     }
 }
 
-// LDS layout of k_backward_view (in 4-byte words)
+// k_backward_view: chunks of whole backward tiles of one driver level, in processing
+// order (levels L..0).  While chunk c computes, the workgroup gathers chunk c+1's
+// forward results (arc delay, input arrival, net delay, driver arrival) and the
+// required times of the gate outputs its sinks feed when those are final, and loads
+// chunk c+2's slot ids.  Required times produced by chunk c reach chunk c+1 through LDS.
 struct BwdLds {
-    int lvl, tsoff, tdoff, sa, so, at, lim, mn, total;
+    int sa_n, so_n, sa, d, ati, ndv, rat, flag, at, f0, f1, tsoff, tdoff, lim, mn, total;
 };
 
-__host__ __device__ inline BwdLds bwd_lds(int L, int capT, int capS, int capD) {
+__host__ __device__ inline BwdLds bwd_lds() {
     BwdLds o{};
-    o.lvl = 0;
-    o.tsoff = o.lvl + (L + 2) * 3;
-    o.tdoff = o.tsoff + capT + 1;
-    o.sa = o.tdoff + capT;
-    o.so = o.sa + capS;
-    o.at = o.so + capS;
-    o.lim = ((o.at + capD) + 1) & ~1;              // 8-byte aligned digits
+    o.sa_n = 0;
+    o.so_n = o.sa_n + kBwdCapS;
+    o.sa = o.so_n + kBwdCapS;
+    o.d = o.sa + kBwdCapS;
+    o.ati = o.d + kBwdCapS;
+    o.ndv = o.ati + kBwdCapS;
+    o.rat = o.ndv + kBwdCapS;
+    o.flag = o.rat + kBwdCapS;                    // bytes
+    o.at = o.flag + kBwdCapS / 4;
+    o.f0 = o.at + kBwdCapD;
+    o.f1 = o.f0 + kBwdCapD;
+    o.tsoff = o.f1 + kBwdCapD;
+    o.tdoff = o.tsoff + kBwdCapT + 1;
+    o.lim = ((o.tdoff + kBwdCapT) + 1) & ~1;      // 8-byte aligned digits
     o.mn = o.lim + 2 * kLimbs;
     o.total = o.mn + kViewWaves;
     return o;
 }
 
-template <int RW>
-__global__ __launch_bounds__(kViewThreads) void k_backward_view(DevGraph G, KViews V, int NV, int L, int E,
-                                                                const int32_t* __restrict__ lvl_g, int capT, int capS,
-                                                                int capD, const float* __restrict__ nd,
+constexpr int kBwdRS = (kBwdCapS + kViewThreads - 1) / kViewThreads;
+constexpr int kBwdRD = (kBwdCapD + kViewThreads - 1) / kViewThreads;
+constexpr int kBwdRT = (kBwdCapT + kViewWaves - 1) / kViewWaves;
+constexpr uint8_t kFlagHead = 1, kFlagFresh = 2, kFlagEndpoint = 4;
+
+__global__ __launch_bounds__(kViewThreads) void k_backward_view(DevGraph G, KViews V, int NV, int NC, int E,
+                                                                const float* __restrict__ nd,
                                                                 const float* __restrict__ drv_ts,
                                                                 const float* __restrict__ arc_ts,
                                                                 const float* __restrict__ arc_delay,
@@ -733,149 +866,196 @@ __global__ __launch_bounds__(kViewThreads) void k_backward_view(DevGraph G, KVie
                                                                 float* __restrict__ arc_slack,
                                                                 double* __restrict__ tns, float* __restrict__ wns) {
     extern __shared__ float s_mem[];
-    const BwdLds lo = bwd_lds(L, capT, capS, capD);
-    int* s_lvl = reinterpret_cast<int*>(s_mem + lo.lvl);
+    const BwdLds lo = bwd_lds();
+    int* s_sa_n = reinterpret_cast<int*>(s_mem + lo.sa_n);
+    int* s_so_n = reinterpret_cast<int*>(s_mem + lo.so_n);
+    int* s_sa = reinterpret_cast<int*>(s_mem + lo.sa);
+    float* s_d = s_mem + lo.d;
+    float* s_ati = s_mem + lo.ati;
+    float* s_ndv = s_mem + lo.ndv;
+    float* s_rat = s_mem + lo.rat;
+    uint8_t* s_flag = reinterpret_cast<uint8_t*>(s_mem + lo.flag);
+    float* s_at = s_mem + lo.at;
+    float* s_f0 = s_mem + lo.f0;                   // two buffers of kBwdCapD, by parity
     int* s_tsoff = reinterpret_cast<int*>(s_mem + lo.tsoff);
     int* s_tdoff = reinterpret_cast<int*>(s_mem + lo.tdoff);
-    int* s_sa = reinterpret_cast<int*>(s_mem + lo.sa);
-    int* s_so = reinterpret_cast<int*>(s_mem + lo.so);
-    float* s_at = s_mem + lo.at;
     unsigned long long* s_l = reinterpret_cast<unsigned long long*>(s_mem + lo.lim);
     float* s_min = s_mem + lo.mn;
     const int v = blockIdx.x;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool early = V.mode[v] == STA_EARLY;
-    for (int i = tid; i < (L + 2) * 3; i += kViewThreads) s_lvl[i] = lvl_g[i];
+    const int* CH = G.bwd_chunk;
     if (tid < kLimbs) s_l[tid] = 0ull;
     __syncthreads();
 
-    int p_sa[RW], p_so[RW];
-    float p_at[RW];
+    int q_sa[kBwdRS], q_so[kBwdRS];
+    int p_sa[kBwdRS];
+    float p_d[kBwdRS], p_ati[kBwdRS], p_nd[kBwdRS], p_rat[kBwdRS], p_at[kBwdRD];
+    uint8_t p_fl[kBwdRS];
     int p_ts = 0, p_td = 0;
-    auto fetch = [&](int l) {
-        const int t0 = s_lvl[l * 3], t1 = s_lvl[(l + 1) * 3];
-        const int sl = s_lvl[l * 3 + 1], sh = s_lvl[(l + 1) * 3 + 1];
-        const int dl = s_lvl[l * 3 + 2], dh = s_lvl[(l + 1) * 3 + 2];
+
+    auto fetch_ids = [&](int c) {
+        const int s0 = CH[c * 8 + 2], s1 = CH[c * 8 + 3];
 #pragma unroll
-        for (int k = 0; k < RW; ++k) {
+        for (int k = 0; k < kBwdRS; ++k) {
             const int i = tid + k * kViewThreads;
-            const bool ok = i < sh - sl;
-            p_sa[k] = ok ? G.bslot_arc[sl + i] : 0;
-            p_so[k] = ok ? G.bslot_out[sl + i] : 0;
-            p_at[k] = (i < dh - dl) ? drv_ts[(size_t(dl + i) * NV + v) * 2] : 0.0f;
+            const bool ok = i < s1 - s0;
+            const int is = ok ? s0 + i : 0;
+            const int a = G.bslot_arc[is];
+            const int o = G.bslot_out[is];
+            q_sa[k] = ok ? a : -1;
+            q_so[k] = ok ? o : 0;
         }
-        p_ts = (tid <= t1 - t0) ? G.btile_slot[t0 + tid] - sl : 0;
-        p_td = (tid < t1 - t0) ? G.btile_drv[t0 + tid] - dl : 0;
     };
-    auto stash = [&](int l) {
-        const int t0 = s_lvl[l * 3], t1 = s_lvl[(l + 1) * 3];
-        const int sl = s_lvl[l * 3 + 1], sh = s_lvl[(l + 1) * 3 + 1];
-        const int dl = s_lvl[l * 3 + 2], dh = s_lvl[(l + 1) * 3 + 2];
+    auto stash_ids = [&](int c) {
+        const int s0 = CH[c * 8 + 2], s1 = CH[c * 8 + 3];
 #pragma unroll
-        for (int k = 0; k < RW; ++k) {
+        for (int k = 0; k < kBwdRS; ++k) {
             const int i = tid + k * kViewThreads;
-            if (i < sh - sl) { s_sa[i] = p_sa[k]; s_so[i] = p_so[k]; }
-            if (i < dh - dl) s_at[i] = p_at[k];
+            if (i < s1 - s0) { s_sa_n[i] = q_sa[k]; s_so_n[i] = q_so[k]; }
+        }
+    };
+    // chunk c's gathers (slot ids in s_sa_n/s_so_n); required times of the drivers in
+    // [fr_lo, fr_hi) are not final yet and are taken from LDS later
+    auto fetch_data = [&](int c, int fr_lo, int fr_hi) {
+        const int t0 = CH[c * 8], t1 = CH[c * 8 + 1];
+        const int s0 = CH[c * 8 + 2], s1 = CH[c * 8 + 3];
+        const int d0 = CH[c * 8 + 4], d1 = CH[c * 8 + 5];
+#pragma unroll
+        for (int k = 0; k < kBwdRS; ++k) {
+            const int i = tid + k * kViewThreads;
+            const bool ok = i < s1 - s0;
+            const int sa = ok ? s_sa_n[i] : -1;
+            const int raw = ok ? s_so_n[i] : 0;
+            const int so = raw & 0x7fffffff;
+            // unconditional loads from clamped indices (no branch forces an early wait)
+            const bool arc = ok && sa >= 0;
+            const bool fresh = arc && so >= fr_lo && so < fr_hi;
+            const bool endp = ok && sa < 0;
+            const int sa_c = arc ? sa : 0;
+            const int so_r = (arc && !fresh) ? so : 0;
+            const int so_e = endp ? so : 0;
+            const float d = arc_delay[size_t(sa_c) * NV + v];
+            const float ati = arc_ts[(size_t(sa_c) * NV + v) * 2];
+            const float ndv = nd[sa_c];
+            const float r_old = drv_rat[size_t(so_r) * NV + v];
+            const float r_ep = (E > 0) ? ep_rat[size_t(so_e) * NV + v] : 0.0f;
+            uint8_t fl = (uint32_t(raw) & kHeadBit) ? kFlagHead : 0;
+            if (fresh) fl |= kFlagFresh;
+            if (endp) fl |= kFlagEndpoint;
+            const float rat = endp ? r_ep : (fresh ? __int_as_float(so - fr_lo) : r_old);
+            p_sa[k] = sa;
+            p_d[k] = d;
+            p_ati[k] = ati;
+            p_nd[k] = ndv;
+            p_rat[k] = rat;
+            p_fl[k] = fl;
+        }
+#pragma unroll
+        for (int k = 0; k < kBwdRD; ++k) {
+            const int i = tid + k * kViewThreads;
+            p_at[k] = drv_ts[(size_t((i < d1 - d0) ? d0 + i : 0) * NV + v) * 2];
+        }
+        p_ts = G.btile_slot[(tid <= t1 - t0) ? t0 + tid : 0] - s0;
+        p_td = G.btile_drv[(tid < t1 - t0) ? t0 + tid : 0] - d0;
+    };
+    auto stash_data = [&](int c) {
+        const int t0 = CH[c * 8], t1 = CH[c * 8 + 1];
+        const int s0 = CH[c * 8 + 2], s1 = CH[c * 8 + 3];
+        const int d0 = CH[c * 8 + 4], d1 = CH[c * 8 + 5];
+#pragma unroll
+        for (int k = 0; k < kBwdRS; ++k) {
+            const int i = tid + k * kViewThreads;
+            if (i < s1 - s0) {
+                s_sa[i] = p_sa[k];
+                s_d[i] = p_d[k];
+                s_ati[i] = p_ati[k];
+                s_ndv[i] = p_nd[k];
+                s_rat[i] = p_rat[k];
+                s_flag[i] = p_fl[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kBwdRD; ++k) {
+            const int i = tid + k * kViewThreads;
+            if (i < d1 - d0) s_at[i] = p_at[k];
         }
         if (tid <= t1 - t0) s_tsoff[tid] = p_ts;
         if (tid < t1 - t0) s_tdoff[tid] = p_td;
     };
-    fetch(L);
-    stash(L);
-    __syncthreads();
 
-    for (int l = L; l >= 0; --l) {
-        const int T = s_lvl[(l + 1) * 3] - s_lvl[l * 3];
-        const int dl = s_lvl[l * 3 + 2];
-        // one-slot-per-lane tiles: every gather first
-        float ro[RW], dlv[RW], ati[RW], ndv[RW], epr[RW];
-        int sa_r[RW];
-        bool big[RW], act[RW], head[RW];
-        int s0r[RW], nr[RW], doff[RW];
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
+    if (NC > 0) {
+        fetch_ids(0);
+        stash_ids(0);
+        __syncthreads();
+        fetch_data(0, 0, 0);
+        if (NC > 1) fetch_ids(1);
+        __syncthreads();
+        stash_data(0);
+        if (NC > 1) stash_ids(1);
+        __syncthreads();
+    }
+
+    for (int c = 0; c < NC; ++c) {
+        const int T = CH[c * 8 + 1] - CH[c * 8];
+        const int d0 = CH[c * 8 + 4], d1 = CH[c * 8 + 5];
+        if (c + 1 < NC) fetch_data(c + 1, d0, d1);
+        if (c + 2 < NC) fetch_ids(c + 2);
+        const float* f_in = s_f0 + ((c + 1) & 1) * kBwdCapD;
+        float* f_out = s_f0 + (c & 1) * kBwdCapD;
+        for (int r = 0; r < kBwdRT; ++r) {
             const int tl = wave + r * kViewWaves;
-            const bool valid = tl < T;
-            s0r[r] = valid ? s_tsoff[tl] : 0;
-            nr[r] = valid ? s_tsoff[tl + 1] - s0r[r] : 0;
-            doff[r] = valid ? s_tdoff[tl] : 0;
-            big[r] = nr[r] > 64;
-            act[r] = !big[r] && lane < nr[r];
-            const int si = s0r[r] + lane;
-            const int sa = act[r] ? s_sa[si] : -1;
-            const int so = act[r] ? s_so[si] : 0;
-            head[r] = act[r] && (uint32_t(so) & kHeadBit) != 0u;
-            const int o = so & 0x7fffffff;
-            sa_r[r] = sa;
-            ro[r] = (sa >= 0) ? drv_rat[size_t(o) * NV + v] : 0.0f;
-            dlv[r] = (sa >= 0) ? arc_delay[size_t(sa) * NV + v] : 0.0f;
-            ati[r] = (sa >= 0) ? arc_ts[(size_t(sa) * NV + v) * 2] : 0.0f;
-            ndv[r] = (sa >= 0) ? nd[sa] : 0.0f;
-            epr[r] = (act[r] && sa < 0) ? ep_rat[size_t(o) * NV + v] : 0.0f;
-        }
-        if (l > 0) fetch(l - 1);
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            if (big[r]) {
-                // one driver with more than 64 sinks: lanes take contiguous runs of them
-                const int n = nr[r], c = (n + 63) >> 6, sb = lane * c, se = min(n, sb + c);
-                float best = 0.0f;
-                bool have = false;
-                for (int s = sb; s < se; ++s) {
-                    const int sa = s_sa[s0r[r] + s];
-                    const int o = s_so[s0r[r] + s] & 0x7fffffff;
-                    const float rin = drv_rat[size_t(o) * NV + v] - arc_delay[size_t(sa) * NV + v];
-                    const float at_i = arc_ts[(size_t(sa) * NV + v) * 2];
+            if (tl >= T) break;                   // uniform per wave
+            const int s_off = s_tsoff[tl];
+            const int n = s_tsoff[tl + 1] - s_off;
+            const int d_off = s_tdoff[tl];
+            // n <= 64, or one driver owning every slot: lanes take contiguous runs
+            const int cs = (n + 63) >> 6;
+            const int sb = lane * cs, se = min(n, sb + cs);
+            float best = 0.0f;
+            bool have = false;
+            for (int q = sb; q < se; ++q) {
+                const int i = s_off + q;
+                const uint8_t fl = s_flag[i];
+                float val;
+                if (fl & kFlagEndpoint) {
+                    val = s_rat[i];
+                } else {
+                    const float ro = (fl & kFlagFresh) ? f_in[__float_as_int(s_rat[i])] : s_rat[i];
+                    const float rin = ro - s_d[i];
+                    const float ati = s_ati[i];
+                    const int sa = s_sa[i];
                     arc_rat[size_t(sa) * NV + v] = rin;
-                    arc_slack[size_t(sa) * NV + v] = early ? (at_i - rin) : (rin - at_i);
-                    const float val = rin - nd[sa];
-                    if (!have || (early ? (val > best) : (val < best))) best = val;
-                    have = true;
+                    arc_slack[size_t(sa) * NV + v] = early ? (ati - rin) : (rin - ati);
+                    val = rin - s_ndv[i];
                 }
-                const int nl = (n + c - 1) / c;
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const float b2 = __shfl_down(best, off, 64);
-                    if ((lane + off) < nl && (early ? (b2 > best) : (b2 < best))) best = b2;
-                }
-                if (lane == 0) {
-                    const int u = dl + doff[r];
-                    const float at = s_at[doff[r]];
-                    drv_rat[size_t(u) * NV + v] = best;
-                    drv_slack[size_t(u) * NV + v] = early ? (at - best) : (best - at);
-                }
-                continue;
+                if (!have || (early ? (val > best) : (val < best))) best = val;
+                have = true;
             }
-            float val = 0.0f;
-            if (sa_r[r] >= 0) {
-                const int sa = sa_r[r];
-                const float rin = ro[r] - dlv[r];
-                arc_rat[size_t(sa) * NV + v] = rin;
-                arc_slack[size_t(sa) * NV + v] = early ? (ati[r] - rin) : (rin - ati[r]);
-                val = rin - ndv[r];
-            } else if (act[r]) {
-                val = epr[r];
-            }
-            const uint64_t heads = __ballot(head[r]);
+            const bool head = (cs > 1) ? (lane == 0) : (sb < n && (s_flag[s_off + sb] & kFlagHead) != 0);
+            const uint64_t heads = __ballot(head);
             const uint64_t le = lanes_le(lane);
             const int gi = __popcll(heads & le) - 1;
             const uint64_t after = heads & ~le;
-            const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : nr[r];
-#pragma unroll
+            const int nl = (n + cs - 1) / cs;
+            const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : nl;
             for (int off = 1; off < 64; off <<= 1) {
-                const float b2 = __shfl_down(val, off, 64);
-                if ((lane + off) < seg_end && (early ? (b2 > val) : (b2 < val))) val = b2;
+                const float b2 = __shfl_down(best, off, 64);
+                if ((lane + off) < seg_end && (early ? (b2 > best) : (b2 < best))) best = b2;
             }
-            if (head[r]) {
-                const int dloc = doff[r] + gi;
-                const int u = dl + dloc;
-                const float at = s_at[dloc];
-                drv_rat[size_t(u) * NV + v] = val;
-                drv_slack[size_t(u) * NV + v] = early ? (at - val) : (val - at);
+            if (head) {
+                const int dl = d_off + gi;
+                const int u = d0 + dl;
+                const float at = s_at[dl];
+                drv_rat[size_t(u) * NV + v] = best;
+                drv_slack[size_t(u) * NV + v] = early ? (at - best) : (best - at);
+                f_out[dl] = best;
             }
         }
         __syncthreads();
-        if (l > 0) stash(l - 1);
+        if (c + 1 < NC) stash_data(c + 1);
+        if (c + 2 < NC) stash_ids(c + 2);
         __syncthreads();
     }
     // endpoint summaries of this view
@@ -884,9 +1064,9 @@ __global__ __launch_bounds__(kViewThreads) void k_backward_view(DevGraph G, KVie
     for (int i = 0; i < kLimbs; ++i) lim[i] = 0ull;
     float mn = __builtin_inff();
     for (int e = tid; e < E; e += kViewThreads) {
-        const float s = drv_slack[size_t(G.ep_drv[e]) * NV + v];
-        mn = (s < mn) ? s : mn;
-        add_neg_slack(lim, s);
+        const float sl = drv_slack[size_t(G.ep_drv[e]) * NV + v];
+        mn = (sl < mn) ? sl : mn;
+        add_neg_slack(lim, sl);
     }
 #pragma unroll
     for (int i = 0; i < kLimbs; ++i)
@@ -990,15 +1170,6 @@ static KViews kviews(const sta_views* v) {
     return k;
 }
 
-// Per-wave tile count of the view schedule (1, 2, 4 or 8; 0 = does not fit), from the
-// widest level: 16 waves, <= 64 arcs or slots per tile and per staged lane load.
-static int view_rw(int max_tiles, int max_items) {
-    const int need = std::max((max_tiles + kViewWaves - 1) / kViewWaves, (max_items + kViewThreads - 1) / kViewThreads);
-    for (int rw = 1; rw <= 8; rw *= 2)
-        if (need <= rw) return rw;
-    return 0;
-}
-
 static size_t lds_limit() {
     static size_t lim = 0;
     if (!lim) {
@@ -1015,19 +1186,15 @@ static size_t lds_limit() {
 // The view schedule runs while one compute unit finishes an average level faster than
 // a device-wide step does (a few thousand cell arcs per level) and the level's staged
 // data and the view's tables fit in LDS.
-static bool use_view_forward(const sta_graph* g, int n_tables, int* rw, size_t* lds) {
-    if (g->L == 0 || double(g->A) / double(g->L) > double(g->view_sched_max_arcs)) return false;
-    *rw = view_rw(g->max_ft, std::max(g->max_fa, g->max_fg));
-    if (!*rw) return false;
-    *lds = size_t(fwd_lds(n_tables, int(g->L), g->max_ft, g->max_fa, g->max_fg).total) * 4;
+static bool use_view_forward(const sta_graph* g, int n_tables, size_t* lds) {
+    if (g->L == 0 || g->n_fchunks == 0 || double(g->A) / double(g->L) > double(g->view_sched_max_arcs)) return false;
+    *lds = size_t(fwd_lds(n_tables).total) * 4;
     return *lds <= lds_limit();
 }
 
-static bool use_view_backward(const sta_graph* g, int* rw, size_t* lds) {
-    if (g->L == 0 || double(g->A) / double(g->L) > double(g->view_sched_max_arcs)) return false;
-    *rw = view_rw(g->max_bt, std::max(g->max_bs, g->max_bd));
-    if (!*rw) return false;
-    *lds = size_t(bwd_lds(int(g->L), g->max_bt, g->max_bs, g->max_bd).total) * 4;
+static bool use_view_backward(const sta_graph* g, size_t* lds) {
+    if (g->L == 0 || g->n_bchunks == 0 || double(g->A) / double(g->L) > double(g->view_sched_max_arcs)) return false;
+    *lds = size_t(bwd_lds().total) * 4;
     return *lds <= lds_limit();
 }
 
@@ -1134,27 +1301,14 @@ static sta_status run_forward_levels(const sta_graph* g, const KLib& lib, const 
     });
 }
 
-template <int RW>
-static void launch_forward_view(const sta_graph* g, int NV, const KLib& lib, const KViews& kv, const float* pi_ts,
-                                const sta_net_out* nd, const sta_timing_out* o, size_t lds, hipStream_t s) {
-    const DevGraph dg = dev_graph(g);
-    const int32_t* lv = reinterpret_cast<const int32_t*>(g->dev + g->lay.fwd_lvl);
-    set_lds(k_forward_view<RW>, lds);
-    prof_launch("k_forward_view", s, [&] {
-        hipLaunchKernelGGL((k_forward_view<RW>), dim3(NV), dim3(kViewThreads), lds, s, dg, lib, kv, NV, int(g->L), lv,
-                           g->max_ft, g->max_fa, g->max_fg, pi_ts, nd->load, nd->net_delay, nd->net_imp2, o->drv_ts,
-                           o->arc_ts, o->arc_delay, o->argmax);
-    });
-}
-
-static void run_forward_views(const sta_graph* g, int rw, size_t lds, int NV, const KLib& lib, const KViews& kv,
+static void run_forward_views(const sta_graph* g, size_t lds, int NV, const KLib& lib, const KViews& kv,
                               const float* pi_ts, const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
-    switch (rw) {
-        case 1: launch_forward_view<1>(g, NV, lib, kv, pi_ts, nd, o, lds, s); break;
-        case 2: launch_forward_view<2>(g, NV, lib, kv, pi_ts, nd, o, lds, s); break;
-        case 4: launch_forward_view<4>(g, NV, lib, kv, pi_ts, nd, o, lds, s); break;
-        default: launch_forward_view<8>(g, NV, lib, kv, pi_ts, nd, o, lds, s); break;
-    }
+    const DevGraph dg = dev_graph(g);
+    set_lds(k_forward_view, lds);
+    prof_launch("k_forward_view", s, [&] {
+        hipLaunchKernelGGL(k_forward_view, dim3(NV), dim3(kViewThreads), lds, s, dg, lib, kv, NV, g->n_fchunks, pi_ts,
+                           nd->load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts, o->arc_delay, o->argmax);
+    });
 }
 
 template <int NV>
@@ -1198,28 +1352,15 @@ static sta_status run_backward_levels(const sta_graph* g, const KViews& kv, cons
     });
 }
 
-template <int RW>
-static void launch_backward_view(const sta_graph* g, int NV, const KViews& kv, const sta_net_out* nd,
-                                 const sta_timing_out* t, const float* ep_rat, const sta_slack_out* o, size_t lds,
-                                 hipStream_t s) {
-    const DevGraph dg = dev_graph(g);
-    const int32_t* lv = reinterpret_cast<const int32_t*>(g->dev + g->lay.bwd_lvl);
-    set_lds(k_backward_view<RW>, lds);
-    prof_launch("k_backward_view", s, [&] {
-        hipLaunchKernelGGL((k_backward_view<RW>), dim3(NV), dim3(kViewThreads), lds, s, dg, kv, NV, int(g->L),
-                           int(g->E), lv, g->max_bt, g->max_bs, g->max_bd, nd->net_delay, t->drv_ts, t->arc_ts,
-                           t->arc_delay, ep_rat, o->drv_rat, o->arc_rat, o->drv_slack, o->arc_slack, o->tns, o->wns);
-    });
-}
-
-static void run_backward_views(const sta_graph* g, int rw, size_t lds, int NV, const KViews& kv, const sta_net_out* nd,
+static void run_backward_views(const sta_graph* g, size_t lds, int NV, const KViews& kv, const sta_net_out* nd,
                                const sta_timing_out* t, const float* ep_rat, const sta_slack_out* o, hipStream_t s) {
-    switch (rw) {
-        case 1: launch_backward_view<1>(g, NV, kv, nd, t, ep_rat, o, lds, s); break;
-        case 2: launch_backward_view<2>(g, NV, kv, nd, t, ep_rat, o, lds, s); break;
-        case 4: launch_backward_view<4>(g, NV, kv, nd, t, ep_rat, o, lds, s); break;
-        default: launch_backward_view<8>(g, NV, kv, nd, t, ep_rat, o, lds, s); break;
-    }
+    const DevGraph dg = dev_graph(g);
+    set_lds(k_backward_view, lds);
+    prof_launch("k_backward_view", s, [&] {
+        hipLaunchKernelGGL(k_backward_view, dim3(NV), dim3(kViewThreads), lds, s, dg, kv, NV, g->n_bchunks, int(g->E),
+                           nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat, o->arc_rat,
+                           o->drv_slack, o->arc_slack, o->tns, o->wns);
+    });
 }
 
 }  // namespace sta
@@ -1267,10 +1408,9 @@ sta_status sta_propagate(const sta_graph* g, const sta_library* lib, const sta_v
     kl.n_tables = lib->n_tables;
     const KViews kv = kviews(views);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int rw = 0;
     size_t lds = 0;
-    if (use_view_forward(g, lib->n_tables, &rw, &lds)) {
-        run_forward_views(g, rw, lds, views->n_views, kl, kv, pi_ts, nd, out, s);
+    if (use_view_forward(g, lib->n_tables, &lds)) {
+        run_forward_views(g, lds, views->n_views, kl, kv, pi_ts, nd, out, s);
     } else {
         sta_status st;
         switch (views->n_views) {
@@ -1297,10 +1437,9 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
         return fail(STA_E_ARG, "sta_slack: null buffer");
     const KViews kv = kviews(views);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int rw = 0;
     size_t lds = 0;
-    if (use_view_backward(g, &rw, &lds)) {
-        run_backward_views(g, rw, lds, views->n_views, kv, nd, t, ep_rat, out, s);
+    if (use_view_backward(g, &lds)) {
+        run_backward_views(g, lds, views->n_views, kv, nd, t, ep_rat, out, s);
     } else {
         sta_status st;
         switch (views->n_views) {
