@@ -50,6 +50,11 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the event-bracketed pass (for counter-collection runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="first run one plain device copy of MB megabytes (a known-size reference "
+                         "dispatch for HBM byte counters)")
     ap.add_argument("--schedule", choices=["auto", "level", "level_plain", "view"], default="auto",
                     help="auto: the library's choice by level width; level_plain: no hipGraph replay")
     args = ap.parse_args()
@@ -99,6 +104,15 @@ def main():
     tm = sta.alloc_timing(g, V)
     sl = sta.alloc_slack(g, V)
 
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     def step():
         sta.delay_calc(g, sta.STA_DC_FP64, out=nd)
         sta.propagate(g, L_lib, views, pi_t, nd, out=tm)
@@ -107,48 +121,65 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # timed region: wall clock over K steps, and HIP events on the same stream around
+    # each library call of every step (per-call device time)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for k in range(args.steps):
+        e = ev[k]
+        e[0].record()
+        sta.delay_calc(g, sta.STA_DC_FP64, out=nd)
+        e[1].record()
+        sta.propagate(g, L_lib, views, pi_t, nd, out=tm)
+        e[2].record()
+        sta.slack(g, views, nd, tm, rat_t, out=sl)
+        e[3].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / args.steps
+    call_ms = {name: float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(args.steps)]))
+               for i, name in enumerate(("delay_calc", "propagate", "slack"))}
+    if args.no_profile:
+        print(json.dumps({"ms_per_step": ms_step, "call_ms": call_ms, "note": "counter run"}), flush=True)
+        return
 
-    # propagate-only rate (same buffers)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sta.propagate(g, L_lib, views, pi_t, nd, out=tm)
-    torch.cuda.synchronize()
-    ms_prop = (time.perf_counter() - t0) * 1e3 / args.steps
-
-    # per-kernel durations from HIP events bracketing every launch, same stream and shapes
+    # which kernels each call launches (library instrumentation, one extra untimed step)
     sta.profile_begin()
-    for _ in range(args.steps):
-        step()
-    kstats = sta.profile_end()
+    sta.delay_calc(g, sta.STA_DC_FP64, out=nd)
+    sta.profile_end()
+    launches = {}
+    for call, fn in (("propagate", lambda: sta.propagate(g, L_lib, views, pi_t, nd, out=tm)),
+                     ("slack", lambda: sta.slack(g, views, nd, tm, rat_t, out=sl))):
+        sta.profile_begin()
+        fn()
+        launches[call] = sta.profile_end()
     torch.cuda.synchronize()
 
     updates = (s["n_pins"] - d.n_pi) * V
     value = updates / (ms_step * 1e-3)
-    # algorithmic bytes of one step, split by the kernel family that moves them
+    # algorithmic bytes of one step by call; the dominant kernel of a call is the one
+    # launched per level (or once per view); its average launch duration is the call's
+    # device time over its launch count (the few helper launches are folded in)
     fam_bytes = {"forward": fwd_bytes_per_pass(G, A, V), "backward": bwd_bytes_per_pass(D, A, V),
                  "delay_calc": dc_bytes(D, A, M)}
-    family = {"k_forward": "forward", "k_forward_view": "forward", "k_copy_pi": None,
-              "k_backward": "backward", "k_backward_view": "backward", "k_delay_calc": "delay_calc",
-              "k_endpoint_partial": None, "k_endpoint_final": None}
+    call_of = {"delay_calc": "delay_calc", "forward": "propagate", "backward": "slack"}
+    main_kernel = {"delay_calc": "k_delay_calc"}
+    for call in ("propagate", "slack"):
+        main_kernel["forward" if call == "propagate" else "backward"] = max(
+            launches[call], key=lambda k: launches[call][k][0])
     kernels = {}
-    for k, (n, ms) in kstats.items():
-        per_step = n / args.steps
-        rec = {"launches_per_step": per_step, "avg_us": 1e3 * ms / n, "ms_per_step": ms / args.steps}
-        fam = family.get(k)
-        if fam is not None:
-            rec["bytes_per_launch"] = fam_bytes[fam] / per_step
-            rec["GB_s"] = rec["bytes_per_launch"] / (ms / n * 1e-3) / 1e9
-        kernels[k] = rec
-    dom = max((k for k in kernels if "GB_s" in kernels[k]), key=lambda k: kernels[k]["ms_per_step"])
+    for fam, kname in main_kernel.items():
+        n = 1 if fam == "delay_calc" else launches[call_of[fam]][kname][0]
+        ms = call_ms[call_of[fam]]
+        kernels[kname] = {"launches_per_step": n, "avg_us": 1e3 * ms / n, "ms_per_step": ms,
+                          "bytes_per_launch": fam_bytes[fam] / n,
+                          "GB_s": fam_bytes[fam] / (ms * 1e-3) / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     dk = kernels[dom]
     achieved = dk["GB_s"]
+    traffic = measured_traffic(dom)
+    ms_prop = call_ms["propagate"]
+    kstats = {k: v for d_ in launches.values() for k, v in d_.items()}
 
     out = {
         "metric": METRIC,
@@ -170,10 +201,11 @@ def main():
                    "levels": L, "endpoints": E, "views": ["late", "early"],
                    "step": "delay_calc + propagate(late,early) + slack(late,early)"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": dk["bytes_per_launch"], "avg_launch_us": dk["avg_us"],
                      "launches_per_step": dk["launches_per_step"]},
         "propagate_ms": ms_prop,
+        "call_ms": call_ms,
         "propagate_pin_updates_per_s": updates / (ms_prop * 1e-3),
         "kernels": kernels,
         "algorithmic_bytes_per_step": fam_bytes,
@@ -186,6 +218,21 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, lib, pa, ps, late, early, updates, args.cpu_seconds, g, nd, tm, sl)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs (FETCH_SIZE and
+    WRITE_SIZE scaled by a known-size copy), or None when the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_c2.json")
+    src = os.path.join(ROOT, "paper_2203_08395_amd", "csrc", "sta_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["kernels"][kernel]["bytes_per_dispatch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(d, lib, pa, ps, late, early, updates, budget_s, g, nd, tm, sl):
