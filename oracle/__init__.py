@@ -184,3 +184,211 @@ def run(d, lib, pi_at, pi_slew, ep_rat_late, ep_rat_early=None, modes=(LATE,)):
         p.update(s)
         res["late" if m == LATE else "early"] = p
     return res
+
+
+# ---- RC-tree nets and the learned-surrogate reference --------------------------------
+
+FEATURES = ("R_path", "load", "Cd_sink", "depth", "M", "n_sinks", "R_first", "C_path",
+            "mean_R", "mean_C", "pin_cap", "drv_slew")
+
+
+def tree_moments(T, features=False):
+    """FP64 Elmore m1 and imp2 per sink, load per net, and optionally the 12 features."""
+    lib = _load()
+    f = lib.orc_tree_moments
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 12
+    f.restype = ctypes.c_int
+    N, S = T.n_nets, T.n_sinks
+    m1 = np.zeros(S, np.float64)
+    imp2 = np.zeros(S, np.float64)
+    load = np.zeros(N, np.float64)
+    feat = np.zeros((S, 12), np.float64) if features else None
+    arrs = [_c(T.net_node_ptr, np.int32), _c(T.node_parent, np.int32), _c(T.node_R, np.float32),
+            _c(T.node_C, np.float32), _c(T.sink_ptr, np.int32), _c(T.sink_node, np.int32),
+            _c(T.sink_pincap, np.float32), _c(T.drv_slew, np.float32)]
+    _check(f(N, *[_p(a) for a in arrs], _p(m1), _p(imp2), _p(load), _p(feat)), "tree_moments")
+    out = {"m1": m1, "imp2": imp2, "load": load}
+    if features:
+        out["feat"] = feat
+    return out
+
+
+def tree_targets(T, mom=None):
+    """The surrogate's targets per sink, as the timing path defines them in FP32:
+    delay = fl32(m1), slew = sqrt(S_drv^2 + fl32(imp2)) (FP32 operations)."""
+    mom = mom if mom is not None else tree_moments(T)
+    nd = mom["m1"].astype(np.float32)
+    ni = mom["imp2"].astype(np.float32)
+    net = np.repeat(np.arange(T.n_nets), np.diff(T.sink_ptr))
+    s = T.drv_slew[net].astype(np.float32)
+    slew = np.sqrt(s * s + ni).astype(np.float32)
+    return np.stack([nd, slew], axis=1)
+
+
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even), via FP32, returned as FP64."""
+    u = np.ascontiguousarray(np.asarray(x, np.float64).astype(np.float32)).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+class MLP:
+    """Reference of the 12-64-64-2 ReLU network (inputs padded to 16) in FP64.
+
+    With ``quant`` the values the GPU feeds to its BF16 matrix products are rounded to
+    bfloat16 at the same points: the input, the weights, both hidden activations, and in
+    the backward pass the output error and both masked hidden gradients."""
+
+    def __init__(self, params):
+        self.p = {k: np.asarray(v, np.float64) for k, v in params.items()}
+
+    @staticmethod
+    def init(seed=0):
+        rng = np.random.default_rng(seed)
+        def he(o, i):
+            return rng.standard_normal((o, i)) * np.sqrt(2.0 / i)
+        W1 = np.zeros((64, 16))
+        W1[:, :12] = he(64, 12)
+        return {"W1": W1, "b1": np.zeros(64), "W2": he(64, 64), "b2": np.zeros(64),
+                "W3": he(2, 64) * 0.5, "b3": np.zeros(2)}
+
+    def forward(self, x, quant=True):
+        q = bf16 if quant else (lambda a: np.asarray(a, np.float64))
+        p = self.p
+        xq = q(x)
+        z1 = xq @ q(p["W1"]).T + p["b1"]
+        h1 = q(np.maximum(z1, 0.0))
+        z2 = h1 @ q(p["W2"]).T + p["b2"]
+        h2 = q(np.maximum(z2, 0.0))
+        y = h2 @ q(p["W3"]).T + p["b3"]
+        return y, {"x": xq, "z1": z1, "h1": h1, "z2": z2, "h2": h2, "quant": quant}
+
+    def loss(self, x, t, quant=True):
+        y, _ = self.forward(x, quant)
+        return 0.5 * np.mean(np.sum((y - t) ** 2, axis=1))
+
+    def grads(self, x, t, quant=True):
+        """Gradients of loss = mean over the batch of 0.5*|y - t|^2."""
+        q = bf16 if quant else (lambda a: np.asarray(a, np.float64))
+        p = self.p
+        y, c = self.forward(x, quant)
+        B = x.shape[0]
+        dy = (y - t) / B
+        dyq = q(dy)
+        g = {"W3": dyq.T @ c["h2"], "b3": dy.sum(0)}
+        dz2 = (dyq @ q(p["W3"])) * (c["z2"] > 0)
+        dz2q = q(dz2)
+        g["W2"] = dz2q.T @ c["h1"]
+        g["b2"] = dz2.sum(0)
+        dz1 = (dz2q @ q(p["W2"])) * (c["z1"] > 0)
+        dz1q = q(dz1)
+        g["W1"] = dz1q.T @ c["x"]
+        g["b1"] = dz1.sum(0)
+        return g
+
+
+def surrogate_targets(T, mom=None):
+    """Normalized targets per sink, in FP64, rounded to FP32.
+
+    With L = R_path*Cd(sink)*1e-3 and U = R_path*load*1e-3 (the two Elmore bounds: every
+    edge on the path sees at least the sink's downstream cap and at most the whole net):
+      alpha = (m1 - L) / (U - L)   (0 where U == L),     gamma = sqrt(imp2) / U."""
+    mom = mom if mom is not None else tree_moments(T, features=True)
+    f = mom["feat"]
+    L = (f[:, 0] * f[:, 2]) * 1e-3
+    U = (f[:, 0] * f[:, 1]) * 1e-3
+    span = U - L
+    alpha = np.where(span > 0, (mom["m1"] - L) / np.where(span > 0, span, 1.0), 0.0)
+    gamma = np.sqrt(mom["imp2"]) / U
+    return np.stack([alpha, gamma], axis=1).astype(np.float32)
+
+
+def decode(feat32, y):
+    """Predicted (delay, slew) per sink in FP32 from the features and the network's
+    (alpha, gamma):  delay = L + alpha*(U-L),  slew = sqrt(S^2 + (gamma*U)^2)."""
+    f = np.asarray(feat32, np.float32)
+    y = np.asarray(y, np.float32)
+    k = np.float32(1e-3)
+    L = (f[:, 0] * f[:, 2]) * k
+    U = (f[:, 0] * f[:, 1]) * k
+    d = L + y[:, 0] * (U - L)
+    g = y[:, 1] * U
+    s = np.sqrt(f[:, 11] * f[:, 11] + g * g)
+    return d.astype(np.float32), s.astype(np.float32)
+
+
+def norm_stats(feat):
+    """Per-feature mean and 1/std of log(feature) over the given rows (FP64, population std)."""
+    lf = np.log(np.asarray(feat, np.float64))
+    mu = lf.mean(axis=0)
+    sd = lf.std(axis=0)
+    return mu, np.where(sd > 0, 1.0 / np.where(sd > 0, sd, 1.0), 1.0)
+
+
+def mlp_input(feat, mu, rstd):
+    """Network input: (log f - mu) * rstd for the 12 features, padded with zeros to 16."""
+    x = np.zeros((feat.shape[0], 16))
+    x[:, :12] = (np.log(np.asarray(feat, np.float64)) - mu) * rstd
+    return x
+
+
+def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba) with bias correction; returns new (p, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** step)
+    vh = v / (1.0 - b2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+N_BINS = 64
+N_BUCKETS = 128
+
+
+def error_bin(feat):
+    """Calibration bin of a sink: 8 depth classes (1..7, >=8) x 8 net-size classes (M in
+    steps of 8 nodes, M<=64; larger nets share the last class)."""
+    depth = np.clip(np.asarray(feat)[:, 3].astype(np.int64), 1, 8) - 1
+    msz = np.clip((np.asarray(feat)[:, 4].astype(np.int64) - 1) // 8, 0, 7)
+    return depth * 8 + msz
+
+
+def error_bucket(e):
+    """Histogram bucket of a normalized FP32 error e >= 0, on quarter-octave edges that are
+    exact in binary: with key = (biased exponent)*4 + (top two mantissa bits) of e, bucket
+    k = clamp(508 - key, 0, 127).  Bucket 0 takes every e >= 1; bucket k > 0 holds the
+    e in [edge(508 - k), edge(509 - k)), edge(key) being the FP32 value with bits key << 21."""
+    e = np.ascontiguousarray(np.abs(np.asarray(e, np.float32)))
+    key = (e.view(np.uint32) >> 21).astype(np.int64)
+    return np.clip(508 - key, 0, N_BUCKETS - 1)
+
+
+def bucket_bound(k):
+    """Upper edge (exclusive) of bucket k > 0 as FP32; +inf for bucket 0."""
+    if k <= 0:
+        return np.inf
+    return float(np.array([(509 - k) << 21], np.uint32).view(np.float32)[0])
+
+
+def calibrate(feat, err, quantile=0.999, min_count=256):
+    """Per (bin, output) upper bound of the `quantile` of the normalized error, read from a
+    histogram of error buckets: the upper edge of the bucket where the count of errors in
+    it and the buckets above first exceeds floor((1-quantile)*n).  Bins with fewer than
+    `min_count` samples, or whose quantile falls in bucket 0, get +inf (always fall back)."""
+    b = error_bin(feat)
+    q = np.full((N_BINS, 2), np.inf)
+    for o in range(2):
+        hist = np.zeros((N_BINS, N_BUCKETS), np.int64)
+        np.add.at(hist, (b, error_bucket(err[:, o])), 1)
+        for i in range(N_BINS):
+            n = hist[i].sum()
+            if n < min_count:
+                continue
+            allow = int(np.floor((1.0 - quantile) * n))
+            c = 0
+            for k in range(N_BUCKETS):
+                c += hist[i, k]
+                if c > allow:
+                    q[i, o] = bucket_bound(k)
+                    break
+    return q

@@ -315,3 +315,90 @@ done:
     free(level); free(topo); free(fo_ptr); free(fo_arc); free(ep_rank);
     return rc;
 }
+
+/* ---- RC-tree nets on their own (learned-surrogate workload) ------------------ */
+
+/* Per sink: FP64 Elmore m1 and imp2 = max(0, 2 m2 - m1^2) at the tapped node, with the
+ * same definition as orc_delay_calc (sink pin caps added in sink order); per net: load.
+ * Per sink also the 12 surrogate features (FP64), when feat is not NULL:
+ *   0 R_path  resistance of the root->sink path          6 R of the path's first edge
+ *   1 load    total net capacitance                      7 sum of node caps on the path (incl. pin caps)
+ *   2 Cd      downstream cap of the sink node            8 mean edge R of the net
+ *   3 depth   edges on the path                          9 mean wire cap of the net
+ *   4 M       nodes in the net                          10 sink pin cap
+ *   5 sinks   sinks of the net                          11 driver slew                  */
+int orc_tree_moments(int n_nets, const int32_t* net_node_ptr, const int32_t* node_parent,
+                     const float* node_R, const float* node_C, const int32_t* sink_ptr,
+                     const int32_t* sink_node, const float* sink_pincap, const float* drv_slew,
+                     double* sink_m1, double* sink_imp2, double* net_load, double* feat)
+{
+    int maxm = 1;
+    for (int n = 0; n < n_nets; ++n) {
+        int m = net_node_ptr[n + 1] - net_node_ptr[n];
+        if (m < 1) return ORC_E_ARG;
+        if (m > maxm) maxm = m;
+    }
+    double* C = (double*)malloc(sizeof(double) * (size_t)maxm);
+    double* Cd = (double*)malloc(sizeof(double) * (size_t)maxm);
+    double* m1 = (double*)malloc(sizeof(double) * (size_t)maxm);
+    double* W = (double*)malloc(sizeof(double) * (size_t)maxm);
+    double* m2 = (double*)malloc(sizeof(double) * (size_t)maxm);
+    int rc = ORC_OK;
+    if (!C || !Cd || !m1 || !W || !m2) { rc = ORC_E_ARG; goto done; }
+    for (int n = 0; n < n_nets; ++n) {
+        const int n0 = net_node_ptr[n], nm = net_node_ptr[n + 1] - n0;
+        const int32_t* par = node_parent + n0;
+        for (int k = 1; k < nm; ++k)
+            if (par[k] < 0 || par[k] >= k) { rc = ORC_E_RANGE; goto done; }
+        for (int k = 0; k < nm; ++k) C[k] = (double)node_C[n0 + k];
+        for (int s = sink_ptr[n]; s < sink_ptr[n + 1]; ++s) {
+            if (sink_node[s] < 0 || sink_node[s] >= nm) { rc = ORC_E_RANGE; goto done; }
+            C[sink_node[s]] += (double)sink_pincap[s];
+        }
+        for (int k = 0; k < nm; ++k) Cd[k] = C[k];
+        for (int k = nm - 1; k >= 1; --k) Cd[par[k]] += Cd[k];
+        net_load[n] = Cd[0];
+        m1[0] = 0.0;
+        for (int k = 1; k < nm; ++k) m1[k] = m1[par[k]] + ((double)node_R[n0 + k] * Cd[k]) * 1e-3;
+        for (int k = 0; k < nm; ++k) W[k] = C[k] * m1[k];
+        for (int k = nm - 1; k >= 1; --k) W[par[k]] += W[k];
+        m2[0] = 0.0;
+        for (int k = 1; k < nm; ++k) m2[k] = m2[par[k]] + ((double)node_R[n0 + k] * W[k]) * 1e-3;
+        double sumR = 0.0, sumC = 0.0;
+        for (int k = 1; k < nm; ++k) sumR += (double)node_R[n0 + k];
+        for (int k = 0; k < nm; ++k) sumC += (double)node_C[n0 + k];
+        for (int s = sink_ptr[n]; s < sink_ptr[n + 1]; ++s) {
+            const int k = sink_node[s];
+            double imp2 = 2.0 * m2[k] - m1[k] * m1[k];
+            if (imp2 < 0.0) imp2 = 0.0;
+            sink_m1[s] = m1[k];
+            sink_imp2[s] = imp2;
+            if (feat) {
+                double rpath = 0.0, cpath = 0.0, rfirst = 0.0;
+                int depth = 0;
+                for (int v = k; v != 0; v = par[v]) {
+                    rpath += (double)node_R[n0 + v];
+                    cpath += C[v];
+                    if (par[v] == 0) rfirst = (double)node_R[n0 + v];
+                    ++depth;
+                }
+                double* f = feat + (size_t)s * 12;
+                f[0] = rpath;
+                f[1] = Cd[0];
+                f[2] = Cd[k];
+                f[3] = (double)depth;
+                f[4] = (double)nm;
+                f[5] = (double)(sink_ptr[n + 1] - sink_ptr[n]);
+                f[6] = rfirst;
+                f[7] = cpath;
+                f[8] = nm > 1 ? sumR / (double)(nm - 1) : 0.0;
+                f[9] = sumC / (double)nm;
+                f[10] = (double)sink_pincap[s];
+                f[11] = (double)drv_slew[n];
+            }
+        }
+    }
+done:
+    free(C); free(Cd); free(m1); free(W); free(m2);
+    return rc;
+}

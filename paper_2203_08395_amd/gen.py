@@ -312,3 +312,66 @@ def c3_designs(n_designs: int = 64, seed: int = 3):
         out.append(dict(n_pins=p, n_levels=lv, fanin="geom", seed=seed * 1000 + i,
                         n_fanout64=int(round(16 * p / 1e6))))
     return out
+
+
+@dataclasses.dataclass
+class TreeSet:
+    """RC-tree nets on their own (the learned-surrogate workload): net n has nodes
+    net_node_ptr[n]..net_node_ptr[n+1]-1 (local node 0 = driver), its sinks are
+    sink_ptr[n]..sink_ptr[n+1]-1 tapping local node sink_node[s] with sink_pincap[s];
+    drv_slew[n] is the slew of the net's driver."""
+    net_node_ptr: np.ndarray   # int32[N+1]
+    node_parent: np.ndarray    # int32[M] local
+    node_R: np.ndarray         # float32[M]
+    node_C: np.ndarray         # float32[M]
+    sink_ptr: np.ndarray       # int32[N+1]
+    sink_node: np.ndarray      # int32[S] local node index
+    sink_pincap: np.ndarray    # float32[S]
+    drv_slew: np.ndarray       # float32[N]
+
+    @property
+    def n_nets(self) -> int:
+        return int(self.net_node_ptr.shape[0] - 1)
+
+    @property
+    def n_sinks(self) -> int:
+        return int(self.sink_node.shape[0])
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.node_R.shape[0])
+
+    def subset(self, n0: int, n1: int) -> "TreeSet":
+        a, b = int(self.net_node_ptr[n0]), int(self.net_node_ptr[n1])
+        s0, s1 = int(self.sink_ptr[n0]), int(self.sink_ptr[n1])
+        return TreeSet(
+            net_node_ptr=(self.net_node_ptr[n0:n1 + 1] - a).astype(np.int32),
+            node_parent=self.node_parent[a:b].copy(), node_R=self.node_R[a:b].copy(),
+            node_C=self.node_C[a:b].copy(),
+            sink_ptr=(self.sink_ptr[n0:n1 + 1] - s0).astype(np.int32),
+            sink_node=self.sink_node[s0:s1].copy(), sink_pincap=self.sink_pincap[s0:s1].copy(),
+            drv_slew=self.drv_slew[n0:n1].copy())
+
+
+def make_rc_trees(n_nets: int, m_range=(2, 64), seed: int = 4) -> TreeSet:
+    """Random recursive RC trees (parent of node k uniform on 0..k-1), M ~ U{m_range},
+    R ~ U[10,500] ohm, wire C ~ U[0.1,5] fF; every leaf is a sink with pin cap U[1,4] fF;
+    driver slew ~ U[5,50] ps."""
+    rng = np.random.default_rng(seed)
+    m, ptr, parent, R, C = _rc_nets(rng, n_nets, m_range[0], m_range[1], tree=True)
+    tot = int(ptr[-1])
+    has_child = np.zeros(tot, dtype=bool)
+    net_of = np.repeat(np.arange(n_nets), m)
+    nonroot = parent >= 0
+    has_child[(ptr[:-1][net_of] + parent)[nonroot]] = True
+    local = np.arange(tot) - np.repeat(ptr[:-1], m)
+    leaf = ~has_child & (local > 0)
+    sink_global = np.nonzero(leaf)[0]
+    sink_net = net_of[sink_global]
+    cnt = np.bincount(sink_net, minlength=n_nets)
+    sptr = np.zeros(n_nets + 1, dtype=np.int64)
+    np.cumsum(cnt, out=sptr[1:])
+    return TreeSet(net_node_ptr=ptr.astype(np.int32), node_parent=parent.astype(np.int32), node_R=R, node_C=C,
+                   sink_ptr=sptr.astype(np.int32), sink_node=local[sink_global].astype(np.int32),
+                   sink_pincap=rng.uniform(1.0, 4.0, size=sink_global.shape[0]).astype(np.float32),
+                   drv_slew=rng.uniform(5.0, 50.0, size=n_nets).astype(np.float32))
