@@ -98,9 +98,7 @@ def main():
     pi_t = torch.from_numpy(pi).to(dev)
     rat = np.stack([late, early], axis=1).astype(np.float32)
     rat_t = torch.from_numpy(rat).to(dev)
-    nd = {"load": torch.empty(D, dtype=torch.float32, device=dev),
-          "net_delay": torch.empty(A, dtype=torch.float32, device=dev),
-          "net_imp2": torch.empty(A, dtype=torch.float32, device=dev)}
+    nd = sta.alloc_net(g)
     tm = sta.alloc_timing(g, V)
     sl = sta.alloc_slack(g, V)
 

@@ -127,6 +127,9 @@ typedef struct {
     float* load;          /* [D]  lumped net capacitance seen by the driver, fF        */
     float* net_delay;     /* [A]  Elmore delay driver -> input pin, ps                  */
     float* net_imp2;      /* [A]  step-response spread 2*m2 - m1^2 at the pin, ps^2     */
+    float* arc_load;      /* [A]  load of the gate output each cell arc drives (= load of
+                                  that gate's net; a per-arc copy the forward pass reads
+                                  with the arc's other data)                              */
 } sta_net_out;
 
 /* Forward outputs, device, internal order, views interleaved. */
@@ -178,8 +181,8 @@ void sta_graph_free(sta_graph* g);
  * m1(k) = m1(parent) + R(k) Cd(k) 1e-3, W = downstream sum of C m1,
  * m2(k) = m2(parent) + R(k) W(k) 1e-3, imp2 = max(0, 2 m2 - m1^2); outputs rounded to
  * FP32 once.  STA_DC_FP64 evaluates exactly that operation sequence in FP64 (the CPU
- * definition's results, bit for bit); STA_DC_FP32 does the same in FP32.  One net per
- * lane; asynchronous on stream. */
+ * definition's results, bit for bit); STA_DC_FP32 does the same in FP32.  Also writes
+ * arc_load.  One net per lane; asynchronous on stream. */
 sta_status sta_delay_calc(const sta_graph* g, sta_dc_precision prec, const sta_net_out* out,
                           void* stream);
 

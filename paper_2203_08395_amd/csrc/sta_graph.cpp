@@ -39,6 +39,7 @@ DevGraph dev_graph(const sta_graph* g) {
     d.fo_cap = reinterpret_cast<const float*>(b + L.fo_cap);
     d.arc_src = reinterpret_cast<const int32_t*>(b + L.arc_src);
     d.arc_meta = reinterpret_cast<const uint32_t*>(b + L.arc_meta);
+    d.gate_arc_ptr = reinterpret_cast<const int32_t*>(b + L.gate_arc_ptr);
     d.ftile_arc = reinterpret_cast<const int32_t*>(b + L.ftile_arc);
     d.ftile_gate = reinterpret_cast<const int32_t*>(b + L.ftile_gate);
     d.btile_drv = reinterpret_cast<const int32_t*>(b + L.btile_drv);
@@ -362,6 +363,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     lay.fo_cap = place(A * 4);
     lay.arc_src = place(A * 4);
     lay.arc_meta = place(A * 4);
+    lay.gate_arc_ptr = place((G + 1) * 4);
     lay.ftile_arc = place((NF + 1) * 4);
     lay.ftile_gate = place((NF + 1) * 4);
     lay.btile_drv = place((NB + 1) * 4);
@@ -387,6 +389,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     put(lay.fo_cap, fo_cap.data(), A * 4);
     put(lay.arc_src, arc_src.data(), A * 4);
     put(lay.arc_meta, arc_meta.data(), A * 4);
+    put(lay.gate_arc_ptr, gate_arc_ptr_int.data(), (G + 1) * 4);
     put(lay.ftile_arc, ftile_arc.data(), (NF + 1) * 4);
     put(lay.ftile_gate, ftile_gate.data(), (NF + 1) * 4);
     put(lay.btile_drv, btile_drv.data(), (NB + 1) * 4);

@@ -26,7 +26,7 @@ constexpr size_t kViewTableLdsMax = 65536;            // LDS bytes for tables + 
 struct DevLayout {
     size_t net_node_ptr, node_parent, node_R, node_C;
     size_t fo_ptr, fo_arc, fo_tap, fo_cap;
-    size_t arc_src, arc_meta;
+    size_t arc_src, arc_meta, gate_arc_ptr;
     size_t ftile_arc, ftile_gate;
     size_t btile_drv, btile_slot, bslot_arc, bslot_out;
     size_t ep_drv;
@@ -49,6 +49,7 @@ struct DevGraph {
     const float* fo_cap;           // [A]   its pin capacitance
     const int32_t* arc_src;        // [A]   internal driver of the net feeding the arc
     const uint32_t* arc_meta;      // [A]   table id | (position in gate) << 16
+    const int32_t* gate_arc_ptr;   // [G+1] cell arcs of each internal gate
     const int32_t* ftile_arc;      // [NF+1] forward tile -> first arc
     const int32_t* ftile_gate;     // [NF+1] forward tile -> first gate
     const int32_t* btile_drv;      // [NB+1] backward tile -> first driver
@@ -97,4 +98,37 @@ void set_error(const std::string& msg);
 sta_status fail(sta_status st, const std::string& msg);
 DevGraph dev_graph(const sta_graph* g);
 size_t scratch_bytes();            // device scratch sta_slack needs (fixed size)
+sta_status launch_check(const char* what);   // STA_E_HIP with the text of hipGetLastError
+
+// Optional per-launch HIP-event bracketing of the calling thread (instrumentation only;
+// sta_profile_begin / sta_profile_end switch it on and collect it).
+struct ProfRec {
+    const char* name;
+    hipEvent_t start, stop;
+};
+struct Prof {
+    bool on = false;
+    bool failed = false;
+    std::vector<ProfRec> recs;
+};
+Prof& prof();
+
+template <typename F>
+void prof_launch(const char* name, hipStream_t s, F&& launch) {
+    Prof& p = prof();
+    if (!p.on) {
+        launch();
+        return;
+    }
+    ProfRec r{name, nullptr, nullptr};
+    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) {
+        p.failed = true;
+        launch();
+        return;
+    }
+    (void)hipEventRecord(r.start, s);
+    launch();
+    (void)hipEventRecord(r.stop, s);
+    p.recs.push_back(r);
+}
 }  // namespace sta

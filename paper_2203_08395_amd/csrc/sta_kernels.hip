@@ -40,7 +40,8 @@ namespace sta {
 template <typename T, int MAXN, int NT>
 __global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict__ load,
                                                    float* __restrict__ net_delay,
-                                                   float* __restrict__ net_imp2) {
+                                                   float* __restrict__ net_imp2,
+                                                   float* __restrict__ arc_load) {
     __shared__ T sA[MAXN * NT];   // C, later m2
     __shared__ T sB[MAXN * NT];   // Cd, later W
     __shared__ T sM[MAXN * NT];   // m1
@@ -61,7 +62,12 @@ __global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict
     for (int e = f0; e < f1; ++e) AT_(A, G.fo_tap[e]) += static_cast<T>(G.fo_cap[e]);
     for (int k = 0; k < nm; ++k) AT_(B, k) = AT_(A, k);
     for (int k = nm - 1; k >= 1; --k) AT_(B, par[k]) += AT_(B, k);
-    load[d] = static_cast<float>(AT_(B, 0));
+    const float ld = static_cast<float>(AT_(B, 0));
+    load[d] = ld;
+    if (d >= G.n_pi) {
+        const int q = d - G.n_pi;
+        for (int a = G.gate_arc_ptr[q]; a < G.gate_arc_ptr[q + 1]; ++a) arc_load[a] = ld;
+    }
     const T milli = static_cast<T>(1e-3);
     AT_(Mm, 0) = T(0);
     for (int k = 1; k < nm; ++k) AT_(Mm, k) = AT_(Mm, par[k]) + (static_cast<T>(R[k]) * AT_(B, k)) * milli;
@@ -104,12 +110,15 @@ __device__ __forceinline__ int seg6(const float* ax, float v) {
     return i;
 }
 
-__device__ __forceinline__ float bilerp(const float* T, int i, int j, float tx, float ty) {
-    const float t00 = T[i * 7 + j], t01 = T[i * 7 + j + 1];
-    const float t10 = T[(i + 1) * 7 + j], t11 = T[(i + 1) * 7 + j + 1];
+// bilinear value from the four corners (i,j), (i,j+1), (i+1,j), (i+1,j+1)
+__device__ __forceinline__ float bilerp4(float t00, float t01, float t10, float t11, float tx, float ty) {
     const float p = t00 + tx * (t10 - t00);
     const float q = t01 + tx * (t11 - t01);
     return p + ty * (q - p);
+}
+
+__device__ __forceinline__ float bilerp(const float* T, int i, int j, float tx, float ty) {
+    return bilerp4(T[i * 7 + j], T[i * 7 + j + 1], T[(i + 1) * 7 + j], T[(i + 1) * 7 + j + 1], tx, ty);
 }
 
 __device__ __forceinline__ uint64_t lanes_le(int lane) {
@@ -234,6 +243,21 @@ __device__ __forceinline__ void bwd_tile(const DevGraph& G, const bool* early, i
     bool head;
     if (c > 1) head = (lane == 0);
     else head = (sb < n) && (uint32_t(G.bslot_out[s0 + sb]) & kHeadBit) != 0u;
+    // segment = lanes of one driver: heads from the slot flags (c == 1) or lane 0 (c > 1)
+    const uint64_t heads = __ballot(head);
+    const uint64_t le = lanes_le(lane);
+    const int gi = __popcll(heads & le) - 1;
+    const uint64_t after = heads & ~le;
+    const int nl = (n + c - 1) / c;               // lanes holding slots
+    const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : nl;
+    // the driver's arrival times, loaded with the sinks' data (not after the reduction)
+    float at_h[NW];
+    {
+        const int u = head ? d0 + gi : 0;
+        const float2* ts = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV + v0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) at_h[w] = ts[w].x;
+    }
     float best[NW];
     bool have = false;
 #pragma unroll
@@ -265,13 +289,6 @@ __device__ __forceinline__ void bwd_tile(const DevGraph& G, const bool* early, i
             if (!have || (early[w] ? (val[w] > best[w]) : (val[w] < best[w]))) best[w] = val[w];
         have = true;
     }
-    // segment = lanes of one driver: heads from the slot flags (c == 1) or lane 0 (c > 1)
-    const uint64_t heads = __ballot(head);
-    const uint64_t le = lanes_le(lane);
-    const int gi = __popcll(heads & le) - 1;
-    const uint64_t after = heads & ~le;
-    const int nl = (n + c - 1) / c;               // lanes holding slots
-    const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : nl;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const bool take = (lane + off) < seg_end;
@@ -283,11 +300,10 @@ __device__ __forceinline__ void bwd_tile(const DevGraph& G, const bool* early, i
     }
     if (head) {
         const int u = d0 + gi;
-        const float2* ts = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV + v0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const float r = best[w];
-            const float at = ts[w].x;
+            const float at = at_h[w];
             drv_rat[size_t(u) * NV + v0 + w] = r;
             drv_slack[size_t(u) * NV + v0 + w] = early[w] ? (at - r) : (r - at);
         }
@@ -386,7 +402,7 @@ struct KTiles {
 // same table set), then gathers the drivers' results and computes.
 template <int NV, bool TAB_LDS>
 __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V, int tile0, int tile1, KTiles kt,
-                                                 const float* __restrict__ load, const float* __restrict__ nd,
+                                                 const float* __restrict__ arc_load, const float* __restrict__ nd,
                                                  const float* __restrict__ ni, float* __restrict__ drv_ts,
                                                  float* __restrict__ arc_ts, float* __restrict__ arc_delay,
                                                  uint8_t* __restrict__ argmax) {
@@ -410,11 +426,16 @@ __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V,
     }
     const bool act = lane < n;
     const int a = a0 + lane;
-    const uint32_t meta = act ? G.arc_meta[a] : 0u;
-    const int u = act ? G.arc_src[a] : 0;
+    const int ac = act ? a : 0;                 // clamped: unconditional first-round loads
+    const uint32_t meta_r = G.arc_meta[ac];
+    const int u_r = G.arc_src[ac];
+    const float nd_r = nd[ac], ni_r = ni[ac], lo_r = arc_load[ac];
+    const uint32_t meta = act ? meta_r : 0u;
+    const int u = act ? u_r : 0;
     FwdLane x;
-    x.nd = act ? nd[a] : 0.0f;
-    x.ni = act ? ni[a] : 0.0f;
+    x.nd = act ? nd_r : 0.0f;
+    x.ni = act ? ni_r : 0.0f;
+    x.Lo = act ? lo_r : 0.0f;
     load_axes(s_ax, lib);
     if (TAB_LDS) {
         const float* gt = lib.tables + size_t(V.set[0]) * lib.n_tables * 98;
@@ -433,14 +454,9 @@ __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V,
     fwd_lane_setup(x, act, meta, n, lane);
     x.a = a;
     x.g = g0 + x.gi;
-    x.Lo = act ? load[G.n_pi + x.g] : 0.0f;
     int j = 0;
     float ty = 0.0f;
     gate_jty(s_ax, x.Lo, j, ty);
-    float2 ts[NV];
-    const float2* srcp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) ts[v] = act ? srcp[v] : make_float2(0.0f, 0.0f);
     const float* tab[NV];
     bool early[NV];
 #pragma unroll
@@ -448,6 +464,11 @@ __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V,
         tab[v] = TAB_LDS ? s_dyn : lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
         early[v] = V.mode[v] == STA_EARLY;
     }
+    // second round: the drivers' results
+    float2 ts[NV];
+    const float2* srcp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ts[v] = srcp[v];
     fwd_finish<NV>(x, ts, j, ty, 64, s_ax, tab, early, NV, 0, G.n_pi, drv_ts, arc_ts, arc_delay, argmax);
 }
 
@@ -1091,37 +1112,10 @@ __global__ __launch_bounds__(kViewThreads) void k_backward_view(DevGraph G, KVie
 // host launchers
 // ---------------------------------------------------------------------------------
 
-// Optional per-launch HIP-event bracketing (instrumentation only).
-struct ProfRec {
-    const char* name;
-    hipEvent_t start, stop;
-};
-struct Prof {
-    bool on = false;
-    bool failed = false;
-    std::vector<ProfRec> recs;
-};
 static thread_local Prof g_prof;
+Prof& prof() { return g_prof; }
 
-template <typename F>
-static void prof_launch(const char* name, hipStream_t s, F&& launch) {
-    if (!g_prof.on) {
-        launch();
-        return;
-    }
-    ProfRec r{name, nullptr, nullptr};
-    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) {
-        g_prof.failed = true;
-        launch();
-        return;
-    }
-    hipEventRecord(r.start, s);
-    launch();
-    hipEventRecord(r.stop, s);
-    g_prof.recs.push_back(r);
-}
-
-static sta_status launch_check(const char* what) {
+sta_status launch_check(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(STA_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
     return STA_OK;
@@ -1132,7 +1126,7 @@ static void launch_dc(const sta_graph* g, const sta_net_out* out, hipStream_t s)
     const int blocks = int((g->D + NT - 1) / NT);
     prof_launch("k_delay_calc", s, [&] {
         hipLaunchKernelGGL((k_delay_calc<T, MAXN, NT>), dim3(blocks), dim3(NT), 0, s, dev_graph(g), out->load,
-                           out->net_delay, out->net_imp2);
+                           out->net_delay, out->net_imp2, out->arc_load);
     });
 }
 
@@ -1275,7 +1269,7 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
         const KTiles kt = ktiles(g->ftile_arc_h, g->ftile_gate_h, t0, t1);
         prof_launch("k_forward", s, [&] {
             hipLaunchKernelGGL((k_forward<NV, TAB_LDS>), dim3((t1 - t0 + 3) / 4), dim3(256), lds, s, dg, lib, kv, t0,
-                               t1, kt, nd->load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts, o->arc_delay,
+                               t1, kt, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts, o->arc_delay,
                                o->argmax);
         });
     }
@@ -1290,7 +1284,7 @@ static sta_status run_forward_levels(const sta_graph* g, const KLib& lib, const 
     // reads it replaces (one level is ~10 blocks that each use a few hundred entries).
     const bool tab_lds = false;
     (void)same_set;
-    std::vector<uint64_t> key = {uint64_t(NV), pk(lib.tables), uint64_t(lib.n_tables), pk(pi_ts), pk(nd->load),
+    std::vector<uint64_t> key = {uint64_t(NV), pk(lib.tables), uint64_t(lib.n_tables), pk(pi_ts), pk(nd->arc_load),
                                  pk(nd->net_delay), pk(nd->net_imp2), pk(o->drv_ts), pk(o->arc_ts), pk(o->arc_delay),
                                  pk(o->argmax), uint64_t(tab_lds)};
     for (int i = 0; i < 26; ++i) { uint32_t b; std::memcpy(&b, &lib.ax[i], 4); key.push_back(b); }
@@ -1374,7 +1368,7 @@ sta_status sta_delay_calc(const sta_graph* g, sta_dc_precision prec, const sta_n
     if (!g->dev) return fail(STA_E_ARG, "sta_delay_calc: graph not uploaded");
     if (prec != STA_DC_FP64 && prec != STA_DC_FP32) return fail(STA_E_ARG, "sta_delay_calc: unknown precision");
     if (g->D == 0) return STA_OK;
-    if (!out->load || (g->A > 0 && (!out->net_delay || !out->net_imp2)))
+    if (!out->load || (g->A > 0 && (!out->net_delay || !out->net_imp2 || !out->arc_load)))
         return fail(STA_E_ARG, "sta_delay_calc: null output buffer");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (prec == STA_DC_FP64) dispatch_dc<double>(g, out, s);
@@ -1398,7 +1392,8 @@ sta_status sta_propagate(const sta_graph* g, const sta_library* lib, const sta_v
             return fail(STA_E_ARG, "sta_propagate: library axes must strictly increase");
     if (g->D == 0) return STA_OK;
     if ((g->n_pi > 0 && !pi_ts) || !out->drv_ts ||
-        (g->A > 0 && (!out->arc_ts || !out->arc_delay || !out->argmax || !nd->net_delay || !nd->net_imp2)) ||
+        (g->A > 0 && (!out->arc_ts || !out->arc_delay || !out->argmax || !nd->net_delay || !nd->net_imp2 ||
+                      !nd->arc_load)) ||
         !nd->load)
         return fail(STA_E_ARG, "sta_propagate: null buffer");
     KLib kl{};

@@ -55,7 +55,7 @@ class ViewsC(ctypes.Structure):
 
 
 class NetOut(ctypes.Structure):
-    _fields_ = [("load", _P), ("net_delay", _P), ("net_imp2", _P)]
+    _fields_ = [("load", _P), ("net_delay", _P), ("net_imp2", _P), ("arc_load", _P)]
 
 
 class TimingOut(ctypes.Structure):
@@ -234,17 +234,24 @@ def delay_calc(g: Graph, precision=STA_DC_FP64, out=None):
     import torch
     D, A = g.sizes["n_drivers"], g.sizes["n_arcs"]
     if out is None:
-        out = {"load": torch.empty(max(D, 1), dtype=torch.float32, device=g.device),
-               "net_delay": torch.empty(max(A, 1), dtype=torch.float32, device=g.device),
-               "net_imp2": torch.empty(max(A, 1), dtype=torch.float32, device=g.device)}
-    no = NetOut(_ptr(out["load"]), _ptr(out["net_delay"]), _ptr(out["net_imp2"]))
+        out = alloc_net(g)
+    no = _netout(out)
     _check(load_library().sta_delay_calc(g.handle, int(precision), ctypes.byref(no), _stream(torch, g.device)),
            "sta_delay_calc")
     return out
 
 
 def _netout(nd):
-    return NetOut(_ptr(nd["load"]), _ptr(nd["net_delay"]), _ptr(nd["net_imp2"]))
+    return NetOut(_ptr(nd["load"]), _ptr(nd["net_delay"]), _ptr(nd["net_imp2"]), _ptr(nd["arc_load"]))
+
+
+def alloc_net(g: Graph):
+    import torch
+    D, A = g.sizes["n_drivers"], g.sizes["n_arcs"]
+    return {"load": torch.empty(max(D, 1), dtype=torch.float32, device=g.device),
+            "net_delay": torch.empty(max(A, 1), dtype=torch.float32, device=g.device),
+            "net_imp2": torch.empty(max(A, 1), dtype=torch.float32, device=g.device),
+            "arc_load": torch.empty(max(A, 1), dtype=torch.float32, device=g.device)}
 
 
 def alloc_timing(g: Graph, n_views):

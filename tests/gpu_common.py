@@ -84,6 +84,8 @@ def compare_all(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, label="
     assert_bitwise("load", g.drv_to_input(h["load"][:D]), load)
     assert_bitwise("net_delay", g.arc_to_input(h["net_delay"][:A]), nd)
     assert_bitwise("net_imp2", g.arc_to_input(h["net_imp2"][:A]), ni)
+    gate_of = np.repeat(np.arange(G), np.diff(d.gate_arc_ptr))
+    assert_bitwise("arc_load", g.arc_to_input(h["arc_load"][:A]), load[d.n_pi + gate_of])
     ep = oracle.endpoints(d)
     for v, m in enumerate(modes):
         tab = lib.tab if lib.tab.ndim == 4 else lib.tab[table_sets[v] if table_sets else 0]
