@@ -292,14 +292,14 @@ def surrogate_targets(T, mom=None):
 
     With L = R_path*Cd(sink)*1e-3 and U = R_path*load*1e-3 (the two Elmore bounds: every
     edge on the path sees at least the sink's downstream cap and at most the whole net):
-      alpha = (m1 - L) / (U - L)   (0 where U == L),     gamma = sqrt(imp2) / U."""
+      alpha = (m1 - L) / (U - L)   (0 where U == L),     gamma = sqrt(imp2) / U  (0 where U == 0)."""
     mom = mom if mom is not None else tree_moments(T, features=True)
     f = mom["feat"]
     L = (f[:, 0] * f[:, 2]) * 1e-3
     U = (f[:, 0] * f[:, 1]) * 1e-3
     span = U - L
     alpha = np.where(span > 0, (mom["m1"] - L) / np.where(span > 0, span, 1.0), 0.0)
-    gamma = np.sqrt(mom["imp2"]) / U
+    gamma = np.where(U > 0, np.sqrt(mom["imp2"]) / np.where(U > 0, U, 1.0), 0.0)
     return np.stack([alpha, gamma], axis=1).astype(np.float32)
 
 
@@ -318,17 +318,18 @@ def decode(feat32, y):
 
 
 def norm_stats(feat):
-    """Per-feature mean and 1/std of log(feature) over the given rows (FP64, population std)."""
-    lf = np.log(np.asarray(feat, np.float64))
+    """Per-feature mean and 1/std of log(1 + feature) over the given rows (FP64, population
+    std; 1/std = 1 where the std is 0)."""
+    lf = np.log(np.asarray(feat, np.float64) + 1.0)
     mu = lf.mean(axis=0)
     sd = lf.std(axis=0)
     return mu, np.where(sd > 0, 1.0 / np.where(sd > 0, sd, 1.0), 1.0)
 
 
 def mlp_input(feat, mu, rstd):
-    """Network input: (log f - mu) * rstd for the 12 features, padded with zeros to 16."""
+    """Network input: (log(1 + f) - mu) * rstd for the 12 features, padded with zeros to 16."""
     x = np.zeros((feat.shape[0], 16))
-    x[:, :12] = (np.log(np.asarray(feat, np.float64)) - mu) * rstd
+    x[:, :12] = (np.log(np.asarray(feat, np.float64) + 1.0) - mu) * rstd
     return x
 
 

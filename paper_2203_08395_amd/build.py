@@ -5,7 +5,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "sta_graph.cpp"), os.path.join(HERE, "csrc", "sta_kernels.hip")]
+SRC = [os.path.join(HERE, "csrc", "sta_graph.cpp"), os.path.join(HERE, "csrc", "sta_kernels.hip"),
+       os.path.join(HERE, "csrc", "sur_kernels.hip")]
 LIB = os.path.join(HERE, "libsta.so")
 
 # -ffp-contract=off: no a*b+c contraction; IEEE-rounded FP32 divide/sqrt; FP32 denormals kept.

@@ -14,8 +14,8 @@ from tests import tiny
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    txt = open(os.path.join(ROOT, "include", "sta.h")).read()
+def _declared(header="sta.h"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(sta_\w+)\s*\(", txt, re.M)))
 
 
@@ -26,6 +26,35 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(sta.EXPORTS)
+
+
+def test_library_exports_every_surrogate_symbol():
+    from paper_2203_08395_amd import surrogate
+    lib = surrogate._lib()
+    names = _declared("sta_surrogate.h")
+    assert len(names) == 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(surrogate.EXPORTS)
+
+
+def test_surrogate_host_validation_without_gpu():
+    """Argument errors are caught before any launch (no device pointer is touched)."""
+    from paper_2203_08395_amd import surrogate
+    lib = surrogate._lib()
+    assert lib.sta_tree_dataset(None, None, None, None, None, None, None) == -1
+    t = surrogate.TreesC(-1, 0)
+    assert lib.sta_tree_exact(ctypes.byref(t), None, None, None, None, None, None) == -1
+    assert lib.sta_mlp_train_step(None, None, None, None, None, None, None, None, 0, None, None, 0, None) == -1
+    assert lib.sta_mlp_grad_scratch_bytes(0) == 0
+    assert lib.sta_mlp_grad_scratch_bytes(33) == 2 * 5380 * 4
+    assert lib.sta_mlp_grad_scratch_bytes(10 ** 6) == 1024 * 5380 * 4
+    assert lib.sta_surrogate_calibrate(None, None, None, 10, 1.5, 0, None, None, 0, None) == -1
+    assert lib.sta_mlp_norm_scratch_bytes() == 256 * 24 * 8
+    assert lib.sta_surrogate_cal_scratch_bytes() == 64 * 2 * 128 * 4
+    # empty tree set: nothing to launch
+    t0 = surrogate.TreesC(0, 0)
+    assert lib.sta_tree_exact(ctypes.byref(t0), None, None, None, None, None, None) == 0
 
 
 @pytest.mark.parametrize("cfg", ["c1", "small_geom"])
