@@ -57,6 +57,9 @@ def main():
                          "dispatch for HBM byte counters)")
     ap.add_argument("--schedule", choices=["auto", "level", "level_plain", "view"], default="auto",
                     help="auto: the library's choice by level width; level_plain: no hipGraph replay")
+    ap.add_argument("--surrogate-nets", type=int, default=1_000_000,
+                    help="RC-tree nets of the learned-surrogate comparison (0: skip it)")
+    ap.add_argument("--surrogate-train-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one design on one GPU); "
@@ -213,9 +216,98 @@ def main():
                  "graph_bytes": s["graph_bytes"]},
     }
 
+    if args.surrogate_nets > 0:
+        out["surrogate"] = surrogate_bench(dev, args.surrogate_nets, args.surrogate_train_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, lib, pa, ps, late, early, updates, args.cpu_seconds, g, nd, tm, sl)
     print(json.dumps(out), flush=True)
+
+
+def _time_ms(fn, reps=5, warm=2):
+    import torch
+    for _ in range(warm):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def surrogate_bench(dev, n_nets, train_steps, tol_ps=1.0):
+    """Exact RC-tree moments vs the learned surrogate on n_nets random RC trees (2-64 nodes):
+    the network is trained on the GPU on the sinks of the first 80% of the nets, calibrated
+    on the next 10% and judged on the last 10%; speeds are for all nets."""
+    import torch
+    from paper_2203_08395_amd import gen, surrogate as sur
+    t0 = time.perf_counter()
+    T = gen.make_rc_trees(n_nets, seed=4)
+    tr = sur.Trees(T, dev)
+    t_gen = time.perf_counter() - t0
+    N, S, M = T.n_nets, T.n_sinks, T.n_nodes
+    data = sur.dataset(tr)
+    torch.cuda.synchronize()
+    tr.check_status()
+    n_tr, n_cal = int(0.8 * N), int(0.9 * N)
+    s_tr, s_cal = int(T.sink_ptr[n_tr]), int(T.sink_ptr[n_cal])
+    feat, target = data["feat"], data["target"]
+    norm = sur.norm_stats(feat[:s_tr])
+    model = sur.Model(sur.init_params(0), norm, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = sur.train(model, feat, target, np.arange(s_tr), steps=train_steps, batch=8192, lr=3e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    y = sur.predict(model, feat)
+    sur.calibrate(model, feat[s_tr:s_cal], target[s_tr:s_cal], y[s_tr:s_cal], quantile=0.999, min_count=256)
+    buf = sur.EvalBuffers(tr)
+    d_ex = torch.empty(S, dtype=torch.float32, device=dev)
+    s_ex = torch.empty(S, dtype=torch.float32, device=dev)
+    ms_exact = _time_ms(lambda: sur.exact(tr, d_ex, s_ex))
+    ms_sur = _time_ms(lambda: sur.evaluate(tr, model, feat, tol_ps, buf))
+    ms_net = _time_ms(lambda: sur.predict(model, feat, y))
+    torch.cuda.synchronize()
+    tr.check_status()
+    served = 1.0 - int(buf.count.item()) / N
+    # errors on the held-out test nets
+    f = feat[s_cal:].cpu().numpy()
+    yt = y[s_cal:].cpu().numpy()
+    exd, exs = data["delay"][s_cal:].cpu().numpy(), data["slew"][s_cal:].cpu().numpy()
+    L, U = f[:, 0] * f[:, 2] * 1e-3, f[:, 0] * f[:, 1] * 1e-3
+    e_net = np.abs(L + np.clip(yt[:, 0], 0, 1) * (U - L) - exd)
+    e_mid = np.abs(0.5 * (L + U) - exd)
+    flag = buf.flag.cpu().numpy()
+    sink_net = np.repeat(np.arange(N), np.diff(T.sink_ptr))
+    trusted = ~flag[sink_net[s_cal:]].astype(bool)
+    ed = np.abs(buf.delay[s_cal:].cpu().numpy() - exd)[trusted]
+    es = np.abs(buf.slew[s_cal:].cpu().numpy() - exs)[trusted]
+    exact_bytes = 12 * M + 16 * S + 12 * N
+    net_bytes = 56 * S
+    net_flops = 9984 * S
+    return {
+        "workload": f"{N} random recursive RC trees, 2-64 nodes (R 10-500 ohm, C 0.1-5 fF), {S} sinks "
+                    f"(leaves), 12 features per sink -> MLP 12-64-64-2, BF16 operands / FP32 accumulate",
+        "nets": N, "sinks": S, "rc_nodes": M, "tol_ps": tol_ps,
+        "exact_ms": ms_exact, "surrogate_ms": ms_sur, "speedup_vs_exact": ms_exact / ms_sur,
+        "nets_served_by_network": served,
+        "network_only_ms": ms_net, "network_only_speedup_vs_exact": ms_exact / ms_net,
+        "exact_GB_s": exact_bytes / (ms_exact * 1e-3) / 1e9,
+        "network_GB_s": net_bytes / (ms_net * 1e-3) / 1e9,
+        "network_TFLOP_s": net_flops / (ms_net * 1e-3) / 1e12,
+        "test_delay_rms_ps": {"network": float(np.sqrt(np.mean(e_net ** 2))),
+                              "elmore_bound_midpoint": float(np.sqrt(np.mean(e_mid ** 2)))},
+        "test_sinks_within_tol": {"network": float(np.mean(e_net <= tol_ps)),
+                                  "elmore_bound_midpoint": float(np.mean(e_mid <= tol_ps))},
+        "test_trusted_sinks": int(trusted.sum()),
+        "test_trusted_max_err_ps": {"delay": float(ed.max()) if ed.size else 0.0,
+                                    "slew": float(es.max()) if es.size else 0.0},
+        "train": {"steps": train_steps, "batch": 8192, "seconds": t_train, "loss_first": float(losses[0]),
+                  "loss_last": float(np.mean(losses[-50:]))},
+        "generate_s": t_gen,
+    }
 
 
 def measured_traffic(kernel):
