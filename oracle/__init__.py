@@ -393,3 +393,155 @@ def calibrate(feat, err, quantile=0.999, min_count=256):
                     q[i, o] = bucket_bound(k)
                     break
     return q
+
+
+# ---- adjoint of TNS and critical paths -----------------------------------------------
+
+def tns_adjoint(d, res_mode, mode=LATE):
+    """dTNS/dAT per driver and dTNS/d(arc delay) per cell arc (FP64 counts) by the chain
+    rule through the saved argmax arcs, from a forward/slack result of this oracle."""
+    lib = _load()
+    f = lib.orc_tns_adjoint
+    f.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 6
+    f.restype = ctypes.c_int
+    D, A = d.n_pi + d.n_gates, d.arc_drv.shape[0]
+    g_at = np.zeros(D, np.float64)
+    g_arc = np.zeros(A, np.float64)
+    arrs = [_c(d.gate_arc_ptr, np.int32), _c(d.arc_drv, np.int32), _c(res_mode["argmax"], np.int32),
+            _c(res_mode["slack_drv"], np.float32)]
+    _check(f(int(mode), d.n_pi, d.n_gates, *[_p(a) for a in arrs], _p(g_at), _p(g_arc)), "tns_adjoint")
+    return g_at, g_arc
+
+
+def _seg(axis, v):
+    """Largest i in 0..5 with axis[i] <= v (FP32 comparisons), per element."""
+    ax = np.asarray(axis, np.float32)
+    v = np.asarray(v, np.float32)
+    return np.sum(ax[None, 1:6] <= v[:, None], axis=1)
+
+
+def bilerp64(x, y, T, s, l):
+    """The bilinear lookup of one table per element in FP64 arithmetic (same segments as
+    the FP32 lookup, no clamping).  T: [n][49]."""
+    x64, y64 = np.asarray(x, np.float64), np.asarray(y, np.float64)
+    i, j = _seg(x, s), _seg(y, l)
+    tx = (np.asarray(s, np.float64) - x64[i]) / (x64[i + 1] - x64[i])
+    ty = (np.asarray(l, np.float64) - y64[j]) / (y64[j + 1] - y64[j])
+    T = np.asarray(T, np.float64)
+    r = np.arange(T.shape[0])
+    p = T[r, i * 7 + j] + tx * (T[r, (i + 1) * 7 + j] - T[r, i * 7 + j])
+    q = T[r, i * 7 + j + 1] + tx * (T[r, (i + 1) * 7 + j + 1] - T[r, i * 7 + j + 1])
+    return p + ty * (q - p), (q - p) / (y64[j + 1] - y64[j])
+
+
+def load_slope(d, libr, res_mode, load, table_set=0):
+    """d(delay of the argmax arc)/d(load) of every gate (FP64 arithmetic), slew held."""
+    G = d.n_gates
+    a = np.asarray(d.gate_arc_ptr[:-1]) + np.asarray(res_mode["argmax"][:G])
+    tb = np.asarray(d.arc_tbl)[a]
+    T = _tables(libr, table_set)
+    _, slope = bilerp64(libr.x, libr.y, T[tb, 0], res_mode["slew_in"][a], np.asarray(load)[d.n_pi + np.arange(G)])
+    return slope
+
+
+def _tables(libr, table_set=0):
+    """[n_tables][2][49] FP32 tables of one set ([sets][K][2][7][7] or [K][2][7][7])."""
+    t = np.asarray(libr.tab, np.float32)
+    if t.ndim == 5:
+        t = t[table_set]
+    return t.reshape(-1, 2, 49)
+
+
+def tns_delta(d, arc_delay, net_delay, pi_at, ep_rat_drv, mode, pert_gate, pert_off, pert_delay):
+    """FP64 TNS of the design and its change under each delay perturbation of one gate."""
+    lib = _load()
+    f = lib.orc_tns_delta
+    f.argtypes = [ctypes.c_int] * 3 + [ctypes.c_void_p] * 6 + [ctypes.c_int] + [ctypes.c_void_p] * 5
+    f.restype = ctypes.c_int
+    n = len(pert_gate)
+    base = np.zeros(1, np.float64)
+    delta = np.zeros(max(n, 1), np.float64)
+    arrs = [_c(d.gate_arc_ptr, np.int32), _c(d.arc_drv, np.int32), _c(arc_delay, np.float64),
+            _c(net_delay, np.float64), _c(pi_at, np.float64), _c(ep_rat_drv, np.float64)]
+    pg, po, pd = _c(pert_gate, np.int32), _c(pert_off, np.int32), _c(pert_delay, np.float64)
+    _check(f(int(mode), d.n_pi, d.n_gates, *[_p(a) for a in arrs], n, _p(pg), _p(po), _p(pd), _p(base),
+             _p(delta)), "tns_delta")
+    return float(base[0]), delta[:n]
+
+
+def _gate_of_arc(d):
+    return np.repeat(np.arange(d.n_gates), np.diff(d.gate_arc_ptr))
+
+
+def fd_arc_delay(d, arc_delay, net_delay, pi_at, ep_rat_drv, mode, arcs, h=1e-3):
+    """Central differences of TNS (FP64) in the delays of the given cell arcs.  Returns
+    (fd, clean): clean marks samples where the two one-sided differences agree (no tie of
+    a maximum and no endpoint slack crossing zero within +-h)."""
+    gate = _gate_of_arc(d)
+    ptr = np.asarray(d.gate_arc_ptr)
+    pg, po, pd = [], [0], []
+    for a in arcs:
+        g = gate[a]
+        base = np.asarray(arc_delay[ptr[g]:ptr[g + 1]], np.float64)
+        for sgn in (1.0, -1.0):
+            x = base.copy()
+            x[a - ptr[g]] += sgn * h
+            pg.append(g)
+            pd.extend(x.tolist())
+            po.append(len(pd))
+    _, dl = tns_delta(d, arc_delay, net_delay, pi_at, ep_rat_drv, mode, pg, po, pd)
+    dp, dm = dl[0::2], dl[1::2]
+    fd = (dp - dm) / (2 * h)
+    clean = np.abs(dp + dm) <= 1e-9 * (1.0 + np.abs(dp) + np.abs(dm))
+    return fd, clean
+
+
+def fd_load(d, libr, res_mode, load, net_delay, pi_at, ep_rat_drv, mode, gates, h=1e-3, table_set=0):
+    """Central differences of TNS (FP64) in the load of the given gates' output nets: the
+    delays of all the gate's arcs are re-evaluated by the FP64 bilinear lookup at load +-h
+    (and at the load itself, the reference point), input slews held."""
+    T = _tables(libr, table_set)
+    ptr = np.asarray(d.gate_arc_ptr)
+    arc_delay = np.asarray(res_mode["arc_delay"], np.float64).copy()
+    pg, po, pd = [], [0], []
+    for g in gates:
+        a = np.arange(ptr[g], ptr[g + 1])
+        L0 = float(load[d.n_pi + g])
+        for dl in (h, -h, 0.0):
+            val, _ = bilerp64(libr.x, libr.y, T[np.asarray(d.arc_tbl)[a], 0], res_mode["slew_in"][a],
+                              np.full(a.size, L0 + dl))
+            pg.append(g)
+            pd.extend(val.tolist())
+            po.append(len(pd))
+    _, dl_ = tns_delta(d, arc_delay, net_delay, pi_at, ep_rat_drv, mode, pg, po, pd)
+    dp, dm, d0 = dl_[0::3], dl_[1::3], dl_[2::3]
+    fd = (dp - dm) / (2 * h)
+    clean = np.abs(dp + dm - 2 * d0) <= 1e-9 * (1.0 + np.abs(dp) + np.abs(dm))
+    return fd, clean
+
+
+def ep_rat_by_driver(d, ep_rat):
+    """Endpoint required times (by endpoint rank) spread into a per-driver FP64 array."""
+    r = np.zeros(d.n_pi + d.n_gates, np.float64)
+    r[endpoints(d)] = np.asarray(ep_rat, np.float64)
+    return r
+
+
+def critical_paths(d, res_mode, k):
+    """The k worst endpoints (slack, then rank) and their argmax paths back to a primary
+    input: lists of drivers (endpoint first) and of the cell arcs leading into them."""
+    ep = endpoints(d)
+    s = np.asarray(res_mode["slack_drv"], np.float32)[ep]
+    order = np.lexsort((np.arange(ep.size), s))[:k]
+    paths = []
+    for r in order:
+        u = int(ep[r])
+        drv, arcs = [u], []
+        while u >= d.n_pi:
+            g = u - d.n_pi
+            a = int(d.gate_arc_ptr[g] + res_mode["argmax"][g])
+            arcs.append(a)
+            u = int(d.arc_drv[a])
+            drv.append(u)
+        paths.append((int(r), float(s[r]), drv, arcs))
+    return paths

@@ -402,3 +402,182 @@ done:
     free(C); free(Cd); free(m1); free(W); free(m2);
     return rc;
 }
+
+/* ---- adjoint of TNS (FP64 reference) ------------------------------------------ */
+
+/* Driver-level CSR of the sink arcs (fanout) and the endpoint flags. */
+static int orc_fanout(int D, int A, const int32_t* arc_drv, int32_t** fo_ptr_out, int32_t** fo_arc_out)
+{
+    int32_t* fo_ptr = (int32_t*)calloc((size_t)D + 2, sizeof(int32_t));
+    int32_t* fo_arc = (int32_t*)malloc(((size_t)A + 1) * sizeof(int32_t));
+    if (!fo_ptr || !fo_arc) { free(fo_ptr); free(fo_arc); return ORC_E_ARG; }
+    for (int a = 0; a < A; ++a) fo_ptr[arc_drv[a] + 2]++;
+    for (int d = 0; d < D; ++d) fo_ptr[d + 2] += fo_ptr[d + 1];
+    for (int a = 0; a < A; ++a) fo_arc[fo_ptr[arc_drv[a] + 1]++] = a;
+    *fo_ptr_out = fo_ptr;
+    *fo_arc_out = fo_arc;
+    return ORC_OK;
+}
+
+/* Chain rule of TNS = sum over endpoints of min(0, slack) through the forward maxima
+ * (minima for early), with the arguments of the maxima fixed: d TNS / d AT(endpoint) is
+ * -1 (late) or +1 (early) where the endpoint slack is negative, 0 otherwise; a gate
+ * output passes its gradient to its argmax arc (the arc's delay and its input pin's
+ * arrival), and a driver collects the gradients of all its sink pins.  FP64 (the values
+ * are integer counts).  Gates are visited in reverse topological order. */
+int orc_tns_adjoint(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr, const int32_t* arc_drv,
+                    const int32_t* argmax, const float* slack_drv, double* g_at, double* g_arc)
+{
+    int D = n_pi + n_gates;
+    int A = gate_arc_ptr[n_gates];
+    int32_t* level = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    int32_t* topo = (int32_t*)malloc(((size_t)n_gates + 1) * sizeof(int32_t));
+    int32_t *fo_ptr = NULL, *fo_arc = NULL;
+    int rc = ORC_OK;
+    if (!level || !topo) { rc = ORC_E_ARG; goto done; }
+    rc = orc_levelize(n_pi, n_gates, gate_arc_ptr, arc_drv, level, topo);
+    if (rc != ORC_OK) goto done;
+    rc = orc_fanout(D, A, arc_drv, &fo_ptr, &fo_arc);
+    if (rc != ORC_OK) goto done;
+    for (int d = 0; d < D; ++d) {
+        g_at[d] = 0.0;
+        if (fo_ptr[d + 1] == fo_ptr[d] && slack_drv[d] < 0.0f) g_at[d] = (mode == 0) ? -1.0 : 1.0;
+    }
+    for (int a = 0; a < A; ++a) g_arc[a] = 0.0;
+    for (int t = n_gates - 1; t >= 0; --t) {
+        int g = topo[t];
+        int o = n_pi + g;
+        int a = gate_arc_ptr[g] + argmax[g];
+        g_arc[a] = g_at[o];
+        g_at[arc_drv[a]] += g_at[o];
+    }
+done:
+    free(level); free(topo); free(fo_ptr); free(fo_arc);
+    return rc;
+}
+
+static double orc_tns_term(int mode, double at, double rat)
+{
+    double s = (mode == 0) ? rat - at : at - rat;
+    return s < 0.0 ? s : 0.0;
+}
+
+/* Change of TNS (FP64, arrivals AT = max/min over arcs of AT(driver) + net delay + arc
+ * delay, from the primary-input arrivals) when the cell-arc delays of one gate are
+ * replaced, for each of n_pert perturbations: gate pert_gate[p] gets delays
+ * pert_delay[pert_off[p] .. pert_off[p+1]) for its arcs in order.  Arrivals are
+ * re-evaluated only where they change, in level order; base_tns receives the
+ * unperturbed TNS (compensated summation).  ep_rat is indexed by driver (used only at
+ * endpoints). */
+int orc_tns_delta(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr, const int32_t* arc_drv,
+                  const double* arc_delay, const double* net_delay, const double* pi_at, const double* ep_rat,
+                  int n_pert, const int32_t* pert_gate, const int32_t* pert_off, const double* pert_delay,
+                  double* base_tns, double* delta)
+{
+    int D = n_pi + n_gates;
+    int A = gate_arc_ptr[n_gates];
+    int32_t* level = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    int32_t* topo = (int32_t*)malloc(((size_t)n_gates + 1) * sizeof(int32_t));
+    double* at = (double*)malloc(((size_t)D + 1) * sizeof(double));
+    double* atw = (double*)malloc(((size_t)D + 1) * sizeof(double));
+    double* dw = (double*)malloc(((size_t)A + 1) * sizeof(double));
+    int32_t* next = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    uint8_t* queued = (uint8_t*)calloc((size_t)D + 1, 1);
+    int32_t* touched = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    int32_t *fo_ptr = NULL, *fo_arc = NULL, *head = NULL;
+    int Lmax = 0, rc = ORC_OK;
+    if (!level || !topo || !at || !atw || !dw || !next || !queued || !touched) { rc = ORC_E_ARG; goto done; }
+    rc = orc_levelize(n_pi, n_gates, gate_arc_ptr, arc_drv, level, topo);
+    if (rc != ORC_OK) goto done;
+    rc = orc_fanout(D, A, arc_drv, &fo_ptr, &fo_arc);
+    if (rc != ORC_OK) goto done;
+    for (int d = 0; d < D; ++d) if (level[d] > Lmax) Lmax = level[d];
+    head = (int32_t*)malloc(((size_t)Lmax + 1) * sizeof(int32_t));
+    if (!head) { rc = ORC_E_ARG; goto done; }
+    for (int l = 0; l <= Lmax; ++l) head[l] = -1;
+    for (int d = 0; d < n_pi; ++d) at[d] = pi_at[d];
+    for (int t = 0; t < n_gates; ++t) {
+        int g = topo[t], o = n_pi + g;
+        double best = 0.0;
+        for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
+            double c = at[arc_drv[a]] + net_delay[a] + arc_delay[a];
+            if (a == gate_arc_ptr[g] || (mode == 0 ? c > best : c < best)) best = c;
+        }
+        at[o] = best;
+    }
+    {
+        double s = 0.0, comp = 0.0;       /* Kahan-Babuska summation of the base TNS */
+        for (int d = 0; d < D; ++d) {
+            if (fo_ptr[d + 1] != fo_ptr[d]) continue;
+            double x = orc_tns_term(mode, at[d], ep_rat[d]);
+            double t = s + x;
+            comp += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+            s = t;
+        }
+        *base_tns = s + comp;
+    }
+    memcpy(atw, at, sizeof(double) * (size_t)D);
+    memcpy(dw, arc_delay, sizeof(double) * (size_t)A);
+    for (int p = 0; p < n_pert; ++p) {
+        int g0 = pert_gate[p];
+        if (g0 < 0 || g0 >= n_gates || pert_off[p + 1] - pert_off[p] != gate_arc_ptr[g0 + 1] - gate_arc_ptr[g0]) {
+            rc = ORC_E_RANGE;
+            goto done;
+        }
+        for (int k = 0; k < pert_off[p + 1] - pert_off[p]; ++k) dw[gate_arc_ptr[g0] + k] = pert_delay[pert_off[p] + k];
+        int nt = 0;
+        double dt = 0.0;
+        int o0 = n_pi + g0;
+        next[o0] = head[level[o0]];
+        head[level[o0]] = o0;
+        queued[o0] = 1;
+        for (int l = level[o0]; l <= Lmax; ++l) {
+            while (head[l] >= 0) {
+                int o = head[l];
+                head[l] = next[o];
+                queued[o] = 0;
+                int g = o - n_pi;
+                double best = 0.0;
+                for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
+                    double c = atw[arc_drv[a]] + net_delay[a] + dw[a];
+                    if (a == gate_arc_ptr[g] || (mode == 0 ? c > best : c < best)) best = c;
+                }
+                if (best == atw[o]) continue;
+                if (atw[o] == at[o]) touched[nt++] = o;
+                atw[o] = best;
+                if (fo_ptr[o + 1] == fo_ptr[o]) continue;
+                for (int e = fo_ptr[o]; e < fo_ptr[o + 1]; ++e) {
+                    int a = fo_arc[e];
+                    int g2 = 0;
+                    /* gate of arc a: arcs are contiguous per gate */
+                    {
+                        int lo = 0, hi = n_gates - 1;
+                        while (lo < hi) {
+                            int mid = (lo + hi + 1) / 2;
+                            if (gate_arc_ptr[mid] <= a) lo = mid; else hi = mid - 1;
+                        }
+                        g2 = lo;
+                    }
+                    int o2 = n_pi + g2;
+                    if (!queued[o2]) {
+                        queued[o2] = 1;
+                        next[o2] = head[level[o2]];
+                        head[level[o2]] = o2;
+                    }
+                }
+            }
+        }
+        for (int i = 0; i < nt; ++i) {
+            int o = touched[i];
+            if (fo_ptr[o + 1] == fo_ptr[o])
+                dt += orc_tns_term(mode, atw[o], ep_rat[o]) - orc_tns_term(mode, at[o], ep_rat[o]);
+            atw[o] = at[o];
+        }
+        for (int k = gate_arc_ptr[g0]; k < gate_arc_ptr[g0 + 1]; ++k) dw[k] = arc_delay[k];
+        delta[p] = dt;
+    }
+done:
+    free(level); free(topo); free(at); free(atw); free(dw); free(next); free(queued); free(touched);
+    free(fo_ptr); free(fo_arc); free(head);
+    return rc;
+}
