@@ -513,7 +513,7 @@ sta_status sta_graph_upload(sta_graph* g, void* dev_buf, size_t bytes, void* str
 
 void sta_graph_free(sta_graph* g) {
     if (!g) return;
-    for (sta::LaunchCache* c : {&g->fwd_cache, &g->bwd_cache}) {
+    for (sta::LaunchCache* c : {&g->fwd_cache, &g->bwd_cache, &g->adj_cache}) {
         if (c->exec) (void)hipGraphExecDestroy(c->exec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
     }

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/sta.h"
+#include "../../include/sta_analysis.h"
 
 namespace sta {
 
@@ -87,7 +88,7 @@ struct sta_graph {
     int32_t view_sched_max_arcs = sta::kDefaultViewSchedMaxArcs;
     bool use_graphs = true;              // replay level-schedule launch sequences from hipGraphs
     mutable std::mutex cache_mu;
-    mutable sta::LaunchCache fwd_cache, bwd_cache;
+    mutable sta::LaunchCache fwd_cache, bwd_cache, adj_cache;
     sta::DevLayout lay{};
     std::vector<uint8_t> image;          // host image of the device buffer
     uint8_t* dev = nullptr;              // caller's device buffer after upload

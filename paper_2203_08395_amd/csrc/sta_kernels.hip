@@ -1357,6 +1357,283 @@ static void run_backward_views(const sta_graph* g, size_t lds, int NV, const KVi
     });
 }
 
+
+// ---------------------------------------------------------------------------------
+// adjoint of TNS (argmax-routed) and the critical-path report
+// ---------------------------------------------------------------------------------
+
+// One backward tile of the adjoint: the gradient of TNS with respect to a driver's
+// arrival is the sum over its sink pins of the gradient of the sink gate's output when
+// that pin's cell arc is the gate's argmax, plus -1 (late) / +1 (early) for an endpoint
+// with negative slack.  All values are integer counts, exact in FP32 in any order.
+template <int NW>
+__device__ __forceinline__ void adj_tile(const DevGraph& G, const bool* early, int NV, int v0, int s0, int n, int d0,
+                                         const uint8_t* __restrict__ argmax, const float* __restrict__ drv_slack,
+                                         float* __restrict__ g_at, float* __restrict__ g_arc,
+                                         float* __restrict__ g_nd) {
+    const int lane = threadIdx.x & 63;
+    const int c = (n + 63) >> 6;
+    const int sb = lane * c;
+    const int se = min(n, sb + c);
+    bool head;
+    if (c > 1) head = (lane == 0);
+    else head = (sb < n) && (uint32_t(G.bslot_out[s0 + sb]) & kHeadBit) != 0u;
+    const uint64_t heads = __ballot(head);
+    const uint64_t le = lanes_le(lane);
+    const int gi = __popcll(heads & le) - 1;
+    const uint64_t after = heads & ~le;
+    const int nl = (n + c - 1) / c;
+    const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : nl;
+    float acc[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) acc[w] = 0.0f;
+    for (int s = sb; s < se; ++s) {
+        const int slot = s0 + s;
+        const int sa = G.bslot_arc[slot];
+        const int so = G.bslot_out[slot] & 0x7fffffff;
+        if (sa >= 0) {
+            const int kpos = int(G.arc_meta[sa] >> 16);
+            const int gq = so - G.n_pi;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const float cv = (int(argmax[size_t(gq) * NV + v0 + w]) == kpos) ? g_at[size_t(so) * NV + v0 + w] : 0.0f;
+                if (g_arc) g_arc[size_t(sa) * NV + v0 + w] = cv;
+                if (g_nd) g_nd[size_t(sa) * NV + v0 + w] = cv;
+                acc[w] += cv;
+            }
+        } else {
+            const int u = d0 + gi;      // an endpoint owns exactly one slot, so this lane heads it
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const float sl = drv_slack[size_t(u) * NV + v0 + w];
+                acc[w] += sl < 0.0f ? (early[w] ? 1.0f : -1.0f) : 0.0f;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const bool take = (lane + off) < seg_end;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const float b2 = __shfl_down(acc[w], off, 64);
+            if (take) acc[w] += b2;
+        }
+    }
+    if (head) {
+        const int u = d0 + gi;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) g_at[size_t(u) * NV + v0 + w] = acc[w];
+    }
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_adjoint(DevGraph G, KViews V, int tile0, int tile1, KTiles kt,
+                                                 const uint8_t* __restrict__ argmax,
+                                                 const float* __restrict__ drv_slack, float* __restrict__ g_at,
+                                                 float* __restrict__ g_arc, float* __restrict__ g_nd) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = tile0 + blockIdx.x * 4 + wave;
+    if (t >= tile1) return;
+    bool early[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
+    int s0, n, d0;
+    if (kt.inl) {
+        s0 = kt.first[t - tile0];
+        n = kt.first[t - tile0 + 1] - s0;
+        d0 = kt.base[t - tile0];
+    } else {
+        s0 = G.btile_slot[t];
+        n = G.btile_slot[t + 1] - s0;
+        d0 = G.btile_drv[t];
+    }
+    adj_tile<NV>(G, early, NV, 0, s0, n, d0, argmax, drv_slack, g_at, g_arc, g_nd);
+}
+
+// d TNS / d load of every gate output: the gradient of its arrival times the NLDM slope
+// of its argmax arc's delay in the load ((q - p) / (y[j+1] - y[j]) of the bilinear
+// lookup), input slews held; 0 at primary inputs.
+template <int NV>
+__global__ __launch_bounds__(256) void k_adj_load(DevGraph G, KLib lib, KViews V, const float* __restrict__ arc_load,
+                                                  const float* __restrict__ arc_ts, const uint8_t* __restrict__ argmax,
+                                                  const float* __restrict__ g_at, float* __restrict__ g_load) {
+    __shared__ float s_ax[26];
+    load_axes(s_ax, lib);
+    __syncthreads();
+    const int d = blockIdx.x * 256 + threadIdx.x;
+    if (d >= G.n_drivers) return;
+    if (d < G.n_pi) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) g_load[size_t(d) * NV + v] = 0.0f;
+        return;
+    }
+    const float* X = s_ax;
+    const float* DX = s_ax + 14;
+    const int q = d - G.n_pi;
+    const int a0 = G.gate_arc_ptr[q];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int a = a0 + int(argmax[size_t(q) * NV + v]);
+        const float si = arc_ts[(size_t(a) * NV + v) * 2 + 1];
+        const float L = arc_load[a];
+        const float* T = lib.tables + (size_t(V.set[v]) * lib.n_tables + (G.arc_meta[a] & 0xffffu)) * 98;
+        const int i = seg6(X, si);
+        const float tx = (si - X[i]) / DX[i];
+        int j;
+        float ty;
+        gate_jty(s_ax, L, j, ty);
+        const float p = T[i * 7 + j] + tx * (T[(i + 1) * 7 + j] - T[i * 7 + j]);
+        const float qv = T[i * 7 + j + 1] + tx * (T[(i + 1) * 7 + j + 1] - T[i * 7 + j + 1]);
+        const float slope = (qv - p) / s_ax[20 + j];
+        g_load[size_t(d) * NV + v] = g_at[size_t(d) * NV + v] * slope;
+    }
+}
+
+__global__ void k_arc_load(DevGraph G, const float* __restrict__ load, float* __restrict__ arc_load) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= G.n_gates) return;
+    const float ld = load[G.n_pi + q];
+    for (int a = G.gate_arc_ptr[q]; a < G.gate_arc_ptr[q + 1]; ++a) arc_load[a] = ld;
+}
+
+// order-preserving key of (slack, endpoint rank): smaller key = worse slack, then lower rank
+__device__ __forceinline__ unsigned long long path_key(float s, int rank) {
+    uint32_t b = __float_as_uint(s);
+    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return (static_cast<unsigned long long>(b) << 32) | static_cast<uint32_t>(rank);
+}
+
+constexpr int kTopkBlocks = 128;
+
+// k smallest keys of a block's share, by k rounds of a block-wide minimum above the last pick
+__device__ void block_topk(const unsigned long long* mine, int cnt, int k, unsigned long long* out) {
+    __shared__ unsigned long long red[256];
+    unsigned long long last = 0ull;
+    bool first = true;
+    for (int r = 0; r < k; ++r) {
+        unsigned long long best = ~0ull;
+        for (int i = 0; i < cnt; ++i) {
+            const unsigned long long x = mine[i];
+            if ((first || x > last) && x < best) best = x;
+        }
+        red[threadIdx.x] = best;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w && red[threadIdx.x + w] < red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + w];
+            __syncthreads();
+        }
+        last = red[0];
+        first = false;
+        if (threadIdx.x == 0) out[r] = last;
+        __syncthreads();
+    }
+}
+
+constexpr int kTopkPerThread = 64;
+
+__global__ __launch_bounds__(256) void k_topk_partial(const int32_t* __restrict__ ep_drv, int E,
+                                                      const float* __restrict__ drv_slack, int NV, int v, int k,
+                                                      unsigned long long* __restrict__ cand) {
+    unsigned long long mine[kTopkPerThread];
+    const int per_block = (E + gridDim.x - 1) / gridDim.x;
+    const int e0 = blockIdx.x * per_block;
+    const int e1 = min(E, e0 + per_block);
+    int cnt = 0;
+    for (int e = e0 + threadIdx.x; e < e1 && cnt < kTopkPerThread; e += 256)
+        mine[cnt++] = path_key(drv_slack[size_t(ep_drv[e]) * NV + v], e);
+    block_topk(mine, cnt, k, cand + size_t(blockIdx.x) * k);
+}
+
+__global__ __launch_bounds__(256) void k_topk_final(const unsigned long long* __restrict__ cand, int n, int k,
+                                                    int32_t* __restrict__ ep_rank, float* __restrict__ slack) {
+    __shared__ unsigned long long out[STA_MAX_PATHS];
+    unsigned long long mine[kTopkPerThread];
+    int cnt = 0;
+    for (int i = threadIdx.x; i < n && cnt < kTopkPerThread; i += 256) mine[cnt++] = cand[i];
+    block_topk(mine, cnt, k, out);
+    if (threadIdx.x < k) {
+        const unsigned long long x = out[threadIdx.x];
+        uint32_t b = uint32_t(x >> 32);
+        b = (b & 0x80000000u) ? (b & 0x7fffffffu) : ~b;
+        ep_rank[threadIdx.x] = int32_t(uint32_t(x));
+        slack[threadIdx.x] = __uint_as_float(b);
+    }
+}
+
+// walk the saved argmax arcs from each selected endpoint back to a primary input
+__global__ void k_backtrace(DevGraph G, int NV, int v, int k, int L, const uint8_t* __restrict__ argmax,
+                            const int32_t* __restrict__ ep_rank, int32_t* __restrict__ len,
+                            int32_t* __restrict__ drv, int32_t* __restrict__ arc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    int u = G.ep_drv[ep_rank[i]];
+    int n = 0;
+    int32_t* pd = drv + size_t(i) * (L + 1);
+    int32_t* pa = arc + size_t(i) * L;
+    while (n <= L) {
+        pd[n++] = u;
+        if (u < G.n_pi || n > L) break;
+        const int q = u - G.n_pi;
+        const int a = G.gate_arc_ptr[q] + int(argmax[size_t(q) * NV + v]);
+        pa[n - 1] = a;
+        u = G.arc_src[a];
+    }
+    len[i] = n;
+}
+
+template <int NV>
+static void enqueue_adjoint_levels(const sta_graph* g, const KLib& kl, const KViews& kv, const sta_net_out* nd,
+                                   const sta_timing_out* t, const sta_slack_out* sl, const sta_adjoint_out* o,
+                                   hipStream_t s) {
+    const DevGraph dg = dev_graph(g);
+    for (int64_t l = g->L; l >= 0; --l) {
+        const int t0 = g->bwd_tile_ptr[l], t1 = g->bwd_tile_ptr[l + 1];
+        if (t1 <= t0) continue;
+        const KTiles kt = ktiles(g->btile_slot_h, g->btile_drv_h, t0, t1);
+        prof_launch("k_adjoint", s, [&] {
+            hipLaunchKernelGGL((k_adjoint<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, kv, t0, t1, kt,
+                               t->argmax, sl->drv_slack, o->g_drv_at, o->g_arc_delay, o->g_net_delay);
+        });
+    }
+    if (o->g_load)
+        prof_launch("k_adj_load", s, [&] {
+            hipLaunchKernelGGL((k_adj_load<NV>), dim3((g->D + 255) / 256), dim3(256), 0, s, dg, kl, kv, nd->arc_load,
+                               t->arc_ts, t->argmax, o->g_drv_at, o->g_load);
+        });
+}
+
+template <int NV>
+static sta_status run_adjoint_levels(const sta_graph* g, const KLib& kl, const KViews& kv, const sta_net_out* nd,
+                                     const sta_timing_out* t, const sta_slack_out* sl, const sta_adjoint_out* o,
+                                     hipStream_t s) {
+    std::vector<uint64_t> key = {uint64_t(NV), pk(nd->arc_load), pk(t->arc_ts), pk(t->argmax), pk(sl->drv_slack),
+                                 pk(o->g_drv_at), pk(o->g_arc_delay), pk(o->g_net_delay), pk(o->g_load),
+                                 pk(kl.tables), uint64_t(kl.n_tables)};
+    for (int i = 0; i < 26; ++i) { uint32_t b; std::memcpy(&b, &kl.ax[i], 4); key.push_back(b); }
+    for (int v = 0; v < NV; ++v) { key.push_back(uint64_t(kv.mode[v])); key.push_back(uint64_t(kv.set[v])); }
+    return run_sequence(g, g->adj_cache, std::move(key), s, [&](hipStream_t q) {
+        enqueue_adjoint_levels<NV>(g, kl, kv, nd, t, sl, o, q);
+    });
+}
+
+static bool lib_axes_ok(const sta_library* lib, int n_tables, std::string& why) {
+    if (lib->n_sets < 1 || lib->n_tables < n_tables || !lib->tables) { why = "library has fewer tables than the design references"; return false; }
+    for (int i = 0; i < 7; ++i)
+        if (!std::isfinite(lib->x[i]) || !std::isfinite(lib->y[i])) { why = "non-finite library axis"; return false; }
+    for (int i = 0; i < 6; ++i)
+        if (!(lib->x[i] < lib->x[i + 1]) || !(lib->y[i] < lib->y[i + 1])) { why = "library axes must strictly increase"; return false; }
+    return true;
+}
+
+static KLib make_klib(const sta_library* lib) {
+    KLib kl{};
+    for (int i = 0; i < 7; ++i) { kl.ax[i] = lib->x[i]; kl.ax[7 + i] = lib->y[i]; }
+    for (int i = 0; i < 6; ++i) { kl.ax[14 + i] = lib->x[i + 1] - lib->x[i]; kl.ax[20 + i] = lib->y[i + 1] - lib->y[i]; }
+    kl.tables = lib->tables;
+    kl.n_tables = lib->n_tables;
+    return kl;
+}
+
 }  // namespace sta
 
 using namespace sta;
@@ -1494,6 +1771,84 @@ sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32
     g->view_sched_max_arcs = view_max_arcs_per_level < 0 ? kDefaultViewSchedMaxArcs : view_max_arcs_per_level;
     g->use_graphs = use_graphs != 0;
     return STA_OK;
+}
+
+sta_status sta_arc_load(const sta_graph* g, const sta_net_out* nd, void* stream) {
+    if (!g || !nd) return fail(STA_E_ARG, "sta_arc_load: null argument");
+    if (!g->dev) return fail(STA_E_ARG, "sta_arc_load: graph not uploaded");
+    if (g->n_gates == 0) return STA_OK;
+    if (!nd->load || !nd->arc_load) return fail(STA_E_ARG, "sta_arc_load: null buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const DevGraph dg = dev_graph(g);
+    prof_launch("k_arc_load", s, [&] {
+        hipLaunchKernelGGL(k_arc_load, dim3((g->n_gates + 255) / 256), dim3(256), 0, s, dg, nd->load, nd->arc_load);
+    });
+    return launch_check("sta_arc_load");
+}
+
+sta_status sta_tns_adjoint(const sta_graph* g, const sta_library* lib, const sta_views* views, const sta_net_out* nd,
+                           const sta_timing_out* t, const sta_slack_out* sl, const sta_adjoint_out* out,
+                           void* stream) {
+    if (!g || !views || !nd || !t || !sl || !out) return fail(STA_E_ARG, "sta_tns_adjoint: null argument");
+    if (!g->dev) return fail(STA_E_ARG, "sta_tns_adjoint: graph not uploaded");
+    std::string why;
+    if (!views_ok(views, lib ? lib->n_sets : -1, why)) return fail(STA_E_ARG, "sta_tns_adjoint: " + why);
+    if (out->g_load && (!lib || !lib_axes_ok(lib, int(g->n_tables), why)))
+        return fail(STA_E_ARG, "sta_tns_adjoint: " + (lib ? why : std::string("g_load needs the library")));
+    if (g->D == 0) return STA_OK;
+    if (!out->g_drv_at || !sl->drv_slack || (g->A > 0 && !t->argmax) ||
+        (out->g_load && (!t->arc_ts || !nd->arc_load)))
+        return fail(STA_E_ARG, "sta_tns_adjoint: null buffer");
+    const KViews kv = kviews(views);
+    const KLib kl = (out->g_load && lib) ? make_klib(lib) : KLib{};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    sta_status st;
+    switch (views->n_views) {
+        case 1: st = run_adjoint_levels<1>(g, kl, kv, nd, t, sl, out, s); break;
+        case 2: st = run_adjoint_levels<2>(g, kl, kv, nd, t, sl, out, s); break;
+        case 4: st = run_adjoint_levels<4>(g, kl, kv, nd, t, sl, out, s); break;
+        default: st = run_adjoint_levels<8>(g, kl, kv, nd, t, sl, out, s); break;
+    }
+    if (st != STA_OK) return st;
+    return launch_check("sta_tns_adjoint");
+}
+
+size_t sta_paths_scratch_bytes(void) { return sizeof(unsigned long long) * kTopkBlocks * STA_MAX_PATHS; }
+
+sta_status sta_critical_paths(const sta_graph* g, const sta_views* views, int32_t view, int32_t k,
+                              const sta_timing_out* t, const sta_slack_out* sl, const sta_paths_out* out,
+                              void* scratch, size_t scratch_bytes_, void* stream) {
+    if (!g || !views || !t || !sl || !out) return fail(STA_E_ARG, "sta_critical_paths: null argument");
+    if (!g->dev) return fail(STA_E_ARG, "sta_critical_paths: graph not uploaded");
+    std::string why;
+    if (!views_ok(views, -1, why)) return fail(STA_E_ARG, "sta_critical_paths: " + why);
+    if (view < 0 || view >= views->n_views) return fail(STA_E_ARG, "sta_critical_paths: view out of range");
+    if (k < 1 || k > STA_MAX_PATHS) return fail(STA_E_ARG, "sta_critical_paths: k must be in 1..STA_MAX_PATHS");
+    if (k > g->E) return fail(STA_E_ARG, "sta_critical_paths: k exceeds the number of endpoints");
+    if (g->E > int64_t(kTopkBlocks) * 256 * kTopkPerThread)
+        return fail(STA_E_ARG, "sta_critical_paths: too many endpoints for the selection kernel");
+    if (!scratch || scratch_bytes_ < sta_paths_scratch_bytes()) return fail(STA_E_ARG, "sta_critical_paths: scratch too small");
+    if (!out->ep_rank || !out->slack || !out->len || !out->drv || !out->arc || !sl->drv_slack || (g->A > 0 && !t->argmax))
+        return fail(STA_E_ARG, "sta_critical_paths: null buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const DevGraph dg = dev_graph(g);
+    const int NV = views->n_views;
+    auto* cand = static_cast<unsigned long long*>(scratch);
+    int blocks = int((g->E + 255) / 256);
+    blocks = blocks < kTopkBlocks ? blocks : kTopkBlocks;
+    prof_launch("k_topk_partial", s, [&] {
+        hipLaunchKernelGGL(k_topk_partial, dim3(blocks), dim3(256), 0, s, dg.ep_drv, int(g->E), sl->drv_slack, NV,
+                           int(view), int(k), cand);
+    });
+    prof_launch("k_topk_final", s, [&] {
+        hipLaunchKernelGGL(k_topk_final, dim3(1), dim3(256), 0, s, cand, blocks * int(k), int(k), out->ep_rank,
+                           out->slack);
+    });
+    prof_launch("k_backtrace", s, [&] {
+        hipLaunchKernelGGL(k_backtrace, dim3(1), dim3(64), 0, s, dg, NV, int(view), int(k), int(g->L), t->argmax,
+                           out->ep_rank, out->len, out->drv, out->arc);
+    });
+    return launch_check("sta_critical_paths");
 }
 
 }  // extern "C"

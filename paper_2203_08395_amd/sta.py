@@ -317,3 +317,99 @@ def profile_end():
     n = ctypes.c_int32(0)
     _check(load_library().sta_profile_end(arr, cap, ctypes.byref(n)), "sta_profile_end")
     return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(min(n.value, cap))}
+
+
+# ---- analyses: adjoint of TNS, critical paths (include/sta_analysis.h) -----------------
+
+class AdjointOut(ctypes.Structure):
+    _fields_ = [("g_drv_at", _P), ("g_arc_delay", _P), ("g_net_delay", _P), ("g_load", _P)]
+
+
+class PathsOut(ctypes.Structure):
+    _fields_ = [("ep_rank", _P), ("slack", _P), ("len", _P), ("drv", _P), ("arc", _P)]
+
+
+MAX_PATHS = 64
+ANALYSIS_EXPORTS = ("sta_tns_adjoint", "sta_arc_load", "sta_paths_scratch_bytes", "sta_critical_paths")
+_ana_bound = False
+
+
+def _ana():
+    global _ana_bound
+    lib = load_library()
+    if not _ana_bound:
+        lib.sta_tns_adjoint.argtypes = [_P, ctypes.POINTER(LibraryC), ctypes.POINTER(ViewsC), ctypes.POINTER(NetOut),
+                                        ctypes.POINTER(TimingOut), ctypes.POINTER(SlackOut),
+                                        ctypes.POINTER(AdjointOut), _P]
+        lib.sta_arc_load.argtypes = [_P, ctypes.POINTER(NetOut), _P]
+        lib.sta_paths_scratch_bytes.argtypes = []
+        lib.sta_paths_scratch_bytes.restype = ctypes.c_size_t
+        lib.sta_critical_paths.argtypes = [_P, ctypes.POINTER(ViewsC), ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(TimingOut), ctypes.POINTER(SlackOut),
+                                           ctypes.POINTER(PathsOut), _P, ctypes.c_size_t, _P]
+        for f in ("sta_tns_adjoint", "sta_arc_load", "sta_critical_paths"):
+            getattr(lib, f).restype = ctypes.c_int
+        _ana_bound = True
+    return lib
+
+
+def _timingout(t):
+    return TimingOut(_ptr(t["drv_ts"]), _ptr(t["arc_ts"]), _ptr(t["arc_delay"]), _ptr(t["argmax"]))
+
+
+def _slackout(o):
+    return SlackOut(_ptr(o["drv_rat"]), _ptr(o["arc_rat"]), _ptr(o["drv_slack"]), _ptr(o["arc_slack"]),
+                    _ptr(o["tns"]), _ptr(o["wns"]))
+
+
+def alloc_adjoint(g: Graph, n_views, arcs=True, load=True):
+    import torch
+    D, A = g.sizes["n_drivers"], g.sizes["n_arcs"]
+    dev = g.device
+    out = {"g_drv_at": torch.empty((max(D, 1), n_views), dtype=torch.float32, device=dev)}
+    if arcs:
+        out["g_arc_delay"] = torch.empty((max(A, 1), n_views), dtype=torch.float32, device=dev)
+        out["g_net_delay"] = torch.empty((max(A, 1), n_views), dtype=torch.float32, device=dev)
+    if load:
+        out["g_load"] = torch.empty((max(D, 1), n_views), dtype=torch.float32, device=dev)
+    return out
+
+
+def tns_adjoint(g: Graph, lib: LibraryC, views: ViewsC, nd, timing, slack_out, out=None):
+    """Gradients of every view's TNS (see sta_tns_adjoint); device tensors, internal order."""
+    import torch
+    if out is None:
+        out = alloc_adjoint(g, views.n_views)
+    ao = AdjointOut(_ptr(out.get("g_drv_at")), _ptr(out.get("g_arc_delay")), _ptr(out.get("g_net_delay")),
+                    _ptr(out.get("g_load")))
+    no, to, so = _netout(nd), _timingout(timing), _slackout(slack_out)
+    _check(_ana().sta_tns_adjoint(g.handle, ctypes.byref(lib) if lib is not None else None, ctypes.byref(views),
+                                  ctypes.byref(no), ctypes.byref(to), ctypes.byref(so), ctypes.byref(ao),
+                                  _stream(torch, g.device)), "sta_tns_adjoint")
+    return out
+
+
+def arc_load(g: Graph, nd):
+    import torch
+    no = _netout(nd)
+    _check(_ana().sta_arc_load(g.handle, ctypes.byref(no), _stream(torch, g.device)), "sta_arc_load")
+
+
+def critical_paths(g: Graph, views: ViewsC, view, k, timing, slack_out):
+    """The k worst endpoints of one view and their argmax paths (device tensors)."""
+    import torch
+    L = g.sizes["n_levels"]
+    dev = g.device
+    out = {"ep_rank": torch.empty(k, dtype=torch.int32, device=dev),
+           "slack": torch.empty(k, dtype=torch.float32, device=dev),
+           "len": torch.empty(k, dtype=torch.int32, device=dev),
+           "drv": torch.empty((k, L + 1), dtype=torch.int32, device=dev),
+           "arc": torch.empty((k, max(L, 1)), dtype=torch.int32, device=dev)}
+    lib = _ana()
+    nb = lib.sta_paths_scratch_bytes()
+    scratch = torch.empty(nb, dtype=torch.uint8, device=dev)
+    po = PathsOut(_ptr(out["ep_rank"]), _ptr(out["slack"]), _ptr(out["len"]), _ptr(out["drv"]), _ptr(out["arc"]))
+    _check(lib.sta_critical_paths(g.handle, ctypes.byref(views), int(view), int(k), ctypes.byref(_timingout(timing)),
+                                  ctypes.byref(_slackout(slack_out)), ctypes.byref(po), _ptr(scratch), nb,
+                                  _stream(torch, dev)), "sta_critical_paths")
+    return out

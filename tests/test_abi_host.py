@@ -38,6 +38,18 @@ def test_library_exports_every_surrogate_symbol():
     assert set(names) == set(surrogate.EXPORTS)
 
 
+def test_library_exports_every_analysis_symbol():
+    lib = sta._ana()
+    names = _declared("sta_analysis.h")
+    assert len(names) == 4
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sta.ANALYSIS_EXPORTS)
+    assert lib.sta_paths_scratch_bytes() == 128 * 64 * 8
+    assert lib.sta_tns_adjoint(None, None, None, None, None, None, None, None) == -1
+    assert lib.sta_critical_paths(None, None, 0, 1, None, None, None, None, 0, None) == -1
+
+
 def test_surrogate_host_validation_without_gpu():
     """Argument errors are caught before any launch (no device pointer is touched)."""
     from paper_2203_08395_amd import surrogate
