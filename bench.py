@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--surrogate-nets", type=int, default=1_000_000,
                     help="RC-tree nets of the learned-surrogate comparison (0: skip it)")
     ap.add_argument("--surrogate-train-steps", type=int, default=3000)
+    ap.add_argument("--batch-designs", type=int, default=64,
+                    help="designs of the batched-corners comparison (0: skip it)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one design on one GPU); "
@@ -216,6 +218,14 @@ def main():
                  "graph_bytes": s["graph_bytes"]},
     }
 
+    # analyses on the same timed design: TNS adjoint (both views) and the 64 worst paths
+    adj = sta.alloc_adjoint(g, V)
+    out["adjoint"] = {"ms": _time_ms(lambda: sta.tns_adjoint(g, L_lib, views, nd, tm, sl, out=adj)),
+                      "what": "dTNS/d(arc delay, net delay, AT, load) for late and early"}
+    out["critical_paths"] = {"ms": _time_ms(lambda: sta.critical_paths(g, views, 0, 64, tm, sl)),
+                             "what": "64 worst late endpoints and their argmax paths"}
+    if args.batch_designs > 0:
+        out["batched"] = batch_bench(dev, args.batch_designs)
     if args.surrogate_nets > 0:
         out["surrogate"] = surrogate_bench(dev, args.surrogate_nets, args.surrogate_train_steps)
     if not args.no_cpu:
@@ -235,6 +245,75 @@ def _time_ms(fn, reps=5, warm=2):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def batch_bench(dev, n_designs, reps=5):
+    """Uneven designs x 4 corners: looping the plain per-design propagation vs one batched
+    launch sequence (persistent launch for the designs the autotuner assigns to it, level
+    launches for the rest, replayed from a hipGraph)."""
+    import torch
+    from paper_2203_08395_amd import autotune, gen, sta
+    specs = gen.c3_designs(n_designs)
+    lib = gen.make_library(kappas=gen.CORNER_KAPPAS)
+    L_lib = sta.make_library(lib.x, lib.y, torch.from_numpy(lib.tab).to(dev))
+    V = len(gen.CORNER_KAPPAS)
+    views = sta.make_views([sta.STA_LATE] * V, list(range(V)))
+    t0 = time.perf_counter()
+    entries = []
+    pins = updates = 0
+    for sp in specs:
+        d = gen.make_design(**sp)
+        g = sta.Graph(d, n_tables=lib.tab.shape[1]).upload(dev)
+        nd = sta.delay_calc(g)
+        pa, ps = gen.make_pi(d)
+        pi = np.zeros((max(d.n_pi, 1), V, 2), np.float32)
+        pi[:d.n_pi, :, 0] = pa[:, None]
+        pi[:d.n_pi, :, 1] = ps[:, None]
+        entries.append([g, torch.from_numpy(pi).to(dev), nd, sta.alloc_timing(g, V), sta.BATCH_PERSISTENT])
+        pins += d.n_pins
+        updates += (d.n_pins - d.n_pi) * V
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+
+    def loop():
+        for g, pi, nd, tm, _ in entries:
+            sta.propagate(g, L_lib, views, pi, nd, out=tm)
+
+    ms_loop = _time_ms(loop, reps=reps)
+    ref = [e[3]["drv_ts"].clone() for e in entries]
+    tuner = autotune.Tuner()
+    t0 = time.perf_counter()
+    unit, level = [], []
+    for g, pi, nd, tm, _ in entries:
+        u, l_ = tuner.timings(g, L_lib, views, pi, nd, tm)
+        unit.append(u)
+        level.append(l_)
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    sched, est = autotune.Tuner.plan(unit, level, V, n_cu)
+    t_tune = time.perf_counter() - t0
+    try:
+        tuner.save()
+    except OSError:
+        pass
+    for e, s_ in zip(entries, sched):
+        e[4] = s_
+    b = sta.Batch([tuple(e) for e in entries], L_lib, views)
+    ms_batch = _time_ms(lambda: b.propagate(use_graph=True), reps=reps)
+    same = all(torch.equal(r, e[3]["drv_ts"]) for r, e in zip(ref, entries))
+    info = b.info()
+    return {
+        "workload": f"{len(specs)} seeded designs, pins log-uniform 5k-500k (sum {pins}), levels 30*sqrt(P/5k), "
+                    f"x {V} corners (tables scaled {list(gen.CORNER_KAPPAS)}), late, FP32",
+        "pins": pins, "pin_updates": updates,
+        "loop_ms": ms_loop, "batched_ms": ms_batch, "speedup_vs_loop": ms_loop / ms_batch,
+        "loop_pin_updates_per_s": updates / (ms_loop * 1e-3),
+        "batched_pin_updates_per_s": updates / (ms_batch * 1e-3),
+        "persistent_units": info["persistent_units"], "level_designs": info["level_designs"],
+        "autotune": {"size_classes_measured": tuner.measured, "seconds": t_tune, "estimated_ms": est,
+                     "cache": tuner.path},
+        "bitwise_equal_to_loop": bool(same),
+        "setup_s": t_setup,
+    }
 
 
 def surrogate_bench(dev, n_nets, train_steps, tol_ps=1.0):

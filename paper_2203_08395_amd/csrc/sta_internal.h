@@ -10,6 +10,7 @@
 
 #include "../../include/sta.h"
 #include "../../include/sta_analysis.h"
+#include "../../include/sta_batch.h"
 
 namespace sta {
 
@@ -62,6 +63,20 @@ struct DevGraph {
     const int32_t* fwd_chunk;      // [NC+1][4] forward chunks
     const int32_t* bwd_chunk;      // [NB+1][4] backward chunks in processing order (+ 4 ints of bounds)
     int32_t n_pi, n_gates, n_drivers, n_arcs;
+};
+
+// One graph of a batched launch: its device layout, chunk count, view count and buffers.
+struct BatchItem {
+    DevGraph G;
+    int32_t NC, NV;
+    const float* pi_ts;
+    const float* load;
+    const float* nd;
+    const float* ni;
+    float* drv_ts;
+    float* arc_ts;
+    float* arc_delay;
+    uint8_t* argmax;
 };
 
 // A captured launch sequence (hipGraph) reused while its arguments stay the same.

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -634,15 +635,13 @@ constexpr int kFwdRA = (kFwdCapA + kViewThreads - 1) / kViewThreads;   // arcs p
 constexpr int kFwdRG = (kFwdCapG + kViewThreads - 1) / kViewThreads;   // gates per lane when staging
 constexpr int kFwdRT = (kFwdCapT + kViewWaves - 1) / kViewWaves;       // tiles per wave
 
-__global__ __launch_bounds__(kViewThreads) void k_forward_view(DevGraph G, KLib lib, KViews V, int NV, int NC,
-                                                               const float* __restrict__ pi_ts,
-                                                               const float* __restrict__ load,
-                                                               const float* __restrict__ nd,
-                                                               const float* __restrict__ ni,
-                                                               float* __restrict__ drv_ts, float* __restrict__ arc_ts,
-                                                               float* __restrict__ arc_delay,
-                                                               uint8_t* __restrict__ argmax) {
-    extern __shared__ float s_mem[];
+// One view of one graph, walked by the whole workgroup (every thread must call it).
+__device__ __forceinline__ void fwd_view_unit(const DevGraph& G, const KLib& lib, const KViews& V, int NV, int NC,
+                                              int v, const float* __restrict__ pi_ts, const float* __restrict__ load,
+                                              const float* __restrict__ nd, const float* __restrict__ ni,
+                                              float* __restrict__ drv_ts, float* __restrict__ arc_ts,
+                                              float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
+                                              float* s_mem) {
     const FwdLds lo = fwd_lds(lib.n_tables);
     float* s_ax = s_mem + lo.ax;
     float* s_tab = s_mem + lo.tab;
@@ -661,7 +660,6 @@ __global__ __launch_bounds__(kViewThreads) void k_forward_view(DevGraph G, KLib 
     int* s_taoff = reinterpret_cast<int*>(s_mem + lo.taoff);
     int* s_tgoff = reinterpret_cast<int*>(s_mem + lo.tgoff);
     int* s_tmaxk = reinterpret_cast<int*>(s_mem + lo.tmaxk);
-    const int v = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const float* gtab = lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
@@ -839,6 +837,41 @@ __global__ __launch_bounds__(kViewThreads) void k_forward_view(DevGraph G, KLib 
         __syncthreads();
     }
 }
+
+__global__ __launch_bounds__(kViewThreads) void k_forward_view(DevGraph G, KLib lib, KViews V, int NV, int NC,
+                                                               const float* __restrict__ pi_ts,
+                                                               const float* __restrict__ load,
+                                                               const float* __restrict__ nd,
+                                                               const float* __restrict__ ni,
+                                                               float* __restrict__ drv_ts, float* __restrict__ arc_ts,
+                                                               float* __restrict__ arc_delay,
+                                                               uint8_t* __restrict__ argmax) {
+    extern __shared__ float s_mem[];
+    fwd_view_unit(G, lib, V, NV, NC, blockIdx.x, pi_ts, load, nd, ni, drv_ts, arc_ts, arc_delay, argmax, s_mem);
+}
+
+// Many graphs and views in one launch: each workgroup claims (graph, view) units from a
+// device counter, largest first (the host orders them), until none is left.
+__global__ __launch_bounds__(kViewThreads) void k_forward_batch(const BatchItem* __restrict__ items,
+                                                                const int2* __restrict__ units, int n_units,
+                                                                int* __restrict__ counter, KLib lib, KViews V) {
+    extern __shared__ float s_mem[];
+    __shared__ int s_u;
+    for (;;) {
+        if (threadIdx.x == 0) s_u = atomicAdd(counter, 1);
+        __syncthreads();
+        const int u = s_u;
+        __syncthreads();
+        if (u >= n_units) break;
+        const int2 w = units[u];
+        const BatchItem it = items[w.x];
+        fwd_view_unit(it.G, lib, V, it.NV, it.NC, w.y, it.pi_ts, it.load, it.nd, it.ni, it.drv_ts, it.arc_ts,
+                      it.arc_delay, it.argmax, s_mem);
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_i32(int* p) { if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0; }
 
 // k_backward_view: chunks of whole backward tiles of one driver level, in processing
 // order (levels L..0).  While chunk c computes, the workgroup gathers chunk c+1's
@@ -1211,13 +1244,13 @@ static KTiles ktiles(const std::vector<int32_t>& first, const std::vector<int32_
 // Runs enqueue(stream) directly, or replays it from the cached hipGraph of this call
 // kind (capturing it first when the key differs).  Profiling always runs it directly.
 template <typename F>
-static sta_status run_sequence(const sta_graph* g, LaunchCache& c, std::vector<uint64_t> key, hipStream_t s,
-                               F&& enqueue) {
-    if (!g->use_graphs || g_prof.on) {
+static sta_status capture_replay(LaunchCache& c, std::mutex& mu, bool use_graphs, std::vector<uint64_t> key,
+                                 hipStream_t s, F&& enqueue) {
+    if (!use_graphs || g_prof.on) {
         enqueue(s);
         return STA_OK;
     }
-    std::lock_guard<std::mutex> lock(g->cache_mu);
+    std::lock_guard<std::mutex> lock(mu);
     if (!c.exec || c.key != key) {
         if (c.exec) { (void)hipGraphExecDestroy(c.exec); c.exec = nullptr; }
         if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
@@ -1248,6 +1281,12 @@ static sta_status run_sequence(const sta_graph* g, LaunchCache& c, std::vector<u
     hipError_t e = hipGraphLaunch(c.exec, s);
     if (e != hipSuccess) return fail(STA_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
     return STA_OK;
+}
+
+template <typename F>
+static sta_status run_sequence(const sta_graph* g, LaunchCache& c, std::vector<uint64_t> key, hipStream_t s,
+                               F&& enqueue) {
+    return capture_replay(c, g->cache_mu, g->use_graphs, std::move(key), s, std::forward<F>(enqueue));
 }
 
 static uint64_t pk(const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); }
@@ -1634,6 +1673,52 @@ static KLib make_klib(const sta_library* lib) {
     return kl;
 }
 
+
+// ---------------------------------------------------------------------------------
+// batches of graphs: one persistent launch plus per-level launches
+// ---------------------------------------------------------------------------------
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <int NV>
+static void enqueue_levels_any(const sta_graph* g, const KLib& kl, const KViews& kv, const float* pi_ts,
+                               const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
+    enqueue_forward_levels<NV, false>(g, kl, kv, pi_ts, nd, o, s);
+}
+
+static void enqueue_levels_nv(int NV, const sta_graph* g, const KLib& kl, const KViews& kv, const float* pi_ts,
+                              const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
+    switch (NV) {
+        case 1: enqueue_levels_any<1>(g, kl, kv, pi_ts, nd, o, s); break;
+        case 2: enqueue_levels_any<2>(g, kl, kv, pi_ts, nd, o, s); break;
+        case 4: enqueue_levels_any<4>(g, kl, kv, pi_ts, nd, o, s); break;
+        default: enqueue_levels_any<8>(g, kl, kv, pi_ts, nd, o, s); break;
+    }
+}
+
+}  // namespace sta
+
+struct sta_batch {
+    struct Lvl {
+        const sta_graph* g;
+        const float* pi_ts;
+        sta_net_out nd;
+        sta_timing_out out;
+    };
+    std::vector<Lvl> level_designs;
+    int n_units = 0;
+    int NV = 0;
+    sta::KLib kl{};
+    sta::KViews kv{};
+    size_t lds = 0;
+    sta::BatchItem* d_items = nullptr;
+    int2* d_units = nullptr;
+    int* d_counter = nullptr;
+    sta::LaunchCache cache;
+    std::mutex mu;
+};
+
+namespace sta {
 }  // namespace sta
 
 using namespace sta;
@@ -1849,6 +1934,127 @@ sta_status sta_critical_paths(const sta_graph* g, const sta_views* views, int32_
                            out->ep_rank, out->len, out->drv, out->arc);
     });
     return launch_check("sta_critical_paths");
+}
+
+size_t sta_batch_workspace_bytes(int32_t n_designs, int32_t n_views) {
+    if (n_designs < 0 || n_views < 1) return 0;
+    return align256(sizeof(BatchItem) * size_t(n_designs)) + align256(sizeof(int2) * size_t(n_designs) * n_views) + 256;
+}
+
+sta_status sta_batch_create(const sta_batch_design* designs, int32_t n, const sta_library* lib,
+                            const sta_views* views, void* workspace, size_t workspace_bytes, sta_batch** out) {
+    if (!out) return fail(STA_E_ARG, "sta_batch_create: null output");
+    *out = nullptr;
+    if (n < 0 || (n > 0 && !designs) || !lib || !views) return fail(STA_E_ARG, "sta_batch_create: null argument");
+    std::string why;
+    if (!views_ok(views, lib->n_sets, why)) return fail(STA_E_ARG, "sta_batch_create: " + why);
+    if (!lib_axes_ok(lib, 0, why)) return fail(STA_E_ARG, "sta_batch_create: " + why);
+    const int NV = views->n_views;
+    if (!workspace || workspace_bytes < sta_batch_workspace_bytes(n, NV))
+        return fail(STA_E_ARG, "sta_batch_create: workspace smaller than sta_batch_workspace_bytes");
+    std::unique_ptr<sta_batch> b(new (std::nothrow) sta_batch());
+    if (!b) return fail(STA_E_ALLOC, "sta_batch_create: out of host memory");
+    b->NV = NV;
+    b->kl = make_klib(lib);
+    b->kv = kviews(views);
+    b->lds = size_t(fwd_lds(lib->n_tables).total) * 4;
+    const bool lds_ok = b->lds <= lds_limit();
+    std::vector<BatchItem> items;
+    std::vector<std::pair<int64_t, int2>> units;
+    for (int i = 0; i < n; ++i) {
+        const sta_batch_design& d = designs[i];
+        if (!d.g || !d.nd || !d.out) return fail(STA_E_ARG, "sta_batch_create: null design entry " + std::to_string(i));
+        const sta_graph* g = d.g;
+        if (!g->dev) return fail(STA_E_ARG, "sta_batch_create: design " + std::to_string(i) + " not uploaded");
+        if (lib->n_tables < g->n_tables) return fail(STA_E_ARG, "sta_batch_create: library has fewer tables than design " + std::to_string(i));
+        if (d.schedule != STA_BATCH_PERSISTENT && d.schedule != STA_BATCH_LEVELS)
+            return fail(STA_E_ARG, "sta_batch_create: bad schedule");
+        if (g->D == 0) continue;
+        if ((g->n_pi > 0 && !d.pi_ts) || !d.out->drv_ts ||
+            (g->A > 0 && (!d.out->arc_ts || !d.out->arc_delay || !d.out->argmax || !d.nd->net_delay ||
+                          !d.nd->net_imp2 || !d.nd->arc_load)) || !d.nd->load)
+            return fail(STA_E_ARG, "sta_batch_create: null buffer in design " + std::to_string(i));
+        const bool pers = d.schedule == STA_BATCH_PERSISTENT && lds_ok && g->L > 0 && g->n_fchunks > 0;
+        if (!pers) {
+            b->level_designs.push_back({g, d.pi_ts, *d.nd, *d.out});
+            continue;
+        }
+        BatchItem it{};
+        it.G = dev_graph(g);
+        it.NC = g->n_fchunks;
+        it.NV = NV;
+        it.pi_ts = d.pi_ts;
+        it.load = d.nd->load;
+        it.nd = d.nd->net_delay;
+        it.ni = d.nd->net_imp2;
+        it.drv_ts = d.out->drv_ts;
+        it.arc_ts = d.out->arc_ts;
+        it.arc_delay = d.out->arc_delay;
+        it.argmax = d.out->argmax;
+        const int idx = int(items.size());
+        items.push_back(it);
+        for (int v = 0; v < NV; ++v) units.push_back({g->A + 64 * g->L, make_int2(idx, v)});
+    }
+    std::stable_sort(units.begin(), units.end(),
+                     [](const std::pair<int64_t, int2>& x, const std::pair<int64_t, int2>& y) { return x.first > y.first; });
+    std::vector<int2> ulist;
+    for (auto& u : units) ulist.push_back(u.second);
+    uint8_t* base = static_cast<uint8_t*>(workspace);
+    b->d_items = reinterpret_cast<BatchItem*>(base);
+    b->d_units = reinterpret_cast<int2*>(base + align256(sizeof(BatchItem) * size_t(n)));
+    b->d_counter = reinterpret_cast<int*>(base + align256(sizeof(BatchItem) * size_t(n)) +
+                                          align256(sizeof(int2) * size_t(n) * NV));
+    b->n_units = int(ulist.size());
+    if (!items.empty()) {
+        hipError_t e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->d_units, ulist.data(), sizeof(int2) * ulist.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(STA_E_HIP, std::string("sta_batch_create: hipMemcpy: ") + hipGetErrorString(e));
+    }
+    *out = b.release();
+    return STA_OK;
+}
+
+sta_status sta_batch_propagate(sta_batch* b, int32_t use_graph, int32_t persistent_blocks, void* stream) {
+    if (!b) return fail(STA_E_ARG, "sta_batch_propagate: null batch");
+    if (persistent_blocks < 0) return fail(STA_E_ARG, "sta_batch_propagate: negative block count");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int blocks = persistent_blocks;
+    if (blocks == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        blocks = cus;
+    }
+    if (blocks > b->n_units) blocks = b->n_units;
+    auto enqueue = [&](hipStream_t q) {
+        if (b->n_units > 0) {
+            prof_launch("k_zero_i32", q, [&] { hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, q, b->d_counter); });
+            set_lds(k_forward_batch, b->lds);
+            prof_launch("k_forward_batch", q, [&] {
+                hipLaunchKernelGGL(k_forward_batch, dim3(blocks), dim3(kViewThreads), b->lds, q, b->d_items,
+                                   b->d_units, b->n_units, b->d_counter, b->kl, b->kv);
+            });
+        }
+        for (auto& d : b->level_designs) enqueue_levels_nv(b->NV, d.g, b->kl, b->kv, d.pi_ts, &d.nd, &d.out, q);
+    };
+    std::vector<uint64_t> key = {uint64_t(blocks)};
+    const sta_status st = capture_replay(b->cache, b->mu, use_graph != 0, std::move(key), s, enqueue);
+    if (st != STA_OK) return st;
+    return launch_check("sta_batch_propagate");
+}
+
+sta_status sta_batch_info(const sta_batch* b, int32_t* persistent_units, int32_t* level_designs) {
+    if (!b) return fail(STA_E_ARG, "sta_batch_info: null batch");
+    if (persistent_units) *persistent_units = b->n_units;
+    if (level_designs) *level_designs = int32_t(b->level_designs.size());
+    return STA_OK;
+}
+
+void sta_batch_free(sta_batch* b) {
+    if (!b) return;
+    if (b->cache.exec) (void)hipGraphExecDestroy(b->cache.exec);
+    if (b->cache.graph) (void)hipGraphDestroy(b->cache.graph);
+    delete b;
 }
 
 }  // extern "C"

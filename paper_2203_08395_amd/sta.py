@@ -413,3 +413,77 @@ def critical_paths(g: Graph, views: ViewsC, view, k, timing, slack_out):
                                   ctypes.byref(_slackout(slack_out)), ctypes.byref(po), _ptr(scratch), nb,
                                   _stream(torch, dev)), "sta_critical_paths")
     return out
+
+
+# ---- batches of designs (include/sta_batch.h) --------------------------------------------
+
+BATCH_PERSISTENT, BATCH_LEVELS = 0, 1
+BATCH_EXPORTS = ("sta_batch_workspace_bytes", "sta_batch_create", "sta_batch_propagate", "sta_batch_info",
+                 "sta_batch_free")
+
+
+class BatchDesignC(ctypes.Structure):
+    _fields_ = [("g", _P), ("pi_ts", _P), ("nd", ctypes.POINTER(NetOut)), ("out", ctypes.POINTER(TimingOut)),
+                ("schedule", ctypes.c_int32)]
+
+
+_batch_bound = False
+
+
+def _batch_lib():
+    global _batch_bound
+    lib = load_library()
+    if not _batch_bound:
+        lib.sta_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        lib.sta_batch_workspace_bytes.restype = ctypes.c_size_t
+        lib.sta_batch_create.argtypes = [ctypes.POINTER(BatchDesignC), ctypes.c_int32, ctypes.POINTER(LibraryC),
+                                         ctypes.POINTER(ViewsC), _P, ctypes.c_size_t, ctypes.POINTER(_P)]
+        lib.sta_batch_propagate.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _P]
+        lib.sta_batch_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        lib.sta_batch_free.argtypes = [_P]
+        lib.sta_batch_free.restype = None
+        for f in ("sta_batch_create", "sta_batch_propagate", "sta_batch_info"):
+            getattr(lib, f).restype = ctypes.c_int
+        _batch_bound = True
+    return lib
+
+
+class Batch:
+    """Several uploaded graphs sharing one library and view set, propagated together.
+
+    entries: list of (graph, pi_ts tensor, net dict, timing dict, schedule)."""
+
+    def __init__(self, entries, lib: LibraryC, views: ViewsC):
+        import torch
+        blib = _batch_lib()
+        self._keep = []
+        arr = (BatchDesignC * max(len(entries), 1))()
+        for i, (g, pi, nd, tm, sched) in enumerate(entries):
+            no, to = _netout(nd), _timingout(tm)
+            self._keep += [g, pi, nd, tm, no, to]
+            arr[i] = BatchDesignC(g.handle, _ptr(pi), ctypes.pointer(no), ctypes.pointer(to), int(sched))
+        self._arr = arr
+        self.device = entries[0][0].device if entries else torch.device("cuda")
+        nb = blib.sta_batch_workspace_bytes(len(entries), views.n_views)
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        h = _P()
+        self._views, self._lib = views, lib
+        _check(blib.sta_batch_create(arr, len(entries), ctypes.byref(lib), ctypes.byref(views),
+                                     _ptr(self.workspace), nb, ctypes.byref(h)), "sta_batch_create")
+        self._h = h
+
+    def propagate(self, use_graph=True, blocks=0):
+        import torch
+        _check(_batch_lib().sta_batch_propagate(self._h, int(use_graph), int(blocks), _stream(torch, self.device)),
+               "sta_batch_propagate")
+
+    def info(self):
+        u, l_ = ctypes.c_int32(), ctypes.c_int32()
+        _check(_batch_lib().sta_batch_info(self._h, ctypes.byref(u), ctypes.byref(l_)), "sta_batch_info")
+        return {"persistent_units": u.value, "level_designs": l_.value}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.sta_batch_free(h)
+            self._h = None
