@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--surrogate-train-steps", type=int, default=3000)
     ap.add_argument("--batch-designs", type=int, default=64,
                     help="designs of the batched-corners comparison (0: skip it)")
+    ap.add_argument("--only", choices=["surrogate", "batched"], default=None,
+                    help="run one side comparison alone and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (one design on one GPU); "
@@ -70,6 +72,15 @@ def main():
 
     import torch
     from paper_2203_08395_amd import gen, sta
+
+    if args.only:
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        if args.only == "surrogate":
+            print(json.dumps(surrogate_bench(dev, args.surrogate_nets, args.surrogate_train_steps)), flush=True)
+        else:
+            print(json.dumps(batch_bench(dev, args.batch_designs)), flush=True)
+        return
 
     name = args.workload
     cfg = gen.CONFIGS[name]

@@ -175,53 +175,160 @@ __global__ __launch_bounds__(NT) void k_tree_dataset(sta_trees T, float* __restr
     }
 }
 
-// Exact delay/slew of every net (list == nullptr) or of the listed nets.  Two FP64
-// arrays per node: B holds C, then Cd (in place), then C*m1, its downstream sum and m2
-// (each in place); M holds m1.  C is rebuilt from the inputs rather than kept.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_tree_exact(sta_trees T, const int32_t* __restrict__ list,
-                                                   const int32_t* __restrict__ count, float* __restrict__ delay,
-                                                   float* __restrict__ slew, int32_t* status) {
-    __shared__ double sB[kMaxN * NT];
-    __shared__ double sM[kMaxN * NT];
-    const int t = threadIdx.x;
-    const int i = blockIdx.x * NT + t;
+#undef NODE
+
+// LDS ordering among the lanes of one wavefront (the wave's LDS operations complete in
+// order once waited for; no workgroup barrier, since waves of a block work on different nets)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+constexpr int kExactWaves = 4;     // nets per 256-lane block, one per wavefront
+
+// Exact delay/slew of every net (list == nullptr) or of the listed nets.  One wavefront
+// per net, lane k = local node k.  Depths by pointer doubling; downstream sums in rounds
+// of decreasing depth, each node adding its children in descending index order (the
+// order of the sequential definition, so the FP64 results are the same bit for bit);
+// prefix sums (m1, m2) in rounds of increasing depth.
+__global__ __launch_bounds__(256) void k_tree_exact(sta_trees T, const int32_t* __restrict__ list,
+                                                    const int32_t* __restrict__ count, float* __restrict__ delay,
+                                                    float* __restrict__ slew, int32_t* status) {
+    __shared__ double s_sum[kExactWaves][kMaxN];    // Cd, later C*m1 summed downstream
+    __shared__ double s_m1[kExactWaves][kMaxN];
+    __shared__ double s_m2[kExactWaves][kMaxN];
+    __shared__ unsigned long long s_ch[kExactWaves][kMaxN];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * kExactWaves + wv;
     int n = i;
     if (list) {
         if (i >= *count) return;
         n = list[i];
         if (n < 0 || n >= T.n_nets) {
-            flag_err(status, STA_TREE_ERR_SIZE);
+            if (lane == 0) flag_err(status, STA_TREE_ERR_SIZE);
             return;
         }
     } else if (i >= T.n_nets) {
         return;
     }
-    int n0, nm, s0, s1;
-    if (!net_ok(T, n, n0, nm, s0, s1, status)) return;
-    const int32_t* par = T.node_parent + n0;
-    const float* R = T.node_R + n0;
-    double* B = sB + t;
-    double* M = sM + t;
-    node_caps<NT>(T, n0, nm, s0, s1, B);
-    up_sum<NT>(par, nm, B);
-    down_sum<NT>(par, R, nm, B, M);
-    node_caps<NT>(T, n0, nm, s0, s1, B);
-    for (int k = 0; k < nm; ++k) NODE(B, k) *= NODE(M, k);
-    up_sum<NT>(par, nm, B);
-    down_sum<NT>(par, R, nm, B, B);
+    const int n0 = T.net_node_ptr[n];
+    const int nm = T.net_node_ptr[n + 1] - n0;
+    const int s0 = T.sink_ptr[n], s1 = T.sink_ptr[n + 1];
+    if (nm < 1 || nm > kMaxN || s1 < s0) {
+        if (lane == 0) flag_err(status, STA_TREE_ERR_SIZE);
+        return;
+    }
+    const bool act = lane < nm;
+    const int p = (act && lane > 0) ? T.node_parent[n0 + lane] : 0;
+    if (__ballot(act && lane > 0 && (p < 0 || p >= lane))) {
+        if (lane == 0) flag_err(status, STA_TREE_ERR_PARENT);
+        return;
+    }
+    const float Rk = act ? T.node_R[n0 + lane] : 0.0f;
+    double Ck = act ? static_cast<double>(T.node_C[n0 + lane]) : 0.0;
+    // sinks 64 at a time: one coalesced load per lane, then the pin caps are added to
+    // their nodes in ascending sink order by broadcasting each sink from its lane
+    for (int c = s0; c < s1; c += 64) {
+        const bool sv = c + lane < s1;
+        const int k = sv ? T.sink_node[c + lane] : 0;
+        const float cap = sv ? T.sink_pincap[c + lane] : 0.0f;
+        if (__ballot(k < 0 || k >= nm)) {
+            if (lane == 0) flag_err(status, STA_TREE_ERR_SINK);
+            return;
+        }
+        const int ns = min(64, s1 - c);
+        for (int j = 0; j < ns; ++j) {
+            const int kj = __builtin_amdgcn_readlane(k, j);
+            const float cj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cap), j));
+            if (kj == lane) Ck += static_cast<double>(cj);
+        }
+    }
+    s_ch[wv][lane] = 0ull;
+    s_m1[wv][lane] = 0.0;
+    s_m2[wv][lane] = 0.0;
+    wave_sync();
+    if (act && lane > 0) atomicOr(&s_ch[wv][p], 1ull << lane);
+    // depth by pointer doubling (depth < 64)
+    int anc = p, dep = (act && lane > 0) ? 1 : 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        const int da = __shfl(dep, anc);
+        const int aa = __shfl(anc, anc);
+        dep += da;
+        anc = aa;
+    }
+    const int maxd = wave_max_i32(dep);
+    wave_sync();
+    const unsigned long long ch = s_ch[wv][lane];
+    // Cd: downstream sums, children in descending index order
+    double cd = Ck;
+    for (int r = maxd; r >= 0; --r) {
+        if (act && dep == r) {
+            double acc = Ck;
+            unsigned long long m = ch;
+            while (m) {
+                const int c = 63 - __clzll(static_cast<long long>(m));
+                acc += s_sum[wv][c];
+                m &= ~(1ull << c);
+            }
+            cd = acc;
+            s_sum[wv][lane] = acc;
+        }
+        wave_sync();
+    }
+    double m1 = 0.0;
+    for (int r = 1; r <= maxd; ++r) {
+        if (act && dep == r) {
+            m1 = s_m1[wv][p] + (static_cast<double>(Rk) * cd) * 1e-3;
+            s_m1[wv][lane] = m1;
+        }
+        wave_sync();
+    }
+    const double w0 = Ck * m1;
+    double wd = w0;
+    for (int r = maxd; r >= 0; --r) {
+        if (act && dep == r) {
+            double acc = w0;
+            unsigned long long m = ch;
+            while (m) {
+                const int c = 63 - __clzll(static_cast<long long>(m));
+                acc += s_sum[wv][c];
+                m &= ~(1ull << c);
+            }
+            wd = acc;
+            s_sum[wv][lane] = acc;
+        }
+        wave_sync();
+    }
+    for (int r = 1; r <= maxd; ++r) {
+        if (act && dep == r) s_m2[wv][lane] = s_m2[wv][p] + (static_cast<double>(Rk) * wd) * 1e-3;
+        wave_sync();
+    }
     const float S = T.drv_slew[n];
-    for (int s = s0; s < s1; ++s) {
-        const int k = T.sink_node[s];
-        float d, sl;
-        double imp2;
-        sink_out(NODE(M, k), NODE(B, k), S, d, sl, imp2);
-        delay[s] = d;
-        slew[s] = sl;
+    for (int c = s0; c < s1; c += 64) {
+        const int s = c + lane;
+        if (s < s1) {
+            const int k = T.sink_node[s];
+            float d, sl;
+            double imp2;
+            sink_out(s_m1[wv][k], s_m2[wv][k], S, d, sl, imp2);
+            delay[s] = d;
+            slew[s] = sl;
+        }
     }
 }
 
-#undef NODE
 
 __global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -562,14 +669,23 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ P, co
     }
 }
 
-// Sum of the per-wave partials in wave order; optional gradient output; optional Adam.
-__global__ void k_mlp_adam(float* __restrict__ P, float* __restrict__ m, float* __restrict__ v,
-                           const float* __restrict__ part, int32_t waves, float* __restrict__ grad, int32_t adam,
-                           float lr, float b1, float b2, float eps, float bc1, float bc2) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > STA_MLP_PARAMS) return;
+// Sum of the per-wave partials (four interleaved groups of waves per parameter, each in
+// wave order, then the groups in order: a fixed order); optional gradient output;
+// optional Adam.  64 parameters per 256-lane block.
+__global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ P, float* __restrict__ m, float* __restrict__ v,
+                                                  const float* __restrict__ part, int32_t waves,
+                                                  float* __restrict__ grad, int32_t adam, float lr, float b1, float b2,
+                                                  float eps, float bc1, float bc2) {
+    __shared__ float red[4][64];
+    const int pl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + pl;
     float gs = 0.0f;
-    for (int w = 0; w < waves; ++w) gs += part[static_cast<size_t>(w) * kPartStride + p];
+    if (p <= STA_MLP_PARAMS)
+        for (int w = grp; w < waves; w += 4) gs += part[static_cast<size_t>(w) * kPartStride + p];
+    red[grp][pl] = gs;
+    __syncthreads();
+    if (grp != 0 || p > STA_MLP_PARAMS) return;
+    gs = ((red[0][pl] + red[1][pl]) + red[2][pl]) + red[3][pl];
     if (grad) grad[p] = gs;
     if (!adam || p == STA_MLP_PARAMS) return;
     const float mm = b1 * m[p] + (1.0f - b1) * gs;
@@ -742,10 +858,9 @@ sta_status sta_tree_exact(const sta_trees* t, const int32_t* net_list, const int
     if (t->n_sinks > 0 && (!delay || !slew)) return fail(STA_E_ARG, "sta_tree_exact: null output");
     if (t->n_nets == 0) return STA_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    constexpr int NT = 64;
     prof_launch("k_tree_exact", s, [&] {
-        hipLaunchKernelGGL((k_tree_exact<NT>), dim3((t->n_nets + NT - 1) / NT), dim3(NT), 0, s, *t, net_list,
-                           net_count, delay, slew, status);
+        hipLaunchKernelGGL(k_tree_exact, dim3((t->n_nets + kExactWaves - 1) / kExactWaves), dim3(256), 0, s, *t,
+                           net_list, net_count, delay, slew, status);
     });
     return launch_check("sta_tree_exact");
 }
@@ -801,7 +916,7 @@ sta_status sta_mlp_train_step(float* params, float* adam_m, float* adam_v, const
         bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(b2), opt->step));
     }
     prof_launch("k_mlp_adam", s, [&] {
-        hipLaunchKernelGGL(k_mlp_adam, dim3((STA_MLP_PARAMS + 1 + 255) / 256), dim3(256), 0, s, params, adam_m,
+        hipLaunchKernelGGL(k_mlp_adam, dim3((STA_MLP_PARAMS + 1 + 63) / 64), dim3(256), 0, s, params, adam_m,
                            adam_v, part, waves, grad, opt ? 1 : 0, lr, b1, b2, eps, bc1, bc2);
     });
     return launch_check("sta_mlp_train_step");
@@ -879,10 +994,9 @@ sta_status sta_surrogate_eval(const sta_trees* t, const float* params, const flo
     prof_launch("k_sur_compact", s, [&] {
         hipLaunchKernelGGL(k_sur_compact, dim3((nn + 255) / 256), dim3(256), 0, s, net_flag, nn, net_list, net_count);
     });
-    constexpr int NT = 64;
     prof_launch("k_tree_exact", s, [&] {
-        hipLaunchKernelGGL((k_tree_exact<NT>), dim3((nn + NT - 1) / NT), dim3(NT), 0, s, *t, net_list, net_count,
-                           delay, slew, status);
+        hipLaunchKernelGGL(k_tree_exact, dim3((nn + kExactWaves - 1) / kExactWaves), dim3(256), 0, s, *t, net_list,
+                           net_count, delay, slew, status);
     });
     return launch_check("sta_surrogate_eval");
 }
