@@ -229,6 +229,23 @@ def main():
                  "graph_bytes": s["graph_bytes"]},
     }
 
+    # cold caches: a 1 GiB write between steps evicts L2 and the 256 MB Infinity Cache;
+    # and a plain 1 GiB device copy as the achievable-bandwidth reference
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cold = []
+    for _ in range(3):
+        flush.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        step()
+        e1.record()
+        torch.cuda.synchronize()
+        cold.append(e0.elapsed_time(e1))
+    dst = torch.empty_like(flush)
+    ms_copy = _time_ms(lambda: dst.copy_(flush), reps=5)
+    out["cold_ms_per_step"] = float(np.median(cold))
+    out["copy_GB_s"] = 2 * flush.numel() * 4 / (ms_copy * 1e-3) / 1e9
+    del flush, dst
     # analyses on the same timed design: TNS adjoint (both views) and the 64 worst paths
     adj = sta.alloc_adjoint(g, V)
     out["adjoint"] = {"ms": _time_ms(lambda: sta.tns_adjoint(g, L_lib, views, nd, tm, sl, out=adj)),

@@ -70,7 +70,8 @@ extern "C" {
    local node 0 is the driver (its R is ignored), local node k > 0 hangs below local node
    node_parent[k] < k through resistance node_R[k] (ohm) and carries wire cap node_C[k]
    (fF).  Sinks sink_ptr[n] .. sink_ptr[n+1]-1 tap local node sink_node[s] with pin cap
-   sink_pincap[s]; sink_net[s] = n.  drv_slew[n] is the driver's output slew (ps).
+   sink_pincap[s]; sink_net[s] = n (optional, not read by the kernels).  drv_slew[n] is the
+   driver's output slew (ps).
    Values must be finite and non-negative (the kernels do not check values). */
 typedef struct {
     int32_t n_nets;
@@ -139,11 +140,13 @@ sta_status sta_surrogate_calibrate(const float* feat, const float* target, const
 
 /* The surrogate path: network, decode and error bound for every sink; nets with an
    untrusted sink are listed (net_list, *net_count; order unspecified) and recomputed
-   exactly.  delay/slew: [S]; net_flag: [n_nets] int32 scratch; net_list: [n_nets];
+   exactly.  delay/slew: [S]; sink_flag: [S] uint8 scratch (1 = untrusted sink);
+   net_flag: [n_nets] int32 output (1 = recomputed exactly); net_list: [n_nets];
    net_count: one device int32. */
 sta_status sta_surrogate_eval(const sta_trees* t, const float* params, const float* norm, const float* calib,
-                              const float* feat, float tol_ps, float* delay, float* slew, int32_t* net_flag,
-                              int32_t* net_list, int32_t* net_count, int32_t* status, void* stream);
+                              const float* feat, float tol_ps, float* delay, float* slew, uint8_t* sink_flag,
+                              int32_t* net_flag, int32_t* net_list, int32_t* net_count, int32_t* status,
+                              void* stream);
 
 #ifdef __cplusplus
 }

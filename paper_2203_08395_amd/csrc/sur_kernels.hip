@@ -335,10 +335,16 @@ __global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void k_sur_compact(const int32_t* __restrict__ flag, int32_t n, int32_t* __restrict__ list,
+// net flag = any untrusted sink; flagged nets are appended to the list (order unspecified)
+__global__ void k_sur_compact(const int32_t* __restrict__ sink_ptr, const uint8_t* __restrict__ sink_flag, int32_t n,
+                              int32_t* __restrict__ net_flag, int32_t* __restrict__ list,
                               int32_t* __restrict__ count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && flag[i]) list[atomicAdd(count, 1)] = i;
+    if (i >= n) return;
+    int f = 0;
+    for (int s = sink_ptr[i]; s < sink_ptr[i + 1]; ++s) f |= sink_flag[s];
+    net_flag[i] = f;
+    if (f) list[atomicAdd(count, 1)] = i;
 }
 
 // ---------------------------------------------------------------------------------
@@ -466,6 +472,42 @@ __device__ __forceinline__ v4s load_x(const float* __restrict__ feat, const floa
         const float v[4] = {f.x, f.y, f.z, f.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) x[j] = bf16r((logf(v[j] + 1.0f) - norm[4 * g + j]) * norm[12 + 4 * g + j]);
+    }
+    return x;
+}
+
+// raw features 4g..4g+3 of sample s (zeros for g == 3 or past the end).  The load is
+// unconditional from a clamped, always valid address and its value is always used (masked
+// by a multiply), so the compiler keeps it branch-free and it can be issued ahead of its use.
+__device__ __forceinline__ float4 load_feat(const float* __restrict__ feat, int g, int s, bool valid, int n) {
+    const int sc = s < n ? s : n - 1;
+    const int gc = g < 3 ? g : 2;
+    const float4 f = *reinterpret_cast<const float4*>(feat + static_cast<size_t>(sc) * 12 + 4 * gc);
+    const float w = (g < 3 && valid) ? 1.0f : 0.0f;
+    return make_float4(f.x * w, f.y * w, f.z * w, f.w * w);
+}
+
+// this lane's normalization constants (features 4g..4g+3), loaded once per wave
+struct NormL {
+    float mu[4], rs[4];
+};
+
+__device__ __forceinline__ NormL load_norm(const float* __restrict__ norm, int g) {
+    NormL q;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        q.mu[j] = g < 3 ? norm[4 * g + j] : 0.0f;
+        q.rs[j] = g < 3 ? norm[12 + 4 * g + j] : 0.0f;
+    }
+    return q;
+}
+
+__device__ __forceinline__ v4s make_x(const NormL& q, int g, float4 f) {
+    v4s x = {0, 0, 0, 0};
+    if (g < 3) {
+        const float v[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = bf16r((logf(v[j] + 1.0f) - q.mu[j]) * q.rs[j]);
     }
     return x;
 }
@@ -704,14 +746,31 @@ __global__ __launch_bounds__(256) void k_mlp_predict(const float* __restrict__ P
     load_wf(P, g, r, W);
     const int tiles = (n + 15) / 16;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    for (int tile = wave; tile < tiles; tile += gridDim.x * 4) {
-        const int s = tile * 16 + r;
-        const bool valid = s < n;
-        float4 f;
-        const v4s x = load_x(feat, norm, g, static_cast<size_t>(valid ? s : 0), valid, f);
+    const int stride = gridDim.x * 4;
+    const NormL q = load_norm(norm, g);
+    // features are loaded three tiles ahead of their use, in three registers with fixed
+    // roles (a manual unroll by three, so no register is copied while its load is in flight)
+    auto ahead = [&](int t) { return load_feat(feat, g, t * 16 + r, t < tiles && t * 16 + r < n, n); };
+    auto tile_step = [&](int tile, float4& pr) {
+        const float4 f = pr;
+        pr = ahead(tile + 3 * stride);
+        const v4s x = make_x(q, g, f);
         Fwd F;
         forward(W, x, F);
-        if (g == 0 && valid) *reinterpret_cast<float2*>(y + 2 * static_cast<size_t>(s)) = make_float2(F.y[0], F.y[1]);
+        // every lane stores (group 0's values; past the end, the last sample's again), so no
+        // store sits in a branch and the waits for later tiles can leave stores in flight
+        const int last = n - 1 - tile * 16;
+        const int re = r < last ? r : last;
+        const float y0 = __shfl(F.y[0], re), y1 = __shfl(F.y[1], re);
+        *reinterpret_cast<float2*>(y + 2 * static_cast<size_t>(tile * 16 + re)) = make_float2(y0, y1);
+    };
+    float4 p0 = ahead(wave), p1 = ahead(wave + stride), p2 = ahead(wave + 2 * stride);
+    for (int tile = wave; tile < tiles; tile += 3 * stride) {
+        tile_step(tile, p0);
+        if (tile + stride >= tiles) break;
+        tile_step(tile + stride, p1);
+        if (tile + 2 * stride >= tiles) break;
+        tile_step(tile + 2 * stride, p2);
     }
 }
 
@@ -733,7 +792,7 @@ __device__ __forceinline__ int err_bucket(float e) {
 __global__ __launch_bounds__(256) void k_sur_eval(sta_trees T, const float* __restrict__ P,
                                                   const float* __restrict__ norm, const float* __restrict__ calib,
                                                   const float* __restrict__ feat, float tol, float* __restrict__ delay,
-                                                  float* __restrict__ slew, int32_t* __restrict__ net_flag) {
+                                                  float* __restrict__ slew, uint8_t* __restrict__ sink_flag) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     Wf W;
@@ -741,37 +800,52 @@ __global__ __launch_bounds__(256) void k_sur_eval(sta_trees T, const float* __re
     const int n = T.n_sinks;
     const int tiles = (n + 15) / 16;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    for (int tile = wave; tile < tiles; tile += gridDim.x * 4) {
-        const int s = tile * 16 + r;
-        const bool valid = s < n;
-        float4 f;
-        const v4s x = load_x(feat, norm, g, static_cast<size_t>(valid ? s : 0), valid, f);
+    const int stride = gridDim.x * 4;
+    const NormL q = load_norm(norm, g);
+    auto ahead = [&](int t) { return load_feat(feat, g, t * 16 + r, t < tiles && t * 16 + r < n, n); };
+    auto tile_step = [&](int tile, float4& pr) {
+        const float4 f = pr;
+        pr = ahead(tile + 3 * stride);
+        const v4s x = make_x(q, g, f);
         Fwd F;
         forward(W, x, F);
         const float msize = __shfl(f.x, r + 16);    // feature 4, held by lane group 1
         const float S = __shfl(f.w, r + 32);        // feature 11, held by lane group 2
-        if (g == 0 && valid) {
-            // alpha is clamped into [0, 1] (the Elmore bounds hold for every RC tree); the
-            // calibrated bound is used when it beats the bound-midpoint estimate's 1/2
-            const int bin = cal_bin(f.w, msize);
-            const float qa = calib[2 * bin], qg = calib[2 * bin + 1];
-            float a = fminf(fmaxf(F.y[0], 0.0f), 1.0f);
-            float qd = fminf(qa, fmaxf(a, 1.0f - a));
-            if (!(qa <= 0.5f)) {
-                a = 0.5f;
-                qd = 0.5f;
-            }
-            const float gm = fmaxf(F.y[1], 0.0f);
-            const float L = (f.x * f.z) * 1e-3f;
-            const float U = (f.x * f.y) * 1e-3f;
-            const float d = L + a * (U - L);
-            const float gg = gm * U;
-            const float sl = sqrtf(S * S + gg * gg);
-            const bool ok = (qd * (U - L) <= tol) && (qg * U <= tol);
-            delay[s] = d;
-            slew[s] = sl;
-            if (!ok) net_flag[T.sink_net[s]] = 1;
+        // computed on every lane, meaningful on lane group 0 (features 0..3).  Alpha is
+        // clamped into [0, 1] (the Elmore bounds hold for every RC tree); the calibrated
+        // bound is used when it beats the bound-midpoint estimate's 1/2
+        const int bin = cal_bin(f.w, msize);
+        const float qa = calib[2 * bin], qg = calib[2 * bin + 1];
+        float a = fminf(fmaxf(F.y[0], 0.0f), 1.0f);
+        float qd = fminf(qa, fmaxf(a, 1.0f - a));
+        if (!(qa <= 0.5f)) {
+            a = 0.5f;
+            qd = 0.5f;
         }
+        const float gm = fmaxf(F.y[1], 0.0f);
+        const float L = (f.x * f.z) * 1e-3f;
+        const float U = (f.x * f.y) * 1e-3f;
+        const float d = L + a * (U - L);
+        const float gg = gm * U;
+        const float sl = sqrtf(S * S + gg * gg);
+        const int bad = ((qd * (U - L) <= tol) && (qg * U <= tol)) ? 0 : 1;
+        // unconditional stores from every lane (see k_mlp_predict)
+        const int last = n - 1 - tile * 16;
+        const int re = r < last ? r : last;
+        const float dv = __shfl(d, re), sv = __shfl(sl, re);
+        const int bv = __shfl(bad, re);
+        const size_t so = static_cast<size_t>(tile * 16 + re);
+        delay[so] = dv;
+        slew[so] = sv;
+        sink_flag[so] = static_cast<uint8_t>(bv);
+    };
+    float4 p0 = ahead(wave), p1 = ahead(wave + stride), p2 = ahead(wave + 2 * stride);
+    for (int tile = wave; tile < tiles; tile += 3 * stride) {
+        tile_step(tile, p0);
+        if (tile + stride >= tiles) break;
+        tile_step(tile + stride, p1);
+        if (tile + 2 * stride >= tiles) break;
+        tile_step(tile + 2 * stride, p2);
     }
 }
 
@@ -968,12 +1042,13 @@ sta_status sta_surrogate_calibrate(const float* feat, const float* target, const
 }
 
 sta_status sta_surrogate_eval(const sta_trees* t, const float* params, const float* norm, const float* calib,
-                              const float* feat, float tol_ps, float* delay, float* slew, int32_t* net_flag,
-                              int32_t* net_list, int32_t* net_count, int32_t* status, void* stream) {
+                              const float* feat, float tol_ps, float* delay, float* slew, uint8_t* sink_flag,
+                              int32_t* net_flag, int32_t* net_list, int32_t* net_count, int32_t* status,
+                              void* stream) {
     std::string why;
-    if (!trees_ok(t, true, why)) return fail(STA_E_ARG, "sta_surrogate_eval: " + why);
+    if (!trees_ok(t, false, why)) return fail(STA_E_ARG, "sta_surrogate_eval: " + why);
     if (!params || !norm || !calib || !net_count || (t->n_nets > 0 && (!net_flag || !net_list)) ||
-        (t->n_sinks > 0 && (!feat || !delay || !slew)))
+        (t->n_sinks > 0 && (!feat || !delay || !slew || !sink_flag)))
         return fail(STA_E_ARG, "sta_surrogate_eval: bad arguments");
     if (!aligned16(feat)) return fail(STA_E_ARG, "sta_surrogate_eval: feat must be 16-byte aligned");
     if (!(tol_ps >= 0.0f)) return fail(STA_E_ARG, "sta_surrogate_eval: tol_ps must be >= 0");
@@ -983,16 +1058,14 @@ sta_status sta_surrogate_eval(const sta_trees* t, const float* params, const flo
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, net_count, 1, 0);
     });
     if (nn == 0) return launch_check("sta_surrogate_eval");
-    prof_launch("k_fill_i32", s, [&] {
-        hipLaunchKernelGGL(k_fill_i32, dim3((nn + 255) / 256), dim3(256), 0, s, net_flag, nn, 0);
-    });
     if (t->n_sinks > 0)
         prof_launch("k_sur_eval", s, [&] {
             hipLaunchKernelGGL(k_sur_eval, dim3(stream_waves_grid(t->n_sinks)), dim3(256), 0, s, *t, params, norm,
-                               calib, feat, tol_ps, delay, slew, net_flag);
+                               calib, feat, tol_ps, delay, slew, sink_flag);
         });
     prof_launch("k_sur_compact", s, [&] {
-        hipLaunchKernelGGL(k_sur_compact, dim3((nn + 255) / 256), dim3(256), 0, s, net_flag, nn, net_list, net_count);
+        hipLaunchKernelGGL(k_sur_compact, dim3((nn + 255) / 256), dim3(256), 0, s, t->sink_ptr, sink_flag, nn,
+                           net_flag, net_list, net_count);
     });
     prof_launch("k_tree_exact", s, [&] {
         hipLaunchKernelGGL(k_tree_exact, dim3((nn + kExactWaves - 1) / kExactWaves), dim3(256), 0, s, *t, net_list,

@@ -56,7 +56,7 @@ def _lib():
         lib.sta_surrogate_cal_scratch_bytes.restype = sz
         lib.sta_surrogate_calibrate.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                                 _P, sz, _P]
-        lib.sta_surrogate_eval.argtypes = [T, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P, _P, _P]
+        lib.sta_surrogate_eval.argtypes = [T, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P, _P, _P, _P]
         for f in ("sta_tree_dataset", "sta_tree_exact", "sta_mlp_norm", "sta_mlp_train_step", "sta_mlp_predict",
                   "sta_surrogate_calibrate", "sta_surrogate_eval"):
             getattr(lib, f).restype = ctypes.c_int
@@ -246,6 +246,7 @@ class EvalBuffers:
         d = tr.device
         self.delay = torch.empty(tr.n_sinks, dtype=torch.float32, device=d)
         self.slew = torch.empty(tr.n_sinks, dtype=torch.float32, device=d)
+        self.sink_flag = torch.empty(max(tr.n_sinks, 1), dtype=torch.uint8, device=d)
         self.flag = torch.empty(max(tr.n_nets, 1), dtype=torch.int32, device=d)
         self.list = torch.empty(max(tr.n_nets, 1), dtype=torch.int32, device=d)
         self.count = torch.zeros(1, dtype=torch.int32, device=d)
@@ -257,7 +258,8 @@ def evaluate(tr: Trees, model: Model, feat, tol_ps=1.0, buf: EvalBuffers = None)
         raise ValueError("the model has no calibration")
     buf = buf or EvalBuffers(tr)
     _check(_lib().sta_surrogate_eval(ctypes.byref(tr.c), _ptr(model.params), _ptr(model.norm), _ptr(model.calib),
-                                     _ptr(feat), float(tol_ps), _ptr(buf.delay), _ptr(buf.slew), _ptr(buf.flag),
+                                     _ptr(feat), float(tol_ps), _ptr(buf.delay), _ptr(buf.slew), _ptr(buf.sink_flag),
+                                     _ptr(buf.flag),
                                      _ptr(buf.list), _ptr(buf.count), _ptr(tr.status), tr.stream()),
            "sta_surrogate_eval")
     return buf
