@@ -55,8 +55,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="first run one plain device copy of MB megabytes (a known-size reference "
                          "dispatch for HBM byte counters)")
-    ap.add_argument("--schedule", choices=["auto", "level", "level_plain", "view"], default="auto",
-                    help="auto: the library's choice by level width; level_plain: no hipGraph replay")
+    ap.add_argument("--schedule", choices=["auto", "span", "level", "level_plain", "view"], default="auto",
+                    help="auto: the library's choice (fused spans for wide levels); level: one launch per "
+                         "level; level_plain: the same without hipGraph replay")
     ap.add_argument("--surrogate-nets", type=int, default=1_000_000,
                     help="RC-tree nets of the learned-surrogate comparison (0: skip it)")
     ap.add_argument("--surrogate-train-steps", type=int, default=3000)
@@ -98,6 +99,7 @@ def main():
     t_build = time.perf_counter() - t0
     if args.schedule != "auto":
         g.set_schedule(1 << 30 if args.schedule == "view" else 0, args.schedule != "level_plain")
+        g.set_level_fusion(args.schedule == "span")
     t0 = time.perf_counter()
     g.upload(dev)
     torch.cuda.synchronize()
@@ -224,7 +226,8 @@ def main():
         "kernels": kernels,
         "algorithmic_bytes_per_step": fam_bytes,
         "pass_GB_s": sum(fam_bytes.values()) / (ms_step * 1e-3) / 1e9,
-        "schedule": ("view" if "k_forward_view" in kstats else "level") + ("" if args.schedule == "auto" else f" (forced {args.schedule})"),
+        "schedule": ("view" if "k_forward_view" in kstats else "span" if "k_forward_span" in kstats else "level")
+                    + ("" if args.schedule == "auto" else f" (forced {args.schedule})"),
         "host": {"generate_s": t_gen, "build_graph_s": t_build, "upload_s": t_upload,
                  "graph_bytes": s["graph_bytes"]},
     }

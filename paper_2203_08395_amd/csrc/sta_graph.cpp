@@ -50,6 +50,11 @@ DevGraph dev_graph(const sta_graph* g) {
     d.ftile_maxk = reinterpret_cast<const int32_t*>(b + L.ftile_maxk);
     d.fwd_chunk = reinterpret_cast<const int32_t*>(b + L.fwd_chunk);
     d.bwd_chunk = reinterpret_cast<const int32_t*>(b + L.bwd_chunk);
+    d.sp_tile = reinterpret_cast<const int32_t*>(b + L.sp_tile);
+    d.sp_chunk = reinterpret_cast<const int32_t*>(b + L.sp_chunk);
+    d.sp_ta_arc = reinterpret_cast<const int32_t*>(b + L.sp_ta_arc);
+    d.sp_ta_src = reinterpret_cast<const int32_t*>(b + L.sp_ta_src);
+    d.sp_ta_gate = reinterpret_cast<const int32_t*>(b + L.sp_ta_gate);
     d.n_pi = g->n_pi;
     d.n_gates = g->n_gates;
     d.n_drivers = static_cast<int32_t>(g->D);
@@ -349,6 +354,129 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
         }
     }
 
+
+    // ---- fused forward spans -------------------------------------------------------------
+    // Span s covers gate levels [1 + s*kSpan, (s+1)*kSpan].  A span tile computes, level by
+    // level inside one wavefront, a set of gates closed under in-span fanin: every in-span
+    // driver of a tile gate is itself in the tile (so it may be computed by several tiles,
+    // identically).  Roots are taken top level first; a tile holds <= 64 arcs per level.
+    std::vector<int32_t> sp_tile, sp_chunk, sp_ta_arc, sp_ta_src, sp_ta_gate;
+    {
+        const int32_t NS = (Lmax + kSpan - 1) / kSpan;
+        g->span_tile_h.assign(NS + 1, 0);
+        g->span_fused_h.assign(std::max<int32_t>(NS, 1), 0);
+        std::vector<int32_t> gate_lv(G);
+        for (int32_t l = 1; l <= Lmax; ++l)
+            for (int32_t q = lvl_gate_ptr[l - 1]; q < lvl_gate_ptr[l]; ++q) gate_lv[q] = l;
+        std::vector<int32_t> mark(G, -1), slot_of(G, -1);
+        std::vector<uint8_t> covered(G, 0);
+        std::vector<int32_t> stack, cone;
+        std::vector<int32_t> tile_mark(G, -1);   // id of the tile being filled that holds the gate
+        int32_t tile_id = 0;                      // unique per filled tile (never reused)
+        for (int32_t s_ = 0; s_ < NS; ++s_) {
+            g->span_tile_h[s_] = int32_t(sp_tile.size() / 4);
+            const int32_t l0 = 1 + s_ * kSpan, l1 = std::min<int32_t>(Lmax, l0 + kSpan - 1);
+            const int32_t q0 = lvl_gate_ptr[l0 - 1], q1 = lvl_gate_ptr[l1];
+            auto in_span = [&](int32_t u) { return u >= P && (u - P) >= q0 && (u - P) < q1; };
+            bool ok = true;
+            // the tile being filled: gates per level in insertion order, arcs per level
+            std::vector<std::vector<int32_t>> tg(kSpan);
+            int32_t tarcs[kSpan] = {};
+            auto flush = [&]() {
+                bool any = false;
+                for (int j = 0; j < kSpan; ++j) any = any || !tg[j].empty();
+                if (!any) return;
+                const int32_t c0 = int32_t(sp_chunk.size() / 4);
+                int32_t slot = 0;
+                for (int j = 0; j < kSpan; ++j)
+                    for (int32_t q : tg[j]) slot_of[q] = slot++;
+                int32_t nch = 0;
+                for (int j = 0; j < kSpan; ++j) {
+                    if (tg[j].empty()) continue;
+                    const int32_t ta0 = int32_t(sp_ta_arc.size());
+                    int32_t maxk = 0;
+                    for (int32_t q : tg[j]) {
+                        maxk = std::max(maxk, gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q]);
+                        for (int32_t a = gate_arc_ptr_int[q]; a < gate_arc_ptr_int[q + 1]; ++a) {
+                            const int32_t u = arc_src[a];
+                            sp_ta_arc.push_back(a);
+                            sp_ta_src.push_back(in_span(u) ? -1 - slot_of[u - P] : u);
+                            sp_ta_gate.push_back(q);
+                        }
+                    }
+                    sp_chunk.insert(sp_chunk.end(), {ta0, int32_t(sp_ta_arc.size()) - ta0, slot_of[tg[j][0]], maxk});
+                    ++nch;
+                }
+                sp_tile.insert(sp_tile.end(), {c0, nch, 0, slot});
+                for (int j = 0; j < kSpan; ++j) { tg[j].clear(); tarcs[j] = 0; }
+                ++tile_id;
+            };
+            for (int32_t l = l1; l >= l0 && ok; --l) {
+                for (int32_t r = lvl_gate_ptr[l - 1]; r < lvl_gate_ptr[l] && ok; ++r) {
+                    if (covered[r]) continue;
+                    // cone of r: r and its in-span ancestors
+                    cone.clear();
+                    stack.assign(1, r);
+                    mark[r] = r;
+                    while (!stack.empty()) {
+                        const int32_t q = stack.back();
+                        stack.pop_back();
+                        cone.push_back(q);
+                        for (int32_t a = gate_arc_ptr_int[q]; a < gate_arc_ptr_int[q + 1]; ++a) {
+                            const int32_t u = arc_src[a];
+                            if (in_span(u) && mark[u - P] != r) { mark[u - P] = r; stack.push_back(u - P); }
+                        }
+                    }
+                    // arcs the cone adds to the current tile, per level
+                    int32_t add[kSpan] = {}, alone[kSpan] = {};
+                    for (int32_t q : cone) {
+                        const int32_t k = gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q];
+                        alone[gate_lv[q] - l0] += k;
+                        if (tile_mark[q] != tile_id) add[gate_lv[q] - l0] += k;
+                    }
+                    bool fits = true, fits_alone = true;
+                    for (int j = 0; j < kSpan; ++j) {
+                        fits = fits && tarcs[j] + add[j] <= kTileSlots;
+                        fits_alone = fits_alone && alone[j] <= kTileSlots;
+                    }
+                    if (!fits_alone) { ok = false; break; }
+                    if (!fits) {
+                        flush();
+                        for (int j = 0; j < kSpan; ++j) add[j] = alone[j];
+                    }
+                    // insert in ascending gate order per level (drivers precede users: lower level)
+                    std::sort(cone.begin(), cone.end());
+                    for (int32_t q : cone) {
+                        if (tile_mark[q] == tile_id) continue;
+                        tile_mark[q] = tile_id;
+                        tg[gate_lv[q] - l0].push_back(q);
+                        covered[q] = 1;
+                    }
+                    for (int j = 0; j < kSpan; ++j) tarcs[j] += add[j];
+                }
+            }
+            if (ok) {
+                flush();
+                g->span_fused_h[s_] = 1;
+            } else {
+                // roll back this span's tiles: it runs level by level
+                const int32_t t0 = g->span_tile_h[s_];
+                const int32_t cfirst = t0 < int32_t(sp_tile.size() / 4) ? sp_tile[t0 * 4] : int32_t(sp_chunk.size() / 4);
+                const int32_t afirst = cfirst < int32_t(sp_chunk.size() / 4) ? sp_chunk[cfirst * 4] : int32_t(sp_ta_arc.size());
+                sp_tile.resize(size_t(t0) * 4);
+                sp_chunk.resize(size_t(cfirst) * 4);
+                sp_ta_arc.resize(afirst);
+                sp_ta_src.resize(afirst);
+                sp_ta_gate.resize(afirst);
+                for (int j = 0; j < kSpan; ++j) { tg[j].clear(); tarcs[j] = 0; }
+                ++tile_id;
+                g->span_fused_h[s_] = 0;
+            }
+        }
+        g->span_tile_h[NS] = int32_t(sp_tile.size() / 4);
+        g->n_sptiles = int64_t(sp_tile.size() / 4);
+    }
+
     // ---- device image --------------------------------------------------------------------
     DevLayout& lay = g->lay;
     size_t off = 0;
@@ -376,6 +504,11 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     lay.fwd_chunk = place(fchunk.size() * 4);
     lay.bwd_chunk = place(bchunk.size() * 4);
     lay.bwd_lvl = place((Lmax + 2) * 12);
+    lay.sp_tile = place(sp_tile.size() * 4);
+    lay.sp_chunk = place(sp_chunk.size() * 4);
+    lay.sp_ta_arc = place(sp_ta_arc.size() * 4);
+    lay.sp_ta_src = place(sp_ta_src.size() * 4);
+    lay.sp_ta_gate = place(sp_ta_gate.size() * 4);
     lay.total = off;
     g->image.assign(off, 0);
     auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) std::memcpy(g->image.data() + o, src, bytes); };
@@ -425,6 +558,11 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     put(lay.fwd_chunk, fchunk.data(), fchunk.size() * 4);
     put(lay.bwd_chunk, bchunk.data(), bchunk.size() * 4);
     put(lay.bwd_lvl, blvl.data(), blvl.size() * 4);
+    put(lay.sp_tile, sp_tile.data(), sp_tile.size() * 4);
+    put(lay.sp_chunk, sp_chunk.data(), sp_chunk.size() * 4);
+    put(lay.sp_ta_arc, sp_ta_arc.data(), sp_ta_arc.size() * 4);
+    put(lay.sp_ta_src, sp_ta_src.data(), sp_ta_src.size() * 4);
+    put(lay.sp_ta_gate, sp_ta_gate.data(), sp_ta_gate.size() * 4);
 
     g->n_pi = int32_t(P);
     g->n_gates = int32_t(G);

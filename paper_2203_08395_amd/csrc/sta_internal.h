@@ -23,6 +23,10 @@ constexpr int kFwdCapA = 2816, kFwdCapG = 1152, kFwdCapT = 96;
 // view-schedule backward chunks: whole tiles of one driver level
 constexpr int kBwdCapS = 4096, kBwdCapD = 2048, kBwdCapT = 128;
 constexpr size_t kViewTableLdsMax = 65536;            // LDS bytes for tables + axes
+// fused forward spans: kSpan consecutive gate levels per launch; a span tile holds at
+// most 64 cell arcs (one wavefront) per level of the span
+constexpr int kSpan = 4;
+constexpr int kSpanSlots = kSpan * 64;
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
 struct DevLayout {
@@ -36,6 +40,8 @@ struct DevLayout {
     size_t ftile_maxk;             // per forward tile: the largest gate fanin in it
     size_t fwd_chunk;              // per forward chunk (first tile, first arc, first gate, level)
     size_t bwd_chunk;              // per backward chunk (first tile, first slot, first driver, level)
+    size_t sp_tile, sp_chunk;      // fused spans: tile records (4 ints), chunk records (4 ints)
+    size_t sp_ta_arc, sp_ta_src, sp_ta_gate;   // per span-tile arc: arc, source, gate
     size_t total;
 };
 
@@ -62,6 +68,11 @@ struct DevGraph {
     const int32_t* ftile_maxk;     // [NF]  largest gate fanin of each forward tile
     const int32_t* fwd_chunk;      // [NC+1][4] forward chunks
     const int32_t* bwd_chunk;      // [NB+1][4] backward chunks in processing order (+ 4 ints of bounds)
+    const int32_t* sp_tile;        // [NT][4] span tile: first chunk, chunks, first slot record, slots
+    const int32_t* sp_chunk;       // [NC][4] span chunk (one level of a tile): first tile arc, arcs, first slot, max fanin
+    const int32_t* sp_ta_arc;      // per tile arc: the cell arc
+    const int32_t* sp_ta_src;      // per tile arc: its driver (>= 0) or -1 - (slot of an in-tile gate)
+    const int32_t* sp_ta_gate;     // per tile arc: its gate
     int32_t n_pi, n_gates, n_drivers, n_arcs;
 };
 
@@ -102,6 +113,10 @@ struct sta_graph {
     int32_t n_fchunks = 0, n_bchunks = 0;
     int32_t view_sched_max_arcs = sta::kDefaultViewSchedMaxArcs;
     bool use_graphs = true;              // replay level-schedule launch sequences from hipGraphs
+    bool use_spans = true;               // fuse kSpan levels per forward launch where possible
+    std::vector<int32_t> span_tile_h;    // [NS+1] tiles of span s: [p[s], p[s+1]); a span
+    std::vector<uint8_t> span_fused_h;   //   with span_fused_h[s] == 0 runs level by level
+    int64_t n_sptiles = 0;
     mutable std::mutex cache_mu;
     mutable sta::LaunchCache fwd_cache, bwd_cache, adj_cache;
     sta::DevLayout lay{};

@@ -473,6 +473,160 @@ __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V,
     fwd_finish<NV>(x, ts, j, ty, 64, s_ax, tab, early, NV, 0, G.n_pi, drv_ts, arc_ts, arc_delay, argmax);
 }
 
+
+// ---------------------------------------------------------------------------------
+// fused forward spans: kSpan levels per launch, one span tile per wavefront
+// ---------------------------------------------------------------------------------
+
+// fwd_finish for a span chunk: the same arithmetic, plus every view's gate result kept
+// in LDS (slot-indexed) for the tile's gates of the levels above
+template <int NW>
+__device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* ts, int j, float ty, int span,
+                                                const float* s_ax, const float* const* tab, const bool* early,
+                                                int n_pi, float* __restrict__ drv_ts, float* __restrict__ arc_ts,
+                                                float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
+                                                float2* lds_res, int slot) {
+    const float* X = s_ax;
+    const float* DX = s_ax + 14;
+    const int lane = threadIdx.x & 63;
+    float cand[NW], slw[NW];
+    int best_k[NW];
+    if (x.active) {
+        float2* dst = reinterpret_cast<float2*>(arc_ts) + size_t(x.a) * NW;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const float ai = ts[w].x + x.nd;
+            const float su2 = ts[w].y * ts[w].y;
+            const float si = sqrtf(su2 + x.ni);
+            const int i = seg6(X, si);
+            const float tx = (si - X[i]) / DX[i];
+            const float* T = tab[w] + size_t(x.tb) * 98;
+            const float dl = bilerp(T, i, j, tx, ty);
+            const float sl = bilerp(T + 49, i, j, tx, ty);
+            dst[w] = make_float2(ai, si);
+            arc_delay[size_t(x.a) * NW + w] = dl;
+            cand[w] = ai + dl;
+            slw[w] = sl;
+            best_k[w] = x.kpos;
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) { cand[w] = 0.0f; slw[w] = 0.0f; best_k[w] = 0; }
+    }
+    for (int off = 1; off < span; off <<= 1) {
+        const bool take = (lane + off) < x.seg_end;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const float c2 = __shfl_down(cand[w], off, 64);
+            const float s2 = __shfl_down(slw[w], off, 64);
+            const int k2 = __shfl_down(best_k[w], off, 64);
+            if (take) {
+                if (early[w] ? (c2 < cand[w]) : (c2 > cand[w])) { cand[w] = c2; best_k[w] = k2; }
+                if (early[w] ? (s2 < slw[w]) : (s2 > slw[w])) slw[w] = s2;
+            }
+        }
+    }
+    if (x.head) {
+        float2* out = reinterpret_cast<float2*>(drv_ts) + size_t(n_pi + x.g) * NW;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            out[w] = make_float2(cand[w], slw[w]);
+            argmax[size_t(x.g) * NW + w] = uint8_t(best_k[w]);
+            lds_res[slot * NW + w] = make_float2(cand[w], slw[w]);
+        }
+    }
+}
+
+// One wavefront per span tile.  Two rounds of loads for the whole tile (its arc records;
+// then the arcs' static data and the arrivals of drivers outside the span), then the
+// levels in order, each reading its in-span inputs from LDS: one table round per level
+// instead of one launch and three rounds per level.
+template <int NV>
+__global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
+                                                      const float* __restrict__ arc_load,
+                                                      const float* __restrict__ nd, const float* __restrict__ ni,
+                                                      float* __restrict__ drv_ts, float* __restrict__ arc_ts,
+                                                      float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
+    __shared__ float s_ax[32];
+    __shared__ float2 s_res[4][kSpanSlots * NV];
+    load_axes(s_ax, lib);
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = tile0 + blockIdx.x * 4 + wave;
+    if (t >= tile1) return;
+    const int lane = threadIdx.x & 63;
+    const int c0 = G.sp_tile[t * 4], nch = G.sp_tile[t * 4 + 1];
+    float2* res = s_res[wave];
+    const float* tab[NV];
+    bool early[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        tab[v] = lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
+        early[v] = V.mode[v] == STA_EARLY;
+    }
+    // round 1: chunk records and the tile's arc records (clamped, unconditional loads)
+    int ta0[kSpan], na[kSpan], sl0[kSpan], mk[kSpan];
+    int ar[kSpan], sc[kSpan], gt[kSpan];
+#pragma unroll
+    for (int c = 0; c < kSpan; ++c) {
+        const int cc = c < nch ? c0 + c : c0;
+        ta0[c] = G.sp_chunk[cc * 4];
+        na[c] = c < nch ? G.sp_chunk[cc * 4 + 1] : 0;
+        sl0[c] = G.sp_chunk[cc * 4 + 2];
+        mk[c] = G.sp_chunk[cc * 4 + 3];
+        const int i = lane < na[c] ? ta0[c] + lane : ta0[c];
+        ar[c] = G.sp_ta_arc[i];
+        sc[c] = G.sp_ta_src[i];
+        gt[c] = G.sp_ta_gate[i];
+    }
+    // round 2: the arcs' static data and the arrivals of drivers outside the span
+    uint32_t meta[kSpan];
+    float ndv[kSpan], niv[kSpan], lov[kSpan];
+    float2 ext[kSpan][NV];
+#pragma unroll
+    for (int c = 0; c < kSpan; ++c) {
+        const int a = ar[c];
+        meta[c] = G.arc_meta[a];
+        ndv[c] = nd[a];
+        niv[c] = ni[a];
+        lov[c] = arc_load[a];
+        const int u = sc[c] >= 0 ? sc[c] : 0;
+        const float2* sp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ext[c][v] = sp[v];
+    }
+    // the levels of the tile, in order
+#pragma unroll
+    for (int c = 0; c < kSpan; ++c) {
+        if (c >= nch) break;                    // uniform
+        const bool act = lane < na[c];
+        FwdLane x;
+        fwd_lane_setup(x, act, act ? meta[c] : 0u, na[c], lane);
+        x.a = ar[c];
+        x.g = gt[c];
+        x.nd = act ? ndv[c] : 0.0f;
+        x.ni = act ? niv[c] : 0.0f;
+        x.Lo = act ? lov[c] : 0.0f;
+        int j = 0;
+        float ty = 0.0f;
+        gate_jty(s_ax, x.Lo, j, ty);
+        float2 ts[NV];
+        if (act && sc[c] < 0) {
+            const int src = -1 - sc[c];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ts[v] = res[src * NV + v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ts[v] = act ? ext[c][v] : make_float2(0.0f, 0.0f);
+        }
+        fwd_finish_span<NV>(x, ts, j, ty, mk[c], s_ax, tab, early, G.n_pi, drv_ts, arc_ts, arc_delay, argmax, res,
+                            sl0[c] + x.gi);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // primary inputs: copy (arrival, slew) of every view
 __global__ void k_copy_pi(const float* __restrict__ pi_ts, float* __restrict__ drv_ts, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1302,16 +1456,37 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
         prof_launch("k_copy_pi", s, [&] {
             hipLaunchKernelGGL(k_copy_pi, dim3((npi + 255) / 256), dim3(256), 0, s, pi_ts, o->drv_ts, npi);
         });
-    for (int64_t l = 1; l <= g->L; ++l) {
+    auto level = [&](int64_t l) {
         const int t0 = g->fwd_tile_ptr[l], t1 = g->fwd_tile_ptr[l + 1];
-        if (t1 <= t0) continue;
+        if (t1 <= t0) return;
         const KTiles kt = ktiles(g->ftile_arc_h, g->ftile_gate_h, t0, t1);
         prof_launch("k_forward", s, [&] {
             hipLaunchKernelGGL((k_forward<NV, TAB_LDS>), dim3((t1 - t0 + 3) / 4), dim3(256), lds, s, dg, lib, kv, t0,
                                t1, kt, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts, o->arc_delay,
                                o->argmax);
         });
+    };
+    if constexpr (NV <= 2) {
+        if (g->use_spans && !TAB_LDS) {
+            const int64_t NS = int64_t(g->span_fused_h.size());
+            for (int64_t sp = 0; sp < NS && sp * kSpan < g->L; ++sp) {
+                const int64_t l0 = 1 + sp * kSpan, l1 = std::min<int64_t>(g->L, l0 + kSpan - 1);
+                if (!g->span_fused_h[sp]) {
+                    for (int64_t l = l0; l <= l1; ++l) level(l);
+                    continue;
+                }
+                const int t0 = g->span_tile_h[sp], t1 = g->span_tile_h[sp + 1];
+                if (t1 <= t0) continue;
+                prof_launch("k_forward_span", s, [&] {
+                    hipLaunchKernelGGL((k_forward_span<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, lib, kv,
+                                       t0, t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts,
+                                       o->arc_delay, o->argmax);
+                });
+            }
+            return;
+        }
     }
+    for (int64_t l = 1; l <= g->L; ++l) level(l);
 }
 
 template <int NV>
@@ -1325,7 +1500,7 @@ static sta_status run_forward_levels(const sta_graph* g, const KLib& lib, const 
     (void)same_set;
     std::vector<uint64_t> key = {uint64_t(NV), pk(lib.tables), uint64_t(lib.n_tables), pk(pi_ts), pk(nd->arc_load),
                                  pk(nd->net_delay), pk(nd->net_imp2), pk(o->drv_ts), pk(o->arc_ts), pk(o->arc_delay),
-                                 pk(o->argmax), uint64_t(tab_lds)};
+                                 pk(o->argmax), uint64_t(tab_lds), uint64_t(g->use_spans)};
     for (int i = 0; i < 26; ++i) { uint32_t b; std::memcpy(&b, &lib.ax[i], 4); key.push_back(b); }
     for (int v = 0; v < NV; ++v) key.push_back((uint64_t(kv.mode[v]) << 32) | uint32_t(kv.set[v]));
     return run_sequence(g, g->fwd_cache, std::move(key), s, [&](hipStream_t q) {
@@ -1849,6 +2024,12 @@ sta_status sta_profile_end(sta_kernel_stat* stats, int32_t cap, int32_t* n) {
     }
     *n = k;
     return st;
+}
+
+sta_status sta_set_level_fusion(sta_graph* g, int32_t enable) {
+    if (!g) return fail(STA_E_ARG, "sta_set_level_fusion: null graph");
+    g->use_spans = enable != 0;
+    return STA_OK;
 }
 
 sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32_t use_graphs) {

@@ -69,7 +69,7 @@ class SlackOut(ctypes.Structure):
 _lib = None
 
 EXPORTS = ("sta_last_error", "sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload",
-           "sta_graph_free", "sta_delay_calc", "sta_propagate", "sta_slack", "sta_set_schedule",
+           "sta_graph_free", "sta_delay_calc", "sta_propagate", "sta_slack", "sta_set_schedule", "sta_set_level_fusion",
            "sta_profile_begin", "sta_profile_end")
 
 
@@ -102,10 +102,12 @@ def load_library():
     lib.sta_slack.argtypes = [_P, ctypes.POINTER(ViewsC), ctypes.POINTER(NetOut), ctypes.POINTER(TimingOut), _P,
                               ctypes.POINTER(SlackOut), _P, ctypes.c_size_t, _P]
     lib.sta_set_schedule.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
+    lib.sta_set_level_fusion.argtypes = [_P, ctypes.c_int32]
     lib.sta_profile_begin.argtypes = []
     lib.sta_profile_end.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     for f in ("sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload", "sta_delay_calc",
-              "sta_propagate", "sta_slack", "sta_set_schedule", "sta_profile_begin", "sta_profile_end"):
+              "sta_propagate", "sta_slack", "sta_set_schedule", "sta_set_level_fusion", "sta_profile_begin",
+              "sta_profile_end"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -177,6 +179,11 @@ class Graph:
         level.  use_graphs: replay the level schedule's launches from a captured hipGraph."""
         _check(load_library().sta_set_schedule(self._h, int(view_max_arcs_per_level), int(bool(use_graphs))),
                "sta_set_schedule")
+        return self
+
+    def set_level_fusion(self, enable):
+        """Fuse four levels per forward launch (span tiles; default on)."""
+        _check(load_library().sta_set_level_fusion(self._h, int(bool(enable))), "sta_set_level_fusion")
         return self
 
     @property

@@ -33,8 +33,9 @@ def assert_bitwise(name, got, want):
         raise AssertionError(f"{name}: {bad.size} of {got.size} differ; first at {i}: got {got[i]!r} want {want[i]!r}")
 
 
-# name: (view-schedule threshold in arcs per level, replay from hipGraphs)
-SCHEDULES = {"level": (0, True), "level_plain": (0, False), "view": (1 << 30, True)}
+# name: (view-schedule threshold in arcs per level, replay from hipGraphs, level fusion)
+SCHEDULES = {"span": (0, True, True), "level": (0, True, False), "level_plain": (0, False, False),
+             "view": (1 << 30, True, True)}
 
 
 def gpu_run(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, precision=sta.STA_DC_FP64, device="cuda",
@@ -45,7 +46,9 @@ def gpu_run(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, precision=s
     V = len(modes)
     g = sta.Graph(d, n_tables=lib.tab.shape[-4]).upload(device)
     if schedule is not None:
-        g.set_schedule(*SCHEDULES[schedule])
+        thr, graphs, fuse = SCHEDULES[schedule]
+        g.set_schedule(thr, graphs)
+        g.set_level_fusion(fuse)
     tables = torch.from_numpy(np.ascontiguousarray(lib.tab)).to(device)
     L = sta.make_library(lib.x, lib.y, tables)
     views = sta.make_views(modes, table_sets)
@@ -70,7 +73,9 @@ def gpu_run(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, precision=s
         # wide levels may not fit a workgroup's LDS: then that pass runs per level
         assert "k_forward_view" in ran or "k_backward_view" in ran, ran
     if schedule in ("level", "level_plain") and g.sizes["n_levels"] > 0:
-        assert "k_forward" in ran and "k_backward" in ran, ran
+        assert "k_forward" in ran and "k_backward" in ran and "k_forward_span" not in ran, ran
+    if schedule == "span" and g.sizes["n_levels"] > 0 and V <= 2:
+        assert "k_forward_span" in ran or "k_forward" in ran, ran
     host = {k: v.cpu().numpy() for k, v in list(nd.items()) + list(t.items()) + list(s.items()) if k != "scratch"}
     return g, host
 

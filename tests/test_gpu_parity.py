@@ -11,7 +11,7 @@ from tests.gpu_common import EARLY, LATE, assert_bitwise, compare_all, gpu_run, 
 
 pytestmark = pytest.mark.gpu
 
-SCHED = pytest.mark.parametrize("schedule", ["level", "level_plain", "view"])
+SCHED = pytest.mark.parametrize("schedule", ["span", "level", "level_plain", "view"])
 
 
 @SCHED
@@ -130,7 +130,7 @@ def test_deterministic_reruns(schedule):
         assert_bitwise("rerun " + k, h1[k].reshape(-1), h2[k].reshape(-1))
 
 
-@pytest.mark.parametrize("schedule", [None, "level_plain", "view"])
+@pytest.mark.parametrize("schedule", [None, "level", "view"])
 def test_c2_full_size_bitwise(schedule):
     # the 1M-pin workload; schedule None is the library's own choice, which the
     # benchmark times
