@@ -55,6 +55,11 @@ DevGraph dev_graph(const sta_graph* g) {
     d.sp_ta_arc = reinterpret_cast<const int32_t*>(b + L.sp_ta_arc);
     d.sp_ta_src = reinterpret_cast<const int32_t*>(b + L.sp_ta_src);
     d.sp_ta_gate = reinterpret_cast<const int32_t*>(b + L.sp_ta_gate);
+    d.bp_tile = reinterpret_cast<const int32_t*>(b + L.bp_tile);
+    d.bp_chunk = reinterpret_cast<const int32_t*>(b + L.bp_chunk);
+    d.bp_slot = reinterpret_cast<const int32_t*>(b + L.bp_slot);
+    d.bp_src = reinterpret_cast<const int32_t*>(b + L.bp_src);
+    d.bp_drv = reinterpret_cast<const int32_t*>(b + L.bp_drv);
     d.n_pi = g->n_pi;
     d.n_gates = g->n_gates;
     d.n_drivers = static_cast<int32_t>(g->D);
@@ -355,6 +360,131 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     }
 
 
+
+    // ---- fused backward spans ------------------------------------------------------------
+    // Span b covers driver levels [max(0, L-(b+1)k+1), L-bk], processed top down.  A tile
+    // is a set of drivers closed under in-span sinks: the output driver of every gate a
+    // tile driver feeds, when its level lies in the span, is in the tile too.  Roots are
+    // taken bottom level first; a tile holds <= 64 slots per level; a driver with more than
+    // 64 slots makes its span run level by level.
+    std::vector<int32_t> bp_tile, bp_chunk, bp_slot, bp_src, bp_drv;
+    {
+        const int32_t NSB = (Lmax + 1 + kSpan - 1) / kSpan;
+        g->bspan_tile_h.assign(NSB + 1, 0);
+        g->bspan_fused_h.assign(std::max<int32_t>(NSB, 1), 0);
+        auto drv_range = [&](int32_t l, int64_t& i0, int64_t& i1) {
+            i0 = (l == 0) ? 0 : P + lvl_gate_ptr[l - 1];
+            i1 = (l == 0) ? P : P + lvl_gate_ptr[l];
+        };
+        std::vector<int32_t> mark(D, -1), dslot(D, -1), tile_mark(D, -1), stack, cone;
+        std::vector<uint8_t> covered(D, 0);
+        int32_t tile_id = 0;
+        for (int32_t b = 0; b < NSB; ++b) {
+            g->bspan_tile_h[b] = int32_t(bp_tile.size() / 4);
+            const int32_t top = Lmax - b * kSpan, bot = std::max<int32_t>(0, top - kSpan + 1);
+            auto lv = [&](int64_t i) { return g->level[i]; };
+            auto in_span = [&](int64_t i) { return lv(i) >= bot && lv(i) <= top; };
+            bool ok = true;
+            std::vector<std::vector<int32_t>> td(kSpan);     // drivers per level (index top - level)
+            int32_t tslots[kSpan] = {};
+            auto nslots = [&](int64_t i) { return slot_ptr[i + 1] - slot_ptr[i]; };
+            auto flush = [&]() {
+                bool any = false;
+                for (int j = 0; j < kSpan; ++j) any = any || !td[j].empty();
+                if (!any) return;
+                const int32_t c0 = int32_t(bp_chunk.size() / 4);
+                int32_t ds = 0;
+                for (int j = 0; j < kSpan; ++j)
+                    for (int32_t i : td[j]) dslot[i] = ds++;
+                int32_t nch = 0;
+                for (int j = 0; j < kSpan; ++j) {      // j = 0 is the top level: processed first
+                    if (td[j].empty()) continue;
+                    const int32_t ts0 = int32_t(bp_slot.size());
+                    for (int32_t i : td[j]) {
+                        for (int32_t sl = slot_ptr[i]; sl < slot_ptr[i + 1]; ++sl) {
+                            const int32_t sa = bslot_arc[sl];
+                            int32_t src = -1;
+                            if (sa >= 0) {
+                                const int32_t o = int32_t(P + int_gate_of_arc[sa]);
+                                if (in_span(o)) src = dslot[o];
+                            }
+                            bp_slot.push_back(sl);
+                            bp_src.push_back(src);
+                            bp_drv.push_back(i);
+                        }
+                    }
+                    bp_chunk.insert(bp_chunk.end(), {ts0, int32_t(bp_slot.size()) - ts0, dslot[td[j][0]], 0});
+                    ++nch;
+                }
+                bp_tile.insert(bp_tile.end(), {c0, nch, 0, ds});
+                for (int j = 0; j < kSpan; ++j) { td[j].clear(); tslots[j] = 0; }
+                ++tile_id;
+            };
+            for (int32_t l = bot; l <= top && ok; ++l) {
+                int64_t i0, i1;
+                drv_range(l, i0, i1);
+                for (int64_t r = i0; r < i1 && ok; ++r) {
+                    if (covered[r]) continue;
+                    cone.clear();
+                    stack.assign(1, int32_t(r));
+                    mark[r] = int32_t(r);
+                    while (!stack.empty()) {
+                        const int32_t i = stack.back();
+                        stack.pop_back();
+                        cone.push_back(i);
+                        for (int32_t sl = slot_ptr[i]; sl < slot_ptr[i + 1]; ++sl) {
+                            const int32_t sa = bslot_arc[sl];
+                            if (sa < 0) continue;
+                            const int32_t o = int32_t(P + int_gate_of_arc[sa]);
+                            if (in_span(o) && mark[o] != r) { mark[o] = int32_t(r); stack.push_back(o); }
+                        }
+                    }
+                    int32_t add[kSpan] = {}, alone[kSpan] = {};
+                    for (int32_t i : cone) {
+                        const int32_t k = nslots(i);
+                        alone[top - lv(i)] += k;
+                        if (tile_mark[i] != tile_id) add[top - lv(i)] += k;
+                    }
+                    bool fits = true, fits_alone = true;
+                    for (int j = 0; j < kSpan; ++j) {
+                        fits = fits && tslots[j] + add[j] <= kTileSlots;
+                        fits_alone = fits_alone && alone[j] <= kTileSlots;
+                    }
+                    if (!fits_alone) { ok = false; break; }
+                    if (!fits) {
+                        flush();
+                        for (int j = 0; j < kSpan; ++j) add[j] = alone[j];
+                    }
+                    std::sort(cone.begin(), cone.end());
+                    for (int32_t i : cone) {
+                        if (tile_mark[i] == tile_id) continue;
+                        tile_mark[i] = tile_id;
+                        td[top - lv(i)].push_back(i);
+                        covered[i] = 1;
+                    }
+                    for (int j = 0; j < kSpan; ++j) tslots[j] += add[j];
+                }
+            }
+            if (ok) {
+                flush();
+                g->bspan_fused_h[b] = 1;
+            } else {
+                const int32_t t0 = g->bspan_tile_h[b];
+                const int32_t cfirst = t0 < int32_t(bp_tile.size() / 4) ? bp_tile[t0 * 4] : int32_t(bp_chunk.size() / 4);
+                const int32_t sfirst = cfirst < int32_t(bp_chunk.size() / 4) ? bp_chunk[cfirst * 4] : int32_t(bp_slot.size());
+                bp_tile.resize(size_t(t0) * 4);
+                bp_chunk.resize(size_t(cfirst) * 4);
+                bp_slot.resize(sfirst);
+                bp_src.resize(sfirst);
+                bp_drv.resize(sfirst);
+                for (int j = 0; j < kSpan; ++j) { td[j].clear(); tslots[j] = 0; }
+                ++tile_id;
+                g->bspan_fused_h[b] = 0;
+            }
+        }
+        g->bspan_tile_h[NSB] = int32_t(bp_tile.size() / 4);
+    }
+
     // ---- fused forward spans -------------------------------------------------------------
     // Span s covers gate levels [1 + s*kSpan, (s+1)*kSpan].  A span tile computes, level by
     // level inside one wavefront, a set of gates closed under in-span fanin: every in-span
@@ -509,6 +639,11 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     lay.sp_ta_arc = place(sp_ta_arc.size() * 4);
     lay.sp_ta_src = place(sp_ta_src.size() * 4);
     lay.sp_ta_gate = place(sp_ta_gate.size() * 4);
+    lay.bp_tile = place(bp_tile.size() * 4);
+    lay.bp_chunk = place(bp_chunk.size() * 4);
+    lay.bp_slot = place(bp_slot.size() * 4);
+    lay.bp_src = place(bp_src.size() * 4);
+    lay.bp_drv = place(bp_drv.size() * 4);
     lay.total = off;
     g->image.assign(off, 0);
     auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) std::memcpy(g->image.data() + o, src, bytes); };
@@ -563,6 +698,11 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     put(lay.sp_ta_arc, sp_ta_arc.data(), sp_ta_arc.size() * 4);
     put(lay.sp_ta_src, sp_ta_src.data(), sp_ta_src.size() * 4);
     put(lay.sp_ta_gate, sp_ta_gate.data(), sp_ta_gate.size() * 4);
+    put(lay.bp_tile, bp_tile.data(), bp_tile.size() * 4);
+    put(lay.bp_chunk, bp_chunk.data(), bp_chunk.size() * 4);
+    put(lay.bp_slot, bp_slot.data(), bp_slot.size() * 4);
+    put(lay.bp_src, bp_src.data(), bp_src.size() * 4);
+    put(lay.bp_drv, bp_drv.data(), bp_drv.size() * 4);
 
     g->n_pi = int32_t(P);
     g->n_gates = int32_t(G);

@@ -42,6 +42,7 @@ struct DevLayout {
     size_t bwd_chunk;              // per backward chunk (first tile, first slot, first driver, level)
     size_t sp_tile, sp_chunk;      // fused spans: tile records (4 ints), chunk records (4 ints)
     size_t sp_ta_arc, sp_ta_src, sp_ta_gate;   // per span-tile arc: arc, source, gate
+    size_t bp_tile, bp_chunk, bp_slot, bp_src, bp_drv;   // backward spans
     size_t total;
 };
 
@@ -73,6 +74,11 @@ struct DevGraph {
     const int32_t* sp_ta_arc;      // per tile arc: the cell arc
     const int32_t* sp_ta_src;      // per tile arc: its driver (>= 0) or -1 - (slot of an in-tile gate)
     const int32_t* sp_ta_gate;     // per tile arc: its gate
+    const int32_t* bp_tile;        // [NT][4] backward span tile: first chunk, chunks, -, drivers
+    const int32_t* bp_chunk;       // [NC][4] one level of a tile: first tile slot, slots, first driver slot, -
+    const int32_t* bp_slot;        // per tile slot: the backward slot
+    const int32_t* bp_src;         // per tile slot: driver slot (in the tile) of the sink's gate output, or -1
+    const int32_t* bp_drv;         // per tile slot: its driver
     int32_t n_pi, n_gates, n_drivers, n_arcs;
 };
 
@@ -117,6 +123,8 @@ struct sta_graph {
     std::vector<int32_t> span_tile_h;    // [NS+1] tiles of span s: [p[s], p[s+1]); a span
     std::vector<uint8_t> span_fused_h;   //   with span_fused_h[s] == 0 runs level by level
     int64_t n_sptiles = 0;
+    std::vector<int32_t> bspan_tile_h;   // backward spans, span b = driver levels
+    std::vector<uint8_t> bspan_fused_h;  //   [max(0, L-(b+1)k+1), L-bk], processed top down
     mutable std::mutex cache_mu;
     mutable sta::LaunchCache fwd_cache, bwd_cache, adj_cache;
     sta::DevLayout lay{};

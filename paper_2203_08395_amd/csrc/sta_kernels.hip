@@ -661,6 +661,121 @@ __global__ __launch_bounds__(256) void k_backward(DevGraph G, KViews V, int tile
                  arc_slack);
 }
 
+
+// One wavefront per backward span tile (views 0..NV-1): two rounds of loads for the whole
+// tile (its slot records; then the slots' arc data, the drivers' arrivals, and the required
+// times of sink gates outside the span or the endpoint required times), then the levels
+// top down, in-span required times handed over through LDS.
+template <int NV>
+__global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
+                                                       const float* __restrict__ nd, const float* __restrict__ drv_ts,
+                                                       const float* __restrict__ arc_ts,
+                                                       const float* __restrict__ arc_delay,
+                                                       const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
+                                                       float* __restrict__ arc_rat, float* __restrict__ drv_slack,
+                                                       float* __restrict__ arc_slack) {
+    __shared__ float s_rat[4][kSpanSlots * NV];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = tile0 + blockIdx.x * 4 + wave;
+    if (t >= tile1) return;
+    const int lane = threadIdx.x & 63;
+    const int c0 = G.bp_tile[t * 4], nch = G.bp_tile[t * 4 + 1];
+    float* rs = s_rat[wave];
+    bool early[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
+    // round 1: chunk records and slot records
+    int ts0[kSpan], ns[kSpan], ds0[kSpan];
+    int slot[kSpan], src[kSpan], drv[kSpan];
+#pragma unroll
+    for (int c = 0; c < kSpan; ++c) {
+        const int cc = c < nch ? c0 + c : c0;
+        ts0[c] = G.bp_chunk[cc * 4];
+        ns[c] = c < nch ? G.bp_chunk[cc * 4 + 1] : 0;
+        ds0[c] = G.bp_chunk[cc * 4 + 2];
+        const int i = lane < ns[c] ? ts0[c] + lane : ts0[c];
+        slot[c] = G.bp_slot[i];
+        src[c] = G.bp_src[i];
+        drv[c] = G.bp_drv[i];
+    }
+    // round 2: slot data (everything that does not come from this tile)
+    int sa_[kSpan], so_[kSpan];
+    bool hd[kSpan];
+    float ndv[kSpan], dl[kSpan][NV], ati[kSpan][NV], ext[kSpan][NV], atd[kSpan][NV];
+#pragma unroll
+    for (int c = 0; c < kSpan; ++c) {
+        const int sl = slot[c];
+        const int sa = G.bslot_arc[sl];
+        const uint32_t bo = uint32_t(G.bslot_out[sl]);
+        sa_[c] = sa;
+        so_[c] = int(bo & 0x7fffffffu);
+        hd[c] = (bo & kHeadBit) != 0u;
+        const int sac = sa >= 0 ? sa : 0;
+        ndv[c] = nd[sac];
+        const float* ext_src = (sa >= 0) ? (drv_rat + size_t(so_[c]) * NV) : (ep_rat + size_t(so_[c]) * NV);
+        const float2* ts = reinterpret_cast<const float2*>(arc_ts) + size_t(sac) * NV;
+        const float2* dt = reinterpret_cast<const float2*>(drv_ts) + size_t(drv[c]) * NV;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            dl[c][v] = arc_delay[size_t(sac) * NV + v];
+            ati[c][v] = ts[v].x;
+            ext[c][v] = (src[c] >= 0) ? 0.0f : ext_src[v];
+            atd[c][v] = dt[v].x;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kSpan; ++c) {
+        if (c >= nch) break;                    // uniform
+        const int n = ns[c];
+        const bool act = lane < n;
+        const bool head = act && hd[c];
+        const uint64_t heads = __ballot(head);
+        const uint64_t le = lanes_le(lane);
+        const int gi = __popcll(heads & le) - 1;
+        const uint64_t after = heads & ~le;
+        const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : n;
+        float best[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            float val = 0.0f;
+            if (act) {
+                if (sa_[c] >= 0) {
+                    const float ro = src[c] >= 0 ? rs[src[c] * NV + v] : ext[c][v];
+                    const float rin = ro - dl[c][v];
+                    arc_rat[size_t(sa_[c]) * NV + v] = rin;
+                    arc_slack[size_t(sa_[c]) * NV + v] = early[v] ? (ati[c][v] - rin) : (rin - ati[c][v]);
+                    val = rin - ndv[c];
+                } else {
+                    val = ext[c][v];
+                }
+            }
+            best[v] = val;
+        }
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const bool take = (lane + off) < seg_end;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const float b2 = __shfl_down(best[v], off, 64);
+                if (take && (early[v] ? (b2 > best[v]) : (b2 < best[v]))) best[v] = b2;
+            }
+        }
+        if (head) {
+            const int u = drv[c];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const float r = best[v];
+                drv_rat[size_t(u) * NV + v] = r;
+                drv_slack[size_t(u) * NV + v] = early[v] ? (atd[c][v] - r) : (r - atd[c][v]);
+                rs[(ds0[c] + gi) * NV + v] = r;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 template <int NV>
 __global__ __launch_bounds__(kK4Threads) void k_endpoint_partial(const int32_t* __restrict__ ep_drv, int E,
                                                                  const float* __restrict__ drv_slack,
@@ -1524,16 +1639,39 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
                                     const sta_timing_out* t, const float* ep_rat, const sta_slack_out* o,
                                     void* scratch, hipStream_t s) {
     const DevGraph dg = dev_graph(g);
-    for (int64_t l = g->L; l >= 0; --l) {
+    auto level = [&](int64_t l) {
         const int t0 = g->bwd_tile_ptr[l], t1 = g->bwd_tile_ptr[l + 1];
-        if (t1 <= t0) continue;
+        if (t1 <= t0) return;
         const KTiles kt = ktiles(g->btile_slot_h, g->btile_drv_h, t0, t1);
         prof_launch("k_backward", s, [&] {
             hipLaunchKernelGGL((k_backward<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, kv, t0, t1, kt,
                                nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat, o->arc_rat,
                                o->drv_slack, o->arc_slack);
         });
+    };
+    bool done = false;
+    if constexpr (NV <= 2) {
+        if (g->use_spans) {
+            const int64_t NSB = int64_t(g->bspan_fused_h.size());
+            for (int64_t b = 0; b < NSB && b * kSpan <= g->L; ++b) {
+                const int64_t top = g->L - b * kSpan, bot = std::max<int64_t>(0, top - kSpan + 1);
+                if (!g->bspan_fused_h[b]) {
+                    for (int64_t l = top; l >= bot; --l) level(l);
+                    continue;
+                }
+                const int t0 = g->bspan_tile_h[b], t1 = g->bspan_tile_h[b + 1];
+                if (t1 <= t0) continue;
+                prof_launch("k_backward_span", s, [&] {
+                    hipLaunchKernelGGL((k_backward_span<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, kv, t0,
+                                       t1, nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat,
+                                       o->arc_rat, o->drv_slack, o->arc_slack);
+                });
+            }
+            done = true;
+        }
     }
+    if (!done)
+        for (int64_t l = g->L; l >= 0; --l) level(l);
     int nblk = int((g->E + kK4Threads - 1) / kK4Threads);
     nblk = nblk < 1 ? 1 : (nblk > kK4Blocks ? kK4Blocks : nblk);
     auto* limbs = static_cast<unsigned long long*>(scratch);
@@ -1553,7 +1691,7 @@ static sta_status run_backward_levels(const sta_graph* g, const KViews& kv, cons
                                       void* scratch, hipStream_t s) {
     std::vector<uint64_t> key = {uint64_t(NV), pk(nd->net_delay), pk(t->drv_ts), pk(t->arc_ts), pk(t->arc_delay),
                                  pk(ep_rat), pk(o->drv_rat), pk(o->arc_rat), pk(o->drv_slack), pk(o->arc_slack),
-                                 pk(o->tns), pk(o->wns), pk(scratch)};
+                                 pk(o->tns), pk(o->wns), pk(scratch), uint64_t(g->use_spans)};
     for (int v = 0; v < NV; ++v) key.push_back(uint64_t(kv.mode[v]));
     return run_sequence(g, g->bwd_cache, std::move(key), s, [&](hipStream_t q) {
         enqueue_backward_levels<NV>(g, kv, nd, t, ep_rat, o, scratch, q);
