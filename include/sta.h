@@ -220,12 +220,14 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
  * Every choice gives identical results. */
 sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32_t use_graphs);
 
-/* Level fusion of the level schedule's forward pass (default on, one or two views):
- * kSpan = 4 consecutive gate levels per launch.  Each wavefront computes one span tile,
- * a set of gates closed under fanin inside the span (<= 64 cell arcs per level), level by
- * level with the in-span arrivals kept in LDS; a gate feeding several tiles is computed in
- * each of them, identically, so results do not change.  A span whose closure does not fit
- * runs level by level.  The view schedule is unaffected. */
+/* Level fusion of the level schedule (default on, one or two views): six consecutive gate
+ * levels per forward launch and four driver levels per backward launch.  Each wavefront
+ * computes one span tile: in the forward pass a set of gates closed under fanin inside the
+ * span (<= 64 cell arcs per level), in the backward pass a set of drivers closed under
+ * their sinks' gate outputs inside the span (<= 64 sink slots per level), level by level,
+ * with the in-span arrival (required) times kept in LDS.  A gate or driver needed by
+ * several tiles is computed in each of them, identically, so results do not change.  A
+ * span whose closure does not fit runs level by level.  The view schedule is unaffected. */
 sta_status sta_set_level_fusion(sta_graph* g, int32_t enable);
 
 /* Per-kernel timing record of the instrumentation calls below. */

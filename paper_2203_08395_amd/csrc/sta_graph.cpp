@@ -369,7 +369,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     // 64 slots makes its span run level by level.
     std::vector<int32_t> bp_tile, bp_chunk, bp_slot, bp_src, bp_drv;
     {
-        const int32_t NSB = (Lmax + 1 + kSpan - 1) / kSpan;
+        const int32_t NSB = (Lmax + 1 + kSpanB - 1) / kSpanB;
         g->bspan_tile_h.assign(NSB + 1, 0);
         g->bspan_fused_h.assign(std::max<int32_t>(NSB, 1), 0);
         auto drv_range = [&](int32_t l, int64_t& i0, int64_t& i1) {
@@ -381,23 +381,23 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
         int32_t tile_id = 0;
         for (int32_t b = 0; b < NSB; ++b) {
             g->bspan_tile_h[b] = int32_t(bp_tile.size() / 4);
-            const int32_t top = Lmax - b * kSpan, bot = std::max<int32_t>(0, top - kSpan + 1);
+            const int32_t top = Lmax - b * kSpanB, bot = std::max<int32_t>(0, top - kSpanB + 1);
             auto lv = [&](int64_t i) { return g->level[i]; };
             auto in_span = [&](int64_t i) { return lv(i) >= bot && lv(i) <= top; };
             bool ok = true;
-            std::vector<std::vector<int32_t>> td(kSpan);     // drivers per level (index top - level)
-            int32_t tslots[kSpan] = {};
+            std::vector<std::vector<int32_t>> td(kSpanB);     // drivers per level (index top - level)
+            int32_t tslots[kSpanB] = {};
             auto nslots = [&](int64_t i) { return slot_ptr[i + 1] - slot_ptr[i]; };
             auto flush = [&]() {
                 bool any = false;
-                for (int j = 0; j < kSpan; ++j) any = any || !td[j].empty();
+                for (int j = 0; j < kSpanB; ++j) any = any || !td[j].empty();
                 if (!any) return;
                 const int32_t c0 = int32_t(bp_chunk.size() / 4);
                 int32_t ds = 0;
-                for (int j = 0; j < kSpan; ++j)
+                for (int j = 0; j < kSpanB; ++j)
                     for (int32_t i : td[j]) dslot[i] = ds++;
                 int32_t nch = 0;
-                for (int j = 0; j < kSpan; ++j) {      // j = 0 is the top level: processed first
+                for (int j = 0; j < kSpanB; ++j) {      // j = 0 is the top level: processed first
                     if (td[j].empty()) continue;
                     const int32_t ts0 = int32_t(bp_slot.size());
                     for (int32_t i : td[j]) {
@@ -417,7 +417,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     ++nch;
                 }
                 bp_tile.insert(bp_tile.end(), {c0, nch, 0, ds});
-                for (int j = 0; j < kSpan; ++j) { td[j].clear(); tslots[j] = 0; }
+                for (int j = 0; j < kSpanB; ++j) { td[j].clear(); tslots[j] = 0; }
                 ++tile_id;
             };
             for (int32_t l = bot; l <= top && ok; ++l) {
@@ -439,21 +439,21 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                             if (in_span(o) && mark[o] != r) { mark[o] = int32_t(r); stack.push_back(o); }
                         }
                     }
-                    int32_t add[kSpan] = {}, alone[kSpan] = {};
+                    int32_t add[kSpanB] = {}, alone[kSpanB] = {};
                     for (int32_t i : cone) {
                         const int32_t k = nslots(i);
                         alone[top - lv(i)] += k;
                         if (tile_mark[i] != tile_id) add[top - lv(i)] += k;
                     }
                     bool fits = true, fits_alone = true;
-                    for (int j = 0; j < kSpan; ++j) {
+                    for (int j = 0; j < kSpanB; ++j) {
                         fits = fits && tslots[j] + add[j] <= kTileSlots;
                         fits_alone = fits_alone && alone[j] <= kTileSlots;
                     }
                     if (!fits_alone) { ok = false; break; }
                     if (!fits) {
                         flush();
-                        for (int j = 0; j < kSpan; ++j) add[j] = alone[j];
+                        for (int j = 0; j < kSpanB; ++j) add[j] = alone[j];
                     }
                     std::sort(cone.begin(), cone.end());
                     for (int32_t i : cone) {
@@ -462,7 +462,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                         td[top - lv(i)].push_back(i);
                         covered[i] = 1;
                     }
-                    for (int j = 0; j < kSpan; ++j) tslots[j] += add[j];
+                    for (int j = 0; j < kSpanB; ++j) tslots[j] += add[j];
                 }
             }
             if (ok) {
@@ -477,7 +477,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                 bp_slot.resize(sfirst);
                 bp_src.resize(sfirst);
                 bp_drv.resize(sfirst);
-                for (int j = 0; j < kSpan; ++j) { td[j].clear(); tslots[j] = 0; }
+                for (int j = 0; j < kSpanB; ++j) { td[j].clear(); tslots[j] = 0; }
                 ++tile_id;
                 g->bspan_fused_h[b] = 0;
             }
@@ -486,13 +486,13 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     }
 
     // ---- fused forward spans -------------------------------------------------------------
-    // Span s covers gate levels [1 + s*kSpan, (s+1)*kSpan].  A span tile computes, level by
+    // Span s covers gate levels [1 + s*kSpanF, (s+1)*kSpanF].  A span tile computes, level by
     // level inside one wavefront, a set of gates closed under in-span fanin: every in-span
     // driver of a tile gate is itself in the tile (so it may be computed by several tiles,
     // identically).  Roots are taken top level first; a tile holds <= 64 arcs per level.
     std::vector<int32_t> sp_tile, sp_chunk, sp_ta_arc, sp_ta_src, sp_ta_gate;
     {
-        const int32_t NS = (Lmax + kSpan - 1) / kSpan;
+        const int32_t NS = (Lmax + kSpanF - 1) / kSpanF;
         g->span_tile_h.assign(NS + 1, 0);
         g->span_fused_h.assign(std::max<int32_t>(NS, 1), 0);
         std::vector<int32_t> gate_lv(G);
@@ -505,23 +505,23 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
         int32_t tile_id = 0;                      // unique per filled tile (never reused)
         for (int32_t s_ = 0; s_ < NS; ++s_) {
             g->span_tile_h[s_] = int32_t(sp_tile.size() / 4);
-            const int32_t l0 = 1 + s_ * kSpan, l1 = std::min<int32_t>(Lmax, l0 + kSpan - 1);
+            const int32_t l0 = 1 + s_ * kSpanF, l1 = std::min<int32_t>(Lmax, l0 + kSpanF - 1);
             const int32_t q0 = lvl_gate_ptr[l0 - 1], q1 = lvl_gate_ptr[l1];
             auto in_span = [&](int32_t u) { return u >= P && (u - P) >= q0 && (u - P) < q1; };
             bool ok = true;
             // the tile being filled: gates per level in insertion order, arcs per level
-            std::vector<std::vector<int32_t>> tg(kSpan);
-            int32_t tarcs[kSpan] = {};
+            std::vector<std::vector<int32_t>> tg(kSpanF);
+            int32_t tarcs[kSpanF] = {};
             auto flush = [&]() {
                 bool any = false;
-                for (int j = 0; j < kSpan; ++j) any = any || !tg[j].empty();
+                for (int j = 0; j < kSpanF; ++j) any = any || !tg[j].empty();
                 if (!any) return;
                 const int32_t c0 = int32_t(sp_chunk.size() / 4);
                 int32_t slot = 0;
-                for (int j = 0; j < kSpan; ++j)
+                for (int j = 0; j < kSpanF; ++j)
                     for (int32_t q : tg[j]) slot_of[q] = slot++;
                 int32_t nch = 0;
-                for (int j = 0; j < kSpan; ++j) {
+                for (int j = 0; j < kSpanF; ++j) {
                     if (tg[j].empty()) continue;
                     const int32_t ta0 = int32_t(sp_ta_arc.size());
                     int32_t maxk = 0;
@@ -538,7 +538,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     ++nch;
                 }
                 sp_tile.insert(sp_tile.end(), {c0, nch, 0, slot});
-                for (int j = 0; j < kSpan; ++j) { tg[j].clear(); tarcs[j] = 0; }
+                for (int j = 0; j < kSpanF; ++j) { tg[j].clear(); tarcs[j] = 0; }
                 ++tile_id;
             };
             for (int32_t l = l1; l >= l0 && ok; --l) {
@@ -558,21 +558,21 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                         }
                     }
                     // arcs the cone adds to the current tile, per level
-                    int32_t add[kSpan] = {}, alone[kSpan] = {};
+                    int32_t add[kSpanF] = {}, alone[kSpanF] = {};
                     for (int32_t q : cone) {
                         const int32_t k = gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q];
                         alone[gate_lv[q] - l0] += k;
                         if (tile_mark[q] != tile_id) add[gate_lv[q] - l0] += k;
                     }
                     bool fits = true, fits_alone = true;
-                    for (int j = 0; j < kSpan; ++j) {
+                    for (int j = 0; j < kSpanF; ++j) {
                         fits = fits && tarcs[j] + add[j] <= kTileSlots;
                         fits_alone = fits_alone && alone[j] <= kTileSlots;
                     }
                     if (!fits_alone) { ok = false; break; }
                     if (!fits) {
                         flush();
-                        for (int j = 0; j < kSpan; ++j) add[j] = alone[j];
+                        for (int j = 0; j < kSpanF; ++j) add[j] = alone[j];
                     }
                     // insert in ascending gate order per level (drivers precede users: lower level)
                     std::sort(cone.begin(), cone.end());
@@ -582,7 +582,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                         tg[gate_lv[q] - l0].push_back(q);
                         covered[q] = 1;
                     }
-                    for (int j = 0; j < kSpan; ++j) tarcs[j] += add[j];
+                    for (int j = 0; j < kSpanF; ++j) tarcs[j] += add[j];
                 }
             }
             if (ok) {
@@ -598,7 +598,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                 sp_ta_arc.resize(afirst);
                 sp_ta_src.resize(afirst);
                 sp_ta_gate.resize(afirst);
-                for (int j = 0; j < kSpan; ++j) { tg[j].clear(); tarcs[j] = 0; }
+                for (int j = 0; j < kSpanF; ++j) { tg[j].clear(); tarcs[j] = 0; }
                 ++tile_id;
                 g->span_fused_h[s_] = 0;
             }

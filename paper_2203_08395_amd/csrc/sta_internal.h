@@ -23,10 +23,13 @@ constexpr int kFwdCapA = 2816, kFwdCapG = 1152, kFwdCapT = 96;
 // view-schedule backward chunks: whole tiles of one driver level
 constexpr int kBwdCapS = 4096, kBwdCapD = 2048, kBwdCapT = 128;
 constexpr size_t kViewTableLdsMax = 65536;            // LDS bytes for tables + axes
-// fused forward spans: kSpan consecutive gate levels per launch; a span tile holds at
-// most 64 cell arcs (one wavefront) per level of the span
-constexpr int kSpan = 4;
-constexpr int kSpanSlots = kSpan * 64;
+// fused spans: kSpanF consecutive gate levels per forward launch, kSpanB driver levels
+// per backward launch (the lengths measured best on the 1M-pin design); a span tile holds
+// at most 64 cell arcs, or 64 sink slots, (one wavefront) per level of the span
+constexpr int kSpanF = 6;
+constexpr int kSpanB = 4;
+constexpr int kSpanSlotsF = kSpanF * 64;
+constexpr int kSpanSlotsB = kSpanB * 64;
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
 struct DevLayout {
@@ -119,7 +122,7 @@ struct sta_graph {
     int32_t n_fchunks = 0, n_bchunks = 0;
     int32_t view_sched_max_arcs = sta::kDefaultViewSchedMaxArcs;
     bool use_graphs = true;              // replay level-schedule launch sequences from hipGraphs
-    bool use_spans = true;               // fuse kSpan levels per forward launch where possible
+    bool use_spans = true;               // fused spans (kSpanF / kSpanB levels per launch) where possible
     std::vector<int32_t> span_tile_h;    // [NS+1] tiles of span s: [p[s], p[s+1]); a span
     std::vector<uint8_t> span_fused_h;   //   with span_fused_h[s] == 0 runs level by level
     int64_t n_sptiles = 0;

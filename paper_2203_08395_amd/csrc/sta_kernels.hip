@@ -475,7 +475,7 @@ __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V,
 
 
 // ---------------------------------------------------------------------------------
-// fused forward spans: kSpan levels per launch, one span tile per wavefront
+// fused forward spans: kSpanF levels per launch, one span tile per wavefront
 // ---------------------------------------------------------------------------------
 
 // fwd_finish for a span chunk: the same arithmetic, plus every view's gate result kept
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
                                                       float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                                       float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
     __shared__ float s_ax[32];
-    __shared__ float2 s_res[4][kSpanSlots * NV];
+    __shared__ float2 s_res[4][kSpanSlotsF * NV];
     load_axes(s_ax, lib);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -565,10 +565,10 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
         early[v] = V.mode[v] == STA_EARLY;
     }
     // round 1: chunk records and the tile's arc records (clamped, unconditional loads)
-    int ta0[kSpan], na[kSpan], sl0[kSpan], mk[kSpan];
-    int ar[kSpan], sc[kSpan], gt[kSpan];
+    int ta0[kSpanF], na[kSpanF], sl0[kSpanF], mk[kSpanF];
+    int ar[kSpanF], sc[kSpanF], gt[kSpanF];
 #pragma unroll
-    for (int c = 0; c < kSpan; ++c) {
+    for (int c = 0; c < kSpanF; ++c) {
         const int cc = c < nch ? c0 + c : c0;
         ta0[c] = G.sp_chunk[cc * 4];
         na[c] = c < nch ? G.sp_chunk[cc * 4 + 1] : 0;
@@ -580,11 +580,11 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
         gt[c] = G.sp_ta_gate[i];
     }
     // round 2: the arcs' static data and the arrivals of drivers outside the span
-    uint32_t meta[kSpan];
-    float ndv[kSpan], niv[kSpan], lov[kSpan];
-    float2 ext[kSpan][NV];
+    uint32_t meta[kSpanF];
+    float ndv[kSpanF], niv[kSpanF], lov[kSpanF];
+    float2 ext[kSpanF][NV];
 #pragma unroll
-    for (int c = 0; c < kSpan; ++c) {
+    for (int c = 0; c < kSpanF; ++c) {
         const int a = ar[c];
         meta[c] = G.arc_meta[a];
         ndv[c] = nd[a];
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
     }
     // the levels of the tile, in order
 #pragma unroll
-    for (int c = 0; c < kSpan; ++c) {
+    for (int c = 0; c < kSpanF; ++c) {
         if (c >= nch) break;                    // uniform
         const bool act = lane < na[c];
         FwdLane x;
@@ -674,7 +674,7 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
                                                        const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
                                                        float* __restrict__ arc_rat, float* __restrict__ drv_slack,
                                                        float* __restrict__ arc_slack) {
-    __shared__ float s_rat[4][kSpanSlots * NV];
+    __shared__ float s_rat[4][kSpanSlotsB * NV];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = tile0 + blockIdx.x * 4 + wave;
     if (t >= tile1) return;
@@ -685,10 +685,10 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
 #pragma unroll
     for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
     // round 1: chunk records and slot records
-    int ts0[kSpan], ns[kSpan], ds0[kSpan];
-    int slot[kSpan], src[kSpan], drv[kSpan];
+    int ts0[kSpanB], ns[kSpanB], ds0[kSpanB];
+    int slot[kSpanB], src[kSpanB], drv[kSpanB];
 #pragma unroll
-    for (int c = 0; c < kSpan; ++c) {
+    for (int c = 0; c < kSpanB; ++c) {
         const int cc = c < nch ? c0 + c : c0;
         ts0[c] = G.bp_chunk[cc * 4];
         ns[c] = c < nch ? G.bp_chunk[cc * 4 + 1] : 0;
@@ -699,11 +699,11 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
         drv[c] = G.bp_drv[i];
     }
     // round 2: slot data (everything that does not come from this tile)
-    int sa_[kSpan], so_[kSpan];
-    bool hd[kSpan];
-    float ndv[kSpan], dl[kSpan][NV], ati[kSpan][NV], ext[kSpan][NV], atd[kSpan][NV];
+    int sa_[kSpanB], so_[kSpanB];
+    bool hd[kSpanB];
+    float ndv[kSpanB], dl[kSpanB][NV], ati[kSpanB][NV], ext[kSpanB][NV], atd[kSpanB][NV];
 #pragma unroll
-    for (int c = 0; c < kSpan; ++c) {
+    for (int c = 0; c < kSpanB; ++c) {
         const int sl = slot[c];
         const int sa = G.bslot_arc[sl];
         const uint32_t bo = uint32_t(G.bslot_out[sl]);
@@ -724,7 +724,7 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
         }
     }
 #pragma unroll
-    for (int c = 0; c < kSpan; ++c) {
+    for (int c = 0; c < kSpanB; ++c) {
         if (c >= nch) break;                    // uniform
         const int n = ns[c];
         const bool act = lane < n;
@@ -1584,8 +1584,8 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
     if constexpr (NV <= 2) {
         if (g->use_spans && !TAB_LDS) {
             const int64_t NS = int64_t(g->span_fused_h.size());
-            for (int64_t sp = 0; sp < NS && sp * kSpan < g->L; ++sp) {
-                const int64_t l0 = 1 + sp * kSpan, l1 = std::min<int64_t>(g->L, l0 + kSpan - 1);
+            for (int64_t sp = 0; sp < NS && sp * kSpanF < g->L; ++sp) {
+                const int64_t l0 = 1 + sp * kSpanF, l1 = std::min<int64_t>(g->L, l0 + kSpanF - 1);
                 if (!g->span_fused_h[sp]) {
                     for (int64_t l = l0; l <= l1; ++l) level(l);
                     continue;
@@ -1653,8 +1653,8 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
     if constexpr (NV <= 2) {
         if (g->use_spans) {
             const int64_t NSB = int64_t(g->bspan_fused_h.size());
-            for (int64_t b = 0; b < NSB && b * kSpan <= g->L; ++b) {
-                const int64_t top = g->L - b * kSpan, bot = std::max<int64_t>(0, top - kSpan + 1);
+            for (int64_t b = 0; b < NSB && b * kSpanB <= g->L; ++b) {
+                const int64_t top = g->L - b * kSpanB, bot = std::max<int64_t>(0, top - kSpanB + 1);
                 if (!g->bspan_fused_h[b]) {
                     for (int64_t l = top; l >= bot; --l) level(l);
                     continue;
