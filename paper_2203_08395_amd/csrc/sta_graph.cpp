@@ -400,7 +400,9 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                 for (int j = 0; j < kSpanB; ++j) {      // j = 0 is the top level: processed first
                     if (td[j].empty()) continue;
                     const int32_t ts0 = int32_t(bp_slot.size());
+                    int32_t maxs = 1;
                     for (int32_t i : td[j]) {
+                        maxs = std::max(maxs, nslots(i));
                         for (int32_t sl = slot_ptr[i]; sl < slot_ptr[i + 1]; ++sl) {
                             const int32_t sa = bslot_arc[sl];
                             int32_t src = -1;
@@ -413,7 +415,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                             bp_drv.push_back(i);
                         }
                     }
-                    bp_chunk.insert(bp_chunk.end(), {ts0, int32_t(bp_slot.size()) - ts0, dslot[td[j][0]], 0});
+                    bp_chunk.insert(bp_chunk.end(), {ts0, int32_t(bp_slot.size()) - ts0, dslot[td[j][0]], maxs});
                     ++nch;
                 }
                 bp_tile.insert(bp_tile.end(), {c0, nch, 0, ds});

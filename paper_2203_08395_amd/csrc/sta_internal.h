@@ -78,7 +78,7 @@ struct DevGraph {
     const int32_t* sp_ta_src;      // per tile arc: its driver (>= 0) or -1 - (slot of an in-tile gate)
     const int32_t* sp_ta_gate;     // per tile arc: its gate
     const int32_t* bp_tile;        // [NT][4] backward span tile: first chunk, chunks, -, drivers
-    const int32_t* bp_chunk;       // [NC][4] one level of a tile: first tile slot, slots, first driver slot, -
+    const int32_t* bp_chunk;       // [NC][4] one level of a tile: first tile slot, slots, first driver slot, most slots of a driver
     const int32_t* bp_slot;        // per tile slot: the backward slot
     const int32_t* bp_src;         // per tile slot: driver slot (in the tile) of the sink's gate output, or -1
     const int32_t* bp_drv;         // per tile slot: its driver

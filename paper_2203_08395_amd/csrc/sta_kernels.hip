@@ -685,7 +685,7 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
 #pragma unroll
     for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
     // round 1: chunk records and slot records
-    int ts0[kSpanB], ns[kSpanB], ds0[kSpanB];
+    int ts0[kSpanB], ns[kSpanB], ds0[kSpanB], ms[kSpanB];
     int slot[kSpanB], src[kSpanB], drv[kSpanB];
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
@@ -693,6 +693,7 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
         ts0[c] = G.bp_chunk[cc * 4];
         ns[c] = c < nch ? G.bp_chunk[cc * 4 + 1] : 0;
         ds0[c] = G.bp_chunk[cc * 4 + 2];
+        ms[c] = G.bp_chunk[cc * 4 + 3];
         const int i = lane < ns[c] ? ts0[c] + lane : ts0[c];
         slot[c] = G.bp_slot[i];
         src[c] = G.bp_src[i];
@@ -751,8 +752,8 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
             }
             best[v] = val;
         }
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
+        // segmented min (max early) over a driver's slots: ceil(log2(most slots)) steps
+        for (int off = 1; off < ms[c]; off <<= 1) {
             const bool take = (lane + off) < seg_end;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
