@@ -478,6 +478,13 @@ __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V,
 // fused forward spans: kSpanF levels per launch, one span tile per wavefront
 // ---------------------------------------------------------------------------------
 
+// Makes a loaded value opaque to the optimizer at this point, so that the load stays where
+// it was issued (ahead of its use) instead of being sunk into the branch that uses it.
+template <typename T>
+__device__ __forceinline__ void pin_value(T& x) {
+    asm volatile("" : "+v"(x));
+}
+
 // fwd_finish for a span chunk: the same arithmetic, plus every view's gate result kept
 // in LDS (slot-indexed) for the tile's gates of the levels above
 template <int NW>
@@ -541,6 +548,7 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
 // then the arcs' static data and the arrivals of drivers outside the span), then the
 // levels in order, each reading its in-span inputs from LDS: one table round per level
 // instead of one launch and three rounds per level.
+// (Staging the tables in LDS per block was measured slower than the L2-resident reads.)
 template <int NV>
 __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
                                                       const float* __restrict__ arc_load,
@@ -549,13 +557,11 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
                                                       float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
     __shared__ float s_ax[32];
     __shared__ float2 s_res[4][kSpanSlotsF * NV];
-    load_axes(s_ax, lib);
-    __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = tile0 + blockIdx.x * 4 + wave;
-    if (t >= tile1) return;
+    const int tc = t < tile1 ? t : tile1 - 1;
     const int lane = threadIdx.x & 63;
-    const int c0 = G.sp_tile[t * 4], nch = G.sp_tile[t * 4 + 1];
+    const int c0 = G.sp_tile[tc * 4], nch = G.sp_tile[tc * 4 + 1];
     float2* res = s_res[wave];
     const float* tab[NV];
     bool early[NV];
@@ -579,6 +585,9 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
         sc[c] = G.sp_ta_src[i];
         gt[c] = G.sp_ta_gate[i];
     }
+    load_axes(s_ax, lib);
+    __syncthreads();
+    if (t >= tile1) return;
     // round 2: the arcs' static data and the arrivals of drivers outside the span
     uint32_t meta[kSpanF];
     float ndv[kSpanF], niv[kSpanF], lov[kSpanF];
@@ -594,6 +603,19 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
         const float2* sp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV;
 #pragma unroll
         for (int v = 0; v < NV; ++v) ext[c][v] = sp[v];
+    }
+    // all of round 2 is in flight; keep it there (one wait before the first level)
+#pragma unroll
+    for (int c = 0; c < kSpanF; ++c) {
+        pin_value(meta[c]);
+        pin_value(ndv[c]);
+        pin_value(niv[c]);
+        pin_value(lov[c]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            pin_value(ext[c][v].x);
+            pin_value(ext[c][v].y);
+        }
     }
     // the levels of the tile, in order
 #pragma unroll
@@ -716,12 +738,24 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
         const float* ext_src = (sa >= 0) ? (drv_rat + size_t(so_[c]) * NV) : (ep_rat + size_t(so_[c]) * NV);
         const float2* ts = reinterpret_cast<const float2*>(arc_ts) + size_t(sac) * NV;
         const float2* dt = reinterpret_cast<const float2*>(drv_ts) + size_t(drv[c]) * NV;
+        const float* ext_ld = src[c] >= 0 ? ep_rat : ext_src;   // in-tile sources: any valid address
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             dl[c][v] = arc_delay[size_t(sac) * NV + v];
             ati[c][v] = ts[v].x;
-            ext[c][v] = (src[c] >= 0) ? 0.0f : ext_src[v];
+            ext[c][v] = ext_ld[v];
             atd[c][v] = dt[v].x;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kSpanB; ++c) {
+        pin_value(ndv[c]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            pin_value(dl[c][v]);
+            pin_value(ati[c][v]);
+            pin_value(ext[c][v]);
+            pin_value(atd[c][v]);
         }
     }
 #pragma unroll
