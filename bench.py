@@ -159,43 +159,57 @@ def main():
         print(json.dumps({"ms_per_step": ms_step, "call_ms": call_ms, "note": "counter run"}), flush=True)
         return
 
-    # which kernels each call launches (library instrumentation, one extra untimed step)
-    sta.profile_begin()
-    sta.delay_calc(g, sta.STA_DC_FP64, out=nd)
-    sta.profile_end()
+    # which kernels each call launches and their durations (library instrumentation:
+    # HIP events around every launch, eager launches; three extra untimed steps, averaged)
     launches = {}
-    for call, fn in (("propagate", lambda: sta.propagate(g, L_lib, views, pi_t, nd, out=tm)),
-                     ("slack", lambda: sta.slack(g, views, nd, tm, rat_t, out=sl))):
-        sta.profile_begin()
-        fn()
-        launches[call] = sta.profile_end()
+    n_prof = 3
+    for _ in range(n_prof):
+        for call, fn in (("delay_calc", lambda: sta.delay_calc(g, sta.STA_DC_FP64, out=nd)),
+                         ("propagate", lambda: sta.propagate(g, L_lib, views, pi_t, nd, out=tm)),
+                         ("slack", lambda: sta.slack(g, views, nd, tm, rat_t, out=sl))):
+            sta.profile_begin()
+            fn()
+            for k, (n, ms) in sta.profile_end().items():
+                n0, ms0 = launches.setdefault(call, {}).get(k, (0, 0.0))
+                launches[call][k] = (n0 + n / n_prof, ms0 + ms / n_prof)
     torch.cuda.synchronize()
 
     updates = (s["n_pins"] - d.n_pi) * V
     value = updates / (ms_step * 1e-3)
-    # algorithmic bytes of one step by call; the dominant kernel of a call is the one
-    # launched per level (or once per view); its average launch duration is the call's
-    # device time over its launch count (the few helper launches are folded in)
+    # algorithmic bytes of one step by pass, and of each timing kernel: the fused-span
+    # kernels cover the gates/arcs (drivers/sink arcs) of the fused spans, each counted
+    # once; the level kernels the rest.  A kernel's device time per step is its call's
+    # time in the timed region (HIP events on the library's stream), apportioned among the
+    # call's kernels by the HIP events the library records around each launch in the
+    # instrumented steps; its average launch duration is that time over its launches.
     fam_bytes = {"forward": fwd_bytes_per_pass(G, A, V), "backward": bwd_bytes_per_pass(D, A, V),
                  "delay_calc": dc_bytes(D, A, M)}
-    call_of = {"delay_calc": "delay_calc", "forward": "propagate", "backward": "slack"}
-    main_kernel = {"delay_calc": "k_delay_calc"}
-    for call in ("propagate", "slack"):
-        main_kernel["forward" if call == "propagate" else "backward"] = max(
-            launches[call], key=lambda k: launches[call][k][0])
+    kstats = {k: v for d_ in launches.values() for k, v in d_.items()}
+    sp = g.spans
+    b_fs = fwd_bytes_per_pass(sp["fwd_span_gates"], sp["fwd_span_arcs"], V) if "k_forward_span" in kstats else 0
+    b_bs = (bwd_bytes_per_pass(sp["bwd_span_drivers"], sp["bwd_span_arcs"], V)
+            if "k_backward_span" in kstats else 0)
+    kbytes = {"k_delay_calc": fam_bytes["delay_calc"],
+              "k_forward_span": b_fs, "k_forward": fam_bytes["forward"] - b_fs,
+              "k_forward_view": fam_bytes["forward"],
+              "k_backward_span": b_bs, "k_backward": fam_bytes["backward"] - b_bs}
     kernels = {}
-    for fam, kname in main_kernel.items():
-        n = 1 if fam == "delay_calc" else launches[call_of[fam]][kname][0]
-        ms = call_ms[call_of[fam]]
-        kernels[kname] = {"launches_per_step": n, "avg_us": 1e3 * ms / n, "ms_per_step": ms,
-                          "bytes_per_launch": fam_bytes[fam] / n,
-                          "GB_s": fam_bytes[fam] / (ms * 1e-3) / 1e9}
+    for call, ks in launches.items():
+        ev_total = sum(ms for _, ms in ks.values())
+        for kname, (n, ev_ms) in ks.items():
+            n = int(round(n))
+            if kname not in kbytes or n == 0:
+                continue
+            ms = call_ms[call] * ev_ms / ev_total
+            kernels[kname] = {"launches_per_step": n, "avg_us": 1e3 * ms / n, "ms_per_step": ms,
+                              "instrumented_avg_us": 1e3 * ev_ms / n,
+                              "bytes_per_launch": kbytes[kname] / n,
+                              "GB_s": kbytes[kname] / (ms * 1e-3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     dk = kernels[dom]
     achieved = dk["GB_s"]
     traffic = measured_traffic(dom)
     ms_prop = call_ms["propagate"]
-    kstats = {k: v for d_ in launches.values() for k, v in d_.items()}
 
     out = {
         "metric": METRIC,
@@ -224,6 +238,7 @@ def main():
         "call_ms": call_ms,
         "propagate_pin_updates_per_s": updates / (ms_prop * 1e-3),
         "kernels": kernels,
+        "fusion_plan": sp,
         "algorithmic_bytes_per_step": fam_bytes,
         "pass_GB_s": sum(fam_bytes.values()) / (ms_step * 1e-3) / 1e9,
         "schedule": ("view" if "k_forward_view" in kstats else "span" if "k_forward_span" in kstats else "level")

@@ -230,6 +230,39 @@ sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32
  * span whose closure does not fit runs level by level.  The view schedule is unaffected. */
 sta_status sta_set_level_fusion(sta_graph* g, int32_t enable);
 
+/* The fusion plan of a built graph (host only; independent of sta_set_level_fusion,
+ * which decides whether it is used).  Launch counts are those of one forward or one
+ * backward pass of one or two views with fusion on; the fused kernels' algorithmic work is
+ * the gates, cell arcs, drivers and sink arcs of their spans counted once, and
+ * *_computed counts evaluations as performed (a cone shared by several tiles is
+ * evaluated in each). */
+typedef struct {
+    int64_t fwd_spans, fwd_spans_fused;         /* forward spans, of which fused          */
+    int64_t fwd_span_launches;                  /* fused forward launches (non-empty)      */
+    int64_t fwd_level_launches;                 /* level launches of the unfused spans     */
+    int64_t fwd_span_gates, fwd_span_arcs;      /* gates and cell arcs of the fused spans   */
+    int64_t fwd_span_arcs_computed;
+    int64_t fwd_span_tiles;
+    int64_t bwd_spans, bwd_spans_fused;
+    int64_t bwd_span_launches, bwd_level_launches;
+    int64_t bwd_span_drivers, bwd_span_arcs;    /* drivers and their sink arcs, fused spans */
+    int64_t bwd_span_slots_computed;            /* sink slots evaluated (a driver without
+                                                   fanout has one slot)                    */
+    int64_t bwd_span_tiles;
+} sta_span_info;
+
+sta_status sta_graph_spans(const sta_graph* g, sta_span_info* out);
+
+/* The spans themselves, host arrays (either may be null):
+ *   fwd[fwd_spans][3]  first gate level, last gate level, fused (1) or level launch (0),
+ *                      in launch order (bottom up)
+ *   bwd[bwd_spans][3]  top driver level, bottom driver level, fused, in launch order
+ *                      (top down)
+ * Spans partition the levels: forward 1..L, backward 0..L.  A span is at most six
+ * (forward) or four (backward) levels long; the builder takes the longest span from the
+ * next uncovered level that can be tiled, and an unfused span is a single level. */
+sta_status sta_graph_span_list(const sta_graph* g, int32_t* fwd, int32_t* bwd);
+
 /* Per-kernel timing record of the instrumentation calls below. */
 typedef struct {
     char name[48];        /* kernel name (template arguments dropped)      */

@@ -362,42 +362,45 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
 
 
     // ---- fused backward spans ------------------------------------------------------------
-    // Span b covers driver levels [max(0, L-(b+1)k+1), L-bk], processed top down.  A tile
-    // is a set of drivers closed under in-span sinks: the output driver of every gate a
-    // tile driver feeds, when its level lies in the span, is in the tile too.  Roots are
-    // taken bottom level first; a tile holds <= 64 slots per level; a driver with more than
-    // 64 slots makes its span run level by level.
+    // Spans of driver levels, processed top down: from the highest level not yet covered,
+    // the longest span [top - n + 1, top] (n <= kSpanB) that can be tiled is taken; a level
+    // that cannot be tiled even alone runs as a level launch.  A tile is a set of drivers
+    // closed under in-span sinks: the output driver of every gate a tile driver feeds, when
+    // its level lies in the span, is in the tile too.  Roots are taken bottom level first;
+    // a tile holds <= 64 slots per level.
     std::vector<int32_t> bp_tile, bp_chunk, bp_slot, bp_src, bp_drv;
     {
-        const int32_t NSB = (Lmax + 1 + kSpanB - 1) / kSpanB;
-        g->bspan_tile_h.assign(NSB + 1, 0);
-        g->bspan_fused_h.assign(std::max<int32_t>(NSB, 1), 0);
+        g->bspan_tile_h.clear();
+        g->bspan_fused_h.clear();
+        g->bspan_lv_h.clear();
         auto drv_range = [&](int32_t l, int64_t& i0, int64_t& i1) {
             i0 = (l == 0) ? 0 : P + lvl_gate_ptr[l - 1];
             i1 = (l == 0) ? P : P + lvl_gate_ptr[l];
         };
         std::vector<int32_t> mark(D, -1), dslot(D, -1), tile_mark(D, -1), stack, cone;
         std::vector<uint8_t> covered(D, 0);
-        int32_t tile_id = 0;
-        for (int32_t b = 0; b < NSB; ++b) {
-            g->bspan_tile_h[b] = int32_t(bp_tile.size() / 4);
-            const int32_t top = Lmax - b * kSpanB, bot = std::max<int32_t>(0, top - kSpanB + 1);
-            auto lv = [&](int64_t i) { return g->level[i]; };
+        int32_t tile_id = 0;   // unique per filled tile (never reused)
+        int32_t stamp = 0;     // unique per cone search (never reused)
+        auto lv = [&](int64_t i) { return g->level[i]; };
+        auto nslots = [&](int64_t i) { return slot_ptr[i + 1] - slot_ptr[i]; };
+        // tiles the span [bot, top]; on failure removes what it appended and returns false
+        auto try_span = [&](int32_t top, int32_t bot) -> bool {
             auto in_span = [&](int64_t i) { return lv(i) >= bot && lv(i) <= top; };
+            const int32_t nl = top - bot + 1;
+            const size_t t0 = bp_tile.size(), c0all = bp_chunk.size(), s0all = bp_slot.size();
             bool ok = true;
-            std::vector<std::vector<int32_t>> td(kSpanB);     // drivers per level (index top - level)
+            std::vector<std::vector<int32_t>> td(nl);     // drivers per level (index top - level)
             int32_t tslots[kSpanB] = {};
-            auto nslots = [&](int64_t i) { return slot_ptr[i + 1] - slot_ptr[i]; };
             auto flush = [&]() {
                 bool any = false;
-                for (int j = 0; j < kSpanB; ++j) any = any || !td[j].empty();
+                for (int j = 0; j < nl; ++j) any = any || !td[j].empty();
                 if (!any) return;
                 const int32_t c0 = int32_t(bp_chunk.size() / 4);
                 int32_t ds = 0;
-                for (int j = 0; j < kSpanB; ++j)
+                for (int j = 0; j < nl; ++j)
                     for (int32_t i : td[j]) dslot[i] = ds++;
                 int32_t nch = 0;
-                for (int j = 0; j < kSpanB; ++j) {      // j = 0 is the top level: processed first
+                for (int j = 0; j < nl; ++j) {      // j = 0 is the top level: processed first
                     if (td[j].empty()) continue;
                     const int32_t ts0 = int32_t(bp_slot.size());
                     int32_t maxs = 1;
@@ -419,7 +422,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     ++nch;
                 }
                 bp_tile.insert(bp_tile.end(), {c0, nch, 0, ds});
-                for (int j = 0; j < kSpanB; ++j) { td[j].clear(); tslots[j] = 0; }
+                for (int j = 0; j < nl; ++j) { td[j].clear(); tslots[j] = 0; }
                 ++tile_id;
             };
             for (int32_t l = bot; l <= top && ok; ++l) {
@@ -429,7 +432,8 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     if (covered[r]) continue;
                     cone.clear();
                     stack.assign(1, int32_t(r));
-                    mark[r] = int32_t(r);
+                    const int32_t st = stamp++;
+                    mark[r] = st;
                     while (!stack.empty()) {
                         const int32_t i = stack.back();
                         stack.pop_back();
@@ -438,7 +442,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                             const int32_t sa = bslot_arc[sl];
                             if (sa < 0) continue;
                             const int32_t o = int32_t(P + int_gate_of_arc[sa]);
-                            if (in_span(o) && mark[o] != r) { mark[o] = int32_t(r); stack.push_back(o); }
+                            if (in_span(o) && mark[o] != st) { mark[o] = st; stack.push_back(o); }
                         }
                     }
                     int32_t add[kSpanB] = {}, alone[kSpanB] = {};
@@ -448,14 +452,14 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                         if (tile_mark[i] != tile_id) add[top - lv(i)] += k;
                     }
                     bool fits = true, fits_alone = true;
-                    for (int j = 0; j < kSpanB; ++j) {
+                    for (int j = 0; j < nl; ++j) {
                         fits = fits && tslots[j] + add[j] <= kTileSlots;
                         fits_alone = fits_alone && alone[j] <= kTileSlots;
                     }
                     if (!fits_alone) { ok = false; break; }
                     if (!fits) {
                         flush();
-                        for (int j = 0; j < kSpanB; ++j) add[j] = alone[j];
+                        for (int j = 0; j < nl; ++j) add[j] = alone[j];
                     }
                     std::sort(cone.begin(), cone.end());
                     for (int32_t i : cone) {
@@ -464,39 +468,54 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                         td[top - lv(i)].push_back(i);
                         covered[i] = 1;
                     }
-                    for (int j = 0; j < kSpanB; ++j) tslots[j] += add[j];
+                    for (int j = 0; j < nl; ++j) tslots[j] += add[j];
                 }
             }
             if (ok) {
                 flush();
-                g->bspan_fused_h[b] = 1;
-            } else {
-                const int32_t t0 = g->bspan_tile_h[b];
-                const int32_t cfirst = t0 < int32_t(bp_tile.size() / 4) ? bp_tile[t0 * 4] : int32_t(bp_chunk.size() / 4);
-                const int32_t sfirst = cfirst < int32_t(bp_chunk.size() / 4) ? bp_chunk[cfirst * 4] : int32_t(bp_slot.size());
-                bp_tile.resize(size_t(t0) * 4);
-                bp_chunk.resize(size_t(cfirst) * 4);
-                bp_slot.resize(sfirst);
-                bp_src.resize(sfirst);
-                bp_drv.resize(sfirst);
-                for (int j = 0; j < kSpanB; ++j) { td[j].clear(); tslots[j] = 0; }
-                ++tile_id;
-                g->bspan_fused_h[b] = 0;
+                return true;
             }
+            bp_tile.resize(t0);
+            bp_chunk.resize(c0all);
+            bp_slot.resize(s0all);
+            bp_src.resize(s0all);
+            bp_drv.resize(s0all);
+            ++tile_id;
+            for (int32_t l = bot; l <= top; ++l) {
+                int64_t i0, i1;
+                drv_range(l, i0, i1);
+                for (int64_t r = i0; r < i1; ++r) covered[r] = 0;
+            }
+            return false;
+        };
+        for (int32_t top = Lmax; top >= 0;) {
+            const int32_t t0 = int32_t(bp_tile.size() / 4);
+            int32_t n = std::min<int32_t>(kSpanB, top + 1);
+            bool ok = try_span(top, top - n + 1);
+            while (!ok && n > 1) {
+                --n;
+                ok = try_span(top, top - n + 1);
+            }
+            g->bspan_tile_h.push_back(t0);
+            g->bspan_fused_h.push_back(uint8_t(ok));
+            g->bspan_lv_h.insert(g->bspan_lv_h.end(), {top, top - n + 1});
+            top -= n;
         }
-        g->bspan_tile_h[NSB] = int32_t(bp_tile.size() / 4);
+        g->bspan_tile_h.push_back(int32_t(bp_tile.size() / 4));
     }
 
     // ---- fused forward spans -------------------------------------------------------------
-    // Span s covers gate levels [1 + s*kSpanF, (s+1)*kSpanF].  A span tile computes, level by
-    // level inside one wavefront, a set of gates closed under in-span fanin: every in-span
-    // driver of a tile gate is itself in the tile (so it may be computed by several tiles,
+    // Spans of gate levels, bottom up: from the lowest level not yet covered, the longest
+    // span [l0, l0 + n - 1] (n <= kSpanF) that can be tiled is taken; a level that cannot
+    // be tiled even alone runs as a level launch.  A span tile computes, level by level
+    // inside one wavefront, a set of gates closed under in-span fanin: every in-span driver
+    // of a tile gate is itself in the tile (so it may be computed by several tiles,
     // identically).  Roots are taken top level first; a tile holds <= 64 arcs per level.
     std::vector<int32_t> sp_tile, sp_chunk, sp_ta_arc, sp_ta_src, sp_ta_gate;
     {
-        const int32_t NS = (Lmax + kSpanF - 1) / kSpanF;
-        g->span_tile_h.assign(NS + 1, 0);
-        g->span_fused_h.assign(std::max<int32_t>(NS, 1), 0);
+        g->span_tile_h.clear();
+        g->span_fused_h.clear();
+        g->span_lv_h.clear();
         std::vector<int32_t> gate_lv(G);
         for (int32_t l = 1; l <= Lmax; ++l)
             for (int32_t q = lvl_gate_ptr[l - 1]; q < lvl_gate_ptr[l]; ++q) gate_lv[q] = l;
@@ -505,25 +524,26 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
         std::vector<int32_t> stack, cone;
         std::vector<int32_t> tile_mark(G, -1);   // id of the tile being filled that holds the gate
         int32_t tile_id = 0;                      // unique per filled tile (never reused)
-        for (int32_t s_ = 0; s_ < NS; ++s_) {
-            g->span_tile_h[s_] = int32_t(sp_tile.size() / 4);
-            const int32_t l0 = 1 + s_ * kSpanF, l1 = std::min<int32_t>(Lmax, l0 + kSpanF - 1);
+        int32_t stamp = 0;                        // unique per cone search (never reused)
+        auto try_span = [&](int32_t l0, int32_t l1) -> bool {
             const int32_t q0 = lvl_gate_ptr[l0 - 1], q1 = lvl_gate_ptr[l1];
             auto in_span = [&](int32_t u) { return u >= P && (u - P) >= q0 && (u - P) < q1; };
+            const int32_t nl = l1 - l0 + 1;
+            const size_t t0 = sp_tile.size(), c0all = sp_chunk.size(), a0all = sp_ta_arc.size();
             bool ok = true;
             // the tile being filled: gates per level in insertion order, arcs per level
-            std::vector<std::vector<int32_t>> tg(kSpanF);
+            std::vector<std::vector<int32_t>> tg(nl);
             int32_t tarcs[kSpanF] = {};
             auto flush = [&]() {
                 bool any = false;
-                for (int j = 0; j < kSpanF; ++j) any = any || !tg[j].empty();
+                for (int j = 0; j < nl; ++j) any = any || !tg[j].empty();
                 if (!any) return;
                 const int32_t c0 = int32_t(sp_chunk.size() / 4);
                 int32_t slot = 0;
-                for (int j = 0; j < kSpanF; ++j)
+                for (int j = 0; j < nl; ++j)
                     for (int32_t q : tg[j]) slot_of[q] = slot++;
                 int32_t nch = 0;
-                for (int j = 0; j < kSpanF; ++j) {
+                for (int j = 0; j < nl; ++j) {
                     if (tg[j].empty()) continue;
                     const int32_t ta0 = int32_t(sp_ta_arc.size());
                     int32_t maxk = 0;
@@ -540,7 +560,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     ++nch;
                 }
                 sp_tile.insert(sp_tile.end(), {c0, nch, 0, slot});
-                for (int j = 0; j < kSpanF; ++j) { tg[j].clear(); tarcs[j] = 0; }
+                for (int j = 0; j < nl; ++j) { tg[j].clear(); tarcs[j] = 0; }
                 ++tile_id;
             };
             for (int32_t l = l1; l >= l0 && ok; --l) {
@@ -549,14 +569,15 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     // cone of r: r and its in-span ancestors
                     cone.clear();
                     stack.assign(1, r);
-                    mark[r] = r;
+                    const int32_t st = stamp++;
+                    mark[r] = st;
                     while (!stack.empty()) {
                         const int32_t q = stack.back();
                         stack.pop_back();
                         cone.push_back(q);
                         for (int32_t a = gate_arc_ptr_int[q]; a < gate_arc_ptr_int[q + 1]; ++a) {
                             const int32_t u = arc_src[a];
-                            if (in_span(u) && mark[u - P] != r) { mark[u - P] = r; stack.push_back(u - P); }
+                            if (in_span(u) && mark[u - P] != st) { mark[u - P] = st; stack.push_back(u - P); }
                         }
                     }
                     // arcs the cone adds to the current tile, per level
@@ -567,14 +588,14 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                         if (tile_mark[q] != tile_id) add[gate_lv[q] - l0] += k;
                     }
                     bool fits = true, fits_alone = true;
-                    for (int j = 0; j < kSpanF; ++j) {
+                    for (int j = 0; j < nl; ++j) {
                         fits = fits && tarcs[j] + add[j] <= kTileSlots;
                         fits_alone = fits_alone && alone[j] <= kTileSlots;
                     }
                     if (!fits_alone) { ok = false; break; }
                     if (!fits) {
                         flush();
-                        for (int j = 0; j < kSpanF; ++j) add[j] = alone[j];
+                        for (int j = 0; j < nl; ++j) add[j] = alone[j];
                     }
                     // insert in ascending gate order per level (drivers precede users: lower level)
                     std::sort(cone.begin(), cone.end());
@@ -584,29 +605,87 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                         tg[gate_lv[q] - l0].push_back(q);
                         covered[q] = 1;
                     }
-                    for (int j = 0; j < kSpanF; ++j) tarcs[j] += add[j];
+                    for (int j = 0; j < nl; ++j) tarcs[j] += add[j];
                 }
             }
             if (ok) {
                 flush();
-                g->span_fused_h[s_] = 1;
-            } else {
-                // roll back this span's tiles: it runs level by level
-                const int32_t t0 = g->span_tile_h[s_];
-                const int32_t cfirst = t0 < int32_t(sp_tile.size() / 4) ? sp_tile[t0 * 4] : int32_t(sp_chunk.size() / 4);
-                const int32_t afirst = cfirst < int32_t(sp_chunk.size() / 4) ? sp_chunk[cfirst * 4] : int32_t(sp_ta_arc.size());
-                sp_tile.resize(size_t(t0) * 4);
-                sp_chunk.resize(size_t(cfirst) * 4);
-                sp_ta_arc.resize(afirst);
-                sp_ta_src.resize(afirst);
-                sp_ta_gate.resize(afirst);
-                for (int j = 0; j < kSpanF; ++j) { tg[j].clear(); tarcs[j] = 0; }
-                ++tile_id;
-                g->span_fused_h[s_] = 0;
+                return true;
             }
+            // roll back this attempt's tiles
+            sp_tile.resize(t0);
+            sp_chunk.resize(c0all);
+            sp_ta_arc.resize(a0all);
+            sp_ta_src.resize(a0all);
+            sp_ta_gate.resize(a0all);
+            ++tile_id;
+            for (int32_t q = q0; q < q1; ++q) covered[q] = 0;
+            return false;
+        };
+        for (int32_t l0 = 1; l0 <= Lmax;) {
+            const int32_t t0 = int32_t(sp_tile.size() / 4);
+            int32_t n = std::min<int32_t>(kSpanF, Lmax - l0 + 1);
+            bool ok = try_span(l0, l0 + n - 1);
+            while (!ok && n > 1) {
+                --n;
+                ok = try_span(l0, l0 + n - 1);
+            }
+            g->span_tile_h.push_back(t0);
+            g->span_fused_h.push_back(uint8_t(ok));
+            g->span_lv_h.insert(g->span_lv_h.end(), {l0, l0 + n - 1});
+            l0 += n;
         }
-        g->span_tile_h[NS] = int32_t(sp_tile.size() / 4);
+        g->span_tile_h.push_back(int32_t(sp_tile.size() / 4));
         g->n_sptiles = int64_t(sp_tile.size() / 4);
+    }
+
+    // ---- fusion plan figures (reports) -----------------------------------------------------
+    {
+        sta_span_info& si = g->span_info;
+        si = sta_span_info{};
+        auto first_of = [](const std::vector<int32_t>& outer, int32_t idx, int64_t n_inner) -> int64_t {
+            return idx < int32_t(outer.size() / 4) ? outer[size_t(idx) * 4] : n_inner;
+        };
+        const int64_t NS = int64_t(g->span_fused_h.size());
+        for (int64_t s_ = 0; s_ < NS; ++s_) {
+            const int32_t l0 = g->span_lv_h[2 * s_], l1 = g->span_lv_h[2 * s_ + 1];
+            ++si.fwd_spans;
+            if (!g->span_fused_h[s_]) {
+                for (int32_t l = l0; l <= l1; ++l) si.fwd_level_launches += g->fwd_tile_ptr[l + 1] > g->fwd_tile_ptr[l];
+                continue;
+            }
+            ++si.fwd_spans_fused;
+            const int32_t t0 = g->span_tile_h[s_], t1 = g->span_tile_h[s_ + 1];
+            si.fwd_span_launches += t1 > t0;
+            si.fwd_span_tiles += t1 - t0;
+            const int32_t q0 = lvl_gate_ptr[l0 - 1], q1 = lvl_gate_ptr[l1];
+            si.fwd_span_gates += q1 - q0;
+            si.fwd_span_arcs += gate_arc_ptr_int[q1] - gate_arc_ptr_int[q0];
+            const int64_t nch = int64_t(sp_chunk.size() / 4), na = int64_t(sp_ta_arc.size());
+            const int64_t a0 = first_of(sp_chunk, int32_t(first_of(sp_tile, t0, nch)), na);
+            const int64_t a1 = first_of(sp_chunk, int32_t(first_of(sp_tile, t1, nch)), na);
+            si.fwd_span_arcs_computed += a1 - a0;
+        }
+        const int64_t NSB = int64_t(g->bspan_fused_h.size());
+        for (int64_t b = 0; b < NSB; ++b) {
+            const int32_t top = g->bspan_lv_h[2 * b], bot = g->bspan_lv_h[2 * b + 1];
+            ++si.bwd_spans;
+            if (!g->bspan_fused_h[b]) {
+                for (int32_t l = top; l >= bot; --l) si.bwd_level_launches += g->bwd_tile_ptr[l + 1] > g->bwd_tile_ptr[l];
+                continue;
+            }
+            ++si.bwd_spans_fused;
+            const int32_t t0 = g->bspan_tile_h[b], t1 = g->bspan_tile_h[b + 1];
+            si.bwd_span_launches += t1 > t0;
+            si.bwd_span_tiles += t1 - t0;
+            const int64_t i0 = (bot == 0) ? 0 : P + lvl_gate_ptr[bot - 1], i1 = P + lvl_gate_ptr[top];
+            si.bwd_span_drivers += i1 - i0;
+            si.bwd_span_arcs += fo_ptr[i1] - fo_ptr[i0];
+            const int64_t nch = int64_t(bp_chunk.size() / 4), ns = int64_t(bp_slot.size());
+            const int64_t s0 = first_of(bp_chunk, int32_t(first_of(bp_tile, t0, nch)), ns);
+            const int64_t s1 = first_of(bp_chunk, int32_t(first_of(bp_tile, t1, nch)), ns);
+            si.bwd_span_slots_computed += s1 - s0;
+        }
     }
 
     // ---- device image --------------------------------------------------------------------
@@ -763,6 +842,29 @@ sta_status sta_graph_sizes(const sta_graph* g, sta_sizes* s) {
     s->n_bwd_tiles = g->n_btiles;
     s->graph_bytes = g->lay.total;
     s->scratch_bytes = sta::scratch_bytes();
+    return STA_OK;
+}
+
+sta_status sta_graph_spans(const sta_graph* g, sta_span_info* out) {
+    if (!g || !out) return sta::fail(STA_E_ARG, "sta_graph_spans: null argument");
+    *out = g->span_info;
+    return STA_OK;
+}
+
+sta_status sta_graph_span_list(const sta_graph* g, int32_t* fwd, int32_t* bwd) {
+    if (!g) return sta::fail(STA_E_ARG, "sta_graph_span_list: null graph");
+    if (fwd)
+        for (size_t s = 0; s < g->span_fused_h.size(); ++s) {
+            fwd[3 * s] = g->span_lv_h[2 * s];
+            fwd[3 * s + 1] = g->span_lv_h[2 * s + 1];
+            fwd[3 * s + 2] = g->span_fused_h[s];
+        }
+    if (bwd)
+        for (size_t b = 0; b < g->bspan_fused_h.size(); ++b) {
+            bwd[3 * b] = g->bspan_lv_h[2 * b];
+            bwd[3 * b + 1] = g->bspan_lv_h[2 * b + 1];
+            bwd[3 * b + 2] = g->bspan_fused_h[b];
+        }
     return STA_OK;
 }
 

@@ -123,11 +123,14 @@ struct sta_graph {
     int32_t view_sched_max_arcs = sta::kDefaultViewSchedMaxArcs;
     bool use_graphs = true;              // replay level-schedule launch sequences from hipGraphs
     bool use_spans = true;               // fused spans (kSpanF / kSpanB levels per launch) where possible
-    std::vector<int32_t> span_tile_h;    // [NS+1] tiles of span s: [p[s], p[s+1]); a span
-    std::vector<uint8_t> span_fused_h;   //   with span_fused_h[s] == 0 runs level by level
+    std::vector<int32_t> span_tile_h;    // [NS+1] tiles of forward span s: [p[s], p[s+1]); a
+    std::vector<uint8_t> span_fused_h;   //   span with span_fused_h[s] == 0 runs as a level launch
+    std::vector<int32_t> span_lv_h;      // [NS][2] first and last gate level of span s (bottom up)
     int64_t n_sptiles = 0;
-    std::vector<int32_t> bspan_tile_h;   // backward spans, span b = driver levels
-    std::vector<uint8_t> bspan_fused_h;  //   [max(0, L-(b+1)k+1), L-bk], processed top down
+    std::vector<int32_t> bspan_tile_h;   // the same for the backward spans, whose driver levels
+    std::vector<uint8_t> bspan_fused_h;  //   are bspan_lv_h[2b] (top) down to bspan_lv_h[2b + 1],
+    std::vector<int32_t> bspan_lv_h;     //   processed top down
+    sta_span_info span_info{};           // fusion plan figures (sta_graph_spans)
     mutable std::mutex cache_mu;
     mutable sta::LaunchCache fwd_cache, bwd_cache, adj_cache;
     sta::DevLayout lay{};

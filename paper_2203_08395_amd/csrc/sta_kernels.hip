@@ -1619,8 +1619,8 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
     if constexpr (NV <= 2) {
         if (g->use_spans && !TAB_LDS) {
             const int64_t NS = int64_t(g->span_fused_h.size());
-            for (int64_t sp = 0; sp < NS && sp * kSpanF < g->L; ++sp) {
-                const int64_t l0 = 1 + sp * kSpanF, l1 = std::min<int64_t>(g->L, l0 + kSpanF - 1);
+            for (int64_t sp = 0; sp < NS; ++sp) {
+                const int64_t l0 = g->span_lv_h[2 * sp], l1 = g->span_lv_h[2 * sp + 1];
                 if (!g->span_fused_h[sp]) {
                     for (int64_t l = l0; l <= l1; ++l) level(l);
                     continue;
@@ -1688,8 +1688,8 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
     if constexpr (NV <= 2) {
         if (g->use_spans) {
             const int64_t NSB = int64_t(g->bspan_fused_h.size());
-            for (int64_t b = 0; b < NSB && b * kSpanB <= g->L; ++b) {
-                const int64_t top = g->L - b * kSpanB, bot = std::max<int64_t>(0, top - kSpanB + 1);
+            for (int64_t b = 0; b < NSB; ++b) {
+                const int64_t top = g->bspan_lv_h[2 * b], bot = g->bspan_lv_h[2 * b + 1];
                 if (!g->bspan_fused_h[b]) {
                     for (int64_t l = top; l >= bot; --l) level(l);
                     continue;

@@ -44,6 +44,14 @@ class Sizes(ctypes.Structure):
                [("graph_bytes", ctypes.c_size_t), ("scratch_bytes", ctypes.c_size_t)]
 
 
+class SpanInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("fwd_spans", "fwd_spans_fused", "fwd_span_launches", "fwd_level_launches", "fwd_span_gates",
+                 "fwd_span_arcs", "fwd_span_arcs_computed", "fwd_span_tiles", "bwd_spans", "bwd_spans_fused",
+                 "bwd_span_launches", "bwd_level_launches", "bwd_span_drivers", "bwd_span_arcs",
+                 "bwd_span_slots_computed", "bwd_span_tiles")]
+
+
 class LibraryC(ctypes.Structure):
     _fields_ = [("x", ctypes.c_float * 7), ("y", ctypes.c_float * 7), ("tables", _P),
                 ("n_sets", ctypes.c_int32), ("n_tables", ctypes.c_int32)]
@@ -70,7 +78,7 @@ _lib = None
 
 EXPORTS = ("sta_last_error", "sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload",
            "sta_graph_free", "sta_delay_calc", "sta_propagate", "sta_slack", "sta_set_schedule", "sta_set_level_fusion",
-           "sta_profile_begin", "sta_profile_end")
+           "sta_graph_spans", "sta_graph_span_list", "sta_profile_begin", "sta_profile_end")
 
 
 class KernelStat(ctypes.Structure):
@@ -103,11 +111,13 @@ def load_library():
                               ctypes.POINTER(SlackOut), _P, ctypes.c_size_t, _P]
     lib.sta_set_schedule.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
     lib.sta_set_level_fusion.argtypes = [_P, ctypes.c_int32]
+    lib.sta_graph_spans.argtypes = [_P, ctypes.POINTER(SpanInfo)]
+    lib.sta_graph_span_list.argtypes = [_P, _P, _P]
     lib.sta_profile_begin.argtypes = []
     lib.sta_profile_end.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     for f in ("sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload", "sta_delay_calc",
-              "sta_propagate", "sta_slack", "sta_set_schedule", "sta_set_level_fusion", "sta_profile_begin",
-              "sta_profile_end"):
+              "sta_propagate", "sta_slack", "sta_set_schedule", "sta_set_level_fusion", "sta_graph_spans",
+              "sta_graph_span_list", "sta_profile_begin", "sta_profile_end"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -182,9 +192,27 @@ class Graph:
         return self
 
     def set_level_fusion(self, enable):
-        """Fuse four levels per forward launch (span tiles; default on)."""
+        """Fused spans: six gate levels per forward launch and four driver levels per
+        backward launch (default on)."""
         _check(load_library().sta_set_level_fusion(self._h, int(bool(enable))), "sta_set_level_fusion")
         return self
+
+    @property
+    def spans(self):
+        """The fusion plan: fused spans, launches and the work they cover."""
+        si = SpanInfo()
+        _check(load_library().sta_graph_spans(self._h, ctypes.byref(si)), "sta_graph_spans")
+        return {f: int(getattr(si, f)) for f, _ in SpanInfo._fields_}
+
+    def span_list(self):
+        """(forward, backward) spans as int32 arrays of rows (first or top level, last or
+        bottom level, fused), in launch order."""
+        sp = self.spans
+        fwd = np.zeros((sp["fwd_spans"], 3), np.int32)
+        bwd = np.zeros((sp["bwd_spans"], 3), np.int32)
+        _check(load_library().sta_graph_span_list(self._h, fwd.ctypes.data if fwd.size else None,
+                                                  bwd.ctypes.data if bwd.size else None), "sta_graph_span_list")
+        return fwd, bwd
 
     @property
     def handle(self):

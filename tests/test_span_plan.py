@@ -1,0 +1,109 @@
+"""Host-side checks of the fusion plan a graph build makes (sta_graph_spans,
+sta_graph_span_list): the spans partition the levels, their lengths respect the caps, and
+the work credited to the fused launches is exactly the gates, arcs, drivers and sink arcs
+of the fused spans.  No GPU is touched."""
+import numpy as np
+import pytest
+
+from paper_2203_08395_amd import gen, sta
+
+K_F, K_B = 6, 4   # most gate levels per forward span, driver levels per backward span
+
+
+def _plan(cfg):
+    d = gen.make_design(**cfg)
+    g = sta.Graph(d, n_tables=128)
+    s = g.sizes
+    D = s["n_drivers"]
+    level = np.zeros(D, np.int32)
+    gate_in = np.zeros(s["n_gates"], np.int32)
+    drv_in = np.zeros(D, np.int32)
+    lib = sta.load_library()
+    assert lib.sta_graph_perm(g.handle, drv_in.ctypes.data, None, gate_in.ctypes.data, level.ctypes.data, None) == 0
+    fanout = np.bincount(d.arc_drv, minlength=D)[drv_in]     # per internal driver
+    fanin = np.diff(d.gate_arc_ptr)[gate_in]                 # per internal gate
+    return d, g, s, level, fanout, fanin
+
+
+CASES = [
+    dict(n_pins=300, n_levels=13, seed=4),
+    dict(n_pins=3000, n_levels=20, fanin="geom", seed=3, n_fanout64=2),
+    dict(n_pins=3000, n_levels=7, fanin="geom", seed=6, n_fanout64=3),
+    gen.CONFIGS["c1"],
+]
+
+
+@pytest.mark.parametrize("cfg", CASES, ids=["tiny", "fanout64", "wide", "c1"])
+def test_spans_partition_levels_and_credit_their_work(cfg):
+    d, g, s, level, fanout, fanin = _plan(cfg)
+    sp = g.spans
+    fwd, bwd = g.span_list()
+    L, P = s["n_levels"], s["n_pi"]
+    gate_lv = level[P:]
+    # forward: consecutive bottom-up spans covering 1..L, each 1..K_F levels, unfused ones single
+    assert fwd[0, 0] == 1 and fwd[-1, 1] == L
+    assert np.all(fwd[1:, 0] == fwd[:-1, 1] + 1)
+    n = fwd[:, 1] - fwd[:, 0] + 1
+    assert np.all((n >= 1) & (n <= K_F))
+    assert np.all((fwd[:, 2] == 1) | (n == 1))
+    # backward: consecutive top-down spans covering L..0
+    assert bwd[0, 0] == L and bwd[-1, 1] == 0
+    assert np.all(bwd[1:, 0] == bwd[:-1, 1] - 1)
+    nb = bwd[:, 0] - bwd[:, 1] + 1
+    assert np.all((nb >= 1) & (nb <= K_B))
+    assert np.all((bwd[:, 2] == 1) | (nb == 1))
+    # counts
+    assert sp["fwd_spans"] == len(fwd) and sp["fwd_spans_fused"] == int(fwd[:, 2].sum())
+    assert sp["bwd_spans"] == len(bwd) and sp["bwd_spans_fused"] == int(bwd[:, 2].sum())
+    # every level of this generator holds gates: one launch per fused span, one per unfused level
+    assert sp["fwd_span_launches"] == sp["fwd_spans_fused"]
+    assert sp["fwd_level_launches"] == sp["fwd_spans"] - sp["fwd_spans_fused"]
+    assert sp["bwd_span_launches"] == sp["bwd_spans_fused"]
+    assert sp["bwd_level_launches"] == sp["bwd_spans"] - sp["bwd_spans_fused"]
+    # credited work: the fused spans' gates/arcs and drivers/sink arcs, each once
+    gates = arcs = drivers = sinks = 0
+    for l0, l1, f in fwd:
+        if f:
+            m = (gate_lv >= l0) & (gate_lv <= l1)
+            gates += int(m.sum())
+            arcs += int(fanin[m].sum())
+    for top, bot, f in bwd:
+        if f:
+            m = (level >= bot) & (level <= top)
+            drivers += int(m.sum())
+            sinks += int(fanout[m].sum())
+    assert (sp["fwd_span_gates"], sp["fwd_span_arcs"]) == (gates, arcs)
+    assert (sp["bwd_span_drivers"], sp["bwd_span_arcs"]) == (drivers, sinks)
+    # evaluations performed cover the work at least once (a driver without fanout has a slot)
+    assert sp["fwd_span_arcs_computed"] >= arcs
+    ends = sum(int(((level >= bot) & (level <= top) & (fanout == 0)).sum()) for top, bot, f in bwd if f)
+    assert sp["bwd_span_slots_computed"] >= sinks + ends
+
+
+def test_every_span_fuses_when_a_level_alone_tiles():
+    """A single level always tiles when no gate has more than 64 arcs and no driver more
+    than 64 sinks, so the builder never falls back to a level launch; a fanout-64 net
+    whose sink gates lie above it shortens the span it would have been inside."""
+    for cfg in CASES[1:]:
+        d, g, s, level, fanout, fanin = _plan(cfg)
+        assert s["max_fanout"] <= 64 and s["max_fanin"] <= 64
+        fwd, bwd = g.span_list()
+        assert np.all(fwd[:, 2] == 1) and np.all(bwd[:, 2] == 1)
+        sp = g.spans
+        assert (sp["fwd_level_launches"], sp["bwd_level_launches"]) == (0, 0)
+
+
+def test_tiny_design_fuses_every_span():
+    d, g, s, level, fanout, fanin = _plan(CASES[0])
+    sp = g.spans
+    assert sp["fwd_spans_fused"] == sp["fwd_spans"] and sp["bwd_spans_fused"] == sp["bwd_spans"]
+    assert sp["fwd_level_launches"] == 0 and sp["bwd_level_launches"] == 0
+    assert (sp["fwd_span_gates"], sp["fwd_span_arcs"]) == (s["n_gates"], s["n_arcs"])
+    assert (sp["bwd_span_drivers"], sp["bwd_span_arcs"]) == (s["n_drivers"], s["n_arcs"])
+    assert sp["bwd_span_slots_computed"] == s["n_arcs"] + int((fanout == 0).sum())
+
+
+def test_null_arguments_are_rejected():
+    lib = sta.load_library()
+    assert lib.sta_graph_spans(None, None) == -1        # STA_E_ARG
+    assert lib.sta_graph_span_list(None, None, None) == -1
