@@ -50,16 +50,10 @@ DevGraph dev_graph(const sta_graph* g) {
     d.ftile_maxk = reinterpret_cast<const int32_t*>(b + L.ftile_maxk);
     d.fwd_chunk = reinterpret_cast<const int32_t*>(b + L.fwd_chunk);
     d.bwd_chunk = reinterpret_cast<const int32_t*>(b + L.bwd_chunk);
-    d.sp_tile = reinterpret_cast<const int32_t*>(b + L.sp_tile);
-    d.sp_chunk = reinterpret_cast<const int32_t*>(b + L.sp_chunk);
-    d.sp_ta_arc = reinterpret_cast<const int32_t*>(b + L.sp_ta_arc);
-    d.sp_ta_src = reinterpret_cast<const int32_t*>(b + L.sp_ta_src);
-    d.sp_ta_gate = reinterpret_cast<const int32_t*>(b + L.sp_ta_gate);
-    d.bp_tile = reinterpret_cast<const int32_t*>(b + L.bp_tile);
-    d.bp_chunk = reinterpret_cast<const int32_t*>(b + L.bp_chunk);
-    d.bp_slot = reinterpret_cast<const int32_t*>(b + L.bp_slot);
-    d.bp_src = reinterpret_cast<const int32_t*>(b + L.bp_src);
-    d.bp_drv = reinterpret_cast<const int32_t*>(b + L.bp_drv);
+    d.sp_crec = reinterpret_cast<const int4*>(b + L.sp_crec);
+    d.sp_arec = reinterpret_cast<const int4*>(b + L.sp_arec);
+    d.bp_crec = reinterpret_cast<const int4*>(b + L.bp_crec);
+    d.bp_srec = reinterpret_cast<const int4*>(b + L.bp_srec);
     d.n_pi = g->n_pi;
     d.n_gates = g->n_gates;
     d.n_drivers = static_cast<int32_t>(g->D);
@@ -688,6 +682,48 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
         }
     }
 
+    // ---- fixed-stride span records (device) ------------------------------------------------
+    // Level c of tile t at t * kSpan + c, lane k of it at (t * kSpan + c) * 64 + k.  Unused
+    // levels and lanes hold indexes that are valid to load from (arc 0, driver 0, endpoint
+    // rank 0), which the kernels mask.
+    const int64_t NTF = int64_t(sp_tile.size() / 4), NTB = int64_t(bp_tile.size() / 4);
+    std::vector<int32_t> sp_crec(size_t(NTF) * kSpanF * 4, 0), sp_arec(size_t(NTF) * kSpanF * 64 * 4, 0);
+    for (int64_t t = 0; t < NTF; ++t) {
+        const int32_t c0 = sp_tile[t * 4], nch = sp_tile[t * 4 + 1];
+        for (int32_t c = 0; c < kSpanF; ++c) {
+            int32_t* cr = &sp_crec[size_t(t * kSpanF + c) * 4];
+            cr[0] = 0; cr[1] = 0; cr[2] = 1; cr[3] = nch;
+            if (c >= nch) continue;
+            const int32_t ch = c0 + c, ta0 = sp_chunk[ch * 4], na = sp_chunk[ch * 4 + 1];
+            cr[0] = na; cr[1] = sp_chunk[ch * 4 + 2]; cr[2] = sp_chunk[ch * 4 + 3];
+            for (int32_t k = 0; k < na; ++k) {
+                int32_t* ar = &sp_arec[(size_t(t * kSpanF + c) * 64 + k) * 4];
+                const int32_t a = sp_ta_arc[ta0 + k];
+                ar[0] = a; ar[1] = sp_ta_src[ta0 + k]; ar[2] = sp_ta_gate[ta0 + k]; ar[3] = int32_t(arc_meta[a]);
+            }
+        }
+    }
+    std::vector<int32_t> bp_crec(size_t(NTB) * kSpanB * 4, 0), bp_srec(size_t(NTB) * kSpanB * 64 * 4, 0);
+    for (size_t i = 0; i < bp_srec.size(); i += 4) {   // unused lanes: endpoint slots of rank 0
+        bp_srec[i] = -1;
+        bp_srec[i + 2] = -1;
+    }
+    for (int64_t t = 0; t < NTB; ++t) {
+        const int32_t c0 = bp_tile[t * 4], nch = bp_tile[t * 4 + 1];
+        for (int32_t c = 0; c < kSpanB; ++c) {
+            int32_t* cr = &bp_crec[size_t(t * kSpanB + c) * 4];
+            cr[0] = 0; cr[1] = 0; cr[2] = 1; cr[3] = nch;
+            if (c >= nch) continue;
+            const int32_t ch = c0 + c, ts0 = bp_chunk[ch * 4], ns = bp_chunk[ch * 4 + 1];
+            cr[0] = ns; cr[1] = bp_chunk[ch * 4 + 2]; cr[2] = bp_chunk[ch * 4 + 3];
+            for (int32_t k = 0; k < ns; ++k) {
+                int32_t* sr = &bp_srec[(size_t(t * kSpanB + c) * 64 + k) * 4];
+                const int32_t sl = bp_slot[ts0 + k];
+                sr[0] = bslot_arc[sl]; sr[1] = bslot_out[sl]; sr[2] = bp_src[ts0 + k]; sr[3] = bp_drv[ts0 + k];
+            }
+        }
+    }
+
     // ---- device image --------------------------------------------------------------------
     DevLayout& lay = g->lay;
     size_t off = 0;
@@ -715,16 +751,10 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     lay.fwd_chunk = place(fchunk.size() * 4);
     lay.bwd_chunk = place(bchunk.size() * 4);
     lay.bwd_lvl = place((Lmax + 2) * 12);
-    lay.sp_tile = place(sp_tile.size() * 4);
-    lay.sp_chunk = place(sp_chunk.size() * 4);
-    lay.sp_ta_arc = place(sp_ta_arc.size() * 4);
-    lay.sp_ta_src = place(sp_ta_src.size() * 4);
-    lay.sp_ta_gate = place(sp_ta_gate.size() * 4);
-    lay.bp_tile = place(bp_tile.size() * 4);
-    lay.bp_chunk = place(bp_chunk.size() * 4);
-    lay.bp_slot = place(bp_slot.size() * 4);
-    lay.bp_src = place(bp_src.size() * 4);
-    lay.bp_drv = place(bp_drv.size() * 4);
+    lay.sp_crec = place(sp_crec.size() * 4);
+    lay.sp_arec = place(sp_arec.size() * 4);
+    lay.bp_crec = place(bp_crec.size() * 4);
+    lay.bp_srec = place(bp_srec.size() * 4);
     lay.total = off;
     g->image.assign(off, 0);
     auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) std::memcpy(g->image.data() + o, src, bytes); };
@@ -774,16 +804,10 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
     put(lay.fwd_chunk, fchunk.data(), fchunk.size() * 4);
     put(lay.bwd_chunk, bchunk.data(), bchunk.size() * 4);
     put(lay.bwd_lvl, blvl.data(), blvl.size() * 4);
-    put(lay.sp_tile, sp_tile.data(), sp_tile.size() * 4);
-    put(lay.sp_chunk, sp_chunk.data(), sp_chunk.size() * 4);
-    put(lay.sp_ta_arc, sp_ta_arc.data(), sp_ta_arc.size() * 4);
-    put(lay.sp_ta_src, sp_ta_src.data(), sp_ta_src.size() * 4);
-    put(lay.sp_ta_gate, sp_ta_gate.data(), sp_ta_gate.size() * 4);
-    put(lay.bp_tile, bp_tile.data(), bp_tile.size() * 4);
-    put(lay.bp_chunk, bp_chunk.data(), bp_chunk.size() * 4);
-    put(lay.bp_slot, bp_slot.data(), bp_slot.size() * 4);
-    put(lay.bp_src, bp_src.data(), bp_src.size() * 4);
-    put(lay.bp_drv, bp_drv.data(), bp_drv.size() * 4);
+    put(lay.sp_crec, sp_crec.data(), sp_crec.size() * 4);
+    put(lay.sp_arec, sp_arec.data(), sp_arec.size() * 4);
+    put(lay.bp_crec, bp_crec.data(), bp_crec.size() * 4);
+    put(lay.bp_srec, bp_srec.data(), bp_srec.size() * 4);
 
     g->n_pi = int32_t(P);
     g->n_gates = int32_t(G);

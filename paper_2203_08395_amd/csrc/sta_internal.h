@@ -43,9 +43,8 @@ struct DevLayout {
     size_t ftile_maxk;             // per forward tile: the largest gate fanin in it
     size_t fwd_chunk;              // per forward chunk (first tile, first arc, first gate, level)
     size_t bwd_chunk;              // per backward chunk (first tile, first slot, first driver, level)
-    size_t sp_tile, sp_chunk;      // fused spans: tile records (4 ints), chunk records (4 ints)
-    size_t sp_ta_arc, sp_ta_src, sp_ta_gate;   // per span-tile arc: arc, source, gate
-    size_t bp_tile, bp_chunk, bp_slot, bp_src, bp_drv;   // backward spans
+    size_t sp_crec, sp_arec;       // fused forward spans: level and arc records per tile
+    size_t bp_crec, bp_srec;       // fused backward spans: level and slot records per tile
     size_t total;
 };
 
@@ -72,16 +71,16 @@ struct DevGraph {
     const int32_t* ftile_maxk;     // [NF]  largest gate fanin of each forward tile
     const int32_t* fwd_chunk;      // [NC+1][4] forward chunks
     const int32_t* bwd_chunk;      // [NB+1][4] backward chunks in processing order (+ 4 ints of bounds)
-    const int32_t* sp_tile;        // [NT][4] span tile: first chunk, chunks, first slot record, slots
-    const int32_t* sp_chunk;       // [NC][4] span chunk (one level of a tile): first tile arc, arcs, first slot, max fanin
-    const int32_t* sp_ta_arc;      // per tile arc: the cell arc
-    const int32_t* sp_ta_src;      // per tile arc: its driver (>= 0) or -1 - (slot of an in-tile gate)
-    const int32_t* sp_ta_gate;     // per tile arc: its gate
-    const int32_t* bp_tile;        // [NT][4] backward span tile: first chunk, chunks, -, drivers
-    const int32_t* bp_chunk;       // [NC][4] one level of a tile: first tile slot, slots, first driver slot, most slots of a driver
-    const int32_t* bp_slot;        // per tile slot: the backward slot
-    const int32_t* bp_src;         // per tile slot: driver slot (in the tile) of the sink's gate output, or -1
-    const int32_t* bp_drv;         // per tile slot: its driver
+    // Fused spans, fixed-stride records so that a wavefront loads all of its tile's records
+    // in one round, indexed by (tile, level c, lane) only:
+    const int4* sp_crec;   // [NT][kSpanF] forward level c of tile t: arcs, first LDS slot,
+                           //   widest gate's arc count, levels of the tile
+    const int4* sp_arec;   // [NT][kSpanF][64] per lane: cell arc, source (driver >= 0 or
+                           //   -1 - LDS slot of an in-tile gate), gate, arc_meta of the arc
+    const int4* bp_crec;   // [NT][kSpanB] backward level c of tile t (top first): slots,
+                           //   first LDS driver slot, most slots of a driver, levels of the tile
+    const int4* bp_srec;   // [NT][kSpanB][64] per lane: sink arc (-1: endpoint slot), the
+                           //   slot's output word (bslot_out), in-tile LDS source or -1, driver
     int32_t n_pi, n_gates, n_drivers, n_arcs;
 };
 

@@ -512,31 +512,44 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
             const float sl = bilerp(T + 49, i, j, tx, ty);
             dst[w] = make_float2(ai, si);
             arc_delay[size_t(x.a) * NW + w] = dl;
-            cand[w] = ai + dl;
-            slw[w] = sl;
+            // early views negated, so that every view takes a maximum (negation is exact)
+            cand[w] = early[w] ? -(ai + dl) : ai + dl;
+            slw[w] = early[w] ? -sl : sl;
             best_k[w] = x.kpos;
         }
     } else {
 #pragma unroll
         for (int w = 0; w < NW; ++w) { cand[w] = 0.0f; slw[w] = 0.0f; best_k[w] = 0; }
     }
-    for (int off = 1; off < span; off <<= 1) {
+    // segmented maximum with argmax over a gate's arcs: ceil(log2(widest gate)) steps,
+    // every shuffle of a step issued before any is used
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int off = 1 << st;
+        if (off >= span) break;                 // uniform
         const bool take = (lane + off) < x.seg_end;
+        float c2[NW], s2[NW];
+        int k2[NW];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            const float c2 = __shfl_down(cand[w], off, 64);
-            const float s2 = __shfl_down(slw[w], off, 64);
-            const int k2 = __shfl_down(best_k[w], off, 64);
-            if (take) {
-                if (early[w] ? (c2 < cand[w]) : (c2 > cand[w])) { cand[w] = c2; best_k[w] = k2; }
-                if (early[w] ? (s2 < slw[w]) : (s2 > slw[w])) slw[w] = s2;
-            }
+            c2[w] = __shfl_down(cand[w], off, 64);
+            s2[w] = __shfl_down(slw[w], off, 64);
+            k2[w] = __shfl_down(best_k[w], off, 64);
+        }
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const bool tc = take && c2[w] > cand[w];
+            cand[w] = tc ? c2[w] : cand[w];
+            best_k[w] = tc ? k2[w] : best_k[w];
+            slw[w] = (take && s2[w] > slw[w]) ? s2[w] : slw[w];
         }
     }
     if (x.head) {
         float2* out = reinterpret_cast<float2*>(drv_ts) + size_t(n_pi + x.g) * NW;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
+            cand[w] = early[w] ? -cand[w] : cand[w];
+            slw[w] = early[w] ? -slw[w] : slw[w];
             out[w] = make_float2(cand[w], slw[w]);
             argmax[size_t(x.g) * NW + w] = uint8_t(best_k[w]);
             lds_res[slot * NW + w] = make_float2(cand[w], slw[w]);
@@ -561,7 +574,6 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
     const int t = tile0 + blockIdx.x * 4 + wave;
     const int tc = t < tile1 ? t : tile1 - 1;
     const int lane = threadIdx.x & 63;
-    const int c0 = G.sp_tile[tc * 4], nch = G.sp_tile[tc * 4 + 1];
     float2* res = s_res[wave];
     const float* tab[NV];
     bool early[NV];
@@ -570,32 +582,33 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
         tab[v] = lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
         early[v] = V.mode[v] == STA_EARLY;
     }
-    // round 1: chunk records and the tile's arc records (clamped, unconditional loads)
-    int ta0[kSpanF], na[kSpanF], sl0[kSpanF], mk[kSpanF];
+    // round 1: the tile's level and arc records, all indexed by (tile, level, lane)
+    int na[kSpanF], sl0[kSpanF], mk[kSpanF];
     int ar[kSpanF], sc[kSpanF], gt[kSpanF];
+    uint32_t meta[kSpanF];
+    int nch = 0;
 #pragma unroll
     for (int c = 0; c < kSpanF; ++c) {
-        const int cc = c < nch ? c0 + c : c0;
-        ta0[c] = G.sp_chunk[cc * 4];
-        na[c] = c < nch ? G.sp_chunk[cc * 4 + 1] : 0;
-        sl0[c] = G.sp_chunk[cc * 4 + 2];
-        mk[c] = G.sp_chunk[cc * 4 + 3];
-        const int i = lane < na[c] ? ta0[c] + lane : ta0[c];
-        ar[c] = G.sp_ta_arc[i];
-        sc[c] = G.sp_ta_src[i];
-        gt[c] = G.sp_ta_gate[i];
+        const int4 cr = G.sp_crec[tc * kSpanF + c];
+        na[c] = cr.x;
+        sl0[c] = cr.y;
+        mk[c] = cr.z;
+        nch = cr.w;
+        const int4 r = G.sp_arec[size_t(tc * kSpanF + c) * 64 + lane];
+        ar[c] = r.x;
+        sc[c] = r.y;
+        gt[c] = r.z;
+        meta[c] = uint32_t(r.w);
     }
     load_axes(s_ax, lib);
     __syncthreads();
     if (t >= tile1) return;
-    // round 2: the arcs' static data and the arrivals of drivers outside the span
-    uint32_t meta[kSpanF];
+    // round 2: the arcs' net data and the arrivals of drivers outside the span
     float ndv[kSpanF], niv[kSpanF], lov[kSpanF];
     float2 ext[kSpanF][NV];
 #pragma unroll
     for (int c = 0; c < kSpanF; ++c) {
         const int a = ar[c];
-        meta[c] = G.arc_meta[a];
         ndv[c] = nd[a];
         niv[c] = ni[a];
         lov[c] = arc_load[a];
@@ -607,7 +620,6 @@ __global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KVie
     // all of round 2 is in flight; keep it there (one wait before the first level)
 #pragma unroll
     for (int c = 0; c < kSpanF; ++c) {
-        pin_value(meta[c]);
         pin_value(ndv[c]);
         pin_value(niv[c]);
         pin_value(lov[c]);
@@ -701,38 +713,35 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
     const int t = tile0 + blockIdx.x * 4 + wave;
     if (t >= tile1) return;
     const int lane = threadIdx.x & 63;
-    const int c0 = G.bp_tile[t * 4], nch = G.bp_tile[t * 4 + 1];
     float* rs = s_rat[wave];
     bool early[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
-    // round 1: chunk records and slot records
-    int ts0[kSpanB], ns[kSpanB], ds0[kSpanB], ms[kSpanB];
-    int slot[kSpanB], src[kSpanB], drv[kSpanB];
+    // round 1: the tile's level and slot records, all indexed by (tile, level, lane)
+    int ns[kSpanB], ds0[kSpanB], ms[kSpanB];
+    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB];
+    bool hd[kSpanB];
+    int nch = 0;
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
-        const int cc = c < nch ? c0 + c : c0;
-        ts0[c] = G.bp_chunk[cc * 4];
-        ns[c] = c < nch ? G.bp_chunk[cc * 4 + 1] : 0;
-        ds0[c] = G.bp_chunk[cc * 4 + 2];
-        ms[c] = G.bp_chunk[cc * 4 + 3];
-        const int i = lane < ns[c] ? ts0[c] + lane : ts0[c];
-        slot[c] = G.bp_slot[i];
-        src[c] = G.bp_src[i];
-        drv[c] = G.bp_drv[i];
+        const int4 cr = G.bp_crec[t * kSpanB + c];
+        ns[c] = cr.x;
+        ds0[c] = cr.y;
+        ms[c] = cr.z;
+        nch = cr.w;
+        const int4 r = G.bp_srec[size_t(t * kSpanB + c) * 64 + lane];
+        const uint32_t bo = uint32_t(r.y);
+        sa_[c] = r.x;
+        so_[c] = int(bo & 0x7fffffffu);
+        hd[c] = (bo & kHeadBit) != 0u;
+        src[c] = r.z;
+        drv[c] = r.w;
     }
     // round 2: slot data (everything that does not come from this tile)
-    int sa_[kSpanB], so_[kSpanB];
-    bool hd[kSpanB];
     float ndv[kSpanB], dl[kSpanB][NV], ati[kSpanB][NV], ext[kSpanB][NV], atd[kSpanB][NV];
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
-        const int sl = slot[c];
-        const int sa = G.bslot_arc[sl];
-        const uint32_t bo = uint32_t(G.bslot_out[sl]);
-        sa_[c] = sa;
-        so_[c] = int(bo & 0x7fffffffu);
-        hd[c] = (bo & kHeadBit) != 0u;
+        const int sa = sa_[c];
         const int sac = sa >= 0 ? sa : 0;
         ndv[c] = nd[sac];
         const float* ext_src = (sa >= 0) ? (drv_rat + size_t(so_[c]) * NV) : (ep_rat + size_t(so_[c]) * NV);
@@ -769,37 +778,45 @@ __global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int
         const int gi = __popcll(heads & le) - 1;
         const uint64_t after = heads & ~le;
         const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : n;
+        const bool on_arc = act && sa_[c] >= 0;
+        // the required times at the sinks' gate outputs: from LDS (in-tile) or prefetched
+        const int si = src[c] >= 0 ? src[c] : 0;
+        float ro[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ro[v] = rs[si * NV + v];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ro[v] = src[c] >= 0 ? ro[v] : ext[c][v];
+        // per slot: the value its driver minimizes (maximizes early), negated for early
+        // views so that every view takes a minimum (negation is exact: same results)
         float best[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            float val = 0.0f;
-            if (act) {
-                if (sa_[c] >= 0) {
-                    const float ro = src[c] >= 0 ? rs[src[c] * NV + v] : ext[c][v];
-                    const float rin = ro - dl[c][v];
-                    arc_rat[size_t(sa_[c]) * NV + v] = rin;
-                    arc_slack[size_t(sa_[c]) * NV + v] = early[v] ? (ati[c][v] - rin) : (rin - ati[c][v]);
-                    val = rin - ndv[c];
-                } else {
-                    val = ext[c][v];
-                }
+            const float rin = ro[v] - dl[c][v];
+            if (on_arc) {
+                arc_rat[size_t(sa_[c]) * NV + v] = rin;
+                arc_slack[size_t(sa_[c]) * NV + v] = early[v] ? (ati[c][v] - rin) : (rin - ati[c][v]);
             }
-            best[v] = val;
+            const float val = on_arc ? rin - ndv[c] : (act ? ext[c][v] : 0.0f);
+            best[v] = early[v] ? -val : val;
         }
-        // segmented min (max early) over a driver's slots: ceil(log2(most slots)) steps
-        for (int off = 1; off < ms[c]; off <<= 1) {
-            const bool take = (lane + off) < seg_end;
+        // segmented minimum over a driver's slots: ceil(log2(most slots)) steps, every
+        // view's shuffle issued before any is used
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const float b2 = __shfl_down(best[v], off, 64);
-                if (take && (early[v] ? (b2 > best[v]) : (b2 < best[v]))) best[v] = b2;
-            }
+        for (int st = 0; st < 6; ++st) {
+            const int off = 1 << st;
+            if (off >= ms[c]) break;            // uniform
+            const bool take = (lane + off) < seg_end;
+            float b2[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) b2[v] = __shfl_down(best[v], off, 64);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) best[v] = (take && b2[v] < best[v]) ? b2[v] : best[v];
         }
         if (head) {
             const int u = drv[c];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const float r = best[v];
+                const float r = early[v] ? -best[v] : best[v];
                 drv_rat[size_t(u) * NV + v] = r;
                 drv_slack[size_t(u) * NV + v] = early[v] ? (atd[c][v] - r) : (r - atd[c][v]);
                 rs[(ds0[c] + gi) * NV + v] = r;
