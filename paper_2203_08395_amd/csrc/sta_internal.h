@@ -30,6 +30,10 @@ constexpr int kSpanF = 6;
 constexpr int kSpanB = 4;
 constexpr int kSpanSlotsF = kSpanF * 64;
 constexpr int kSpanSlotsB = kSpanB * 64;
+// Span tiles per workgroup: one, so that the few tiles of a span launch spread over as
+// many compute units as possible (a tile's gathers and table reads are issued by its own
+// unit's address pipeline instead of queueing behind three other tiles').
+constexpr int kSpanWaves = 1;
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
 struct DevLayout {

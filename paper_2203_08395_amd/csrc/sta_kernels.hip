@@ -563,15 +563,15 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
 // instead of one launch and three rounds per level.
 // (Staging the tables in LDS per block was measured slower than the L2-resident reads.)
 template <int NV>
-__global__ __launch_bounds__(256) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
+__global__ __launch_bounds__(64 * kSpanWaves) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
                                                       const float* __restrict__ arc_load,
                                                       const float* __restrict__ nd, const float* __restrict__ ni,
                                                       float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                                       float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
     __shared__ float s_ax[32];
-    __shared__ float2 s_res[4][kSpanSlotsF * NV];
+    __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NV];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = tile0 + blockIdx.x * 4 + wave;
+    const int t = tile0 + blockIdx.x * kSpanWaves + wave;
     const int tc = t < tile1 ? t : tile1 - 1;
     const int lane = threadIdx.x & 63;
     float2* res = s_res[wave];
@@ -701,16 +701,16 @@ __global__ __launch_bounds__(256) void k_backward(DevGraph G, KViews V, int tile
 // times of sink gates outside the span or the endpoint required times), then the levels
 // top down, in-span required times handed over through LDS.
 template <int NV>
-__global__ __launch_bounds__(256) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
+__global__ __launch_bounds__(64 * kSpanWaves) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
                                                        const float* __restrict__ nd, const float* __restrict__ drv_ts,
                                                        const float* __restrict__ arc_ts,
                                                        const float* __restrict__ arc_delay,
                                                        const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
                                                        float* __restrict__ arc_rat, float* __restrict__ drv_slack,
                                                        float* __restrict__ arc_slack) {
-    __shared__ float s_rat[4][kSpanSlotsB * NV];
+    __shared__ float s_rat[kSpanWaves][kSpanSlotsB * NV];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = tile0 + blockIdx.x * 4 + wave;
+    const int t = tile0 + blockIdx.x * kSpanWaves + wave;
     if (t >= tile1) return;
     const int lane = threadIdx.x & 63;
     float* rs = s_rat[wave];
@@ -1645,7 +1645,8 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                 const int t0 = g->span_tile_h[sp], t1 = g->span_tile_h[sp + 1];
                 if (t1 <= t0) continue;
                 prof_launch("k_forward_span", s, [&] {
-                    hipLaunchKernelGGL((k_forward_span<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, lib, kv,
+                    hipLaunchKernelGGL((k_forward_span<NV>), dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves),
+                                       dim3(64 * kSpanWaves), 0, s, dg, lib, kv,
                                        t0, t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts,
                                        o->arc_delay, o->argmax);
                 });
@@ -1714,7 +1715,8 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
                 const int t0 = g->bspan_tile_h[b], t1 = g->bspan_tile_h[b + 1];
                 if (t1 <= t0) continue;
                 prof_launch("k_backward_span", s, [&] {
-                    hipLaunchKernelGGL((k_backward_span<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, kv, t0,
+                    hipLaunchKernelGGL((k_backward_span<NV>), dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves),
+                                       dim3(64 * kSpanWaves), 0, s, dg, kv, t0,
                                        t1, nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat,
                                        o->arc_rat, o->drv_slack, o->arc_slack);
                 });
