@@ -34,6 +34,8 @@ constexpr int kSpanSlotsB = kSpanB * 64;
 // many compute units as possible (a tile's gathers and table reads are issued by its own
 // unit's address pipeline instead of queueing behind three other tiles').
 constexpr int kSpanWaves = 1;
+// Level-kernel tiles per workgroup (the same reasoning: a level has a few hundred tiles).
+constexpr int kLevelWaves = 1;
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
 struct DevLayout {

@@ -398,11 +398,11 @@ struct KTiles {
     int32_t base[kArgTiles];       // first gate (forward) or driver (backward) of each tile
 };
 
-// Level schedule, forward: 4 tiles per 256-lane block.  The block first issues its
+// Level schedule, forward: one tile per 64-lane block.  The block first issues its
 // tiles' arc loads, then copies the view tables into LDS (TAB_LDS: every view reads the
 // same table set), then gathers the drivers' results and computes.
 template <int NV, bool TAB_LDS>
-__global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V, int tile0, int tile1, KTiles kt,
+__global__ __launch_bounds__(64 * kLevelWaves) void k_forward(DevGraph G, KLib lib, KViews V, int tile0, int tile1, KTiles kt,
                                                  const float* __restrict__ arc_load, const float* __restrict__ nd,
                                                  const float* __restrict__ ni, float* __restrict__ drv_ts,
                                                  float* __restrict__ arc_ts, float* __restrict__ arc_delay,
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void k_forward(DevGraph G, KLib lib, KViews V,
     __shared__ float s_ax[26];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = tile0 + blockIdx.x * 4 + wave;
+    const int t = tile0 + blockIdx.x * kLevelWaves + wave;
     const bool valid = t < tile1;
     int a0 = 0, n = 0, g0 = 0;
     if (valid) {
@@ -668,7 +668,7 @@ __global__ void k_copy_pi(const float* __restrict__ pi_ts, float* __restrict__ d
 }
 
 template <int NV>
-__global__ __launch_bounds__(256) void k_backward(DevGraph G, KViews V, int tile0, int tile1, KTiles kt,
+__global__ __launch_bounds__(64 * kLevelWaves) void k_backward(DevGraph G, KViews V, int tile0, int tile1, KTiles kt,
                                                   const float* __restrict__ nd, const float* __restrict__ drv_ts,
                                                   const float* __restrict__ arc_ts,
                                                   const float* __restrict__ arc_delay,
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(256) void k_backward(DevGraph G, KViews V, int tile
                                                   float* __restrict__ arc_rat, float* __restrict__ drv_slack,
                                                   float* __restrict__ arc_slack) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = tile0 + blockIdx.x * 4 + wave;
+    const int t = tile0 + blockIdx.x * kLevelWaves + wave;
     if (t >= tile1) return;
     bool early[NV];
 #pragma unroll
@@ -1628,7 +1628,8 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
         if (t1 <= t0) return;
         const KTiles kt = ktiles(g->ftile_arc_h, g->ftile_gate_h, t0, t1);
         prof_launch("k_forward", s, [&] {
-            hipLaunchKernelGGL((k_forward<NV, TAB_LDS>), dim3((t1 - t0 + 3) / 4), dim3(256), lds, s, dg, lib, kv, t0,
+            hipLaunchKernelGGL((k_forward<NV, TAB_LDS>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves),
+                               dim3(64 * kLevelWaves), lds, s, dg, lib, kv, t0,
                                t1, kt, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts, o->arc_delay,
                                o->argmax);
         });
@@ -1697,7 +1698,8 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
         if (t1 <= t0) return;
         const KTiles kt = ktiles(g->btile_slot_h, g->btile_drv_h, t0, t1);
         prof_launch("k_backward", s, [&] {
-            hipLaunchKernelGGL((k_backward<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, kv, t0, t1, kt,
+            hipLaunchKernelGGL((k_backward<NV>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves),
+                               dim3(64 * kLevelWaves), 0, s, dg, kv, t0, t1, kt,
                                nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat, o->arc_rat,
                                o->drv_slack, o->arc_slack);
         });
@@ -1833,12 +1835,12 @@ __device__ __forceinline__ void adj_tile(const DevGraph& G, const bool* early, i
 }
 
 template <int NV>
-__global__ __launch_bounds__(256) void k_adjoint(DevGraph G, KViews V, int tile0, int tile1, KTiles kt,
+__global__ __launch_bounds__(64 * kLevelWaves) void k_adjoint(DevGraph G, KViews V, int tile0, int tile1, KTiles kt,
                                                  const uint8_t* __restrict__ argmax,
                                                  const float* __restrict__ drv_slack, float* __restrict__ g_at,
                                                  float* __restrict__ g_arc, float* __restrict__ g_nd) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = tile0 + blockIdx.x * 4 + wave;
+    const int t = tile0 + blockIdx.x * kLevelWaves + wave;
     if (t >= tile1) return;
     bool early[NV];
 #pragma unroll
@@ -1997,7 +1999,8 @@ static void enqueue_adjoint_levels(const sta_graph* g, const KLib& kl, const KVi
         if (t1 <= t0) continue;
         const KTiles kt = ktiles(g->btile_slot_h, g->btile_drv_h, t0, t1);
         prof_launch("k_adjoint", s, [&] {
-            hipLaunchKernelGGL((k_adjoint<NV>), dim3((t1 - t0 + 3) / 4), dim3(256), 0, s, dg, kv, t0, t1, kt,
+            hipLaunchKernelGGL((k_adjoint<NV>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves),
+                               dim3(64 * kLevelWaves), 0, s, dg, kv, t0, t1, kt,
                                t->argmax, sl->drv_slack, o->g_drv_at, o->g_arc_delay, o->g_net_delay);
         });
     }
