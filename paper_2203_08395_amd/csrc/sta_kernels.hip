@@ -1858,6 +1858,127 @@ __global__ __launch_bounds__(64 * kLevelWaves) void k_adjoint(DevGraph G, KViews
     adj_tile<NV>(G, early, NV, 0, s0, n, d0, argmax, drv_slack, g_at, g_arc, g_nd);
 }
 
+// The adjoint on the backward span tiles: the same dependency structure as the required
+// times (a driver's gradient needs the gradients of its sink gates' outputs), so one
+// launch walks up to four driver levels top down with in-tile gradients in LDS.  Two
+// rounds of loads: the tile's records, then per slot the argmax test's operands (the
+// arc's position, the sink gate's argmax), the gradient of a sink gate outside the tile,
+// or an endpoint's slack.  Integer counts, so the segmented sums are exact in any order
+// and the results equal the level kernel's.
+template <int NV>
+__global__ __launch_bounds__(64 * kSpanWaves) void k_adjoint_span(DevGraph G, KViews V, int tile0, int tile1,
+                                                                  const uint8_t* __restrict__ argmax,
+                                                                  const float* __restrict__ drv_slack,
+                                                                  float* __restrict__ g_at, float* __restrict__ g_arc,
+                                                                  float* __restrict__ g_nd) {
+    __shared__ float s_g[kSpanWaves][kSpanSlotsB * NV];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = tile0 + blockIdx.x * kSpanWaves + wave;
+    if (t >= tile1) return;
+    const int lane = threadIdx.x & 63;
+    float* gs = s_g[wave];
+    bool early[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
+    // round 1: the tile's level and slot records
+    int ns[kSpanB], ds0[kSpanB], ms[kSpanB];
+    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB];
+    bool hd[kSpanB];
+    int nch = 0;
+#pragma unroll
+    for (int c = 0; c < kSpanB; ++c) {
+        const int4 cr = G.bp_crec[t * kSpanB + c];
+        ns[c] = cr.x;
+        ds0[c] = cr.y;
+        ms[c] = cr.z;
+        nch = cr.w;
+        const int4 r = G.bp_srec[size_t(t * kSpanB + c) * 64 + lane];
+        const uint32_t bo = uint32_t(r.y);
+        sa_[c] = r.x;
+        so_[c] = int(bo & 0x7fffffffu);
+        hd[c] = (bo & kHeadBit) != 0u;
+        src[c] = r.z;
+        drv[c] = r.w;
+    }
+    // round 2
+    int kp[kSpanB], am[kSpanB][NV];
+    float ext[kSpanB][NV];
+#pragma unroll
+    for (int c = 0; c < kSpanB; ++c) {
+        const int sa = sa_[c];
+        const int sac = sa >= 0 ? sa : 0;
+        kp[c] = int(G.arc_meta[sac] >> 16);
+        const int gq = sa >= 0 ? so_[c] - G.n_pi : 0;
+        const float* ep = sa >= 0 ? (src[c] >= 0 ? drv_slack : g_at + size_t(so_[c]) * NV)
+                                  : drv_slack + size_t(drv[c]) * NV;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            am[c][v] = int(argmax[size_t(gq) * NV + v]);
+            ext[c][v] = ep[v];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kSpanB; ++c) {
+        pin_value(kp[c]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            pin_value(am[c][v]);
+            pin_value(ext[c][v]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kSpanB; ++c) {
+        if (c >= nch) break;                    // uniform
+        const int n = ns[c];
+        const bool act = lane < n;
+        const bool head = act && hd[c];
+        const uint64_t heads = __ballot(head);
+        const uint64_t le = lanes_le(lane);
+        const int gi = __popcll(heads & le) - 1;
+        const uint64_t after = heads & ~le;
+        const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : n;
+        const bool on_arc = act && sa_[c] >= 0;
+        const int si = src[c] >= 0 ? src[c] : 0;
+        float gin[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gin[v] = gs[si * NV + v];
+        float acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const float go = src[c] >= 0 ? gin[v] : ext[c][v];
+            const float cv = (am[c][v] == kp[c]) ? go : 0.0f;
+            if (on_arc) {
+                if (g_arc) g_arc[size_t(sa_[c]) * NV + v] = cv;
+                if (g_nd) g_nd[size_t(sa_[c]) * NV + v] = cv;
+            }
+            const float ep = ext[c][v] < 0.0f ? (early[v] ? 1.0f : -1.0f) : 0.0f;
+            acc[v] = on_arc ? cv : (act ? ep : 0.0f);
+        }
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const int off = 1 << st;
+            if (off >= ms[c]) break;            // uniform
+            const bool take = (lane + off) < seg_end;
+            float b2[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) b2[v] = __shfl_down(acc[v], off, 64);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] = take ? acc[v] + b2[v] : acc[v];
+        }
+        if (head) {
+            const int u = drv[c];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                g_at[size_t(u) * NV + v] = acc[v];
+                gs[(ds0[c] + gi) * NV + v] = acc[v];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // d TNS / d load of every gate output: the gradient of its arrival times the NLDM slope
 // of its argmax arc's delay in the load ((q - p) / (y[j+1] - y[j]) of the bilinear
 // lookup), input slews held; 0 at primary inputs.
@@ -1994,16 +2115,39 @@ static void enqueue_adjoint_levels(const sta_graph* g, const KLib& kl, const KVi
                                    const sta_timing_out* t, const sta_slack_out* sl, const sta_adjoint_out* o,
                                    hipStream_t s) {
     const DevGraph dg = dev_graph(g);
-    for (int64_t l = g->L; l >= 0; --l) {
+    auto level = [&](int64_t l) {
         const int t0 = g->bwd_tile_ptr[l], t1 = g->bwd_tile_ptr[l + 1];
-        if (t1 <= t0) continue;
+        if (t1 <= t0) return;
         const KTiles kt = ktiles(g->btile_slot_h, g->btile_drv_h, t0, t1);
         prof_launch("k_adjoint", s, [&] {
             hipLaunchKernelGGL((k_adjoint<NV>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves),
                                dim3(64 * kLevelWaves), 0, s, dg, kv, t0, t1, kt,
                                t->argmax, sl->drv_slack, o->g_drv_at, o->g_arc_delay, o->g_net_delay);
         });
+    };
+    bool done = false;
+    if constexpr (NV <= 2) {
+        if (g->use_spans) {
+            const int64_t NSB = int64_t(g->bspan_fused_h.size());
+            for (int64_t b = 0; b < NSB; ++b) {
+                const int64_t top = g->bspan_lv_h[2 * b], bot = g->bspan_lv_h[2 * b + 1];
+                if (!g->bspan_fused_h[b]) {
+                    for (int64_t l = top; l >= bot; --l) level(l);
+                    continue;
+                }
+                const int t0 = g->bspan_tile_h[b], t1 = g->bspan_tile_h[b + 1];
+                if (t1 <= t0) continue;
+                prof_launch("k_adjoint_span", s, [&] {
+                    hipLaunchKernelGGL((k_adjoint_span<NV>), dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves),
+                                       dim3(64 * kSpanWaves), 0, s, dg, kv, t0, t1, t->argmax, sl->drv_slack,
+                                       o->g_drv_at, o->g_arc_delay, o->g_net_delay);
+                });
+            }
+            done = true;
+        }
     }
+    if (!done)
+        for (int64_t l = g->L; l >= 0; --l) level(l);
     if (o->g_load)
         prof_launch("k_adj_load", s, [&] {
             hipLaunchKernelGGL((k_adj_load<NV>), dim3((g->D + 255) / 256), dim3(256), 0, s, dg, kl, kv, nd->arc_load,
@@ -2017,7 +2161,7 @@ static sta_status run_adjoint_levels(const sta_graph* g, const KLib& kl, const K
                                      hipStream_t s) {
     std::vector<uint64_t> key = {uint64_t(NV), pk(nd->arc_load), pk(t->arc_ts), pk(t->argmax), pk(sl->drv_slack),
                                  pk(o->g_drv_at), pk(o->g_arc_delay), pk(o->g_net_delay), pk(o->g_load),
-                                 pk(kl.tables), uint64_t(kl.n_tables)};
+                                 pk(kl.tables), uint64_t(kl.n_tables), uint64_t(g->use_spans)};
     for (int i = 0; i < 26; ++i) { uint32_t b; std::memcpy(&b, &kl.ax[i], 4); key.push_back(b); }
     for (int v = 0; v < NV; ++v) { key.push_back(uint64_t(kv.mode[v])); key.push_back(uint64_t(kv.set[v])); }
     return run_sequence(g, g->adj_cache, std::move(key), s, [&](hipStream_t q) {

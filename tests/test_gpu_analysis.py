@@ -26,9 +26,10 @@ def _setup(cfg_name=None, seed=None, n_pins=None, n_levels=None, modes=(LATE, EA
     return d, lib, pa, ps, late, early, modes
 
 
-def _gpu(d, lib, pa, ps, late, early, modes):
+def _gpu(d, lib, pa, ps, late, early, modes, fusion=True):
     import torch
     g = sta.Graph(d, n_tables=lib.n_tables).upload("cuda")
+    g.set_level_fusion(fusion)
     L = sta.make_library(lib.x, lib.y, torch.from_numpy(lib.tab).cuda())
     views = sta.make_views(modes)
     V = len(modes)
@@ -48,21 +49,32 @@ def _oracle(d, lib, pa, ps, late, early):
     return oracle.run(d, lib, pa, ps, late, early, modes=(oracle.LATE, oracle.EARLY))
 
 
-@pytest.mark.parametrize("case", ["c1", "geom_a", "geom_b", "late_only"])
-def test_adjoint_matches_oracle(case):
+@pytest.mark.parametrize("fusion", [True, False], ids=["spans", "levels"])
+@pytest.mark.parametrize("case", ["c1", "geom_a", "geom_b", "late_only", "wide"])
+def test_adjoint_matches_oracle(case, fusion):
     import torch
     if case == "c1":
         args = _setup("c1")
     elif case == "late_only":
         args = _setup(seed=44, n_pins=6000, n_levels=40, modes=(LATE,))
+    elif case == "wide":
+        from tests import tiny
+        d = tiny.wide_fanout_design(7)
+        pa, ps = gen.make_pi(d)
+        late, early = gen.make_rat(d, 25, late_per_level=55.0, hold=120.0)
+        args = (d, gen.make_library(), pa, ps, late, early, (LATE, EARLY))
     else:
         args = _setup(seed={"geom_a": 41, "geom_b": 42}[case], n_pins=20000, n_levels=70)
     d, lib, pa, ps, late, early, modes = args
-    say(f"[gpu case] adjoint {case}: pins={d.n_pins} views={list(modes)}")
-    r = _gpu(*args)
+    say(f"[gpu case] adjoint {case} fusion={fusion}: pins={d.n_pins} views={list(modes)}")
+    r = _gpu(*args, fusion=fusion)
     g = r["g"]
     adj = sta.tns_adjoint(g, r["L"], r["views"], r["nd"], r["t"], r["s"])
     torch.cuda.synchronize()
+    sta.profile_begin()
+    sta.tns_adjoint(g, r["L"], r["views"], r["nd"], r["t"], r["s"])
+    kinds = sta.profile_end()
+    assert ("k_adjoint_span" in kinds) == (fusion and len(modes) <= 2), kinds
     h = {k: v.cpu().numpy() for k, v in adj.items()}
     res = _oracle(d, lib, pa, ps, late, early)
     D, A = d.n_drivers, d.n_arcs

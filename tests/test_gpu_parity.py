@@ -76,6 +76,21 @@ def test_ragged_tiles_and_extremes(schedule):
 
 
 @SCHED
+@pytest.mark.parametrize("seed", [5, 6])
+def test_drivers_wider_than_a_tile(seed, schedule):
+    # two drivers with 100+ sinks: their backward levels cannot be tiled and run as level
+    # launches between fused spans
+    d = tiny.wide_fanout_design(seed)
+    lib = gen.make_library()
+    rng = np.random.default_rng(seed)
+    pa = rng.uniform(0, 50, d.n_pi).astype(np.float32)
+    ps = rng.uniform(5, 50, d.n_pi).astype(np.float32)
+    ep = oracle.endpoints(d)
+    rat = [rng.uniform(200, 1500, ep.size).astype(np.float32) for _ in range(2)]
+    compare_all(d, lib, pa, ps, rat, [LATE, EARLY], label=f"wide drivers seed {seed}", schedule=schedule)
+
+
+@SCHED
 def test_ties_on_gpu(schedule):
     same = tiny.chain_net([100.0, 50.0], [0.5, 0.5, 0.5])
     one = ([-1], [0.0], [0.4])

@@ -107,3 +107,23 @@ def test_null_arguments_are_rejected():
     lib = sta.load_library()
     assert lib.sta_graph_spans(None, None) == -1        # STA_E_ARG
     assert lib.sta_graph_span_list(None, None, None) == -1
+
+
+def test_level_with_a_wider_driver_runs_as_a_level_launch():
+    from tests import tiny
+    d = tiny.wide_fanout_design(5)
+    g = sta.Graph(d, n_tables=128)
+    s, sp = g.sizes, g.spans
+    assert s["max_fanout"] > 64
+    fwd, bwd = g.span_list()
+    D = s["n_drivers"]
+    level = np.zeros(D, np.int32)
+    drv_in = np.zeros(D, np.int32)
+    assert sta.load_library().sta_graph_perm(g.handle, drv_in.ctypes.data, None, None, level.ctypes.data, None) == 0
+    fanout = np.bincount(d.arc_drv, minlength=D)[drv_in]
+    wide = sorted(set(level[fanout > 64].tolist()))
+    assert wide
+    unfused = [int(r[0]) for r in bwd if r[2] == 0]
+    assert unfused == sorted(wide, reverse=True)          # exactly those levels, single-level
+    assert sp["bwd_level_launches"] == len(wide)
+    assert sp["fwd_level_launches"] == 0                   # no gate has more than 64 arcs
