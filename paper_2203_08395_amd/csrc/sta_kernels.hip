@@ -2032,60 +2032,77 @@ __device__ __forceinline__ unsigned long long path_key(float s, int rank) {
     return (static_cast<unsigned long long>(b) << 32) | static_cast<uint32_t>(rank);
 }
 
-constexpr int kTopkBlocks = 128;
+// Selection of the k worst endpoints: every wavefront keeps the 64 smallest keys it has
+// seen as an ascending list, one key per lane.  A batch of 64 new keys is sorted across the
+// lanes (bitonic network) and merged in: the lane-wise minimum of the list and the reversed
+// batch holds the 64 smallest of both as a bitonic sequence, which a half-cleaner network
+// sorts.  Keys are unique (the rank is in the low bits), so the result is exact and the
+// same in any order.
+constexpr int kTopkWaves = 128;       // selection wavefronts (lists of 64 keys in the scratch)
 
-// k smallest keys of a block's share, by k rounds of a block-wide minimum above the last pick
-__device__ void block_topk(const unsigned long long* mine, int cnt, int k, unsigned long long* out) {
-    __shared__ unsigned long long red[256];
-    unsigned long long last = 0ull;
-    bool first = true;
-    for (int r = 0; r < k; ++r) {
-        unsigned long long best = ~0ull;
-        for (int i = 0; i < cnt; ++i) {
-            const unsigned long long x = mine[i];
-            if ((first || x > last) && x < best) best = x;
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) { return a < b ? a : b; }
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) { return a < b ? b : a; }
+
+__device__ __forceinline__ unsigned long long wave_sort64(unsigned long long x, int lane) {
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const unsigned long long y = __shfl_xor(x, stride, 64);
+            const bool up = (lane & size) == 0 || size == 64;
+            const bool lower = (lane & stride) == 0;
+            x = (lower == up) ? umin64(x, y) : umax64(x, y);
         }
-        red[threadIdx.x] = best;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (threadIdx.x < w && red[threadIdx.x + w] < red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + w];
-            __syncthreads();
-        }
-        last = red[0];
-        first = false;
-        if (threadIdx.x == 0) out[r] = last;
-        __syncthreads();
     }
+    return x;
 }
 
-constexpr int kTopkPerThread = 64;
+// the 64 smallest of two ascending lists (a, b one key per lane), ascending
+__device__ __forceinline__ unsigned long long wave_merge64(unsigned long long a, unsigned long long b, int lane) {
+    unsigned long long c = umin64(a, __shfl(b, 63 - lane, 64));
+#pragma unroll
+    for (int stride = 32; stride > 0; stride >>= 1) {
+        const unsigned long long y = __shfl_xor(c, stride, 64);
+        c = ((lane & stride) == 0) ? umin64(c, y) : umax64(c, y);
+    }
+    return c;
+}
 
 __global__ __launch_bounds__(256) void k_topk_partial(const int32_t* __restrict__ ep_drv, int E,
-                                                      const float* __restrict__ drv_slack, int NV, int v, int k,
+                                                      const float* __restrict__ drv_slack, int NV, int v,
                                                       unsigned long long* __restrict__ cand) {
-    unsigned long long mine[kTopkPerThread];
-    const int per_block = (E + gridDim.x - 1) / gridDim.x;
-    const int e0 = blockIdx.x * per_block;
-    const int e1 = min(E, e0 + per_block);
-    int cnt = 0;
-    for (int e = e0 + threadIdx.x; e < e1 && cnt < kTopkPerThread; e += 256)
-        mine[cnt++] = path_key(drv_slack[size_t(ep_drv[e]) * NV + v], e);
-    block_topk(mine, cnt, k, cand + size_t(blockIdx.x) * k);
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int W = gridDim.x * 4;
+    unsigned long long best = ~0ull;
+    const int nb = (E + 63) / 64;
+    for (int b = gw; b < nb; b += W) {
+        const int e = b * 64 + lane;
+        unsigned long long x = ~0ull;
+        if (e < E) x = path_key(drv_slack[size_t(ep_drv[e]) * NV + v], e);
+        const unsigned long long worst = __shfl(best, 63, 64);
+        if (__ballot(x < worst) == 0ull) continue;        // nothing in this batch gets in
+        best = wave_merge64(best, wave_sort64(x, lane), lane);
+    }
+    cand[size_t(gw) * 64 + lane] = best;
 }
 
-__global__ __launch_bounds__(256) void k_topk_final(const unsigned long long* __restrict__ cand, int n, int k,
+__global__ __launch_bounds__(256) void k_topk_final(const unsigned long long* __restrict__ cand, int n_lists, int k,
                                                     int32_t* __restrict__ ep_rank, float* __restrict__ slack) {
-    __shared__ unsigned long long out[STA_MAX_PATHS];
-    unsigned long long mine[kTopkPerThread];
-    int cnt = 0;
-    for (int i = threadIdx.x; i < n && cnt < kTopkPerThread; i += 256) mine[cnt++] = cand[i];
-    block_topk(mine, cnt, k, out);
-    if (threadIdx.x < k) {
-        const unsigned long long x = out[threadIdx.x];
+    __shared__ unsigned long long s_l[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    unsigned long long best = ~0ull;
+    for (int i = w; i < n_lists; i += 4) best = wave_merge64(best, cand[size_t(i) * 64 + lane], lane);
+    s_l[w][lane] = best;
+    __syncthreads();
+    if (w != 0) return;
+    for (int i = 1; i < 4; ++i) best = wave_merge64(best, s_l[i][lane], lane);
+    if (lane < k) {
+        const unsigned long long x = best;
         uint32_t b = uint32_t(x >> 32);
         b = (b & 0x80000000u) ? (b & 0x7fffffffu) : ~b;
-        ep_rank[threadIdx.x] = int32_t(uint32_t(x));
-        slack[threadIdx.x] = __uint_as_float(b);
+        ep_rank[lane] = int32_t(uint32_t(x));
+        slack[lane] = __uint_as_float(b);
     }
 }
 
@@ -2418,7 +2435,7 @@ sta_status sta_tns_adjoint(const sta_graph* g, const sta_library* lib, const sta
     return launch_check("sta_tns_adjoint");
 }
 
-size_t sta_paths_scratch_bytes(void) { return sizeof(unsigned long long) * kTopkBlocks * STA_MAX_PATHS; }
+size_t sta_paths_scratch_bytes(void) { return sizeof(unsigned long long) * kTopkWaves * 64; }
 
 sta_status sta_critical_paths(const sta_graph* g, const sta_views* views, int32_t view, int32_t k,
                               const sta_timing_out* t, const sta_slack_out* sl, const sta_paths_out* out,
@@ -2430,8 +2447,6 @@ sta_status sta_critical_paths(const sta_graph* g, const sta_views* views, int32_
     if (view < 0 || view >= views->n_views) return fail(STA_E_ARG, "sta_critical_paths: view out of range");
     if (k < 1 || k > STA_MAX_PATHS) return fail(STA_E_ARG, "sta_critical_paths: k must be in 1..STA_MAX_PATHS");
     if (k > g->E) return fail(STA_E_ARG, "sta_critical_paths: k exceeds the number of endpoints");
-    if (g->E > int64_t(kTopkBlocks) * 256 * kTopkPerThread)
-        return fail(STA_E_ARG, "sta_critical_paths: too many endpoints for the selection kernel");
     if (!scratch || scratch_bytes_ < sta_paths_scratch_bytes()) return fail(STA_E_ARG, "sta_critical_paths: scratch too small");
     if (!out->ep_rank || !out->slack || !out->len || !out->drv || !out->arc || !sl->drv_slack || (g->A > 0 && !t->argmax))
         return fail(STA_E_ARG, "sta_critical_paths: null buffer");
@@ -2439,14 +2454,16 @@ sta_status sta_critical_paths(const sta_graph* g, const sta_views* views, int32_
     const DevGraph dg = dev_graph(g);
     const int NV = views->n_views;
     auto* cand = static_cast<unsigned long long*>(scratch);
-    int blocks = int((g->E + 255) / 256);
-    blocks = blocks < kTopkBlocks ? blocks : kTopkBlocks;
+    // about eight batches of 64 endpoints per selection wavefront, at most kTopkWaves of them
+    const int64_t nb = (g->E + 63) / 64;
+    int blocks = int((nb + 31) / 32);
+    blocks = blocks < 1 ? 1 : (blocks > kTopkWaves / 4 ? kTopkWaves / 4 : blocks);
     prof_launch("k_topk_partial", s, [&] {
         hipLaunchKernelGGL(k_topk_partial, dim3(blocks), dim3(256), 0, s, dg.ep_drv, int(g->E), sl->drv_slack, NV,
-                           int(view), int(k), cand);
+                           int(view), cand);
     });
     prof_launch("k_topk_final", s, [&] {
-        hipLaunchKernelGGL(k_topk_final, dim3(1), dim3(256), 0, s, cand, blocks * int(k), int(k), out->ep_rank,
+        hipLaunchKernelGGL(k_topk_final, dim3(1), dim3(256), 0, s, cand, blocks * 4, int(k), out->ep_rank,
                            out->slack);
     });
     prof_launch("k_backtrace", s, [&] {
