@@ -220,14 +220,15 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
  * Every choice gives identical results. */
 sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32_t use_graphs);
 
-/* Level fusion of the level schedule (default on, one or two views): six consecutive gate
- * levels per forward launch and four driver levels per backward launch.  Each wavefront
- * computes one span tile: in the forward pass a set of gates closed under fanin inside the
- * span (<= 64 cell arcs per level), in the backward pass a set of drivers closed under
- * their sinks' gate outputs inside the span (<= 64 sink slots per level), level by level,
- * with the in-span arrival (required) times kept in LDS.  A gate or driver needed by
- * several tiles is computed in each of them, identically, so results do not change.  A
- * span whose closure does not fit runs level by level.  The view schedule is unaffected. */
+/* Level fusion of the level schedule (default on, one or two views): up to eight
+ * consecutive gate levels per forward launch and up to eight driver levels per backward
+ * launch (the same spans serve the TNS adjoint).  Each workgroup (one wavefront) computes
+ * one span tile: in the forward pass a set of gates closed under fanin inside the span
+ * (<= 64 cell arcs per level), in the backward pass a set of drivers closed under their
+ * sinks' gate outputs inside the span (<= 64 sink slots per level), level by level, with
+ * the in-span arrival (required) times kept in LDS.  A gate or driver needed by several
+ * tiles is computed in each of them, identically, so results do not change.  A level that
+ * cannot be tiled even alone runs as a level launch.  The view schedule is unaffected. */
 sta_status sta_set_level_fusion(sta_graph* g, int32_t enable);
 
 /* The fusion plan of a built graph (host only; independent of sta_set_level_fusion,
@@ -258,9 +259,9 @@ sta_status sta_graph_spans(const sta_graph* g, sta_span_info* out);
  *                      in launch order (bottom up)
  *   bwd[bwd_spans][3]  top driver level, bottom driver level, fused, in launch order
  *                      (top down)
- * Spans partition the levels: forward 1..L, backward 0..L.  A span is at most six
- * (forward) or four (backward) levels long; the builder takes the longest span from the
- * next uncovered level that can be tiled, and an unfused span is a single level. */
+ * Spans partition the levels: forward 1..L, backward 0..L.  A span is at most eight
+ * levels long; the builder takes the longest span from the next uncovered level that can
+ * be tiled, and an unfused span is a single level. */
 sta_status sta_graph_span_list(const sta_graph* g, int32_t* fwd, int32_t* bwd);
 
 /* Per-kernel timing record of the instrumentation calls below. */

@@ -26,14 +26,16 @@ constexpr size_t kViewTableLdsMax = 65536;            // LDS bytes for tables + 
 // fused spans: kSpanF consecutive gate levels per forward launch, kSpanB driver levels
 // per backward launch (the lengths measured best on the 1M-pin design); a span tile holds
 // at most 64 cell arcs, or 64 sink slots, (one wavefront) per level of the span
-constexpr int kSpanF = 6;
-constexpr int kSpanB = 4;
+constexpr int kSpanF = 8;
+constexpr int kSpanB = 8;
 constexpr int kSpanSlotsF = kSpanF * 64;
 constexpr int kSpanSlotsB = kSpanB * 64;
 // Span tiles per workgroup: one, so that the few tiles of a span launch spread over as
 // many compute units as possible (a tile's gathers and table reads are issued by its own
 // unit's address pipeline instead of queueing behind three other tiles').
 constexpr int kSpanWaves = 1;
+// (The span kernels hold a whole tile's prefetched records in registers; they are compiled
+// for one wavefront per SIMD, so that long spans do not spill.)
 // Level-kernel tiles per workgroup (the same reasoning: a level has a few hundred tiles).
 constexpr int kLevelWaves = 1;
 

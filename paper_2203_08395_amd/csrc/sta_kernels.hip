@@ -563,7 +563,7 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
 // instead of one launch and three rounds per level.
 // (Staging the tables in LDS per block was measured slower than the L2-resident reads.)
 template <int NV>
-__global__ __launch_bounds__(64 * kSpanWaves) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
+__global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
                                                       const float* __restrict__ arc_load,
                                                       const float* __restrict__ nd, const float* __restrict__ ni,
                                                       float* __restrict__ drv_ts, float* __restrict__ arc_ts,
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(64 * kLevelWaves) void k_backward(DevGraph G, KView
 // times of sink gates outside the span or the endpoint required times), then the levels
 // top down, in-span required times handed over through LDS.
 template <int NV>
-__global__ __launch_bounds__(64 * kSpanWaves) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
+__global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
                                                        const float* __restrict__ nd, const float* __restrict__ drv_ts,
                                                        const float* __restrict__ arc_ts,
                                                        const float* __restrict__ arc_delay,
@@ -1860,13 +1860,13 @@ __global__ __launch_bounds__(64 * kLevelWaves) void k_adjoint(DevGraph G, KViews
 
 // The adjoint on the backward span tiles: the same dependency structure as the required
 // times (a driver's gradient needs the gradients of its sink gates' outputs), so one
-// launch walks up to four driver levels top down with in-tile gradients in LDS.  Two
+// launch walks up to kSpanB driver levels top down with in-tile gradients in LDS.  Two
 // rounds of loads: the tile's records, then per slot the argmax test's operands (the
 // arc's position, the sink gate's argmax), the gradient of a sink gate outside the tile,
 // or an endpoint's slack.  Integer counts, so the segmented sums are exact in any order
 // and the results equal the level kernel's.
 template <int NV>
-__global__ __launch_bounds__(64 * kSpanWaves) void k_adjoint_span(DevGraph G, KViews V, int tile0, int tile1,
+__global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint_span(DevGraph G, KViews V, int tile0, int tile1,
                                                                   const uint8_t* __restrict__ argmax,
                                                                   const float* __restrict__ drv_slack,
                                                                   float* __restrict__ g_at, float* __restrict__ g_arc,

@@ -192,8 +192,8 @@ class Graph:
         return self
 
     def set_level_fusion(self, enable):
-        """Fused spans: six gate levels per forward launch and four driver levels per
-        backward launch (default on)."""
+        """Fused spans: up to eight gate levels per forward launch and eight driver levels
+        per backward launch (default on)."""
         _check(load_library().sta_set_level_fusion(self._h, int(bool(enable))), "sta_set_level_fusion")
         return self
 

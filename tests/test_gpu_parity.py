@@ -32,14 +32,15 @@ def test_random_tiny_designs(seed, schedule):
 
 
 @SCHED
-@pytest.mark.parametrize("nv", [1, 4, 8])
+@pytest.mark.parametrize("nv", [1, 2, 4, 8])
 def test_view_counts_and_corners(nv, schedule):
     d = gen.make_design(n_pins=30000, n_levels=40, fanin="geom", seed=21, n_fanout64=2)
     lib = gen.make_library(kappas=gen.CORNER_KAPPAS)
     pa, ps = gen.make_pi(d, seed=5)
     late, early = gen.make_rat(d, 40, late_per_level=70.0, hold=120.0)
     modes = [LATE if v % 2 == 0 else EARLY for v in range(nv)]
-    sets = [(v // 2) % 4 for v in range(nv)]
+    # two views on two corners: two distinct table sets in one launch
+    sets = [1, 3] if nv == 2 else [(v // 2) % 4 for v in range(nv)]
     rats = [late if m == LATE else early for m in modes]
     compare_all(d, lib, pa, ps, rats, modes, sets, label=f"{nv} views over corners", schedule=schedule)
 
@@ -76,12 +77,13 @@ def test_ragged_tiles_and_extremes(schedule):
 
 
 @SCHED
-@pytest.mark.parametrize("seed", [5, 6])
-def test_drivers_wider_than_a_tile(seed, schedule):
+@pytest.mark.parametrize("seed,n_tables", [(5, 128), (6, 129)])
+def test_drivers_wider_than_a_tile(seed, n_tables, schedule):
     # two drivers with 100+ sinks: their backward levels cannot be tiled and run as level
-    # launches between fused spans
+    # launches between fused spans; an odd table count (sets not a whole number of 16-byte
+    # pieces) keeps the forward span's table reads in global memory
     d = tiny.wide_fanout_design(seed)
-    lib = gen.make_library()
+    lib = gen.make_library(n_tables=n_tables)
     rng = np.random.default_rng(seed)
     pa = rng.uniform(0, 50, d.n_pi).astype(np.float32)
     ps = rng.uniform(5, 50, d.n_pi).astype(np.float32)

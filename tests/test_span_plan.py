@@ -7,7 +7,7 @@ import pytest
 
 from paper_2203_08395_amd import gen, sta
 
-K_F, K_B = 6, 4   # most gate levels per forward span, driver levels per backward span
+K_F, K_B = 8, 8   # most gate levels per forward span, driver levels per backward span
 
 
 def _plan(cfg):
