@@ -63,6 +63,13 @@ DevGraph dev_graph(const sta_graph* g) {
 
 static bool finite_nonneg(float v) { return std::isfinite(v) && v >= 0.0f; }
 
+// Lane after placing a gate of k cell arcs at lane pos of a forward span chunk: a gate of
+// up to 16 arcs never straddles a 16-lane row (the kernel reduces such gates inside rows).
+static int32_t span_lane(int32_t pos, int32_t k) {
+    if (k <= 16 && (pos & 15) + k > 16) pos = (pos + 15) & ~15;
+    return pos + k;
+}
+
 static sta_status build(const sta_design_desc* d, sta_graph* g) {
     if (!d) return fail(STA_E_ARG, "sta_build_graph: null design");
     if (d->n_pi < 0 || d->n_gates < 0) return fail(STA_E_ARG, "sta_build_graph: negative n_pi or n_gates");
@@ -525,9 +532,10 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
             const int32_t nl = l1 - l0 + 1;
             const size_t t0 = sp_tile.size(), c0all = sp_chunk.size(), a0all = sp_ta_arc.size();
             bool ok = true;
-            // the tile being filled: gates per level in insertion order, arcs per level
+            // the tile being filled: gates per level in insertion order, lanes used per level
             std::vector<std::vector<int32_t>> tg(nl);
             int32_t tarcs[kSpanF] = {};
+            auto nk = [&](int32_t q) { return gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q]; };
             auto flush = [&]() {
                 bool any = false;
                 for (int j = 0; j < nl; ++j) any = any || !tg[j].empty();
@@ -542,7 +550,14 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     const int32_t ta0 = int32_t(sp_ta_arc.size());
                     int32_t maxk = 0;
                     for (int32_t q : tg[j]) {
-                        maxk = std::max(maxk, gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q]);
+                        maxk = std::max(maxk, nk(q));
+                        // padding lanes (gate -1) keep a gate of <= 16 arcs inside one 16-lane row
+                        const int32_t at = span_lane(int32_t(sp_ta_arc.size()) - ta0, nk(q)) - nk(q);
+                        while (int32_t(sp_ta_arc.size()) - ta0 < at) {
+                            sp_ta_arc.push_back(0);
+                            sp_ta_src.push_back(0);
+                            sp_ta_gate.push_back(-1);
+                        }
                         for (int32_t a = gate_arc_ptr_int[q]; a < gate_arc_ptr_int[q + 1]; ++a) {
                             const int32_t u = arc_src[a];
                             sp_ta_arc.push_back(a);
@@ -574,16 +589,19 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                             if (in_span(u) && mark[u - P] != st) { mark[u - P] = st; stack.push_back(u - P); }
                         }
                     }
-                    // arcs the cone adds to the current tile, per level
-                    int32_t add[kSpanF] = {}, alone[kSpanF] = {};
+                    // inserted in ascending gate order per level (drivers precede users: lower
+                    // level); lanes per level after adding the cone to the current tile, or alone
+                    std::sort(cone.begin(), cone.end());
+                    int32_t add[kSpanF], alone[kSpanF] = {};
+                    for (int j = 0; j < nl; ++j) add[j] = tarcs[j];
                     for (int32_t q : cone) {
-                        const int32_t k = gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q];
-                        alone[gate_lv[q] - l0] += k;
-                        if (tile_mark[q] != tile_id) add[gate_lv[q] - l0] += k;
+                        const int32_t j = gate_lv[q] - l0;
+                        alone[j] = span_lane(alone[j], nk(q));
+                        if (tile_mark[q] != tile_id) add[j] = span_lane(add[j], nk(q));
                     }
                     bool fits = true, fits_alone = true;
                     for (int j = 0; j < nl; ++j) {
-                        fits = fits && tarcs[j] + add[j] <= kTileSlots;
+                        fits = fits && add[j] <= kTileSlots;
                         fits_alone = fits_alone && alone[j] <= kTileSlots;
                     }
                     if (!fits_alone) { ok = false; break; }
@@ -591,15 +609,13 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                         flush();
                         for (int j = 0; j < nl; ++j) add[j] = alone[j];
                     }
-                    // insert in ascending gate order per level (drivers precede users: lower level)
-                    std::sort(cone.begin(), cone.end());
                     for (int32_t q : cone) {
                         if (tile_mark[q] == tile_id) continue;
                         tile_mark[q] = tile_id;
                         tg[gate_lv[q] - l0].push_back(q);
                         covered[q] = 1;
                     }
-                    for (int j = 0; j < nl; ++j) tarcs[j] += add[j];
+                    for (int j = 0; j < nl; ++j) tarcs[j] = add[j];
                 }
             }
             if (ok) {
@@ -658,7 +674,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
             const int64_t nch = int64_t(sp_chunk.size() / 4), na = int64_t(sp_ta_arc.size());
             const int64_t a0 = first_of(sp_chunk, int32_t(first_of(sp_tile, t0, nch)), na);
             const int64_t a1 = first_of(sp_chunk, int32_t(first_of(sp_tile, t1, nch)), na);
-            si.fwd_span_arcs_computed += a1 - a0;
+            for (int64_t i = a0; i < a1; ++i) si.fwd_span_arcs_computed += sp_ta_gate[i] >= 0;
         }
         const int64_t NSB = int64_t(g->bspan_fused_h.size());
         for (int64_t b = 0; b < NSB; ++b) {

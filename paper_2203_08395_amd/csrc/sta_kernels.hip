@@ -485,6 +485,33 @@ __device__ __forceinline__ void pin_value(T& x) {
     asm volatile("" : "+v"(x));
 }
 
+// lane l takes lane l + OFF of its 16-lane row (DPP row shift; lanes past the row end keep
+// their own value, which the callers never take)
+template <int OFF>
+__device__ __forceinline__ int row_down(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x100 + OFF, 0xf, 0xf, false);
+}
+
+// one step of the segmented maximum with argmax (and maximum slew) inside 16-lane rows
+template <int OFF, int NW>
+__device__ __forceinline__ void span_max_step(float* cand, float* slw, int* best_k, bool take) {
+    float c2[NW], s2[NW];
+    int k2[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        c2[w] = __int_as_float(row_down<OFF>(__float_as_int(cand[w])));
+        s2[w] = __int_as_float(row_down<OFF>(__float_as_int(slw[w])));
+        k2[w] = row_down<OFF>(best_k[w]);
+    }
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const bool tc = take && c2[w] > cand[w];
+        cand[w] = tc ? c2[w] : cand[w];
+        best_k[w] = tc ? k2[w] : best_k[w];
+        slw[w] = (take && s2[w] > slw[w]) ? s2[w] : slw[w];
+    }
+}
+
 // fwd_finish for a span chunk: the same arithmetic, plus every view's gate result kept
 // in LDS (slot-indexed) for the tile's gates of the levels above
 template <int NW>
@@ -518,30 +545,40 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
             best_k[w] = x.kpos;
         }
     } else {
+        // padding and idle lanes can sit inside a gate's lane range: they never win
 #pragma unroll
-        for (int w = 0; w < NW; ++w) { cand[w] = 0.0f; slw[w] = 0.0f; best_k[w] = 0; }
+        for (int w = 0; w < NW; ++w) { cand[w] = -__builtin_inff(); slw[w] = -__builtin_inff(); best_k[w] = 0; }
     }
-    // segmented maximum with argmax over a gate's arcs: ceil(log2(widest gate)) steps,
-    // every shuffle of a step issued before any is used
+    // segmented maximum with argmax over a gate's arcs: ceil(log2(widest gate)) steps.
+    // Gates of <= 16 arcs lie inside 16-lane rows, so the steps are row shifts (DPP, no
+    // LDS round trip); wider gates use cross-lane permutes, every one of a step issued
+    // before any is used.
+    if (span <= 16) {
+        if (span > 1) span_max_step<1, NW>(cand, slw, best_k, (lane + 1) < x.seg_end);
+        if (span > 2) span_max_step<2, NW>(cand, slw, best_k, (lane + 2) < x.seg_end);
+        if (span > 4) span_max_step<4, NW>(cand, slw, best_k, (lane + 4) < x.seg_end);
+        if (span > 8) span_max_step<8, NW>(cand, slw, best_k, (lane + 8) < x.seg_end);
+    } else {
 #pragma unroll
-    for (int st = 0; st < 6; ++st) {
-        const int off = 1 << st;
-        if (off >= span) break;                 // uniform
-        const bool take = (lane + off) < x.seg_end;
-        float c2[NW], s2[NW];
-        int k2[NW];
+        for (int st = 0; st < 6; ++st) {
+            const int off = 1 << st;
+            if (off >= span) break;             // uniform
+            const bool take = (lane + off) < x.seg_end;
+            float c2[NW], s2[NW];
+            int k2[NW];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            c2[w] = __shfl_down(cand[w], off, 64);
-            s2[w] = __shfl_down(slw[w], off, 64);
-            k2[w] = __shfl_down(best_k[w], off, 64);
-        }
+            for (int w = 0; w < NW; ++w) {
+                c2[w] = __shfl_down(cand[w], off, 64);
+                s2[w] = __shfl_down(slw[w], off, 64);
+                k2[w] = __shfl_down(best_k[w], off, 64);
+            }
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const bool tc = take && c2[w] > cand[w];
-            cand[w] = tc ? c2[w] : cand[w];
-            best_k[w] = tc ? k2[w] : best_k[w];
-            slw[w] = (take && s2[w] > slw[w]) ? s2[w] : slw[w];
+            for (int w = 0; w < NW; ++w) {
+                const bool tc = take && c2[w] > cand[w];
+                cand[w] = tc ? c2[w] : cand[w];
+                best_k[w] = tc ? k2[w] : best_k[w];
+                slw[w] = (take && s2[w] > slw[w]) ? s2[w] : slw[w];
+            }
         }
     }
     if (x.head) {
@@ -633,7 +670,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
     for (int c = 0; c < kSpanF; ++c) {
         if (c >= nch) break;                    // uniform
-        const bool act = lane < na[c];
+        const bool act = lane < na[c] && gt[c] >= 0;   // gate -1: padding lane
         FwdLane x;
         fwd_lane_setup(x, act, act ? meta[c] : 0u, na[c], lane);
         x.a = ar[c];
