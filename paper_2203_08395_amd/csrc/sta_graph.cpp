@@ -63,8 +63,8 @@ DevGraph dev_graph(const sta_graph* g) {
 
 static bool finite_nonneg(float v) { return std::isfinite(v) && v >= 0.0f; }
 
-// Lane after placing a gate of k cell arcs at lane pos of a forward span chunk: a gate of
-// up to 16 arcs never straddles a 16-lane row (the kernel reduces such gates inside rows).
+// Lane after placing a gate of k cell arcs (a driver of k sink slots) at lane pos of a span
+// chunk: one of up to 16 never straddles a 16-lane row (the kernels reduce it inside rows).
 static int32_t span_lane(int32_t pos, int32_t k) {
     if (k <= 16 && (pos & 15) + k > 16) pos = (pos + 15) & ~15;
     return pos + k;
@@ -407,6 +407,13 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     int32_t maxs = 1;
                     for (int32_t i : td[j]) {
                         maxs = std::max(maxs, nslots(i));
+                        // padding lanes (slot -1) keep a driver of <= 16 slots inside one row
+                        const int32_t at = span_lane(int32_t(bp_slot.size()) - ts0, nslots(i)) - nslots(i);
+                        while (int32_t(bp_slot.size()) - ts0 < at) {
+                            bp_slot.push_back(-1);
+                            bp_src.push_back(-2);
+                            bp_drv.push_back(0);
+                        }
                         for (int32_t sl = slot_ptr[i]; sl < slot_ptr[i + 1]; ++sl) {
                             const int32_t sa = bslot_arc[sl];
                             int32_t src = -1;
@@ -446,15 +453,19 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                             if (in_span(o) && mark[o] != st) { mark[o] = st; stack.push_back(o); }
                         }
                     }
-                    int32_t add[kSpanB] = {}, alone[kSpanB] = {};
+                    // lanes per level after adding the cone (in insertion order) to the
+                    // current tile, or alone
+                    std::sort(cone.begin(), cone.end());
+                    int32_t add[kSpanB], alone[kSpanB] = {};
+                    for (int j = 0; j < nl; ++j) add[j] = tslots[j];
                     for (int32_t i : cone) {
-                        const int32_t k = nslots(i);
-                        alone[top - lv(i)] += k;
-                        if (tile_mark[i] != tile_id) add[top - lv(i)] += k;
+                        const int32_t j = top - lv(i);
+                        alone[j] = span_lane(alone[j], nslots(i));
+                        if (tile_mark[i] != tile_id) add[j] = span_lane(add[j], nslots(i));
                     }
                     bool fits = true, fits_alone = true;
                     for (int j = 0; j < nl; ++j) {
-                        fits = fits && tslots[j] + add[j] <= kTileSlots;
+                        fits = fits && add[j] <= kTileSlots;
                         fits_alone = fits_alone && alone[j] <= kTileSlots;
                     }
                     if (!fits_alone) { ok = false; break; }
@@ -462,14 +473,13 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                         flush();
                         for (int j = 0; j < nl; ++j) add[j] = alone[j];
                     }
-                    std::sort(cone.begin(), cone.end());
                     for (int32_t i : cone) {
                         if (tile_mark[i] == tile_id) continue;
                         tile_mark[i] = tile_id;
                         td[top - lv(i)].push_back(i);
                         covered[i] = 1;
                     }
-                    for (int j = 0; j < nl; ++j) tslots[j] += add[j];
+                    for (int j = 0; j < nl; ++j) tslots[j] = add[j];
                 }
             }
             if (ok) {
@@ -694,7 +704,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
             const int64_t nch = int64_t(bp_chunk.size() / 4), ns = int64_t(bp_slot.size());
             const int64_t s0 = first_of(bp_chunk, int32_t(first_of(bp_tile, t0, nch)), ns);
             const int64_t s1 = first_of(bp_chunk, int32_t(first_of(bp_tile, t1, nch)), ns);
-            si.bwd_span_slots_computed += s1 - s0;
+            for (int64_t i = s0; i < s1; ++i) si.bwd_span_slots_computed += bp_slot[i] >= 0;
         }
     }
 
@@ -735,6 +745,10 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
             for (int32_t k = 0; k < ns; ++k) {
                 int32_t* sr = &bp_srec[(size_t(t * kSpanB + c) * 64 + k) * 4];
                 const int32_t sl = bp_slot[ts0 + k];
+                if (sl < 0) {            // padding lane: source -2, loads from endpoint rank 0 and driver 0
+                    sr[0] = -1; sr[1] = 0; sr[2] = -2; sr[3] = 0;
+                    continue;
+                }
                 sr[0] = bslot_arc[sl]; sr[1] = bslot_out[sl]; sr[2] = bp_src[ts0 + k]; sr[3] = bp_drv[ts0 + k];
             }
         }

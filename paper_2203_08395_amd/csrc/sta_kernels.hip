@@ -512,6 +512,24 @@ __device__ __forceinline__ void span_max_step(float* cand, float* slw, int* best
     }
 }
 
+// one step of a segmented minimum / sum inside 16-lane rows
+template <int OFF, int NV>
+__device__ __forceinline__ void span_min_step(float* best, bool take) {
+    float b2[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) b2[v] = __int_as_float(row_down<OFF>(__float_as_int(best[v])));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) best[v] = (take && b2[v] < best[v]) ? b2[v] : best[v];
+}
+template <int OFF, int NV>
+__device__ __forceinline__ void span_sum_step(float* acc, bool take) {
+    float b2[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) b2[v] = __int_as_float(row_down<OFF>(__float_as_int(acc[v])));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = take ? acc[v] + b2[v] : acc[v];
+}
+
 // fwd_finish for a span chunk: the same arithmetic, plus every view's gate result kept
 // in LDS (slot-indexed) for the tile's gates of the levels above
 template <int NW>
@@ -808,7 +826,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     for (int c = 0; c < kSpanB; ++c) {
         if (c >= nch) break;                    // uniform
         const int n = ns[c];
-        const bool act = lane < n;
+        const bool act = lane < n && src[c] != -2;   // source -2: padding lane
         const bool head = act && hd[c];
         const uint64_t heads = __ballot(head);
         const uint64_t le = lanes_le(lane);
@@ -833,21 +851,28 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
                 arc_rat[size_t(sa_[c]) * NV + v] = rin;
                 arc_slack[size_t(sa_[c]) * NV + v] = early[v] ? (ati[c][v] - rin) : (rin - ati[c][v]);
             }
-            const float val = on_arc ? rin - ndv[c] : (act ? ext[c][v] : 0.0f);
-            best[v] = early[v] ? -val : val;
+            const float val = on_arc ? rin - ndv[c] : ext[c][v];
+            best[v] = act ? (early[v] ? -val : val) : __builtin_inff();   // idle lanes never win
         }
-        // segmented minimum over a driver's slots: ceil(log2(most slots)) steps, every
-        // view's shuffle issued before any is used
+        // segmented minimum over a driver's slots: ceil(log2(most slots)) steps; drivers of
+        // <= 16 slots lie inside 16-lane rows (DPP row shifts), wider ones use permutes
+        if (ms[c] <= 16) {
+            if (ms[c] > 1) span_min_step<1, NV>(best, (lane + 1) < seg_end);
+            if (ms[c] > 2) span_min_step<2, NV>(best, (lane + 2) < seg_end);
+            if (ms[c] > 4) span_min_step<4, NV>(best, (lane + 4) < seg_end);
+            if (ms[c] > 8) span_min_step<8, NV>(best, (lane + 8) < seg_end);
+        } else {
 #pragma unroll
-        for (int st = 0; st < 6; ++st) {
-            const int off = 1 << st;
-            if (off >= ms[c]) break;            // uniform
-            const bool take = (lane + off) < seg_end;
-            float b2[NV];
+            for (int st = 0; st < 6; ++st) {
+                const int off = 1 << st;
+                if (off >= ms[c]) break;        // uniform
+                const bool take = (lane + off) < seg_end;
+                float b2[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) b2[v] = __shfl_down(best[v], off, 64);
+                for (int v = 0; v < NV; ++v) b2[v] = __shfl_down(best[v], off, 64);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) best[v] = (take && b2[v] < best[v]) ? b2[v] : best[v];
+                for (int v = 0; v < NV; ++v) best[v] = (take && b2[v] < best[v]) ? b2[v] : best[v];
+            }
         }
         if (head) {
             const int u = drv[c];
@@ -1967,7 +1992,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     for (int c = 0; c < kSpanB; ++c) {
         if (c >= nch) break;                    // uniform
         const int n = ns[c];
-        const bool act = lane < n;
+        const bool act = lane < n && src[c] != -2;   // source -2: padding lane
         const bool head = act && hd[c];
         const uint64_t heads = __ballot(head);
         const uint64_t le = lanes_le(lane);
@@ -1991,16 +2016,23 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
             const float ep = ext[c][v] < 0.0f ? (early[v] ? 1.0f : -1.0f) : 0.0f;
             acc[v] = on_arc ? cv : (act ? ep : 0.0f);
         }
+        if (ms[c] <= 16) {
+            if (ms[c] > 1) span_sum_step<1, NV>(acc, (lane + 1) < seg_end);
+            if (ms[c] > 2) span_sum_step<2, NV>(acc, (lane + 2) < seg_end);
+            if (ms[c] > 4) span_sum_step<4, NV>(acc, (lane + 4) < seg_end);
+            if (ms[c] > 8) span_sum_step<8, NV>(acc, (lane + 8) < seg_end);
+        } else {
 #pragma unroll
-        for (int st = 0; st < 6; ++st) {
-            const int off = 1 << st;
-            if (off >= ms[c]) break;            // uniform
-            const bool take = (lane + off) < seg_end;
-            float b2[NV];
+            for (int st = 0; st < 6; ++st) {
+                const int off = 1 << st;
+                if (off >= ms[c]) break;        // uniform
+                const bool take = (lane + off) < seg_end;
+                float b2[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) b2[v] = __shfl_down(acc[v], off, 64);
+                for (int v = 0; v < NV; ++v) b2[v] = __shfl_down(acc[v], off, 64);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] = take ? acc[v] + b2[v] : acc[v];
+                for (int v = 0; v < NV; ++v) acc[v] = take ? acc[v] + b2[v] : acc[v];
+            }
         }
         if (head) {
             const int u = drv[c];
