@@ -38,17 +38,12 @@ namespace sta {
 
 // Lane t of the block owns net (blockIdx.x*NT + t).  Node temporaries live in LDS,
 // interleaved by lane: slot (k, t) at [k*NT + t].
+// One net's moments (the driver d's lane), node temporaries in the caller's LDS arrays
+// sA, sB, sM of MAXN * NT values interleaved by lane t.
 template <typename T, int MAXN, int NT>
-__global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict__ load,
-                                                   float* __restrict__ net_delay,
-                                                   float* __restrict__ net_imp2,
-                                                   float* __restrict__ arc_load) {
-    __shared__ T sA[MAXN * NT];   // C, later m2
-    __shared__ T sB[MAXN * NT];   // Cd, later W
-    __shared__ T sM[MAXN * NT];   // m1
-    const int t = threadIdx.x;
-    const int d = blockIdx.x * NT + t;
-    if (d >= G.n_drivers) return;
+__device__ __forceinline__ void dc_net(const DevGraph& G, int d, int t, T* sA, T* sB, T* sM, float* __restrict__ load,
+                                       float* __restrict__ net_delay, float* __restrict__ net_imp2,
+                                       float* __restrict__ arc_load) {
     const int n0 = G.net_node_ptr[d];
     const int nm = G.net_node_ptr[d + 1] - n0;
     const int16_t* par = G.node_parent + n0;
@@ -86,6 +81,109 @@ __global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict
         net_imp2[a] = static_cast<float>(imp2);
     }
 #undef AT_
+}
+
+// dc_net for nets of at most 8 nodes: the node data and the first eight sinks are loaded
+// into registers in one round (clamped, unconditional loads) instead of inside the loops
+// that use them, so a net costs a few memory round trips instead of one per loop step.
+// The arithmetic and its order are dc_net's.
+template <typename T, int NT>
+__device__ __forceinline__ void dc_net8(const DevGraph& G, int d, int t, T* sA, T* sB, T* sM, float* __restrict__ load,
+                                        float* __restrict__ net_delay, float* __restrict__ net_imp2,
+                                        float* __restrict__ arc_load) {
+    const int n0 = G.net_node_ptr[d];
+    const int nm = G.net_node_ptr[d + 1] - n0;
+    const int f0 = G.fo_ptr[d], f1 = G.fo_ptr[d + 1];
+    int par[8];
+    float R[8], Cw[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int kk = n0 + (k < nm ? k : 0);
+        par[k] = G.node_parent[kk];
+        R[k] = G.node_R[kk];
+        Cw[k] = G.node_C[kk];
+    }
+    int tap[8], arc[8];
+    float cap[8];
+    auto load_sinks = [&](int e0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = e0 + j < f1 ? e0 + j : f0;
+            tap[j] = G.fo_tap[e];
+            cap[j] = G.fo_cap[e];
+            arc[j] = G.fo_arc[e];
+        }
+    };
+    if (f1 > f0) load_sinks(f0);
+    T* A = sA + t;
+    T* B = sB + t;
+    T* Mm = sM + t;
+#define AT_(arr, k) arr[(k) * NT]
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (k < nm) AT_(A, k) = static_cast<T>(Cw[k]);
+    for (int e0 = f0; e0 < f1; e0 += 8) {
+        if (e0 != f0) load_sinks(e0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (e0 + j < f1) AT_(A, tap[j]) += static_cast<T>(cap[j]);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (k < nm) AT_(B, k) = AT_(A, k);
+#pragma unroll
+    for (int k = 7; k >= 1; --k)
+        if (k < nm) AT_(B, par[k]) += AT_(B, k);
+    const float ld = static_cast<float>(AT_(B, 0));
+    load[d] = ld;
+    if (d >= G.n_pi) {
+        const int q = d - G.n_pi;
+        for (int a = G.gate_arc_ptr[q]; a < G.gate_arc_ptr[q + 1]; ++a) arc_load[a] = ld;
+    }
+    const T milli = static_cast<T>(1e-3);
+    AT_(Mm, 0) = T(0);
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+        if (k < nm) AT_(Mm, k) = AT_(Mm, par[k]) + (static_cast<T>(R[k]) * AT_(B, k)) * milli;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (k < nm) AT_(B, k) = AT_(A, k) * AT_(Mm, k);
+#pragma unroll
+    for (int k = 7; k >= 1; --k)
+        if (k < nm) AT_(B, par[k]) += AT_(B, k);
+    AT_(A, 0) = T(0);
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+        if (k < nm) AT_(A, k) = AT_(A, par[k]) + (static_cast<T>(R[k]) * AT_(B, k)) * milli;
+    for (int e0 = f0; e0 < f1; e0 += 8) {
+        if (e0 != f0 || f1 - f0 > 8) load_sinks(e0);    // the first eight are still in registers
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (e0 + j >= f1) break;
+            const int k = tap[j];
+            const T m1 = AT_(Mm, k);
+            T imp2 = T(2) * AT_(A, k) - m1 * m1;
+            if (imp2 < T(0)) imp2 = T(0);
+            net_delay[arc[j]] = static_cast<float>(m1);
+            net_imp2[arc[j]] = static_cast<float>(imp2);
+        }
+    }
+#undef AT_
+}
+
+template <typename T, int MAXN, int NT>
+__global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict__ load,
+                                                   float* __restrict__ net_delay,
+                                                   float* __restrict__ net_imp2,
+                                                   float* __restrict__ arc_load) {
+    __shared__ T sA[MAXN * NT];   // C, later m2
+    __shared__ T sB[MAXN * NT];   // Cd, later W
+    __shared__ T sM[MAXN * NT];   // m1
+    const int t = threadIdx.x;
+    const int d = blockIdx.x * NT + t;
+    if (d >= G.n_drivers) return;
+    if constexpr (MAXN == 8) dc_net8<T, NT>(G, d, t, sA, sB, sM, load, net_delay, net_imp2, arc_load);
+    else dc_net<T, MAXN, NT>(G, d, t, sA, sB, sM, load, net_delay, net_imp2, arc_load);
 }
 
 // ---------------------------------------------------------------------------------

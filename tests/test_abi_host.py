@@ -50,6 +50,20 @@ def test_library_exports_every_analysis_symbol():
     assert lib.sta_critical_paths(None, None, 0, 1, None, None, None, None, 0, None) == -1
 
 
+def test_timing_calls_validate_before_launching():
+    """Null arguments and a graph that is not uploaded are errors, caught on the host."""
+    lib = sta.load_library()
+    assert lib.sta_propagate(None, None, None, None, None, None, None) == -1
+    g = sta.Graph(_ok_design(), n_tables=4)
+    L = sta.LibraryC()
+    v = sta.ViewsC()
+    no, to = sta.NetOut(), sta.TimingOut()
+    st = lib.sta_propagate(g.handle, ctypes.byref(L), ctypes.byref(v), None, ctypes.byref(no), ctypes.byref(to), None)
+    assert st == -1 and b"not uploaded" in lib.sta_last_error()
+    st = lib.sta_delay_calc(g.handle, 0, ctypes.byref(no), None)
+    assert st == -1 and b"not uploaded" in lib.sta_last_error()
+
+
 def test_surrogate_host_validation_without_gpu():
     """Argument errors are caught before any launch (no device pointer is touched)."""
     from paper_2203_08395_amd import surrogate
