@@ -260,6 +260,36 @@ __device__ __forceinline__ void gate_jty(const float* s_ax, float Lo, int& j, fl
     ty = (Lo - Y[j]) / DY[j];
 }
 
+// One table axis as named wave-uniform scalars (no array, so nothing is ever indexed
+// through memory): the first six points and the six segment widths.
+struct Axis6 {
+    float p0, p1, p2, p3, p4, p5;
+    float w0, w1, w2, w3, w4, w5;
+};
+
+__device__ __forceinline__ Axis6 axis6(const KLib& lib, int base, int wbase) {
+    return Axis6{lib.ax[base], lib.ax[base + 1], lib.ax[base + 2], lib.ax[base + 3], lib.ax[base + 4],
+                 lib.ax[base + 5], lib.ax[wbase], lib.ax[wbase + 1], lib.ax[wbase + 2], lib.ax[wbase + 3],
+                 lib.ax[wbase + 4], lib.ax[wbase + 5]};
+}
+
+// seg6 by compares and selects, also returning the segment's origin and width.  The axes
+// strictly increase, so the compares are true for a prefix of the points: the count of
+// true compares and the last true one are the same index.
+__device__ __forceinline__ int seg6_sel(const Axis6& a, float v, float& x0, float& dx) {
+    int i = 0;
+    x0 = a.p0;
+    dx = a.w0;
+#define SEG6_STEP_(P, W) { const bool ge = (P) <= v; i += ge ? 1 : 0; x0 = ge ? (P) : x0; dx = ge ? (W) : dx; }
+    SEG6_STEP_(a.p1, a.w1)
+    SEG6_STEP_(a.p2, a.w2)
+    SEG6_STEP_(a.p3, a.w3)
+    SEG6_STEP_(a.p4, a.w4)
+    SEG6_STEP_(a.p5, a.w5)
+#undef SEG6_STEP_
+    return i;
+}
+
 // arc arithmetic, per-gate max/argmax (min for early views) and the writes.  span: the
 // largest gate fanin in the tile (the reduction needs ceil(log2(span)) steps).
 // fresh_out (optional, LDS): the gate outputs of the first view, by gate index - gbase.
@@ -632,12 +662,10 @@ __device__ __forceinline__ void span_sum_step(float* acc, bool take) {
 // in LDS (slot-indexed) for the tile's gates of the levels above
 template <int NW>
 __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* ts, int j, float ty, int span,
-                                                const float* s_ax, const float* const* tab, const bool* early,
+                                                const Axis6& ax_x, const float* const* tab, const bool* early,
                                                 int n_pi, float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                                 float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
                                                 float2* lds_res, int slot) {
-    const float* X = s_ax;
-    const float* DX = s_ax + 14;
     const int lane = threadIdx.x & 63;
     float cand[NW], slw[NW];
     int best_k[NW];
@@ -648,8 +676,9 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
             const float ai = ts[w].x + x.nd;
             const float su2 = ts[w].y * ts[w].y;
             const float si = sqrtf(su2 + x.ni);
-            const int i = seg6(X, si);
-            const float tx = (si - X[i]) / DX[i];
+            float x0, dx;
+            const int i = seg6_sel(ax_x, si, x0, dx);
+            const float tx = (si - x0) / dx;
             const float* T = tab[w] + size_t(x.tb) * 98;
             const float dl = bilerp(T, i, j, tx, ty);
             const float sl = bilerp(T + 49, i, j, tx, ty);
@@ -721,8 +750,9 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
                                                       const float* __restrict__ nd, const float* __restrict__ ni,
                                                       float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                                       float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
-    __shared__ float s_ax[32];
     __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NV];
+    // the table axes in wave-uniform registers
+    const Axis6 ax_x = axis6(lib, 0, 14), ax_y = axis6(lib, 7, 20);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = tile0 + blockIdx.x * kSpanWaves + wave;
     const int tc = t < tile1 ? t : tile1 - 1;
@@ -753,8 +783,6 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         gt[c] = r.z;
         meta[c] = uint32_t(r.w);
     }
-    load_axes(s_ax, lib);
-    __syncthreads();
     if (t >= tile1) return;
     // round 2: the arcs' net data and the arrivals of drivers outside the span
     float ndv[kSpanF], niv[kSpanF], lov[kSpanF];
@@ -796,7 +824,11 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         x.Lo = act ? lov[c] : 0.0f;
         int j = 0;
         float ty = 0.0f;
-        gate_jty(s_ax, x.Lo, j, ty);
+        {
+            float y0, dy;
+            j = seg6_sel(ax_y, x.Lo, y0, dy);
+            ty = (x.Lo - y0) / dy;
+        }
         float2 ts[NV];
         if (act && sc[c] < 0) {
             const int src = -1 - sc[c];
@@ -806,7 +838,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
             for (int v = 0; v < NV; ++v) ts[v] = act ? ext[c][v] : make_float2(0.0f, 0.0f);
         }
-        fwd_finish_span<NV>(x, ts, j, ty, mk[c], s_ax, tab, early, G.n_pi, drv_ts, arc_ts, arc_delay, argmax, res,
+        fwd_finish_span<NV>(x, ts, j, ty, mk[c], ax_x, tab, early, G.n_pi, drv_ts, arc_ts, arc_delay, argmax, res,
                             sl0[c] + x.gi);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
