@@ -922,7 +922,9 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         src[c] = r.z;
         drv[c] = r.w;
     }
-    // round 2: slot data (everything that does not come from this tile)
+    // round 2: the slot data the required times need (net delay, arc delay, required
+    // times from outside the tile), waited for before the first level; then the arrivals
+    // that only the slacks need, issued behind them and used after the last level
     float ndv[kSpanB], dl[kSpanB][NV], ati[kSpanB][NV], ext[kSpanB][NV], atd[kSpanB][NV];
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
@@ -930,28 +932,36 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         const int sac = sa >= 0 ? sa : 0;
         ndv[c] = nd[sac];
         const float* ext_src = (sa >= 0) ? (drv_rat + size_t(so_[c]) * NV) : (ep_rat + size_t(so_[c]) * NV);
-        const float2* ts = reinterpret_cast<const float2*>(arc_ts) + size_t(sac) * NV;
-        const float2* dt = reinterpret_cast<const float2*>(drv_ts) + size_t(drv[c]) * NV;
         const float* ext_ld = src[c] >= 0 ? ep_rat : ext_src;   // in-tile sources: any valid address
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             dl[c][v] = arc_delay[size_t(sac) * NV + v];
-            ati[c][v] = ts[v].x;
             ext[c][v] = ext_ld[v];
-            atd[c][v] = dt[v].x;
         }
     }
+    asm volatile("" ::: "memory");             // the loads above issue first
+#pragma unroll
+    for (int c = 0; c < kSpanB; ++c) {
+        const int sac = sa_[c] >= 0 ? sa_[c] : 0;
+        const float* ts = arc_ts + size_t(sac) * NV * 2;
+        const float* dt = drv_ts + size_t(drv[c]) * NV * 2;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            ati[c][v] = ts[2 * v];
+            atd[c][v] = dt[2 * v];
+        }
+    }
+    asm volatile("" ::: "memory");             // and these stay here, in flight
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
         pin_value(ndv[c]);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             pin_value(dl[c][v]);
-            pin_value(ati[c][v]);
             pin_value(ext[c][v]);
-            pin_value(atd[c][v]);
         }
     }
+    float rin_[kSpanB][NV], rdrv[kSpanB][NV];
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
         if (c >= nch) break;                    // uniform
@@ -977,10 +987,8 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const float rin = ro[v] - dl[c][v];
-            if (on_arc) {
-                arc_rat[size_t(sa_[c]) * NV + v] = rin;
-                arc_slack[size_t(sa_[c]) * NV + v] = early[v] ? (ati[c][v] - rin) : (rin - ati[c][v]);
-            }
+            rin_[c][v] = rin;
+            if (on_arc) arc_rat[size_t(sa_[c]) * NV + v] = rin;
             const float val = on_arc ? rin - ndv[c] : ext[c][v];
             best[v] = act ? (early[v] ? -val : val) : __builtin_inff();   // idle lanes never win
         }
@@ -1010,13 +1018,31 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
             for (int v = 0; v < NV; ++v) {
                 const float r = early[v] ? -best[v] : best[v];
                 drv_rat[size_t(u) * NV + v] = r;
-                drv_slack[size_t(u) * NV + v] = early[v] ? (atd[c][v] - r) : (r - atd[c][v]);
                 rs[(ds0[c] + gi) * NV + v] = r;
             }
         }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) rdrv[c][v] = early[v] ? -best[v] : best[v];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // the slacks, once the arrivals have landed
+#pragma unroll
+    for (int c = 0; c < kSpanB; ++c) {
+        if (c >= nch) break;                    // uniform
+        const bool act = lane < ns[c] && src[c] != -2;
+        if (act && sa_[c] >= 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                arc_slack[size_t(sa_[c]) * NV + v] = early[v] ? (ati[c][v] - rin_[c][v]) : (rin_[c][v] - ati[c][v]);
+        }
+        if (act && hd[c]) {
+            const int u = drv[c];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                drv_slack[size_t(u) * NV + v] = early[v] ? (atd[c][v] - rdrv[c][v]) : (rdrv[c][v] - atd[c][v]);
+        }
     }
 }
 
