@@ -527,15 +527,15 @@ struct KTiles {
 };
 
 // Level schedule, forward: one tile per 64-lane block.  The block first issues its
-// tiles' arc loads, then copies the view tables into LDS (TAB_LDS: every view reads the
-// same table set), then gathers the drivers' results and computes.
-template <int NV, bool TAB_LDS>
+// tile's arc loads, then gathers the drivers' results and computes (the tables stay in
+// global memory: copying them into each block's LDS was measured slower than the
+// L2-resident reads it replaces).
+template <int NV>
 __global__ __launch_bounds__(64 * kLevelWaves) void k_forward(DevGraph G, KLib lib, KViews V, int tile0, int tile1, KTiles kt,
                                                  const float* __restrict__ arc_load, const float* __restrict__ nd,
                                                  const float* __restrict__ ni, float* __restrict__ drv_ts,
                                                  float* __restrict__ arc_ts, float* __restrict__ arc_delay,
                                                  uint8_t* __restrict__ argmax) {
-    extern __shared__ float s_dyn[];
     __shared__ float s_ax[26];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -566,18 +566,6 @@ __global__ __launch_bounds__(64 * kLevelWaves) void k_forward(DevGraph G, KLib l
     x.ni = act ? ni_r : 0.0f;
     x.Lo = act ? lo_r : 0.0f;
     load_axes(s_ax, lib);
-    if (TAB_LDS) {
-        const float* gt = lib.tables + size_t(V.set[0]) * lib.n_tables * 98;
-        const int nt = lib.n_tables * 98;
-        int done = 0;
-        if ((reinterpret_cast<uintptr_t>(gt) & 15u) == 0) {
-            const float4* src = reinterpret_cast<const float4*>(gt);
-            float4* dst = reinterpret_cast<float4*>(s_dyn);
-            done = (nt / 4) * 4;
-            for (int i = threadIdx.x; i < nt / 4; i += 256) dst[i] = src[i];
-        }
-        for (int i = done + threadIdx.x; i < nt; i += 256) s_dyn[i] = gt[i];
-    }
     __syncthreads();
     if (!valid) return;
     fwd_lane_setup(x, act, meta, n, lane);
@@ -590,7 +578,7 @@ __global__ __launch_bounds__(64 * kLevelWaves) void k_forward(DevGraph G, KLib l
     bool early[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        tab[v] = TAB_LDS ? s_dyn : lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
+        tab[v] = lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
         early[v] = V.mode[v] == STA_EARLY;
     }
     // second round: the drivers' results
@@ -1830,13 +1818,11 @@ static sta_status run_sequence(const sta_graph* g, LaunchCache& c, std::vector<u
 
 static uint64_t pk(const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); }
 
-template <int NV, bool TAB_LDS>
+template <int NV>
 static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KViews& kv, const float* pi_ts,
                                    const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
     const DevGraph dg = dev_graph(g);
     const int npi = int(g->n_pi) * NV * 2;
-    const size_t lds = TAB_LDS ? size_t(lib.n_tables) * 98 * 4 : 0;
-    if (TAB_LDS) set_lds(k_forward<NV, TAB_LDS>, lds);
     if (npi > 0)
         prof_launch("k_copy_pi", s, [&] {
             hipLaunchKernelGGL(k_copy_pi, dim3((npi + 255) / 256), dim3(256), 0, s, pi_ts, o->drv_ts, npi);
@@ -1846,14 +1832,14 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
         if (t1 <= t0) return;
         const KTiles kt = ktiles(g->ftile_arc_h, g->ftile_gate_h, t0, t1);
         prof_launch("k_forward", s, [&] {
-            hipLaunchKernelGGL((k_forward<NV, TAB_LDS>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves),
-                               dim3(64 * kLevelWaves), lds, s, dg, lib, kv, t0,
+            hipLaunchKernelGGL((k_forward<NV>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves),
+                               dim3(64 * kLevelWaves), 0, s, dg, lib, kv, t0,
                                t1, kt, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts, o->arc_delay,
                                o->argmax);
         });
     };
     if constexpr (NV <= 2) {
-        if (g->use_spans && !TAB_LDS) {
+        if (g->use_spans) {
             const int64_t NS = int64_t(g->span_fused_h.size());
             for (int64_t sp = 0; sp < NS; ++sp) {
                 const int64_t l0 = g->span_lv_h[2 * sp], l1 = g->span_lv_h[2 * sp + 1];
@@ -1879,20 +1865,13 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
 template <int NV>
 static sta_status run_forward_levels(const sta_graph* g, const KLib& lib, const KViews& kv, const float* pi_ts,
                                      const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
-    bool same_set = true;
-    for (int v = 1; v < NV; ++v) same_set = same_set && kv.set[v] == kv.set[0];
-    // Copying the tables into every block's LDS costs more than the L2-resident global
-    // reads it replaces (one level is ~10 blocks that each use a few hundred entries).
-    const bool tab_lds = false;
-    (void)same_set;
     std::vector<uint64_t> key = {uint64_t(NV), pk(lib.tables), uint64_t(lib.n_tables), pk(pi_ts), pk(nd->arc_load),
                                  pk(nd->net_delay), pk(nd->net_imp2), pk(o->drv_ts), pk(o->arc_ts), pk(o->arc_delay),
-                                 pk(o->argmax), uint64_t(tab_lds), uint64_t(g->use_spans)};
+                                 pk(o->argmax), uint64_t(g->use_spans)};
     for (int i = 0; i < 26; ++i) { uint32_t b; std::memcpy(&b, &lib.ax[i], 4); key.push_back(b); }
     for (int v = 0; v < NV; ++v) key.push_back((uint64_t(kv.mode[v]) << 32) | uint32_t(kv.set[v]));
     return run_sequence(g, g->fwd_cache, std::move(key), s, [&](hipStream_t q) {
-        if (tab_lds) enqueue_forward_levels<NV, true>(g, lib, kv, pi_ts, nd, o, q);
-        else enqueue_forward_levels<NV, false>(g, lib, kv, pi_ts, nd, o, q);
+        enqueue_forward_levels<NV>(g, lib, kv, pi_ts, nd, o, q);
     });
 }
 
@@ -2439,7 +2418,7 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 template <int NV>
 static void enqueue_levels_any(const sta_graph* g, const KLib& kl, const KViews& kv, const float* pi_ts,
                                const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
-    enqueue_forward_levels<NV, false>(g, kl, kv, pi_ts, nd, o, s);
+    enqueue_forward_levels<NV>(g, kl, kv, pi_ts, nd, o, s);
 }
 
 static void enqueue_levels_nv(int NV, const sta_graph* g, const KLib& kl, const KViews& kv, const float* pi_ts,
