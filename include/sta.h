@@ -212,8 +212,10 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
 /* Schedule of sta_propagate and sta_slack on graph g.  The view schedule (one workgroup
  * per view walks every level, a workgroup barrier between levels) is used when the
  * design's mean cell arcs per level is at most view_max_arcs_per_level (and the level
- * data fits in LDS), the level schedule (one launch per level, all views per launch)
- * otherwise.  0 forces the level schedule; a negative value restores the default (512).
+ * data fits in LDS), the level schedule (launches per level or per fused span, all views
+ * per launch) otherwise.  0 forces the level schedule.  A negative value restores the
+ * library's choice (the default): the level schedule with fused spans for one or two
+ * views, and for more views the view schedule up to 512 mean cell arcs per level.
  * use_graphs != 0 (the default) lets the level schedule capture its launch sequence in a
  * hipGraph on first use and replay it while the call's arguments stay the same (the
  * capture is per graph and per call kind; a change of any pointer or view re-captures).

@@ -68,7 +68,7 @@ class Tuner:
             t_view = self._time(lambda: sta.propagate(g, lib, views, pi_ts, nd, out=tm))
             g.set_schedule(0, True)
             t_level = self._time(lambda: sta.propagate(g, lib, views, pi_ts, nd, out=tm))
-            g.set_schedule(512, True)
+            g.set_schedule(-1, True)
             self.cache[key] = {"unit_ms": t_view, "level_ms": t_level}
             self.measured += 1
         c = self.cache[key]

@@ -128,6 +128,7 @@ struct sta_graph {
     int32_t max_ft = 0, max_fa = 0, max_fg = 0, max_bt = 0, max_bs = 0, max_bd = 0;
     int32_t n_fchunks = 0, n_bchunks = 0;
     int32_t view_sched_max_arcs = sta::kDefaultViewSchedMaxArcs;
+    bool view_auto = true;               // schedule left to the library (sta_set_schedule < 0)
     bool use_graphs = true;              // replay level-schedule launch sequences from hipGraphs
     bool use_spans = true;               // fused spans (kSpanF / kSpanB levels per launch) where possible
     std::vector<int32_t> span_tile_h;    // [NS+1] tiles of forward span s: [p[s], p[s+1]); a
