@@ -70,6 +70,20 @@ static int32_t span_lane(int32_t pos, int32_t k) {
     return pos + k;
 }
 
+// A tile level may take several 64-lane chunks.  Placement state of a level: chunks
+// opened * 128 + lanes used in the last one.  Adding k (<= 64) lanes opens a chunk when
+// the last one cannot take them whole.
+static int32_t span_place(int32_t st, int32_t k) {
+    int32_t ch = st >> 7, ln = st & 127;
+    if (ch == 0) ch = 1;
+    int32_t p = span_lane(ln, k);
+    if (p > 64) {
+        ++ch;
+        p = k;
+    }
+    return ch * 128 + p;
+}
+
 static sta_status build(const sta_design_desc* d, sta_graph* g) {
     if (!d) return fail(STA_E_ARG, "sta_build_graph: null design");
     if (d->n_pi < 0 || d->n_gates < 0) return fail(STA_E_ARG, "sta_build_graph: negative n_pi or n_gates");
@@ -391,7 +405,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
             const size_t t0 = bp_tile.size(), c0all = bp_chunk.size(), s0all = bp_slot.size();
             bool ok = true;
             std::vector<std::vector<int32_t>> td(nl);     // drivers per level (index top - level)
-            int32_t tslots[kSpanB] = {};
+            int32_t tslots[kSpanB] = {};                  // placement state per level (span_place)
             auto flush = [&]() {
                 bool any = false;
                 for (int j = 0; j < nl; ++j) any = any || !td[j].empty();
@@ -403,9 +417,17 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                 int32_t nch = 0;
                 for (int j = 0; j < nl; ++j) {      // j = 0 is the top level: processed first
                     if (td[j].empty()) continue;
-                    const int32_t ts0 = int32_t(bp_slot.size());
-                    int32_t maxs = 1;
+                    int32_t ts0 = int32_t(bp_slot.size());
+                    int32_t maxs = 1, first = td[j][0];
                     for (int32_t i : td[j]) {
+                        if (span_lane(int32_t(bp_slot.size()) - ts0, nslots(i)) > kTileSlots) {
+                            // the level continues in a new chunk
+                            bp_chunk.insert(bp_chunk.end(), {ts0, int32_t(bp_slot.size()) - ts0, dslot[first], maxs});
+                            ++nch;
+                            ts0 = int32_t(bp_slot.size());
+                            maxs = 1;
+                            first = i;
+                        }
                         maxs = std::max(maxs, nslots(i));
                         // padding lanes (slot -1) keep a driver of <= 16 slots inside one row
                         const int32_t at = span_lane(int32_t(bp_slot.size()) - ts0, nslots(i)) - nslots(i);
@@ -426,7 +448,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                             bp_drv.push_back(i);
                         }
                     }
-                    bp_chunk.insert(bp_chunk.end(), {ts0, int32_t(bp_slot.size()) - ts0, dslot[td[j][0]], maxs});
+                    bp_chunk.insert(bp_chunk.end(), {ts0, int32_t(bp_slot.size()) - ts0, dslot[first], maxs});
                     ++nch;
                 }
                 bp_tile.insert(bp_tile.end(), {c0, nch, 0, ds});
@@ -453,21 +475,25 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                             if (in_span(o) && mark[o] != st) { mark[o] = st; stack.push_back(o); }
                         }
                     }
-                    // lanes per level after adding the cone (in insertion order) to the
-                    // current tile, or alone
+                    // chunks per level after adding the cone (in insertion order) to the
+                    // current tile, or alone; a tile holds at most kSpanB chunks in all
                     std::sort(cone.begin(), cone.end());
                     int32_t add[kSpanB], alone[kSpanB] = {};
+                    bool wide = false;
                     for (int j = 0; j < nl; ++j) add[j] = tslots[j];
                     for (int32_t i : cone) {
                         const int32_t j = top - lv(i);
-                        alone[j] = span_lane(alone[j], nslots(i));
-                        if (tile_mark[i] != tile_id) add[j] = span_lane(add[j], nslots(i));
+                        wide = wide || nslots(i) > kTileSlots;
+                        alone[j] = span_place(alone[j], nslots(i));
+                        if (tile_mark[i] != tile_id) add[j] = span_place(add[j], nslots(i));
                     }
-                    bool fits = true, fits_alone = true;
+                    int32_t ch_add = 0, ch_alone = 0;
                     for (int j = 0; j < nl; ++j) {
-                        fits = fits && add[j] <= kTileSlots;
-                        fits_alone = fits_alone && alone[j] <= kTileSlots;
+                        ch_add += add[j] >> 7;
+                        ch_alone += alone[j] >> 7;
                     }
+                    const bool fits = ch_add <= kSpanB;
+                    const bool fits_alone = !wide && ch_alone <= kSpanB;
                     if (!fits_alone) { ok = false; break; }
                     if (!fits) {
                         flush();
@@ -542,7 +568,8 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
             const int32_t nl = l1 - l0 + 1;
             const size_t t0 = sp_tile.size(), c0all = sp_chunk.size(), a0all = sp_ta_arc.size();
             bool ok = true;
-            // the tile being filled: gates per level in insertion order, lanes used per level
+            // the tile being filled: gates per level in insertion order, placement state
+            // per level (span_place)
             std::vector<std::vector<int32_t>> tg(nl);
             int32_t tarcs[kSpanF] = {};
             auto nk = [&](int32_t q) { return gate_arc_ptr_int[q + 1] - gate_arc_ptr_int[q]; };
@@ -557,9 +584,17 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                 int32_t nch = 0;
                 for (int j = 0; j < nl; ++j) {
                     if (tg[j].empty()) continue;
-                    const int32_t ta0 = int32_t(sp_ta_arc.size());
-                    int32_t maxk = 0;
+                    int32_t ta0 = int32_t(sp_ta_arc.size());
+                    int32_t maxk = 0, first = tg[j][0];
                     for (int32_t q : tg[j]) {
+                        if (span_lane(int32_t(sp_ta_arc.size()) - ta0, nk(q)) > kTileSlots) {
+                            // the level continues in a new chunk
+                            sp_chunk.insert(sp_chunk.end(), {ta0, int32_t(sp_ta_arc.size()) - ta0, slot_of[first], maxk});
+                            ++nch;
+                            ta0 = int32_t(sp_ta_arc.size());
+                            maxk = 0;
+                            first = q;
+                        }
                         maxk = std::max(maxk, nk(q));
                         // padding lanes (gate -1) keep a gate of <= 16 arcs inside one 16-lane row
                         const int32_t at = span_lane(int32_t(sp_ta_arc.size()) - ta0, nk(q)) - nk(q);
@@ -575,7 +610,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                             sp_ta_gate.push_back(q);
                         }
                     }
-                    sp_chunk.insert(sp_chunk.end(), {ta0, int32_t(sp_ta_arc.size()) - ta0, slot_of[tg[j][0]], maxk});
+                    sp_chunk.insert(sp_chunk.end(), {ta0, int32_t(sp_ta_arc.size()) - ta0, slot_of[first], maxk});
                     ++nch;
                 }
                 sp_tile.insert(sp_tile.end(), {c0, nch, 0, slot});
@@ -603,16 +638,20 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     // level); lanes per level after adding the cone to the current tile, or alone
                     std::sort(cone.begin(), cone.end());
                     int32_t add[kSpanF], alone[kSpanF] = {};
+                    bool wide = false;
                     for (int j = 0; j < nl; ++j) add[j] = tarcs[j];
                     for (int32_t q : cone) {
                         const int32_t j = gate_lv[q] - l0;
-                        alone[j] = span_lane(alone[j], nk(q));
-                        if (tile_mark[q] != tile_id) add[j] = span_lane(add[j], nk(q));
+                        wide = wide || nk(q) > kTileSlots;
+                        alone[j] = span_place(alone[j], nk(q));
+                        if (tile_mark[q] != tile_id) add[j] = span_place(add[j], nk(q));
                     }
-                    bool fits = true, fits_alone = true;
+                    // forward levels keep one chunk each: a level's chunks run one after
+                    // another in the wavefront, and a forward level is the expensive one
+                    bool fits = true, fits_alone = !wide;
                     for (int j = 0; j < nl; ++j) {
-                        fits = fits && add[j] <= kTileSlots;
-                        fits_alone = fits_alone && alone[j] <= kTileSlots;
+                        fits = fits && (add[j] >> 7) <= 1;
+                        fits_alone = fits_alone && (alone[j] >> 7) <= 1;
                     }
                     if (!fits_alone) { ok = false; break; }
                     if (!fits) {
