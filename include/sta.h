@@ -227,8 +227,9 @@ sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32
  * launch (the same spans serve the TNS adjoint).  Each workgroup (one wavefront) computes
  * one span tile: in the forward pass a set of gates closed under fanin inside the span
  * (<= 64 cell arcs per level), in the backward pass a set of drivers closed under their
- * sinks' gate outputs inside the span (<= 64 sink slots per level), level by level, with
- * the in-span arrival (required) times kept in LDS.  A gate or driver needed by several
+ * sinks' gate outputs inside the span (each level in one or more chunks of <= 64 sink
+ * slots, at most eight chunks per tile), level by level, with the in-span arrival
+ * (required) times kept in LDS.  A gate or driver needed by several
  * tiles is computed in each of them, identically, so results do not change.  A level that
  * cannot be tiled even alone runs as a level launch.  The view schedule is unaffected. */
 sta_status sta_set_level_fusion(sta_graph* g, int32_t enable);
