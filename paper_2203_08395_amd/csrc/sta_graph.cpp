@@ -464,10 +464,13 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     stack.assign(1, int32_t(r));
                     const int32_t st = stamp++;
                     mark[r] = st;
-                    while (!stack.empty()) {
+                    // (a cone of more slots than a whole tile holds cannot be tiled: stop there)
+                    int64_t cone_slots = 0;
+                    while (!stack.empty() && cone_slots <= int64_t(kSpanB) * kTileSlots) {
                         const int32_t i = stack.back();
                         stack.pop_back();
                         cone.push_back(i);
+                        cone_slots += nslots(i);
                         for (int32_t sl = slot_ptr[i]; sl < slot_ptr[i + 1]; ++sl) {
                             const int32_t sa = bslot_arc[sl];
                             if (sa < 0) continue;
@@ -475,6 +478,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                             if (in_span(o) && mark[o] != st) { mark[o] = st; stack.push_back(o); }
                         }
                     }
+                    if (cone_slots > int64_t(kSpanB) * kTileSlots) { ok = false; break; }
                     // chunks per level after adding the cone (in insertion order) to the
                     // current tile, or alone; a tile holds at most kSpanB chunks in all
                     std::sort(cone.begin(), cone.end());
@@ -625,15 +629,19 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
                     stack.assign(1, r);
                     const int32_t st = stamp++;
                     mark[r] = st;
-                    while (!stack.empty()) {
+                    // (a cone of more arcs than a whole tile holds cannot be tiled: stop there)
+                    int64_t cone_arcs = 0;
+                    while (!stack.empty() && cone_arcs <= int64_t(kSpanF) * kTileSlots) {
                         const int32_t q = stack.back();
                         stack.pop_back();
                         cone.push_back(q);
+                        cone_arcs += nk(q);
                         for (int32_t a = gate_arc_ptr_int[q]; a < gate_arc_ptr_int[q + 1]; ++a) {
                             const int32_t u = arc_src[a];
                             if (in_span(u) && mark[u - P] != st) { mark[u - P] = st; stack.push_back(u - P); }
                         }
                     }
+                    if (cone_arcs > int64_t(kSpanF) * kTileSlots) { ok = false; break; }
                     // inserted in ascending gate order per level (drivers precede users: lower
                     // level); lanes per level after adding the cone to the current tile, or alone
                     std::sort(cone.begin(), cone.end());
