@@ -38,6 +38,8 @@ constexpr int kSpanWaves = 1;
 // for one wavefront per SIMD, so that long spans do not spill.)
 // Level-kernel tiles per workgroup (the same reasoning: a level has a few hundred tiles).
 constexpr int kLevelWaves = 1;
+// Views a forward span wavefront computes (the others run as separate workgroups).
+constexpr int kSpanViewsPerWave = 1;
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
 struct DevLayout {

@@ -651,14 +651,14 @@ __device__ __forceinline__ void span_sum_step(float* acc, bool take) {
 template <int NW>
 __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* ts, int j, float ty, int span,
                                                 const Axis6& ax_x, const float* const* tab, const bool* early,
-                                                int n_pi, float* __restrict__ drv_ts, float* __restrict__ arc_ts,
-                                                float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
-                                                float2* lds_res, int slot) {
+                                                int NV, int v0, int n_pi, float* __restrict__ drv_ts,
+                                                float* __restrict__ arc_ts, float* __restrict__ arc_delay,
+                                                uint8_t* __restrict__ argmax, float2* lds_res, int slot) {
     const int lane = threadIdx.x & 63;
     float cand[NW], slw[NW];
     int best_k[NW];
     if (x.active) {
-        float2* dst = reinterpret_cast<float2*>(arc_ts) + size_t(x.a) * NW;
+        float2* dst = reinterpret_cast<float2*>(arc_ts) + size_t(x.a) * NV + v0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const float ai = ts[w].x + x.nd;
@@ -671,7 +671,7 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
             const float dl = bilerp(T, i, j, tx, ty);
             const float sl = bilerp(T + 49, i, j, tx, ty);
             dst[w] = make_float2(ai, si);
-            arc_delay[size_t(x.a) * NW + w] = dl;
+            arc_delay[size_t(x.a) * NV + v0 + w] = dl;
             // early views negated, so that every view takes a maximum (negation is exact)
             cand[w] = early[w] ? -(ai + dl) : ai + dl;
             slw[w] = early[w] ? -sl : sl;
@@ -715,13 +715,13 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
         }
     }
     if (x.head) {
-        float2* out = reinterpret_cast<float2*>(drv_ts) + size_t(n_pi + x.g) * NW;
+        float2* out = reinterpret_cast<float2*>(drv_ts) + size_t(n_pi + x.g) * NV + v0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             cand[w] = early[w] ? -cand[w] : cand[w];
             slw[w] = early[w] ? -slw[w] : slw[w];
             out[w] = make_float2(cand[w], slw[w]);
-            argmax[size_t(x.g) * NW + w] = uint8_t(best_k[w]);
+            argmax[size_t(x.g) * NV + v0 + w] = uint8_t(best_k[w]);
             lds_res[slot * NW + w] = make_float2(cand[w], slw[w]);
         }
     }
@@ -732,13 +732,16 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
 // levels in order, each reading its in-span inputs from LDS: one table round per level
 // instead of one launch and three rounds per level.
 // (Staging the tables in LDS per block was measured slower than the L2-resident reads.)
-template <int NV>
+// NV views stored, NW of them computed per wavefront: views v0 .. v0 + NW - 1 with
+// v0 = blockIdx.y * NW (so the views of a tile can run on different compute units).
+template <int NV, int NW>
 __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
                                                       const float* __restrict__ arc_load,
                                                       const float* __restrict__ nd, const float* __restrict__ ni,
                                                       float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                                       float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
-    __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NV];
+    __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NW];
+    const int v0 = int(blockIdx.y) * NW;
     // the table axes in wave-uniform registers
     const Axis6 ax_x = axis6(lib, 0, 14), ax_y = axis6(lib, 7, 20);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -746,12 +749,12 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     const int tc = t < tile1 ? t : tile1 - 1;
     const int lane = threadIdx.x & 63;
     float2* res = s_res[wave];
-    const float* tab[NV];
-    bool early[NV];
+    const float* tab[NW];
+    bool early[NW];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        tab[v] = lib.tables + size_t(V.set[v]) * lib.n_tables * 98;
-        early[v] = V.mode[v] == STA_EARLY;
+    for (int w = 0; w < NW; ++w) {
+        tab[w] = lib.tables + size_t(V.set[v0 + w]) * lib.n_tables * 98;
+        early[w] = V.mode[v0 + w] == STA_EARLY;
     }
     // round 1: the tile's level and arc records, all indexed by (tile, level, lane)
     int na[kSpanF], sl0[kSpanF], mk[kSpanF];
@@ -774,7 +777,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     if (t >= tile1) return;
     // round 2: the arcs' net data and the arrivals of drivers outside the span
     float ndv[kSpanF], niv[kSpanF], lov[kSpanF];
-    float2 ext[kSpanF][NV];
+    float2 ext[kSpanF][NW];
 #pragma unroll
     for (int c = 0; c < kSpanF; ++c) {
         const int a = ar[c];
@@ -782,9 +785,9 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         niv[c] = ni[a];
         lov[c] = arc_load[a];
         const int u = sc[c] >= 0 ? sc[c] : 0;
-        const float2* sp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV;
+        const float2* sp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV + v0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) ext[c][v] = sp[v];
+        for (int w = 0; w < NW; ++w) ext[c][w] = sp[w];
     }
     // all of round 2 is in flight; keep it there (one wait before the first level)
 #pragma unroll
@@ -793,9 +796,9 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         pin_value(niv[c]);
         pin_value(lov[c]);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            pin_value(ext[c][v].x);
-            pin_value(ext[c][v].y);
+        for (int w = 0; w < NW; ++w) {
+            pin_value(ext[c][w].x);
+            pin_value(ext[c][w].y);
         }
     }
     // the levels of the tile, in order
@@ -817,17 +820,17 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
             j = seg6_sel(ax_y, x.Lo, y0, dy);
             ty = (x.Lo - y0) / dy;
         }
-        float2 ts[NV];
+        float2 ts[NW];
         if (act && sc[c] < 0) {
             const int src = -1 - sc[c];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) ts[v] = res[src * NV + v];
+            for (int w = 0; w < NW; ++w) ts[w] = res[src * NW + w];
         } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) ts[v] = act ? ext[c][v] : make_float2(0.0f, 0.0f);
+            for (int w = 0; w < NW; ++w) ts[w] = act ? ext[c][w] : make_float2(0.0f, 0.0f);
         }
-        fwd_finish_span<NV>(x, ts, j, ty, mk[c], ax_x, tab, early, G.n_pi, drv_ts, arc_ts, arc_delay, argmax, res,
-                            sl0[c] + x.gi);
+        fwd_finish_span<NW>(x, ts, j, ty, mk[c], ax_x, tab, early, NV, v0, G.n_pi, drv_ts, arc_ts, arc_delay,
+                            argmax, res, sl0[c] + x.gi);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1856,7 +1859,9 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                 const int t0 = g->span_tile_h[sp], t1 = g->span_tile_h[sp + 1];
                 if (t1 <= t0) continue;
                 prof_launch("k_forward_span", s, [&] {
-                    hipLaunchKernelGGL((k_forward_span<NV>), dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves),
+                    hipLaunchKernelGGL((k_forward_span<NV, kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV>),
+                                       dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves,
+                                            NV / (kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV)),
                                        dim3(64 * kSpanWaves), 0, s, dg, lib, kv,
                                        t0, t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts,
                                        o->arc_delay, o->argmax);
