@@ -38,8 +38,11 @@ constexpr int kSpanWaves = 1;
 // for one wavefront per SIMD, so that long spans do not spill.)
 // Level-kernel tiles per workgroup (the same reasoning: a level has a few hundred tiles).
 constexpr int kLevelWaves = 1;
-// Views a forward span wavefront computes (the others run as separate workgroups).
+// Views a span wavefront computes (the others run as separate workgroups of the same
+// launch): one for the forward and adjoint spans, whose levels are long chains; both for
+// the backward span, whose levels are short and whose slot records serve both views.
 constexpr int kSpanViewsPerWave = 1;
+constexpr int kBwdViewsPerWave = 2;
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
 struct DevLayout {

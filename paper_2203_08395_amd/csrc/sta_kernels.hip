@@ -876,7 +876,8 @@ __global__ __launch_bounds__(64 * kLevelWaves) void k_backward(DevGraph G, KView
 // tile (its slot records; then the slots' arc data, the drivers' arrivals, and the required
 // times of sink gates outside the span or the endpoint required times), then the levels
 // top down, in-span required times handed over through LDS.
-template <int NV>
+// NV views stored, NW computed per wavefront (views v0 = blockIdx.y * NW onwards).
+template <int NV, int NW>
 __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
                                                        const float* __restrict__ nd, const float* __restrict__ drv_ts,
                                                        const float* __restrict__ arc_ts,
@@ -884,15 +885,16 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
                                                        const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
                                                        float* __restrict__ arc_rat, float* __restrict__ drv_slack,
                                                        float* __restrict__ arc_slack) {
-    __shared__ float s_rat[kSpanWaves][kSpanSlotsB * NV];
+    __shared__ float s_rat[kSpanWaves][kSpanSlotsB * NW];
+    const int v0 = int(blockIdx.y) * NW;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = tile0 + blockIdx.x * kSpanWaves + wave;
     if (t >= tile1) return;
     const int lane = threadIdx.x & 63;
     float* rs = s_rat[wave];
-    bool early[NV];
+    bool early[NW];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
+    for (int v = 0; v < NW; ++v) early[v] = V.mode[v0 + v] == STA_EARLY;
     // round 1: the tile's level and slot records, all indexed by (tile, level, lane)
     int ns[kSpanB], ds0[kSpanB], ms[kSpanB];
     int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB];
@@ -916,17 +918,17 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     // round 2: the slot data the required times need (net delay, arc delay, required
     // times from outside the tile), waited for before the first level; then the arrivals
     // that only the slacks need, issued behind them and used after the last level
-    float ndv[kSpanB], dl[kSpanB][NV], ati[kSpanB][NV], ext[kSpanB][NV], atd[kSpanB][NV];
+    float ndv[kSpanB], dl[kSpanB][NW], ati[kSpanB][NW], ext[kSpanB][NW], atd[kSpanB][NW];
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
         const int sa = sa_[c];
         const int sac = sa >= 0 ? sa : 0;
         ndv[c] = nd[sac];
-        const float* ext_src = (sa >= 0) ? (drv_rat + size_t(so_[c]) * NV) : (ep_rat + size_t(so_[c]) * NV);
+        const float* ext_src = (sa >= 0) ? (drv_rat + size_t(so_[c]) * NV + v0) : (ep_rat + size_t(so_[c]) * NV + v0);
         const float* ext_ld = src[c] >= 0 ? ep_rat : ext_src;   // in-tile sources: any valid address
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            dl[c][v] = arc_delay[size_t(sac) * NV + v];
+        for (int v = 0; v < NW; ++v) {
+            dl[c][v] = arc_delay[size_t(sac) * NV + v0 + v];
             ext[c][v] = ext_ld[v];
         }
     }
@@ -937,9 +939,9 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         const float* ts = arc_ts + size_t(sac) * NV * 2;
         const float* dt = drv_ts + size_t(drv[c]) * NV * 2;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            ati[c][v] = ts[2 * v];
-            atd[c][v] = dt[2 * v];
+        for (int v = 0; v < NW; ++v) {
+            ati[c][v] = ts[2 * (v0 + v)];
+            atd[c][v] = dt[2 * (v0 + v)];
         }
     }
     asm volatile("" ::: "memory");             // and these stay here, in flight
@@ -947,12 +949,12 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     for (int c = 0; c < kSpanB; ++c) {
         pin_value(ndv[c]);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
+        for (int v = 0; v < NW; ++v) {
             pin_value(dl[c][v]);
             pin_value(ext[c][v]);
         }
     }
-    float rin_[kSpanB][NV], rdrv[kSpanB][NV];
+    float rin_[kSpanB][NW], rdrv[kSpanB][NW];
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
         if (c >= nch) break;                    // uniform
@@ -967,53 +969,53 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         const bool on_arc = act && sa_[c] >= 0;
         // the required times at the sinks' gate outputs: from LDS (in-tile) or prefetched
         const int si = src[c] >= 0 ? src[c] : 0;
-        float ro[NV];
+        float ro[NW];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) ro[v] = rs[si * NV + v];
+        for (int v = 0; v < NW; ++v) ro[v] = rs[si * NW + v];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) ro[v] = src[c] >= 0 ? ro[v] : ext[c][v];
+        for (int v = 0; v < NW; ++v) ro[v] = src[c] >= 0 ? ro[v] : ext[c][v];
         // per slot: the value its driver minimizes (maximizes early), negated for early
         // views so that every view takes a minimum (negation is exact: same results)
-        float best[NV];
+        float best[NW];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
+        for (int v = 0; v < NW; ++v) {
             const float rin = ro[v] - dl[c][v];
             rin_[c][v] = rin;
-            if (on_arc) arc_rat[size_t(sa_[c]) * NV + v] = rin;
+            if (on_arc) arc_rat[size_t(sa_[c]) * NV + v0 + v] = rin;
             const float val = on_arc ? rin - ndv[c] : ext[c][v];
             best[v] = act ? (early[v] ? -val : val) : __builtin_inff();   // idle lanes never win
         }
         // segmented minimum over a driver's slots: ceil(log2(most slots)) steps; drivers of
         // <= 16 slots lie inside 16-lane rows (DPP row shifts), wider ones use permutes
         if (ms[c] <= 16) {
-            if (ms[c] > 1) span_min_step<1, NV>(best, (lane + 1) < seg_end);
-            if (ms[c] > 2) span_min_step<2, NV>(best, (lane + 2) < seg_end);
-            if (ms[c] > 4) span_min_step<4, NV>(best, (lane + 4) < seg_end);
-            if (ms[c] > 8) span_min_step<8, NV>(best, (lane + 8) < seg_end);
+            if (ms[c] > 1) span_min_step<1, NW>(best, (lane + 1) < seg_end);
+            if (ms[c] > 2) span_min_step<2, NW>(best, (lane + 2) < seg_end);
+            if (ms[c] > 4) span_min_step<4, NW>(best, (lane + 4) < seg_end);
+            if (ms[c] > 8) span_min_step<8, NW>(best, (lane + 8) < seg_end);
         } else {
 #pragma unroll
             for (int st = 0; st < 6; ++st) {
                 const int off = 1 << st;
                 if (off >= ms[c]) break;        // uniform
                 const bool take = (lane + off) < seg_end;
-                float b2[NV];
+                float b2[NW];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) b2[v] = __shfl_down(best[v], off, 64);
+                for (int v = 0; v < NW; ++v) b2[v] = __shfl_down(best[v], off, 64);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) best[v] = (take && b2[v] < best[v]) ? b2[v] : best[v];
+                for (int v = 0; v < NW; ++v) best[v] = (take && b2[v] < best[v]) ? b2[v] : best[v];
             }
         }
         if (head) {
             const int u = drv[c];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
+            for (int v = 0; v < NW; ++v) {
                 const float r = early[v] ? -best[v] : best[v];
-                drv_rat[size_t(u) * NV + v] = r;
-                rs[(ds0[c] + gi) * NV + v] = r;
+                drv_rat[size_t(u) * NV + v0 + v] = r;
+                rs[(ds0[c] + gi) * NW + v] = r;
             }
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) rdrv[c][v] = early[v] ? -best[v] : best[v];
+        for (int v = 0; v < NW; ++v) rdrv[c][v] = early[v] ? -best[v] : best[v];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1025,14 +1027,14 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         const bool act = lane < ns[c] && src[c] != -2;
         if (act && sa_[c] >= 0) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                arc_slack[size_t(sa_[c]) * NV + v] = early[v] ? (ati[c][v] - rin_[c][v]) : (rin_[c][v] - ati[c][v]);
+            for (int v = 0; v < NW; ++v)
+                arc_slack[size_t(sa_[c]) * NV + v0 + v] = early[v] ? (ati[c][v] - rin_[c][v]) : (rin_[c][v] - ati[c][v]);
         }
         if (act && hd[c]) {
             const int u = drv[c];
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                drv_slack[size_t(u) * NV + v] = early[v] ? (atd[c][v] - rdrv[c][v]) : (rdrv[c][v] - atd[c][v]);
+            for (int v = 0; v < NW; ++v)
+                drv_slack[size_t(u) * NV + v0 + v] = early[v] ? (atd[c][v] - rdrv[c][v]) : (rdrv[c][v] - atd[c][v]);
         }
     }
 }
@@ -1925,7 +1927,9 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
                 const int t0 = g->bspan_tile_h[b], t1 = g->bspan_tile_h[b + 1];
                 if (t1 <= t0) continue;
                 prof_launch("k_backward_span", s, [&] {
-                    hipLaunchKernelGGL((k_backward_span<NV>), dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves),
+                    hipLaunchKernelGGL((k_backward_span<NV, kBwdViewsPerWave < NV ? kBwdViewsPerWave : NV>),
+                                       dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves,
+                                            NV / (kBwdViewsPerWave < NV ? kBwdViewsPerWave : NV)),
                                        dim3(64 * kSpanWaves), 0, s, dg, kv, t0,
                                        t1, nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat,
                                        o->arc_rat, o->drv_slack, o->arc_slack);
@@ -2073,21 +2077,22 @@ __global__ __launch_bounds__(64 * kLevelWaves) void k_adjoint(DevGraph G, KViews
 // arc's position, the sink gate's argmax), the gradient of a sink gate outside the tile,
 // or an endpoint's slack.  Integer counts, so the segmented sums are exact in any order
 // and the results equal the level kernel's.
-template <int NV>
+template <int NV, int NW>
 __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_adjoint_span(DevGraph G, KViews V, int tile0, int tile1,
                                                                   const uint8_t* __restrict__ argmax,
                                                                   const float* __restrict__ drv_slack,
                                                                   float* __restrict__ g_at, float* __restrict__ g_arc,
                                                                   float* __restrict__ g_nd) {
-    __shared__ float s_g[kSpanWaves][kSpanSlotsB * NV];
+    __shared__ float s_g[kSpanWaves][kSpanSlotsB * NW];
+    const int v0 = int(blockIdx.y) * NW;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = tile0 + blockIdx.x * kSpanWaves + wave;
     if (t >= tile1) return;
     const int lane = threadIdx.x & 63;
     float* gs = s_g[wave];
-    bool early[NV];
+    bool early[NW];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
+    for (int v = 0; v < NW; ++v) early[v] = V.mode[v0 + v] == STA_EARLY;
     // round 1: the tile's level and slot records
     int ns[kSpanB], ds0[kSpanB], ms[kSpanB];
     int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB];
@@ -2109,19 +2114,19 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         drv[c] = r.w;
     }
     // round 2
-    int kp[kSpanB], am[kSpanB][NV];
-    float ext[kSpanB][NV];
+    int kp[kSpanB], am[kSpanB][NW];
+    float ext[kSpanB][NW];
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
         const int sa = sa_[c];
         const int sac = sa >= 0 ? sa : 0;
         kp[c] = int(G.arc_meta[sac] >> 16);
         const int gq = sa >= 0 ? so_[c] - G.n_pi : 0;
-        const float* ep = sa >= 0 ? (src[c] >= 0 ? drv_slack : g_at + size_t(so_[c]) * NV)
-                                  : drv_slack + size_t(drv[c]) * NV;
+        const float* ep = sa >= 0 ? (src[c] >= 0 ? drv_slack : g_at + size_t(so_[c]) * NV + v0)
+                                  : drv_slack + size_t(drv[c]) * NV + v0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            am[c][v] = int(argmax[size_t(gq) * NV + v]);
+        for (int v = 0; v < NW; ++v) {
+            am[c][v] = int(argmax[size_t(gq) * NV + v0 + v]);
             ext[c][v] = ep[v];
         }
     }
@@ -2129,7 +2134,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     for (int c = 0; c < kSpanB; ++c) {
         pin_value(kp[c]);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
+        for (int v = 0; v < NW; ++v) {
             pin_value(am[c][v]);
             pin_value(ext[c][v]);
         }
@@ -2147,45 +2152,45 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : n;
         const bool on_arc = act && sa_[c] >= 0;
         const int si = src[c] >= 0 ? src[c] : 0;
-        float gin[NV];
+        float gin[NW];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) gin[v] = gs[si * NV + v];
-        float acc[NV];
+        for (int v = 0; v < NW; ++v) gin[v] = gs[si * NW + v];
+        float acc[NW];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
+        for (int v = 0; v < NW; ++v) {
             const float go = src[c] >= 0 ? gin[v] : ext[c][v];
             const float cv = (am[c][v] == kp[c]) ? go : 0.0f;
             if (on_arc) {
-                if (g_arc) g_arc[size_t(sa_[c]) * NV + v] = cv;
-                if (g_nd) g_nd[size_t(sa_[c]) * NV + v] = cv;
+                if (g_arc) g_arc[size_t(sa_[c]) * NV + v0 + v] = cv;
+                if (g_nd) g_nd[size_t(sa_[c]) * NV + v0 + v] = cv;
             }
             const float ep = ext[c][v] < 0.0f ? (early[v] ? 1.0f : -1.0f) : 0.0f;
             acc[v] = on_arc ? cv : (act ? ep : 0.0f);
         }
         if (ms[c] <= 16) {
-            if (ms[c] > 1) span_sum_step<1, NV>(acc, (lane + 1) < seg_end);
-            if (ms[c] > 2) span_sum_step<2, NV>(acc, (lane + 2) < seg_end);
-            if (ms[c] > 4) span_sum_step<4, NV>(acc, (lane + 4) < seg_end);
-            if (ms[c] > 8) span_sum_step<8, NV>(acc, (lane + 8) < seg_end);
+            if (ms[c] > 1) span_sum_step<1, NW>(acc, (lane + 1) < seg_end);
+            if (ms[c] > 2) span_sum_step<2, NW>(acc, (lane + 2) < seg_end);
+            if (ms[c] > 4) span_sum_step<4, NW>(acc, (lane + 4) < seg_end);
+            if (ms[c] > 8) span_sum_step<8, NW>(acc, (lane + 8) < seg_end);
         } else {
 #pragma unroll
             for (int st = 0; st < 6; ++st) {
                 const int off = 1 << st;
                 if (off >= ms[c]) break;        // uniform
                 const bool take = (lane + off) < seg_end;
-                float b2[NV];
+                float b2[NW];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) b2[v] = __shfl_down(acc[v], off, 64);
+                for (int v = 0; v < NW; ++v) b2[v] = __shfl_down(acc[v], off, 64);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) acc[v] = take ? acc[v] + b2[v] : acc[v];
+                for (int v = 0; v < NW; ++v) acc[v] = take ? acc[v] + b2[v] : acc[v];
             }
         }
         if (head) {
             const int u = drv[c];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                g_at[size_t(u) * NV + v] = acc[v];
-                gs[(ds0[c] + gi) * NV + v] = acc[v];
+            for (int v = 0; v < NW; ++v) {
+                g_at[size_t(u) * NV + v0 + v] = acc[v];
+                gs[(ds0[c] + gi) * NW + v] = acc[v];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -2370,7 +2375,9 @@ static void enqueue_adjoint_levels(const sta_graph* g, const KLib& kl, const KVi
                 const int t0 = g->bspan_tile_h[b], t1 = g->bspan_tile_h[b + 1];
                 if (t1 <= t0) continue;
                 prof_launch("k_adjoint_span", s, [&] {
-                    hipLaunchKernelGGL((k_adjoint_span<NV>), dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves),
+                    hipLaunchKernelGGL((k_adjoint_span<NV, kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV>),
+                                       dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves,
+                                            NV / (kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV)),
                                        dim3(64 * kSpanWaves), 0, s, dg, kv, t0, t1, t->argmax, sl->drv_slack,
                                        o->g_drv_at, o->g_arc_delay, o->g_net_delay);
                 });
