@@ -23,9 +23,11 @@ constexpr int kFwdCapA = 2816, kFwdCapG = 1152, kFwdCapT = 96;
 // view-schedule backward chunks: whole tiles of one driver level
 constexpr int kBwdCapS = 4096, kBwdCapD = 2048, kBwdCapT = 128;
 constexpr size_t kViewTableLdsMax = 65536;            // LDS bytes for tables + axes
-// fused spans: kSpanF consecutive gate levels per forward launch, kSpanB driver levels
-// per backward launch (the lengths measured best on the 1M-pin design); a span tile holds
-// at most 64 cell arcs, or 64 sink slots, (one wavefront) per level of the span
+// fused spans: up to kSpanF consecutive gate levels per forward launch and kSpanB driver
+// levels per backward launch (the lengths measured best on the 1M-pin design).  A span
+// tile is processed in chunks of at most 64 lanes (cell arcs or sink slots): one chunk per
+// level in the forward pass, one or more per level in the backward pass, at most kSpanF /
+// kSpanB chunks per tile (the chunk records are held in registers).
 constexpr int kSpanF = 8;
 constexpr int kSpanB = 8;
 constexpr int kSpanSlotsF = kSpanF * 64;
