@@ -186,3 +186,38 @@ def test_graph_replays_match_plain_launches():
             if k == "scratch":
                 continue
             assert_bitwise(f"replay {rep} {k}", v.cpu().numpy().reshape(-1), ref[k].reshape(-1))
+
+
+def test_default_schedule_choice():
+    # left to the library: fused spans for one or two views at any size, the view schedule
+    # for more views on a narrow design; an explicit threshold selects the view schedule
+    import torch
+    d, lib, pa, ps, late, early = workload("c1")
+    say("[gpu case] default schedule choice c1")
+    for modes, want in (([LATE], "k_forward_span"), ([LATE, EARLY], "k_forward_span"),
+                        ([LATE, EARLY, LATE, EARLY], "k_forward_view")):
+        g = sta.Graph(d, n_tables=lib.n_tables).upload("cuda")
+        L = sta.make_library(lib.x, lib.y, torch.from_numpy(lib.tab).cuda())
+        views = sta.make_views(modes)
+        nd = sta.delay_calc(g)
+        pi = np.zeros((d.n_pi, len(modes), 2), np.float32)
+        pi[:, :, 0] = pa[:, None]
+        pi[:, :, 1] = ps[:, None]
+        pit = torch.from_numpy(pi).cuda()
+        sta.profile_begin()
+        sta.propagate(g, L, views, pit, nd)
+        ran = sta.profile_end()
+        torch.cuda.synchronize()
+        assert want in ran, (modes, ran)
+        g.set_schedule(1 << 30, True)
+        sta.profile_begin()
+        sta.propagate(g, L, views, pit, nd)
+        ran = sta.profile_end()
+        torch.cuda.synchronize()
+        assert "k_forward_view" in ran, (modes, ran)
+        g.set_schedule(-1, True)
+        sta.profile_begin()
+        sta.propagate(g, L, views, pit, nd)
+        ran = sta.profile_end()
+        torch.cuda.synchronize()
+        assert want in ran, (modes, ran)
