@@ -214,15 +214,15 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
  * design's mean cell arcs per level is at most view_max_arcs_per_level (and the level
  * data fits in LDS), the level schedule (launches per level or per fused span, all views
  * per launch) otherwise.  0 forces the level schedule.  A negative value restores the
- * library's choice (the default): the level schedule with fused spans for one or two
- * views, and for more views the view schedule up to 512 mean cell arcs per level.
+ * library's choice (the default): the level schedule with fused spans (the view schedule
+ * only when fusion is off, up to 512 mean cell arcs per level).
  * use_graphs != 0 (the default) lets the level schedule capture its launch sequence in a
  * hipGraph on first use and replay it while the call's arguments stay the same (the
  * capture is per graph and per call kind; a change of any pointer or view re-captures).
  * Every choice gives identical results. */
 sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32_t use_graphs);
 
-/* Level fusion of the level schedule (default on, one or two views): up to eight
+/* Level fusion of the level schedule (default on): up to eight
  * consecutive gate levels per forward launch and up to eight driver levels per backward
  * launch (the same spans serve the TNS adjoint).  Each workgroup (one wavefront) computes
  * one span tile: in the forward pass a set of gates closed under fanin inside the span
@@ -236,7 +236,7 @@ sta_status sta_set_level_fusion(sta_graph* g, int32_t enable);
 
 /* The fusion plan of a built graph (host only; independent of sta_set_level_fusion,
  * which decides whether it is used).  Launch counts are those of one forward or one
- * backward pass of one or two views with fusion on; the fused kernels' algorithmic work is
+ * backward pass with fusion on (any view count); the fused kernels' algorithmic work is
  * the gates, cell arcs, drivers and sink arcs of their spans counted once, and
  * *_computed counts evaluations as performed (a cone shared by several tiles is
  * evaluated in each). */

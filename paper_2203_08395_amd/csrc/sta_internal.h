@@ -45,6 +45,9 @@ constexpr int kLevelWaves = 1;
 // the backward span, whose levels are short and whose slot records serve both views.
 constexpr int kSpanViewsPerWave = 1;
 constexpr int kBwdViewsPerWave = 2;
+// Largest view count the fused spans serve: all (1, 2, 4, 8; measured faster than the level
+// and view schedules for every count).
+constexpr int kSpanMaxViews = 8;
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
 struct DevLayout {

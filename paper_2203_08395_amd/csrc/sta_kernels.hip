@@ -1744,10 +1744,10 @@ static size_t lds_limit() {
 
 // The view schedule runs while one compute unit finishes an average level faster than
 // a device-wide step does (a few thousand cell arcs per level) and the level's staged
-// data and the view's tables fit in LDS.  Left to the library (the default), one or two
-// views take the fused spans instead: measured faster at every size (10k pins: 0.15 vs
-// 0.30 ms per step).
-static bool view_auto_off(const sta_graph* g, int n_views) { return g->view_auto && n_views <= 2 && g->use_spans; }
+// data and the view's tables fit in LDS.  Left to the library (the default), the fused
+// spans are taken instead: measured faster at every size and view count (10k pins, two
+// views: 0.15 vs 0.30 ms per step; four views: propagate 0.07 vs 0.13 ms).
+static bool view_auto_off(const sta_graph* g, int n_views) { return g->view_auto && n_views <= kSpanMaxViews && g->use_spans; }
 
 static bool use_view_forward(const sta_graph* g, int n_tables, int n_views, size_t* lds) {
     if (view_auto_off(g, n_views)) return false;
@@ -1849,7 +1849,7 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                                o->argmax);
         });
     };
-    if constexpr (NV <= 2) {
+    if constexpr (NV <= kSpanMaxViews) {
         if (g->use_spans) {
             const int64_t NS = int64_t(g->span_fused_h.size());
             for (int64_t sp = 0; sp < NS; ++sp) {
@@ -1915,7 +1915,7 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
         });
     };
     bool done = false;
-    if constexpr (NV <= 2) {
+    if constexpr (NV <= kSpanMaxViews) {
         if (g->use_spans) {
             const int64_t NSB = int64_t(g->bspan_fused_h.size());
             for (int64_t b = 0; b < NSB; ++b) {
@@ -2363,7 +2363,7 @@ static void enqueue_adjoint_levels(const sta_graph* g, const KLib& kl, const KVi
         });
     };
     bool done = false;
-    if constexpr (NV <= 2) {
+    if constexpr (NV <= kSpanMaxViews) {
         if (g->use_spans) {
             const int64_t NSB = int64_t(g->bspan_fused_h.size());
             for (int64_t b = 0; b < NSB; ++b) {

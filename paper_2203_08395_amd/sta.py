@@ -193,7 +193,7 @@ class Graph:
 
     def set_level_fusion(self, enable):
         """Fused spans: up to eight gate levels per forward launch and eight driver levels
-        per backward launch (default on)."""
+        per backward launch, any view count (default on)."""
         _check(load_library().sta_set_level_fusion(self._h, int(bool(enable))), "sta_set_level_fusion")
         return self
 

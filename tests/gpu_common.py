@@ -74,7 +74,7 @@ def gpu_run(d, lib, pi_at, pi_slew, ep_rats, modes, table_sets=None, precision=s
         assert "k_forward_view" in ran or "k_backward_view" in ran, ran
     if schedule in ("level", "level_plain") and g.sizes["n_levels"] > 0:
         assert "k_forward" in ran and "k_backward" in ran and "k_forward_span" not in ran, ran
-    if schedule == "span" and g.sizes["n_levels"] > 0 and V <= 2:
+    if schedule == "span" and g.sizes["n_levels"] > 0:
         assert "k_forward_span" in ran or "k_forward" in ran, ran
     host = {k: v.cpu().numpy() for k, v in list(nd.items()) + list(t.items()) + list(s.items()) if k != "scratch"}
     return g, host

@@ -74,7 +74,7 @@ def test_adjoint_matches_oracle(case, fusion):
     sta.profile_begin()
     sta.tns_adjoint(g, r["L"], r["views"], r["nd"], r["t"], r["s"])
     kinds = sta.profile_end()
-    assert ("k_adjoint_span" in kinds) == (fusion and len(modes) <= 2), kinds
+    assert ("k_adjoint_span" in kinds) == fusion, kinds
     h = {k: v.cpu().numpy() for k, v in adj.items()}
     res = _oracle(d, lib, pa, ps, late, early)
     D, A = d.n_drivers, d.n_arcs

@@ -189,13 +189,13 @@ def test_graph_replays_match_plain_launches():
 
 
 def test_default_schedule_choice():
-    # left to the library: fused spans for one or two views at any size, the view schedule
-    # for more views on a narrow design; an explicit threshold selects the view schedule
+    # left to the library: fused spans for every view count at any size; an explicit
+    # threshold selects the view schedule, a negative one restores the library's choice
     import torch
     d, lib, pa, ps, late, early = workload("c1")
     say("[gpu case] default schedule choice c1")
     for modes, want in (([LATE], "k_forward_span"), ([LATE, EARLY], "k_forward_span"),
-                        ([LATE, EARLY, LATE, EARLY], "k_forward_view")):
+                        ([LATE, EARLY, LATE, EARLY], "k_forward_span")):
         g = sta.Graph(d, n_tables=lib.n_tables).upload("cuda")
         L = sta.make_library(lib.x, lib.y, torch.from_numpy(lib.tab).cuda())
         views = sta.make_views(modes)
