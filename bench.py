@@ -42,6 +42,18 @@ def dc_bytes(D, A, M):
     return 12 * D + 10 * M + 17 * A
 
 
+def cpu_model():
+    """Model name of the host processor (first entry of /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,7 +256,7 @@ def main():
         "schedule": ("view" if "k_forward_view" in kstats else "span" if "k_forward_span" in kstats else "level")
                     + ("" if args.schedule == "auto" else f" (forced {args.schedule})"),
         "host": {"generate_s": t_gen, "build_graph_s": t_build, "upload_s": t_upload,
-                 "graph_bytes": s["graph_bytes"]},
+                 "graph_bytes": s["graph_bytes"], "nproc": os.cpu_count(), "cpu_model": cpu_model()},
     }
 
     # cold caches: a 1 GiB write between steps evicts L2 and the 256 MB Infinity Cache;

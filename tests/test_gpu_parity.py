@@ -155,6 +155,15 @@ def test_c2_full_size_bitwise(schedule):
     compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label="c2 1M pins", schedule=schedule)
 
 
+def test_c2_four_views_two_corners_bitwise():
+    # the 1M-pin workload with late and early views on two corners (four views per launch)
+    # through the library's default schedule
+    d, _, pa, ps, late, early = workload("c2")
+    lib = gen.make_library(kappas=gen.CORNER_KAPPAS)
+    compare_all(d, lib, pa, ps, [late, early, late, early], [LATE, EARLY, LATE, EARLY], [1, 1, 3, 3],
+                label="c2 1M pins, four views", schedule=None)
+
+
 def test_graph_replays_match_plain_launches():
     # the level schedule replays a captured hipGraph; replay it several times with torch's
     # own work (zeroing every output) and synchronizations in between, and compare every
