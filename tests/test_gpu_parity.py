@@ -120,6 +120,17 @@ def test_pi_only_and_empty_designs(schedule):
     assert h["tns"][0] == 0.0 and np.isinf(h["wns"][0])
 
 
+@pytest.mark.parametrize("m_range", [(2, 8), (2, 16), (9, 32), (33, 64), (65, 128), (129, 200)])
+def test_rc_tree_nets_every_size_class(m_range):
+    # random recursive RC trees instead of chains, in each node-count class the delay
+    # calculation dispatches on; the whole pipeline bit for bit
+    d = gen.make_design(n_pins=3000, n_levels=12, fanin="geom", seed=31, m_range=m_range, tree=True)
+    lib = gen.make_library()
+    pa, ps = gen.make_pi(d, seed=5)
+    late, early = gen.make_rat(d, 12, late_per_level=70.0, hold=120.0)
+    compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label=f"RC trees {m_range}")
+
+
 def test_fp32_delay_calc_within_1e5():
     d, lib, pa, ps, late, early = workload("c1")
     say("[gpu case] fp32 delay calc c1")
