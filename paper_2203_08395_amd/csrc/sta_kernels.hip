@@ -449,6 +449,7 @@ __device__ __forceinline__ void bwd_tile(const DevGraph& G, const bool* early, i
 constexpr int kLimbs = 10;
 constexpr int kK4Blocks = 256;
 constexpr int kK4Threads = 256;
+static_assert(kK4Blocks <= 256, "k_endpoint_final's 256 threads read one partial block each");
 
 size_t scratch_bytes() {
     return size_t(kK4Blocks) * STA_MAX_VIEWS * kLimbs * 8 + size_t(kK4Blocks) * STA_MAX_VIEWS * 4;
@@ -1049,13 +1050,23 @@ __global__ __launch_bounds__(kK4Threads) void k_endpoint_partial(const int32_t* 
     for (int i = threadIdx.x; i < NV * kLimbs; i += blockDim.x) s_l[i] = 0ull;
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the thread's first endpoint: its slacks in every view in one round
+    const int e1 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    float s1[NV];
+    {
+        const int u = e1 < E ? ep_drv[e1] : 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s1[v] = e1 < E ? drv_slack[size_t(u) * NV + v] : __builtin_inff();
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         unsigned long long l[kLimbs];
 #pragma unroll
         for (int i = 0; i < kLimbs; ++i) l[i] = 0ull;
-        float mn = __builtin_inff();
-        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
+        float mn = s1[v];
+        add_neg_slack(l, s1[v]);
+        for (int e = e1 + stride; e < E; e += stride) {
             const float s = drv_slack[size_t(ep_drv[e]) * NV + v];
             mn = (s < mn) ? s : mn;
             add_neg_slack(l, s);
@@ -1086,19 +1097,29 @@ __global__ __launch_bounds__(256) void k_endpoint_final(int nblk, const unsigned
     __shared__ unsigned long long s_sum[NV * kLimbs];
     __shared__ float s_min[NV][4];
     for (int i = threadIdx.x; i < NV * kLimbs; i += blockDim.x) s_sum[i] = 0ull;
+    // nblk <= kK4Blocks == blockDim.x: each thread reads at most one block's minima, and
+    // its share of the digits in rounds of eight loads issued before any is added
+    float pmn[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        pmn[v] = int(threadIdx.x) < nblk ? part_wns[size_t(threadIdx.x) * NV + v] : __builtin_inff();
     __syncthreads();
-    for (int i = threadIdx.x; i < nblk * NV * kLimbs; i += blockDim.x) {
-        const unsigned long long x = part_limbs[i];
-        if (x) atomicAdd(&s_sum[i % (NV * kLimbs)], x);
+    const int n = nblk * NV * kLimbs;
+    for (int i0 = threadIdx.x; i0 < n; i0 += 8 * blockDim.x) {
+        unsigned long long x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = i0 + r * int(blockDim.x);
+            x[r] = i < n ? part_limbs[i] : 0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (x[r]) atomicAdd(&s_sum[(i0 + r * int(blockDim.x)) % (NV * kLimbs)], x[r]);
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        float mn = __builtin_inff();
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-            const float x = part_wns[size_t(b) * NV + v];
-            mn = (x < mn) ? x : mn;
-        }
+        float mn = pmn[v];
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const float o2 = __shfl_xor(mn, off, 64);
