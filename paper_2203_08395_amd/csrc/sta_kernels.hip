@@ -26,6 +26,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "sta_internal.h"
@@ -602,6 +603,17 @@ __device__ __forceinline__ void pin_value(T& x) {
     asm volatile("" : "+v"(x));
 }
 
+// f(integral_constant<int, C>) for C = C0 .. N-1 in order: a loop expanded at compile time,
+// so that per-level register arrays are indexed by constants (the loop unroller leaves a
+// long level loop rolled, and its arrays then go to LDS or indexed register moves)
+template <int C0, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (C0 < N) {
+        f(std::integral_constant<int, C0>{});
+        static_for<C0 + 1, N>(f);
+    }
+}
+
 // lane l takes lane l + OFF of its 16-lane row (DPP row shift; lanes past the row end keep
 // their own value, which the callers never take)
 template <int OFF>
@@ -803,9 +815,9 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         }
     }
     // the levels of the tile, in order
-#pragma unroll
-    for (int c = 0; c < kSpanF; ++c) {
-        if (c >= nch) break;                    // uniform
+    static_for<0, kSpanF>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        if (c >= nch) return;                   // uniform
         const bool act = lane < na[c] && gt[c] >= 0;   // gate -1: padding lane
         FwdLane x;
         fwd_lane_setup(x, act, act ? meta[c] : 0u, na[c], lane);
@@ -835,7 +847,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    });
 }
 
 // primary inputs: copy (arrival, slew) of every view
