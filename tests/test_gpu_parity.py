@@ -166,6 +166,13 @@ def test_c2_full_size_bitwise(schedule):
     compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label="c2 1M pins", schedule=schedule)
 
 
+def test_c5_two_million_pins_bitwise():
+    # the largest design of the test set (2M pins, 400 levels, 32 fanout-64 nets) through
+    # the library's default schedule
+    d, lib, pa, ps, late, early = workload("c5")
+    compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label="c5 2M pins", schedule=None)
+
+
 def test_c2_four_views_two_corners_bitwise():
     # the 1M-pin workload with late and early views on two corners (four views per launch)
     # through the library's default schedule
