@@ -127,3 +127,18 @@ def test_level_with_a_wider_driver_runs_as_a_level_launch():
     assert unfused == sorted(wide, reverse=True)          # exactly those levels, single-level
     assert sp["bwd_level_launches"] == len(wide)
     assert sp["fwd_level_launches"] == 0                   # no gate has more than 64 arcs
+
+
+def test_million_pin_plan_fuses_every_level():
+    # the 1M-pin workload: every gate level and every driver level runs inside a fused
+    # span (no level launches), in 40 forward and 45 backward launches, and the redundant
+    # work of cone closure stays what the layout was sized for
+    d = gen.make_design(**gen.CONFIGS["c2"])
+    sp = sta.Graph(d, n_tables=128).spans
+    assert sp["fwd_level_launches"] == 0 and sp["bwd_level_launches"] == 0
+    assert sp["fwd_spans"] == sp["fwd_spans_fused"] == sp["fwd_span_launches"] == 40
+    assert sp["bwd_spans"] == sp["bwd_spans_fused"] == sp["bwd_span_launches"] == 45
+    assert sp["fwd_span_gates"] == d.n_gates and sp["fwd_span_arcs"] == d.n_arcs
+    assert sp["bwd_span_arcs"] == d.n_arcs
+    assert sp["fwd_span_arcs_computed"] <= 2.5 * d.n_arcs
+    assert sp["bwd_span_slots_computed"] <= 1.5 * d.n_arcs
