@@ -31,9 +31,10 @@ def fwd_bytes_per_pass(G, A, n_views):
 
 def bwd_bytes_per_pass(D, A, n_views):
     """Per sink arc: its id 4, gathered RAT of the gate output 4, arc delay 4, net delay 4,
-    input-pin arrival 4, required time and slack out 8 (28 B); per driver: arrival 4,
-    required time and slack out 8, sink pointer 4 (16 B), plus 8 B per further view and arc."""
-    return (28 + 16 * (n_views - 1)) * A + (16 + 12 * (n_views - 1)) * D
+    input-pin arrival 4, required time and slack out 8 (28 B), and 20 B for each further
+    view (all but the id and the net delay); per driver: arrival 4, required time and slack
+    out 8, sink pointer 4 (16 B), and 12 B for each further view."""
+    return (28 + 20 * (n_views - 1)) * A + (16 + 12 * (n_views - 1)) * D
 
 
 def dc_bytes(D, A, M):
