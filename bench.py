@@ -22,11 +22,12 @@ HBM_PEAK_GBS = 8000.0
 
 
 def fwd_bytes_per_pass(G, A, n_views):
-    """Algorithmic bytes of the forward pass: per gate 20 B for the first view (arc
-    pointer, load, arrival+slew out, argmax) and 12 B for each further view; per arc 34 B
-    for the first view (driver id, gathered arrival+slew, net delay+spread, table id,
-    input-pin arrival+slew, arc delay) and 20 B for each further view."""
-    return (20 + 12 * (n_views - 1)) * G + (34 + 20 * (n_views - 1)) * A
+    """Algorithmic bytes of the forward pass: per gate 17 B for the first view (arc
+    pointer 4, load 4, arrival+slew out 8, argmax 1: it is stored as one byte) and 9 B for
+    each further view; per arc 34 B for the first view (driver id, gathered arrival+slew,
+    net delay+spread, table id, input-pin arrival+slew, arc delay) and 20 B for each
+    further view."""
+    return (17 + 9 * (n_views - 1)) * G + (34 + 20 * (n_views - 1)) * A
 
 
 def bwd_bytes_per_pass(D, A, n_views):
