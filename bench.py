@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the event-bracketed pass (for counter-collection runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -465,35 +465,48 @@ def measured_traffic(kernel):
 
 
 def cpu_baseline(d, lib, pa, ps, late, early, updates, budget_s, g, nd, tm, sl):
-    """The oracle as it stands, single-threaded on a host core, over whole passes of the
-    same workload; its last results are also compared bit for bit with the GPU's."""
+    """The oracle as it stands over whole passes of the same workload, timed twice: the
+    OpenMP build on the host's cores (level by level, each level's gates in parallel; the
+    reported value) and the serial build on one core.  Each leg gets half the budget; the
+    last results of both are compared bit for bit with the GPU's."""
     import oracle
-    t_pass = []
-    res = None
-    t_all = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        res = oracle.run(d, lib, pa, ps, late, early, modes=(oracle.LATE, oracle.EARLY))
-        t_pass.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_all > budget_s or len(t_pass) >= 200:
-            break
-    sec = float(np.median(t_pass))
+
+    def leg(par, seconds):
+        t_pass, res = [], None
+        t_all = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            res = oracle.run(d, lib, pa, ps, late, early, modes=(oracle.LATE, oracle.EARLY), par=par)
+            t_pass.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_all > seconds or len(t_pass) >= 200:
+                break
+        return float(np.median(t_pass)), len(t_pass), res
+
+    cores = oracle.threads()
+    sec_par, n_par, res_par = leg(True, 0.5 * budget_s)
+    sec_1, n_1, res_1 = leg(False, 0.5 * budget_s)
     D, A = d.n_drivers, d.n_arcs
-    same = True
     h = {k: v.cpu().numpy() for k, v in list(nd.items()) + list(tm.items()) + list(sl.items()) if k != "scratch"}
-    chk = [(g.drv_to_input(h["load"][:D]), res["load"]), (g.arc_to_input(h["net_delay"][:A]), res["net_delay"])]
-    for v, m in enumerate(("late", "early")):
-        r = res[m]
-        chk += [(g.drv_to_input(h["drv_ts"][:D, v, 0]), r["at_drv"]), (g.drv_to_input(h["drv_ts"][:D, v, 1]), r["slew_drv"]),
-                (g.arc_to_input(h["arc_ts"][:A, v, 0]), r["at_in"]), (g.arc_to_input(h["arc_delay"][:A, v]), r["arc_delay"]),
-                (g.drv_to_input(h["drv_slack"][:D, v]), r["slack_drv"]), (g.arc_to_input(h["arc_slack"][:A, v]), r["slack_in"]),
-                (np.array([h["tns"][v]]), np.array([r["tns"]]))]
-    for got, want in chk:
-        same = same and np.array_equal(np.ascontiguousarray(got).view(np.uint8), np.ascontiguousarray(want).view(np.uint8))
-    return {"value": updates / sec, "unit": "pin-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(t_pass)} whole passes of the same workload (delay calc + late/early propagate + slack), "
-                      f"median {sec * 1e3:.1f} ms per pass, single-threaded C (gcc -O2)",
-            "gpu_bitwise_equal": bool(same)}
+
+    def same_as_gpu(res):
+        chk = [(g.drv_to_input(h["load"][:D]), res["load"]), (g.arc_to_input(h["net_delay"][:A]), res["net_delay"])]
+        for v, m in enumerate(("late", "early")):
+            r = res[m]
+            chk += [(g.drv_to_input(h["drv_ts"][:D, v, 0]), r["at_drv"]), (g.drv_to_input(h["drv_ts"][:D, v, 1]), r["slew_drv"]),
+                    (g.arc_to_input(h["arc_ts"][:A, v, 0]), r["at_in"]), (g.arc_to_input(h["arc_delay"][:A, v]), r["arc_delay"]),
+                    (g.drv_to_input(h["drv_slack"][:D, v]), r["slack_drv"]), (g.arc_to_input(h["arc_slack"][:A, v]), r["slack_in"]),
+                    (np.array([h["tns"][v]]), np.array([r["tns"]]))]
+        return all(np.array_equal(np.ascontiguousarray(a).view(np.uint8), np.ascontiguousarray(b).view(np.uint8))
+                   for a, b in chk)
+
+    return {"value": updates / sec_par, "unit": "pin-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_par} whole passes of the same workload (delay calc + late/early propagate + slack), "
+                      f"median {sec_par * 1e3:.1f} ms per pass, the oracle's OpenMP build (gcc -O2 -fopenmp) on "
+                      f"{cores} threads, level by level",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_core": {"value": updates / sec_1, "unit": "pin-updates/s", "cores": 1,
+                            "sample": f"{n_1} whole passes, median {sec_1 * 1e3:.1f} ms per pass, serial build"},
+            "gpu_bitwise_equal": bool(same_as_gpu(res_par) and same_as_gpu(res_1))}
 
 
 if __name__ == "__main__":

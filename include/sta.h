@@ -27,7 +27,10 @@
  *    during execution surface at the caller's next synchronization of the stream.
  *  - Threads: calls on distinct graphs are independent.  A graph is read-only after
  *    sta_graph_upload, so concurrent calls on it from several streams are allowed as
- *    long as their output buffers differ.  No C++ exception crosses this ABI.
+ *    long as their output (and scratch) buffers differ.  The launch sequences a graph
+ *    replays are cached per argument set (up to four per call kind), so such callers
+ *    replay without re-capturing; a fifth argument set evicts the least recently used
+ *    one after waiting for the device.  No C++ exception crosses this ABI.
  */
 #ifndef STA_H
 #define STA_H
@@ -152,12 +155,16 @@ typedef struct {
 
 const char* sta_last_error(void);
 
-/* Levelizes the design (Kahn; level(PI) = 0, level(g) = 1 + max level of g's fanin
+/* Passage: Section II-A (a computation waits until the quantities it depends on have
+ * arrived: here a gate waits for its fanin drivers) and Section IV-A (the circuit a timer
+ * analyses).  The paper gives no levelization; the definition is Kahn's algorithm.
+ * Levelizes the design (Kahn; level(PI) = 0, level(g) = 1 + max level of g's fanin
  * drivers), checks it, and builds the level-sorted CSR and the wave-sized work tiles.
  * Host only and synchronous; copies what it needs.  Errors: STA_E_ARG, STA_E_RANGE,
  * STA_E_CYCLE, STA_E_NONFINITE, STA_E_ALLOC.  *out is set only on STA_OK. */
 sta_status sta_build_graph(const sta_design_desc* d, sta_graph** out);
 
+/* Sizes of a built graph (host, synchronous).  Errors: STA_E_ARG (null argument). */
 sta_status sta_graph_sizes(const sta_graph* g, sta_sizes* out);
 
 /* Host copies of the maps (each pointer may be null):
@@ -169,14 +176,23 @@ sta_status sta_graph_sizes(const sta_graph* g, sta_sizes* out);
 sta_status sta_graph_perm(const sta_graph* g, int32_t* drv_input, int32_t* arc_input,
                           int32_t* gate_input, int32_t* level, int32_t* ep_driver);
 
-/* Copies the graph's device arrays into dev_buf (caller-owned device memory of at least
- * graph_bytes, 256-byte aligned) on stream s and keeps dev_buf's address; dev_buf must
- * outlive every later call on g.  The host arrays stay owned by g. */
+/* Passage: Section III-A, pull task (host data copied into device memory the runtime
+ * provides; here the caller provides it).
+ * Copies the graph's device arrays into dev_buf (caller-owned device memory of at least
+ * graph_bytes, 256-byte aligned) on stream s, waits for the copy, and keeps dev_buf's
+ * address; dev_buf must outlive every later call on g.  A graph may be uploaded again
+ * (to the same or another buffer): the launch sequences captured against the previous
+ * buffer are dropped first (after waiting for the device), so the old buffer may be
+ * freed once this returns.  The host arrays stay owned by g.  Errors: STA_E_ARG (null,
+ * undersized or unaligned buffer), STA_E_HIP. */
 sta_status sta_graph_upload(sta_graph* g, void* dev_buf, size_t bytes, void* stream);
 
 void sta_graph_free(sta_graph* g);
 
-/* RC delay calculation of every net: per node total cap C = wire cap + tapped pin caps
+/* Passage: Section IV-A (the timer's delay calculation, a black box there).  The paper
+ * states no formula; the moments below are the Elmore / second-moment definitions of
+ * RC trees (Rubinstein, Penfield and Horowitz).
+ * RC delay calculation of every net: per node total cap C = wire cap + tapped pin caps
  * (sinks in ascending input arc id), downstream cap Cd, load = Cd(driver), Elmore
  * m1(k) = m1(parent) + R(k) Cd(k) 1e-3, W = downstream sum of C m1,
  * m2(k) = m2(parent) + R(k) W(k) 1e-3, imp2 = max(0, 2 m2 - m1^2); outputs rounded to
@@ -186,7 +202,10 @@ void sta_graph_free(sta_graph* g);
 sta_status sta_delay_calc(const sta_graph* g, sta_dc_precision prec, const sta_net_out* out,
                           void* stream);
 
-/* Forward propagation of all views, level by level.  pi_ts: device [n_pi][V][2]
+/* Passage: Section IV-A (a timer evaluated per view, a view being one corner combined
+ * with one analysis mode).  The paper states no timing formula; these are the standard
+ * NLDM lookup and max/min arrival propagation, written out here.
+ * Forward propagation of all views, level by level.  pi_ts: device [n_pi][V][2]
  * (arrival, slew) of the primary inputs.  For each gate output o and each cell arc a
  * (input pin i, net driver u):
  *   AT_i = AT_u + net_delay_a;  S_i = sqrt(S_u*S_u + net_imp2_a);
@@ -199,7 +218,10 @@ sta_status sta_propagate(const sta_graph* g, const sta_library* lib, const sta_v
                          const float* pi_ts, const sta_net_out* nd, const sta_timing_out* out,
                          void* stream);
 
-/* Backward required times, slacks and endpoint summaries of all views.  ep_rat: device
+/* Passage: Section IV-A (the timing reports the correlation layer reads: slacks,
+ * critical paths).  Required times and slack follow the standard definition, written
+ * out here (the paper states none).
+ * Backward required times, slacks and endpoint summaries of all views.  ep_rat: device
  * [E][V] required time of every endpoint (rank order).  Late views:
  *   RAT_u = min over u's sink pins i of (RAT_i - net_delay_i), or ep_rat at an endpoint;
  *   RAT_i = RAT_o - d_a;  slack = RAT - AT.
@@ -209,7 +231,9 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
                      const sta_timing_out* t, const float* ep_rat, const sta_slack_out* out,
                      void* scratch, size_t scratch_bytes, void* stream);
 
-/* Schedule of sta_propagate and sta_slack on graph g.  The view schedule (one workgroup
+/* Passage: Section III-B (a task graph run many times, run_n: here the captured launch
+ * sequence replayed as a hipGraph).
+ * Schedule of sta_propagate and sta_slack on graph g.  The view schedule (one workgroup
  * per view walks every level, a workgroup barrier between levels) is used when the
  * design's mean cell arcs per level is at most view_max_arcs_per_level (and the level
  * data fits in LDS), the level schedule (launches per level or per fused span, all views
@@ -218,11 +242,15 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
  * only when fusion is off, up to 512 mean cell arcs per level).
  * use_graphs != 0 (the default) lets the level schedule capture its launch sequence in a
  * hipGraph on first use and replay it while the call's arguments stay the same (the
- * capture is per graph and per call kind; a change of any pointer or view re-captures).
+ * captures are per graph and per call kind, up to four argument sets each; an argument
+ * set not among them is captured, evicting the least recently used after waiting for
+ * the device).
  * Every choice gives identical results. */
 sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32_t use_graphs);
 
-/* Level fusion of the level schedule (default on): up to eight
+/* No passage: a scheduling choice of this library (the paper's kernels are one task
+ * each).  Errors: STA_E_ARG (null graph).
+ * Level fusion of the level schedule (default on): up to eight
  * consecutive gate levels per forward launch and up to eight driver levels per backward
  * launch (the same spans serve the TNS adjoint).  Each workgroup (one wavefront) computes
  * one span tile: in the forward pass a set of gates closed under fanin inside the span

@@ -42,17 +42,24 @@ typedef struct {
                                      or NULL                                               */
 } sta_adjoint_out;
 
-/* Adjoint of TNS for every view of a completed sta_propagate + sta_slack on the same
+/* Passage: Section IV-A (the correlation layer fits regression models by gradient
+ * descent on the timing results); the chain rule through the saved argmax is written out
+ * above (the paper states none).
+ * Adjoint of TNS for every view of a completed sta_propagate + sta_slack on the same
  * graph, views and net data (nd->arc_load, t->argmax, t->arc_ts, sl->drv_slack are
- * read).  One launch per driver level in reverse level order (a gather over each
- * driver's sink pins, no atomics), then one launch for the load gradient.  lib is needed
- * only for g_load (NULL otherwise). */
+ * read).  The driver levels are walked top down on the backward span tiles: each launch
+ * covers up to eight driver levels (a gather over each driver's sink pins with the
+ * in-tile gradients in LDS, no atomics); a level that cannot be tiled, and every level
+ * when level fusion is off, gets one launch of its own.  Then one launch forms the load
+ * gradient.  lib is needed only for g_load (NULL otherwise).  Errors: STA_E_ARG (graph
+ * not uploaded, bad views, null or missing buffers), STA_E_HIP. */
 sta_status sta_tns_adjoint(const sta_graph* g, const sta_library* lib, const sta_views* views,
                            const sta_net_out* nd, const sta_timing_out* t, const sta_slack_out* sl,
                            const sta_adjoint_out* out, void* stream);
 
-/* Refreshes nd->arc_load (the load each cell arc sees) from nd->load (per driver), for
- * callers that supply loads of their own instead of running sta_delay_calc. */
+/* No passage (a data-layout helper).  Refreshes nd->arc_load (the load each cell arc
+ * sees) from nd->load (per driver), for callers that supply loads of their own instead
+ * of running sta_delay_calc.  Errors: STA_E_ARG (graph not uploaded, null buffer). */
 sta_status sta_arc_load(const sta_graph* g, const sta_net_out* nd, void* stream);
 
 #define STA_MAX_PATHS 64
@@ -70,7 +77,9 @@ typedef struct {
 /* Device scratch that sta_critical_paths needs. */
 size_t sta_paths_scratch_bytes(void);
 
-/* The k (1..STA_MAX_PATHS, <= endpoints) worst endpoints of one view and their critical
+/* Passage: Section IV-A (the correlation layer extracts critical paths from each
+ * view's timing).
+ * The k (1..STA_MAX_PATHS, <= endpoints) worst endpoints of one view and their critical
  * paths, by walking the saved argmax arcs back to the primary inputs.  L is the number of
  * levels (sta_sizes.n_levels). */
 sta_status sta_critical_paths(const sta_graph* g, const sta_views* views, int32_t view, int32_t k,

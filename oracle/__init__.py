@@ -26,7 +26,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_lib_omp = None
 
 LATE, EARLY = 0, 1
 
@@ -35,28 +37,46 @@ class OracleError(RuntimeError):
     pass
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH) or (
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(os.path.join(_HERE, "sta_oracle.c"))):
+def _load(par: bool = False):
+    """The serial oracle, or (par) the OpenMP build of the same source."""
+    global _lib, _lib_omp
+    if (_lib_omp if par else _lib) is not None:
+        return _lib_omp if par else _lib
+    src = os.path.join(_HERE, "sta_oracle.c")
+    if any(not os.path.exists(p) or os.path.getmtime(p) < os.path.getmtime(src) for p in (_LIB_PATH, _LIB_OMP_PATH)):
         from . import build as _b
         _b.build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(_LIB_OMP_PATH if par else _LIB_PATH)
     P = ctypes.c_void_p
     I = ctypes.c_int
     lib.orc_levelize.argtypes = [I, I, P, P, P, P]
-    lib.orc_delay_calc.argtypes = [I, P, P, P, P, I, P, P, P, P, P, P, P, P, P]
+    for f in ("orc_delay_calc", "orc_delay_calc_lv"):
+        getattr(lib, f).argtypes = [I, P, P, P, P, I, P, P, P, P, P, P, P, P, P]
     lib.orc_bilerp.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float]
     lib.orc_bilerp.restype = ctypes.c_float
     lib.orc_bilerp_many.argtypes = [P, P, P, I, P, P, P]
-    lib.orc_propagate.argtypes = [I, I, I, P, P, P, I, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
-    lib.orc_slack.argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P, P]
-    for f in ("orc_levelize", "orc_delay_calc", "orc_propagate", "orc_slack"):
+    for f in ("orc_propagate", "orc_propagate_lv"):
+        getattr(lib, f).argtypes = [I, I, I, P, P, P, I, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    for f in ("orc_slack", "orc_slack_lv"):
+        getattr(lib, f).argtypes = [I, I, I, P, P, P, P, P, P, P, P, P, P, P]
+    for f in ("orc_levelize", "orc_delay_calc", "orc_propagate", "orc_slack", "orc_delay_calc_lv",
+              "orc_propagate_lv", "orc_slack_lv", "orc_num_threads"):
         getattr(lib, f).restype = ctypes.c_int
-    _lib = lib
+    lib.orc_set_threads.argtypes = [I]
+    lib.orc_set_threads.restype = None
+    if par:
+        _lib_omp = lib
+    else:
+        _lib = lib
     return lib
+
+
+def threads(n=None) -> int:
+    """Threads of the OpenMP build: sets them when n is given; returns the count in use."""
+    lib = _load(True)
+    if n is not None:
+        lib.orc_set_threads(int(n))
+    return int(lib.orc_num_threads())
 
 
 def _p(a):
@@ -84,11 +104,12 @@ def levelize(d):
     return level, topo[: d.n_gates]
 
 
-def delay_calc(d, moments: bool = False):
+def delay_calc(d, moments: bool = False, par: bool = False):
     """Step 2 (FP64 per net): load per driver, Elmore delay and imp2 per sink arc (FP32 rounded).
 
-    With ``moments`` also returns the FP64 node arrays (m1, m2, downstream cap)."""
-    lib = _load()
+    With ``moments`` also returns the FP64 node arrays (m1, m2, downstream cap).  With
+    ``par`` the OpenMP build spreads the nets over its threads (same results)."""
+    lib = _load(par)
     D, A, M = d.n_pi + d.n_gates, d.arc_drv.shape[0], d.node_R.shape[0]
     load = np.zeros(D, dtype=np.float32)
     nd = np.zeros(A, dtype=np.float32)
@@ -99,7 +120,7 @@ def delay_calc(d, moments: bool = False):
     arrs = [_c(d.net_node_ptr, np.int32), _c(d.node_parent, np.int32), _c(d.node_R, np.float32),
             _c(d.node_C, np.float32), _c(d.arc_drv, np.int32), _c(d.arc_tap, np.int32),
             _c(d.arc_pincap, np.float32)]
-    rc = lib.orc_delay_calc(D, _p(arrs[0]), _p(arrs[1]), _p(arrs[2]), _p(arrs[3]), A,
+    rc = (lib.orc_delay_calc_lv if par else lib.orc_delay_calc)(D, _p(arrs[0]), _p(arrs[1]), _p(arrs[2]), _p(arrs[3]), A,
                             _p(arrs[4]), _p(arrs[5]), _p(arrs[6]), _p(load), _p(nd), _p(ni),
                             _p(m1), _p(m2), _p(cd))
     _check(rc, "delay_calc")
@@ -119,9 +140,10 @@ def bilerp(x, y, T, s, l):
     return out
 
 
-def propagate(d, lib_x, lib_y, lib_tab, load, net_delay, net_imp2, pi_at, pi_slew, mode=LATE):
-    """Steps 4-5 (FP32): arrival time and slew of every pin, arc delays and the argmax arc."""
-    lib = _load()
+def propagate(d, lib_x, lib_y, lib_tab, load, net_delay, net_imp2, pi_at, pi_slew, mode=LATE, par=False):
+    """Steps 4-5 (FP32): arrival time and slew of every pin, arc delays and the argmax arc.
+    With ``par`` the OpenMP build runs level by level, each level's gates in parallel."""
+    lib = _load(par)
     D, A, G = d.n_pi + d.n_gates, d.arc_drv.shape[0], d.n_gates
     tab = _c(lib_tab, np.float32)
     K = tab.shape[0]
@@ -132,7 +154,7 @@ def propagate(d, lib_x, lib_y, lib_tab, load, net_delay, net_imp2, pi_at, pi_sle
            _c(lib_x, np.float32), _c(lib_y, np.float32), tab, _c(load, np.float32),
            _c(net_delay, np.float32), _c(net_imp2, np.float32), _c(pi_at, np.float32),
            _c(pi_slew, np.float32)]
-    rc = lib.orc_propagate(int(mode), d.n_pi, G, _p(ins[0]), _p(ins[1]), _p(ins[2]), K,
+    rc = (lib.orc_propagate_lv if par else lib.orc_propagate)(int(mode), d.n_pi, G, _p(ins[0]), _p(ins[1]), _p(ins[2]), K,
                            _p(ins[3]), _p(ins[4]), _p(ins[5]), _p(ins[6]), _p(ins[7]), _p(ins[8]),
                            _p(ins[9]), _p(ins[10]), _p(out["at_drv"]), _p(out["slew_drv"]),
                            _p(out["at_in"]), _p(out["slew_in"]), _p(out["arc_delay"]),
@@ -147,16 +169,17 @@ def endpoints(d):
     return np.nonzero(fo == 0)[0]
 
 
-def slack(d, net_delay, arc_delay, at_drv, at_in, ep_rat, mode=LATE):
-    """Step 6 (FP32): required times and slacks of every pin, then WNS and TNS."""
-    lib = _load()
+def slack(d, net_delay, arc_delay, at_drv, at_in, ep_rat, mode=LATE, par=False):
+    """Step 6 (FP32): required times and slacks of every pin, then WNS and TNS.  With
+    ``par`` the OpenMP build runs level by level from the top, in parallel per level."""
+    lib = _load(par)
     D, A, G = d.n_pi + d.n_gates, d.arc_drv.shape[0], d.n_gates
     out = dict(rat_drv=np.zeros(D, np.float32), rat_in=np.zeros(A, np.float32),
                slack_drv=np.zeros(D, np.float32), slack_in=np.zeros(A, np.float32))
     ins = [_c(d.gate_arc_ptr, np.int32), _c(d.arc_drv, np.int32), _c(net_delay, np.float32),
            _c(arc_delay, np.float32), _c(at_drv, np.float32), _c(at_in, np.float32),
            _c(ep_rat, np.float32)]
-    rc = lib.orc_slack(int(mode), d.n_pi, G, *[_p(a) for a in ins], _p(out["rat_drv"]),
+    rc = (lib.orc_slack_lv if par else lib.orc_slack)(int(mode), d.n_pi, G, *[_p(a) for a in ins], _p(out["rat_drv"]),
                        _p(out["rat_in"]), _p(out["slack_drv"]), _p(out["slack_in"]))
     _check(rc, "slack")
     ep = endpoints(d)
@@ -173,14 +196,15 @@ def tns(endpoint_slack) -> float:
     return math.fsum(neg.tolist())
 
 
-def run(d, lib, pi_at, pi_slew, ep_rat_late, ep_rat_early=None, modes=(LATE,)):
-    """Whole path for the given modes: delay calc, then propagate and slack per mode."""
-    load, nd, ni = delay_calc(d)
+def run(d, lib, pi_at, pi_slew, ep_rat_late, ep_rat_early=None, modes=(LATE,), par=False):
+    """Whole path for the given modes: delay calc, then propagate and slack per mode
+    (``par``: the OpenMP build's level-parallel entry points)."""
+    load, nd, ni = delay_calc(d, par=par)
     res = {"load": load, "net_delay": nd, "net_imp2": ni}
     for m in modes:
         rat = ep_rat_late if m == LATE else ep_rat_early
-        p = propagate(d, lib.x, lib.y, lib.tab, load, nd, ni, pi_at, pi_slew, m)
-        s = slack(d, nd, p["arc_delay"], p["at_drv"], p["at_in"], rat, m)
+        p = propagate(d, lib.x, lib.y, lib.tab, load, nd, ni, pi_at, pi_slew, m, par=par)
+        s = slack(d, nd, p["arc_delay"], p["at_drv"], p["at_in"], rat, m, par=par)
         p.update(s)
         res["late" if m == LATE else "early"] = p
     return res

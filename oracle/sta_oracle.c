@@ -24,12 +24,20 @@
  *           (early).  WNS/TNS are formed by the Python wrapper from the endpoint slacks.
  *
  * Build: gcc -O2 -ffp-contract=off (x86-64 SSE arithmetic: every float/double
- * operation is a single IEEE-754 round-to-nearest-even operation).
+ * operation is a single IEEE-754 round-to-nearest-even operation).  The same source is
+ * built twice: liboracle.so (serial) and, with -fopenmp, liboracle_omp.so, where the
+ * level-ordered entry points (orc_*_lv) run each level's gates (drivers, nets) in
+ * parallel.  Every gate, driver or net is computed by the one routine both orders call,
+ * from operands fixed before its level starts, so both builds and both orders give the
+ * same bits.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_E_ARG (-1)
@@ -106,59 +114,174 @@ done:
  *   imp2  = max(0, 2*m2 - m1*m1)
  * Per sink arc: net_delay = fl32(m1[tap]), net_imp2 = fl32(imp2[tap]); load[d] = fl32(load).
  * node_m1/node_m2/node_cd (FP64, per global node) are optional outputs for the tests. */
+
+/* Driver-level CSR of the sink arcs (fanout), each driver's arcs in ascending arc id. */
+static int orc_fanout(int D, int A, const int32_t* arc_drv, int32_t** fo_ptr_out, int32_t** fo_arc_out)
+{
+    int32_t* fo_ptr = (int32_t*)calloc((size_t)D + 2, sizeof(int32_t));
+    int32_t* fo_arc = (int32_t*)malloc(((size_t)A + 1) * sizeof(int32_t));
+    if (!fo_ptr || !fo_arc) { free(fo_ptr); free(fo_arc); return ORC_E_ARG; }
+    for (int a = 0; a < A; ++a) fo_ptr[arc_drv[a] + 2]++;
+    for (int d = 0; d < D; ++d) fo_ptr[d + 2] += fo_ptr[d + 1];
+    for (int a = 0; a < A; ++a) fo_arc[fo_ptr[arc_drv[a] + 1]++] = a;
+    *fo_ptr_out = fo_ptr;
+    *fo_arc_out = fo_arc;
+    return ORC_OK;
+}
+
+/* Checks the RC data of every net: parents before children, taps inside their net. */
+static int orc_check_nets(int n_drv, const int32_t* net_node_ptr, const int32_t* node_parent,
+                          int n_arcs, const int32_t* arc_drv, const int32_t* arc_tap)
+{
+    for (int a = 0; a < n_arcs; ++a) {
+        int d = arc_drv[a];
+        if (d < 0 || d >= n_drv) return ORC_E_RANGE;
+        int nm = net_node_ptr[d + 1] - net_node_ptr[d];
+        if (arc_tap[a] < 0 || arc_tap[a] >= nm) return ORC_E_RANGE;
+    }
+    for (int d = 0; d < n_drv; ++d) {
+        int n0 = net_node_ptr[d], nm = net_node_ptr[d + 1] - n0;
+        if (nm < 1) return ORC_E_ARG;
+        for (int k = 1; k < nm; ++k)
+            if (node_parent[n0 + k] < 0 || node_parent[n0 + k] >= k) return ORC_E_RANGE;
+    }
+    return ORC_OK;
+}
+
+/* The moments of net d (the definition above), its sinks being fo_arc[fo_ptr[d] ..
+ * fo_ptr[d+1]) in ascending arc id.  C, Cd, m1, W, m2: FP64 work arrays of the net's
+ * node count. */
+static void net_moments(int d, const int32_t* net_node_ptr, const int32_t* node_parent,
+                        const float* node_R, const float* node_C, const int32_t* fo_ptr,
+                        const int32_t* fo_arc, const int32_t* arc_tap, const float* arc_pincap,
+                        double* C, double* Cd, double* m1, double* W, double* m2,
+                        float* load, float* net_delay, float* net_imp2,
+                        double* node_m1, double* node_m2, double* node_cd)
+{
+    const int n0 = net_node_ptr[d], nm = net_node_ptr[d + 1] - n0;
+    const int32_t* par = node_parent + n0;
+    for (int k = 0; k < nm; ++k) C[k] = (double)node_C[n0 + k];
+    for (int i = fo_ptr[d]; i < fo_ptr[d + 1]; ++i) C[arc_tap[fo_arc[i]]] += (double)arc_pincap[fo_arc[i]];
+    for (int k = 0; k < nm; ++k) Cd[k] = C[k];
+    for (int k = nm - 1; k >= 1; --k) Cd[par[k]] += Cd[k];
+    load[d] = (float)Cd[0];
+    m1[0] = 0.0;
+    for (int k = 1; k < nm; ++k) m1[k] = m1[par[k]] + ((double)node_R[n0 + k] * Cd[k]) * 1e-3;
+    for (int k = 0; k < nm; ++k) W[k] = C[k] * m1[k];
+    for (int k = nm - 1; k >= 1; --k) W[par[k]] += W[k];
+    m2[0] = 0.0;
+    for (int k = 1; k < nm; ++k) m2[k] = m2[par[k]] + ((double)node_R[n0 + k] * W[k]) * 1e-3;
+    for (int i = fo_ptr[d]; i < fo_ptr[d + 1]; ++i) {
+        const int a = fo_arc[i], k = arc_tap[a];
+        double imp2 = 2.0 * m2[k] - m1[k] * m1[k];
+        if (imp2 < 0.0) imp2 = 0.0;
+        net_delay[a] = (float)m1[k];
+        net_imp2[a] = (float)imp2;
+    }
+    if (node_m1) memcpy(node_m1 + n0, m1, sizeof(double) * (size_t)nm);
+    if (node_m2) memcpy(node_m2 + n0, m2, sizeof(double) * (size_t)nm);
+    if (node_cd) memcpy(node_cd + n0, Cd, sizeof(double) * (size_t)nm);
+}
+
+/* par = 0: nets one after another; par = 1: nets in parallel (OpenMP build). */
+static int delay_calc_impl(int par, int n_drv, const int32_t* net_node_ptr, const int32_t* node_parent,
+                           const float* node_R, const float* node_C,
+                           int n_arcs, const int32_t* arc_drv, const int32_t* arc_tap, const float* arc_pincap,
+                           float* load, float* net_delay, float* net_imp2,
+                           double* node_m1, double* node_m2, double* node_cd)
+{
+    int rc = orc_check_nets(n_drv, net_node_ptr, node_parent, n_arcs, arc_drv, arc_tap);
+    if (rc != ORC_OK) return rc;
+    int32_t *fo_ptr = NULL, *fo_arc = NULL;
+    rc = orc_fanout(n_drv, n_arcs, arc_drv, &fo_ptr, &fo_arc);
+    if (rc != ORC_OK) return rc;
+    int maxm = 1;
+    for (int d = 0; d < n_drv; ++d)
+        if (net_node_ptr[d + 1] - net_node_ptr[d] > maxm) maxm = net_node_ptr[d + 1] - net_node_ptr[d];
+    int bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel if (par) reduction(| : bad)
+#endif
+    {
+        double* work = (double*)malloc(sizeof(double) * 5 * (size_t)maxm);
+        if (!work) {
+            bad = 1;
+        } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1024)
+#endif
+            for (int d = 0; d < n_drv; ++d)
+                net_moments(d, net_node_ptr, node_parent, node_R, node_C, fo_ptr, fo_arc, arc_tap, arc_pincap,
+                            work, work + maxm, work + 2 * (size_t)maxm, work + 3 * (size_t)maxm,
+                            work + 4 * (size_t)maxm, load, net_delay, net_imp2, node_m1, node_m2, node_cd);
+        }
+        free(work);
+    }
+    free(fo_ptr); free(fo_arc);
+    (void)par;
+    return bad ? ORC_E_ARG : ORC_OK;
+}
+
 int orc_delay_calc(int n_drv, const int32_t* net_node_ptr, const int32_t* node_parent,
                    const float* node_R, const float* node_C,
                    int n_arcs, const int32_t* arc_drv, const int32_t* arc_tap, const float* arc_pincap,
                    float* load, float* net_delay, float* net_imp2,
                    double* node_m1, double* node_m2, double* node_cd)
 {
-    int M = net_node_ptr[n_drv];
-    double* C = (double*)malloc(((size_t)M + 1) * sizeof(double));
-    double* Cd = (double*)malloc(((size_t)M + 1) * sizeof(double));
-    double* m1 = (double*)malloc(((size_t)M + 1) * sizeof(double));
-    double* W = (double*)malloc(((size_t)M + 1) * sizeof(double));
-    double* m2 = (double*)malloc(((size_t)M + 1) * sizeof(double));
-    int rc = ORC_OK;
-    if (!C || !Cd || !m1 || !W || !m2) { rc = ORC_E_ARG; goto done; }
+    return delay_calc_impl(0, n_drv, net_node_ptr, node_parent, node_R, node_C, n_arcs, arc_drv, arc_tap,
+                           arc_pincap, load, net_delay, net_imp2, node_m1, node_m2, node_cd);
+}
 
-    for (int k = 0; k < M; ++k) C[k] = (double)node_C[k];
-    for (int a = 0; a < n_arcs; ++a) {
-        int d = arc_drv[a];
-        if (d < 0 || d >= n_drv) { rc = ORC_E_RANGE; goto done; }
-        int n0 = net_node_ptr[d], nm = net_node_ptr[d + 1] - n0;
-        if (arc_tap[a] < 0 || arc_tap[a] >= nm) { rc = ORC_E_RANGE; goto done; }
-        C[n0 + arc_tap[a]] += (double)arc_pincap[a];
-    }
-    for (int d = 0; d < n_drv; ++d) {
-        int n0 = net_node_ptr[d], nm = net_node_ptr[d + 1] - n0;
-        const int32_t* par = node_parent + n0;
-        for (int k = 1; k < nm; ++k)
-            if (par[k] < 0 || par[k] >= k) { rc = ORC_E_RANGE; goto done; }
-        for (int k = 0; k < nm; ++k) Cd[n0 + k] = C[n0 + k];
-        for (int k = nm - 1; k >= 1; --k) Cd[n0 + par[k]] += Cd[n0 + k];
-        load[d] = (float)Cd[n0];
-        m1[n0] = 0.0;
-        for (int k = 1; k < nm; ++k)
-            m1[n0 + k] = m1[n0 + par[k]] + ((double)node_R[n0 + k] * Cd[n0 + k]) * 1e-3;
-        for (int k = 0; k < nm; ++k) W[n0 + k] = C[n0 + k] * m1[n0 + k];
-        for (int k = nm - 1; k >= 1; --k) W[n0 + par[k]] += W[n0 + k];
-        m2[n0] = 0.0;
-        for (int k = 1; k < nm; ++k)
-            m2[n0 + k] = m2[n0 + par[k]] + ((double)node_R[n0 + k] * W[n0 + k]) * 1e-3;
-    }
-    for (int a = 0; a < n_arcs; ++a) {
-        int k = net_node_ptr[arc_drv[a]] + arc_tap[a];
-        double imp2 = 2.0 * m2[k] - m1[k] * m1[k];
-        if (imp2 < 0.0) imp2 = 0.0;
-        net_delay[a] = (float)m1[k];
-        net_imp2[a] = (float)imp2;
-    }
-    if (node_m1) memcpy(node_m1, m1, sizeof(double) * (size_t)M);
-    if (node_m2) memcpy(node_m2, m2, sizeof(double) * (size_t)M);
-    if (node_cd) memcpy(node_cd, Cd, sizeof(double) * (size_t)M);
-done:
-    free(C); free(Cd); free(m1); free(W); free(m2);
-    return rc;
+/* The same, the nets spread over the OpenMP threads (nets are independent). */
+int orc_delay_calc_lv(int n_drv, const int32_t* net_node_ptr, const int32_t* node_parent,
+                      const float* node_R, const float* node_C,
+                      int n_arcs, const int32_t* arc_drv, const int32_t* arc_tap, const float* arc_pincap,
+                      float* load, float* net_delay, float* net_imp2,
+                      double* node_m1, double* node_m2, double* node_cd)
+{
+    return delay_calc_impl(1, n_drv, net_node_ptr, node_parent, node_R, node_C, n_arcs, arc_drv, arc_tap,
+                           arc_pincap, load, net_delay, net_imp2, node_m1, node_m2, node_cd);
+}
+
+/* Threads the OpenMP entry points use (1 in the serial build). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* Drivers bucketed by level, ascending id inside a level: drivers of level l are
+ * by_lv[lv_ptr[l] .. lv_ptr[l+1]).  *n_lv = highest level + 1. */
+static int orc_level_buckets(int D, const int32_t* level, int32_t** lv_ptr_out, int32_t** by_lv_out, int* n_lv)
+{
+    int L = 0;
+    for (int d = 0; d < D; ++d) if (level[d] > L) L = level[d];
+    int32_t* lv_ptr = (int32_t*)calloc((size_t)L + 2, sizeof(int32_t));
+    int32_t* by_lv = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    if (!lv_ptr || !by_lv) { free(lv_ptr); free(by_lv); return ORC_E_ARG; }
+    for (int d = 0; d < D; ++d) lv_ptr[level[d] + 1]++;
+    for (int l = 0; l <= L; ++l) lv_ptr[l + 1] += lv_ptr[l];
+    int32_t* fill = (int32_t*)malloc(((size_t)L + 1) * sizeof(int32_t));
+    if (!fill) { free(lv_ptr); free(by_lv); return ORC_E_ARG; }
+    memcpy(fill, lv_ptr, sizeof(int32_t) * ((size_t)L + 1));
+    for (int d = 0; d < D; ++d) by_lv[fill[level[d]]++] = d;
+    free(fill);
+    *lv_ptr_out = lv_ptr;
+    *by_lv_out = by_lv;
+    *n_lv = L + 1;
+    return ORC_OK;
 }
 
 /* ---- step 3: NLDM bilinear lookup (FP32) ------------------------------------ */
@@ -196,8 +319,95 @@ void orc_bilerp_many(const float* x, const float* y, const float* T, int n,
 /* ---- steps 4-5: forward propagation (FP32) ----------------------------------- */
 
 /* mode 0 = late (max), 1 = early (min).  lib_tab holds n_tables pairs, each 2x49 floats:
- * [t][0] delay table, [t][1] slew table.  Gates are evaluated in a topological order
- * (Kahn's), which fixes every operand, so the result does not depend on that order. */
+ * [t][0] delay table, [t][1] slew table.  A gate's step reads only its drivers' results,
+ * so any topological order (Kahn's queue, or level by level) gives the same bits. */
+
+/* One gate g: per cell arc the input pin's arrival and slew, the NLDM delay and output
+ * slew at the gate's load; then the max (late) / min (early) over the arcs with the
+ * smallest arc index winning ties, and the worst slew. */
+static void gate_forward(int mode, int n_pi, int g, const int32_t* gate_arc_ptr, const int32_t* arc_drv,
+                         const int32_t* arc_tbl, const float* lib_x, const float* lib_y, const float* lib_tab,
+                         const float* load, const float* net_delay, const float* net_imp2,
+                         float* at_drv, float* slew_drv, float* at_in, float* slew_in,
+                         float* arc_delay, int32_t* argmax)
+{
+    int o = n_pi + g;
+    float best_at = 0.0f, best_slew = 0.0f;
+    int best_k = -1;
+    for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
+        int u = arc_drv[a];
+        int tb = arc_tbl[a];
+        float ai = at_drv[u] + net_delay[a];
+        float su2 = slew_drv[u] * slew_drv[u];
+        float si = sqrtf(su2 + net_imp2[a]);
+        at_in[a] = ai;
+        slew_in[a] = si;
+        float d = orc_bilerp(lib_x, lib_y, lib_tab + (size_t)tb * 98, si, load[o]);
+        float s = orc_bilerp(lib_x, lib_y, lib_tab + (size_t)tb * 98 + 49, si, load[o]);
+        arc_delay[a] = d;
+        float cand = ai + d;
+        int k = a - gate_arc_ptr[g];
+        if (best_k < 0) {
+            best_at = cand; best_slew = s; best_k = k;
+        } else if (mode == 0) {
+            if (cand > best_at) { best_at = cand; best_k = k; }
+            if (s > best_slew) best_slew = s;
+        } else {
+            if (cand < best_at) { best_at = cand; best_k = k; }
+            if (s < best_slew) best_slew = s;
+        }
+    }
+    at_drv[o] = best_at;
+    slew_drv[o] = best_slew;
+    argmax[g] = best_k;
+}
+
+/* par = 0: gates in Kahn's order; par = 1: level by level, each level's gates in
+ * parallel (OpenMP build). */
+static int propagate_impl(int par, int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr,
+                          const int32_t* arc_drv, const int32_t* arc_tbl, int n_tables,
+                          const float* lib_x, const float* lib_y, const float* lib_tab,
+                          const float* load, const float* net_delay, const float* net_imp2,
+                          const float* pi_at, const float* pi_slew,
+                          float* at_drv, float* slew_drv, float* at_in, float* slew_in,
+                          float* arc_delay, int32_t* argmax)
+{
+    int D = n_pi + n_gates;
+    int A = gate_arc_ptr[n_gates];
+    int32_t* level = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    int32_t* topo = (int32_t*)malloc(((size_t)n_gates + 1) * sizeof(int32_t));
+    int32_t *lv_ptr = NULL, *by_lv = NULL;
+    int n_lv = 0;
+    int rc = ORC_OK;
+    if (!level || !topo) { rc = ORC_E_ARG; goto done; }
+    for (int a = 0; a < A; ++a)
+        if (arc_tbl[a] < 0 || arc_tbl[a] >= n_tables) { rc = ORC_E_RANGE; goto done; }
+    rc = orc_levelize(n_pi, n_gates, gate_arc_ptr, arc_drv, level, topo);
+    if (rc != ORC_OK) goto done;
+
+    for (int d = 0; d < n_pi; ++d) { at_drv[d] = pi_at[d]; slew_drv[d] = pi_slew[d]; }
+    if (!par) {
+        for (int t = 0; t < n_gates; ++t)
+            gate_forward(mode, n_pi, topo[t], gate_arc_ptr, arc_drv, arc_tbl, lib_x, lib_y, lib_tab, load,
+                         net_delay, net_imp2, at_drv, slew_drv, at_in, slew_in, arc_delay, argmax);
+        goto done;
+    }
+    rc = orc_level_buckets(D, level, &lv_ptr, &by_lv, &n_lv);
+    if (rc != ORC_OK) goto done;
+    for (int l = 1; l < n_lv; ++l) {
+        const int i0 = lv_ptr[l], i1 = lv_ptr[l + 1];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+        for (int i = i0; i < i1; ++i)
+            gate_forward(mode, n_pi, by_lv[i] - n_pi, gate_arc_ptr, arc_drv, arc_tbl, lib_x, lib_y, lib_tab, load,
+                         net_delay, net_imp2, at_drv, slew_drv, at_in, slew_in, arc_delay, argmax);
+    }
+done:
+    free(level); free(topo); free(lv_ptr); free(by_lv);
+    return rc;
+}
+
 int orc_propagate(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr,
                   const int32_t* arc_drv, const int32_t* arc_tbl, int n_tables,
                   const float* lib_x, const float* lib_y, const float* lib_tab,
@@ -206,51 +416,23 @@ int orc_propagate(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr,
                   float* at_drv, float* slew_drv, float* at_in, float* slew_in,
                   float* arc_delay, int32_t* argmax)
 {
-    int D = n_pi + n_gates;
-    int32_t* level = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
-    int32_t* topo = (int32_t*)malloc(((size_t)n_gates + 1) * sizeof(int32_t));
-    int rc = ORC_OK;
-    if (!level || !topo) { rc = ORC_E_ARG; goto done; }
-    rc = orc_levelize(n_pi, n_gates, gate_arc_ptr, arc_drv, level, topo);
-    if (rc != ORC_OK) goto done;
+    return propagate_impl(0, mode, n_pi, n_gates, gate_arc_ptr, arc_drv, arc_tbl, n_tables, lib_x, lib_y,
+                          lib_tab, load, net_delay, net_imp2, pi_at, pi_slew, at_drv, slew_drv, at_in, slew_in,
+                          arc_delay, argmax);
+}
 
-    for (int d = 0; d < n_pi; ++d) { at_drv[d] = pi_at[d]; slew_drv[d] = pi_slew[d]; }
-    for (int t = 0; t < n_gates; ++t) {
-        int g = topo[t];
-        int o = n_pi + g;
-        float best_at = 0.0f, best_slew = 0.0f;
-        int best_k = -1;
-        for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
-            int u = arc_drv[a];
-            int tb = arc_tbl[a];
-            if (tb < 0 || tb >= n_tables) { rc = ORC_E_RANGE; goto done; }
-            float ai = at_drv[u] + net_delay[a];
-            float su2 = slew_drv[u] * slew_drv[u];
-            float si = sqrtf(su2 + net_imp2[a]);
-            at_in[a] = ai;
-            slew_in[a] = si;
-            float d = orc_bilerp(lib_x, lib_y, lib_tab + (size_t)tb * 98, si, load[o]);
-            float s = orc_bilerp(lib_x, lib_y, lib_tab + (size_t)tb * 98 + 49, si, load[o]);
-            arc_delay[a] = d;
-            float cand = ai + d;
-            int k = a - gate_arc_ptr[g];
-            if (best_k < 0) {
-                best_at = cand; best_slew = s; best_k = k;
-            } else if (mode == 0) {
-                if (cand > best_at) { best_at = cand; best_k = k; }
-                if (s > best_slew) best_slew = s;
-            } else {
-                if (cand < best_at) { best_at = cand; best_k = k; }
-                if (s < best_slew) best_slew = s;
-            }
-        }
-        at_drv[o] = best_at;
-        slew_drv[o] = best_slew;
-        argmax[g] = best_k;
-    }
-done:
-    free(level); free(topo);
-    return rc;
+/* The same, level by level with each level's gates spread over the OpenMP threads. */
+int orc_propagate_lv(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr,
+                     const int32_t* arc_drv, const int32_t* arc_tbl, int n_tables,
+                     const float* lib_x, const float* lib_y, const float* lib_tab,
+                     const float* load, const float* net_delay, const float* net_imp2,
+                     const float* pi_at, const float* pi_slew,
+                     float* at_drv, float* slew_drv, float* at_in, float* slew_in,
+                     float* arc_delay, int32_t* argmax)
+{
+    return propagate_impl(1, mode, n_pi, n_gates, gate_arc_ptr, arc_drv, arc_tbl, n_tables, lib_x, lib_y,
+                          lib_tab, load, net_delay, net_imp2, pi_at, pi_slew, at_drv, slew_drv, at_in, slew_in,
+                          arc_delay, argmax);
 }
 
 /* ---- step 6: required times and slack (FP32) --------------------------------- */
@@ -258,62 +440,103 @@ done:
 /* Endpoints are drivers without sinks; ep_rat[r] is the required time of the r-th
  * endpoint in ascending driver id.  Late: RAT_drv = min over its sink arcs of
  * (RAT_in - net_delay), RAT_in = RAT_out - arc_delay, slack = RAT - AT.
- * Early: max instead of min, slack = AT - RAT.  Gates are visited in reverse
- * topological order so that every sink's RAT_in exists before its driver needs it. */
-int orc_slack(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr, const int32_t* arc_drv,
-              const float* net_delay, const float* arc_delay,
-              const float* at_drv, const float* at_in, const float* ep_rat,
-              float* rat_drv, float* rat_in, float* slack_drv, float* slack_in)
+ * Early: max instead of min, slack = AT - RAT.  A driver needs the RAT_in of its sinks,
+ * which belong to gates of higher level: drivers are visited in reverse topological
+ * order (Kahn's, or level by level from the top). */
+
+/* One driver o: its required time and slack, then (a gate output) the required times
+ * and slacks of its gate's input pins. */
+static void driver_backward(int mode, int n_pi, int o, const int32_t* gate_arc_ptr, const int32_t* fo_ptr,
+                            const int32_t* fo_arc, const int32_t* ep_rank, const float* net_delay,
+                            const float* arc_delay, const float* at_drv, const float* at_in, const float* ep_rat,
+                            float* rat_drv, float* rat_in, float* slack_drv, float* slack_in)
+{
+    float r;
+    if (ep_rank[o] >= 0) {
+        r = ep_rat[ep_rank[o]];
+    } else {
+        r = 0.0f;
+        for (int i = fo_ptr[o]; i < fo_ptr[o + 1]; ++i) {
+            int a = fo_arc[i];
+            float v = rat_in[a] - net_delay[a];
+            if (i == fo_ptr[o]) r = v;
+            else if (mode == 0) { if (v < r) r = v; }
+            else { if (v > r) r = v; }
+        }
+    }
+    rat_drv[o] = r;
+    slack_drv[o] = (mode == 0) ? (r - at_drv[o]) : (at_drv[o] - r);
+    if (o >= n_pi) {
+        int g = o - n_pi;
+        for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
+            rat_in[a] = r - arc_delay[a];
+            slack_in[a] = (mode == 0) ? (rat_in[a] - at_in[a]) : (at_in[a] - rat_in[a]);
+        }
+    }
+}
+
+static int slack_impl(int par, int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr, const int32_t* arc_drv,
+                      const float* net_delay, const float* arc_delay,
+                      const float* at_drv, const float* at_in, const float* ep_rat,
+                      float* rat_drv, float* rat_in, float* slack_drv, float* slack_in)
 {
     int D = n_pi + n_gates;
     int A = gate_arc_ptr[n_gates];
     int32_t* level = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
     int32_t* topo = (int32_t*)malloc(((size_t)n_gates + 1) * sizeof(int32_t));
-    int32_t* fo_ptr = (int32_t*)calloc((size_t)D + 2, sizeof(int32_t));
-    int32_t* fo_arc = (int32_t*)malloc(((size_t)A + 1) * sizeof(int32_t));
     int32_t* ep_rank = (int32_t*)malloc(((size_t)D + 1) * sizeof(int32_t));
+    int32_t *fo_ptr = NULL, *fo_arc = NULL, *lv_ptr = NULL, *by_lv = NULL;
+    int n_lv = 0;
     int rc = ORC_OK;
-    if (!level || !topo || !fo_ptr || !fo_arc || !ep_rank) { rc = ORC_E_ARG; goto done; }
+    if (!level || !topo || !ep_rank) { rc = ORC_E_ARG; goto done; }
     rc = orc_levelize(n_pi, n_gates, gate_arc_ptr, arc_drv, level, topo);
     if (rc != ORC_OK) goto done;
-
-    for (int a = 0; a < A; ++a) fo_ptr[arc_drv[a] + 2]++;
-    for (int d = 0; d < D; ++d) fo_ptr[d + 2] += fo_ptr[d + 1];
-    for (int a = 0; a < A; ++a) fo_arc[fo_ptr[arc_drv[a] + 1]++] = a;
+    rc = orc_fanout(D, A, arc_drv, &fo_ptr, &fo_arc);
+    if (rc != ORC_OK) goto done;
     {
         int r = 0;
         for (int d = 0; d < D; ++d) ep_rank[d] = (fo_ptr[d + 1] == fo_ptr[d]) ? r++ : -1;
     }
-
-    for (int t = n_gates - 1; t >= -n_pi; --t) {
-        /* t >= 0: gate topo[t]; t < 0: primary input -t-1 */
-        int o = (t >= 0) ? n_pi + topo[t] : -t - 1;
-        float r;
-        if (ep_rank[o] >= 0) {
-            r = ep_rat[ep_rank[o]];
-        } else {
-            r = 0.0f;
-            for (int i = fo_ptr[o]; i < fo_ptr[o + 1]; ++i) {
-                int a = fo_arc[i];
-                float v = rat_in[a] - net_delay[a];
-                if (i == fo_ptr[o]) r = v;
-                else if (mode == 0) { if (v < r) r = v; }
-                else { if (v > r) r = v; }
-            }
-        }
-        rat_drv[o] = r;
-        slack_drv[o] = (mode == 0) ? (r - at_drv[o]) : (at_drv[o] - r);
-        if (t >= 0) {
-            int g = topo[t];
-            for (int a = gate_arc_ptr[g]; a < gate_arc_ptr[g + 1]; ++a) {
-                rat_in[a] = r - arc_delay[a];
-                slack_in[a] = (mode == 0) ? (rat_in[a] - at_in[a]) : (at_in[a] - rat_in[a]);
-            }
-        }
+    if (!par) {
+        for (int t = n_gates - 1; t >= -n_pi; --t)   /* t >= 0: gate topo[t]; t < 0: primary input -t-1 */
+            driver_backward(mode, n_pi, (t >= 0) ? n_pi + topo[t] : -t - 1, gate_arc_ptr, fo_ptr, fo_arc, ep_rank,
+                            net_delay, arc_delay, at_drv, at_in, ep_rat, rat_drv, rat_in, slack_drv, slack_in);
+        goto done;
+    }
+    rc = orc_level_buckets(D, level, &lv_ptr, &by_lv, &n_lv);
+    if (rc != ORC_OK) goto done;
+    for (int l = n_lv - 1; l >= 0; --l) {
+        const int i0 = lv_ptr[l], i1 = lv_ptr[l + 1];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+        for (int i = i0; i < i1; ++i)
+            driver_backward(mode, n_pi, by_lv[i], gate_arc_ptr, fo_ptr, fo_arc, ep_rank, net_delay, arc_delay, at_drv,
+                            at_in, ep_rat, rat_drv, rat_in, slack_drv, slack_in);
     }
 done:
-    free(level); free(topo); free(fo_ptr); free(fo_arc); free(ep_rank);
+    free(level); free(topo); free(fo_ptr); free(fo_arc); free(ep_rank); free(lv_ptr); free(by_lv);
     return rc;
+}
+
+int orc_slack(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr, const int32_t* arc_drv,
+              const float* net_delay, const float* arc_delay,
+              const float* at_drv, const float* at_in, const float* ep_rat,
+              float* rat_drv, float* rat_in, float* slack_drv, float* slack_in)
+{
+    return slack_impl(0, mode, n_pi, n_gates, gate_arc_ptr, arc_drv, net_delay, arc_delay, at_drv, at_in, ep_rat,
+                      rat_drv, rat_in, slack_drv, slack_in);
+}
+
+/* The same, level by level from the top with each level's drivers spread over the
+ * OpenMP threads. */
+int orc_slack_lv(int mode, int n_pi, int n_gates, const int32_t* gate_arc_ptr, const int32_t* arc_drv,
+                 const float* net_delay, const float* arc_delay,
+                 const float* at_drv, const float* at_in, const float* ep_rat,
+                 float* rat_drv, float* rat_in, float* slack_drv, float* slack_in)
+{
+    return slack_impl(1, mode, n_pi, n_gates, gate_arc_ptr, arc_drv, net_delay, arc_delay, at_drv, at_in, ep_rat,
+                      rat_drv, rat_in, slack_drv, slack_in);
 }
 
 /* ---- RC-tree nets on their own (learned-surrogate workload) ------------------ */
@@ -404,20 +627,6 @@ done:
 }
 
 /* ---- adjoint of TNS (FP64 reference) ------------------------------------------ */
-
-/* Driver-level CSR of the sink arcs (fanout) and the endpoint flags. */
-static int orc_fanout(int D, int A, const int32_t* arc_drv, int32_t** fo_ptr_out, int32_t** fo_arc_out)
-{
-    int32_t* fo_ptr = (int32_t*)calloc((size_t)D + 2, sizeof(int32_t));
-    int32_t* fo_arc = (int32_t*)malloc(((size_t)A + 1) * sizeof(int32_t));
-    if (!fo_ptr || !fo_arc) { free(fo_ptr); free(fo_arc); return ORC_E_ARG; }
-    for (int a = 0; a < A; ++a) fo_ptr[arc_drv[a] + 2]++;
-    for (int d = 0; d < D; ++d) fo_ptr[d + 2] += fo_ptr[d + 1];
-    for (int a = 0; a < A; ++a) fo_arc[fo_ptr[arc_drv[a] + 1]++] = a;
-    *fo_ptr_out = fo_ptr;
-    *fo_arc_out = fo_arc;
-    return ORC_OK;
-}
 
 /* Chain rule of TNS = sum over endpoints of min(0, slack) through the forward maxima
  * (minima for early), with the arguments of the maxima fixed: d TNS / d AT(endpoint) is

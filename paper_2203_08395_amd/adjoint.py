@@ -23,22 +23,36 @@ class TimedDesign:
         self.tm = sta.alloc_timing(g, views.n_views)
         self.sl = sta.alloc_slack(g, views.n_views)
         self.adj = sta.alloc_adjoint(g, views.n_views)
+        self.run = 0          # forward passes made on these buffers
+
+    def evaluate(self, net_delay, load) -> int:
+        """Fills the buffers for (net_delay, load): propagation and slack; returns the
+        pass number the buffers now hold."""
+        self.nd["net_delay"].copy_(net_delay)
+        self.nd["load"].copy_(load)
+        sta.arc_load(self.g, self.nd)
+        sta.propagate(self.g, self.lib, self.views, self.pi_ts, self.nd, out=self.tm)
+        sta.slack(self.g, self.views, self.nd, self.tm, self.ep_rat, out=self.sl)
+        self.run += 1
+        return self.run
 
 
 class TNS(torch.autograd.Function):
     @staticmethod
     def forward(ctx, net_delay, load, td: TimedDesign):
-        td.nd["net_delay"].copy_(net_delay)
-        td.nd["load"].copy_(load)
-        sta.arc_load(td.g, td.nd)
-        sta.propagate(td.g, td.lib, td.views, td.pi_ts, td.nd, out=td.tm)
-        sta.slack(td.g, td.views, td.nd, td.tm, td.ep_rat, out=td.sl)
+        ctx.run = td.evaluate(net_delay, load)
         ctx.td = td
+        ctx.save_for_backward(net_delay, load)
         return td.sl["tns"].clone()
 
     @staticmethod
     def backward(ctx, grad_tns):
         td = ctx.td
+        if td.run != ctx.run:
+            # the design's buffers were overwritten by a later forward pass: restore this
+            # pass's argmax and slack state from its own inputs before the adjoint
+            net_delay, load = ctx.saved_tensors
+            ctx.run = td.evaluate(net_delay, load)
         adj = sta.tns_adjoint(td.g, td.lib, td.views, td.nd, td.tm, td.sl, out=td.adj)
         w = grad_tns.to(torch.float32)
         A = td.g.sizes["n_arcs"]

@@ -990,16 +990,18 @@ sta_status sta_graph_upload(sta_graph* g, void* dev_buf, size_t bytes, void* str
     if (e != hipSuccess) return sta::fail(STA_E_HIP, std::string("sta_graph_upload: hipMemcpyAsync: ") + hipGetErrorString(e));
     e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return sta::fail(STA_E_HIP, std::string("sta_graph_upload: hipStreamSynchronize: ") + hipGetErrorString(e));
+    // sequences captured against the previous buffer are dropped (their keys name it too)
+    {
+        std::lock_guard<std::mutex> lock(g->cache_mu);
+        for (sta::LaunchCache* c : {&g->fwd_cache, &g->bwd_cache, &g->adj_cache}) sta::drop_launches(*c);
+    }
     g->dev = static_cast<uint8_t*>(dev_buf);
     return STA_OK;
 }
 
 void sta_graph_free(sta_graph* g) {
     if (!g) return;
-    for (sta::LaunchCache* c : {&g->fwd_cache, &g->bwd_cache, &g->adj_cache}) {
-        if (c->exec) (void)hipGraphExecDestroy(c->exec);
-        if (c->graph) (void)hipGraphDestroy(c->graph);
-    }
+    for (sta::LaunchCache* c : {&g->fwd_cache, &g->bwd_cache, &g->adj_cache}) sta::drop_launches(*c);
     delete g;
 }
 

@@ -116,12 +116,26 @@ struct BatchItem {
     uint8_t* argmax;
 };
 
-// A captured launch sequence (hipGraph) reused while its arguments stay the same.
-struct LaunchCache {
+// Captured launch sequences (hipGraphs) of one call kind, each reused while its arguments
+// (the key: every device pointer the launches bake in, the graph's own device buffer
+// included, and every launch parameter) stay the same.  A few argument sets are kept,
+// least recently used evicted, so that callers alternating between output sets (one per
+// stream) replay instead of re-capturing on every call.  An exec is destroyed only after
+// the device has drained, since it may still run on some stream.
+constexpr int kLaunchCacheEntries = 4;
+struct LaunchEntry {
     std::vector<uint64_t> key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
 };
+struct LaunchCache {
+    std::vector<LaunchEntry> e;
+    uint64_t tick = 0;
+};
+// Waits for the device (hipDeviceSynchronize) if anything is cached, then destroys every
+// captured sequence of c.
+void drop_launches(LaunchCache& c);
 
 }  // namespace sta
 

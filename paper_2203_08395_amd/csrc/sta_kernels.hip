@@ -1813,7 +1813,18 @@ static KTiles ktiles(const std::vector<int32_t>& first, const std::vector<int32_
 }
 
 // Runs enqueue(stream) directly, or replays it from the cached hipGraph of this call
-// kind (capturing it first when the key differs).  Profiling always runs it directly.
+// kind and key (capturing it first when no cached entry has the key; the least recently
+// used entry makes room, after the device has drained).  Profiling always runs it directly.
+void drop_launches(LaunchCache& c) {
+    if (c.e.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (LaunchEntry& x : c.e) {
+        if (x.exec) (void)hipGraphExecDestroy(x.exec);
+        if (x.graph) (void)hipGraphDestroy(x.graph);
+    }
+    c.e.clear();
+}
+
 template <typename F>
 static sta_status capture_replay(LaunchCache& c, std::mutex& mu, bool use_graphs, std::vector<uint64_t> key,
                                  hipStream_t s, F&& enqueue) {
@@ -1822,10 +1833,10 @@ static sta_status capture_replay(LaunchCache& c, std::mutex& mu, bool use_graphs
         return STA_OK;
     }
     std::lock_guard<std::mutex> lock(mu);
-    if (!c.exec || c.key != key) {
-        if (c.exec) { (void)hipGraphExecDestroy(c.exec); c.exec = nullptr; }
-        if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
-        c.key.clear();
+    LaunchEntry* hit = nullptr;
+    for (LaunchEntry& x : c.e)
+        if (x.key == key) hit = &x;
+    if (!hit) {
         hipStream_t cap = nullptr;
         hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
         if (e != hipSuccess) return fail(STA_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
@@ -1845,11 +1856,21 @@ static sta_status capture_replay(LaunchCache& c, std::mutex& mu, bool use_graphs
             (void)hipGraphDestroy(gr);
             return fail(STA_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
         }
-        c.graph = gr;
-        c.exec = ex;
-        c.key = std::move(key);
+        if (int(c.e.size()) >= kLaunchCacheEntries) {
+            size_t lru = 0;
+            for (size_t i = 1; i < c.e.size(); ++i)
+                if (c.e[i].used < c.e[lru].used) lru = i;
+            // the evicted exec may still be running on another stream
+            (void)hipDeviceSynchronize();
+            (void)hipGraphExecDestroy(c.e[lru].exec);
+            (void)hipGraphDestroy(c.e[lru].graph);
+            c.e.erase(c.e.begin() + std::ptrdiff_t(lru));
+        }
+        c.e.push_back(LaunchEntry{std::move(key), gr, ex, 0});
+        hit = &c.e.back();
     }
-    hipError_t e = hipGraphLaunch(c.exec, s);
+    hit->used = ++c.tick;
+    hipError_t e = hipGraphLaunch(hit->exec, s);
     if (e != hipSuccess) return fail(STA_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
     return STA_OK;
 }
@@ -1911,7 +1932,7 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
 template <int NV>
 static sta_status run_forward_levels(const sta_graph* g, const KLib& lib, const KViews& kv, const float* pi_ts,
                                      const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
-    std::vector<uint64_t> key = {uint64_t(NV), pk(lib.tables), uint64_t(lib.n_tables), pk(pi_ts), pk(nd->arc_load),
+    std::vector<uint64_t> key = {pk(g->dev), uint64_t(NV), pk(lib.tables), uint64_t(lib.n_tables), pk(pi_ts), pk(nd->arc_load),
                                  pk(nd->net_delay), pk(nd->net_imp2), pk(o->drv_ts), pk(o->arc_ts), pk(o->arc_delay),
                                  pk(o->argmax), uint64_t(g->use_spans)};
     for (int i = 0; i < 26; ++i) { uint32_t b; std::memcpy(&b, &lib.ax[i], 4); key.push_back(b); }
@@ -1990,7 +2011,7 @@ template <int NV>
 static sta_status run_backward_levels(const sta_graph* g, const KViews& kv, const sta_net_out* nd,
                                       const sta_timing_out* t, const float* ep_rat, const sta_slack_out* o,
                                       void* scratch, hipStream_t s) {
-    std::vector<uint64_t> key = {uint64_t(NV), pk(nd->net_delay), pk(t->drv_ts), pk(t->arc_ts), pk(t->arc_delay),
+    std::vector<uint64_t> key = {pk(g->dev), uint64_t(NV), pk(nd->net_delay), pk(t->drv_ts), pk(t->arc_ts), pk(t->arc_delay),
                                  pk(ep_rat), pk(o->drv_rat), pk(o->arc_rat), pk(o->drv_slack), pk(o->arc_slack),
                                  pk(o->tns), pk(o->wns), pk(scratch), uint64_t(g->use_spans)};
     for (int v = 0; v < NV; ++v) key.push_back(uint64_t(kv.mode[v]));
@@ -2431,7 +2452,7 @@ template <int NV>
 static sta_status run_adjoint_levels(const sta_graph* g, const KLib& kl, const KViews& kv, const sta_net_out* nd,
                                      const sta_timing_out* t, const sta_slack_out* sl, const sta_adjoint_out* o,
                                      hipStream_t s) {
-    std::vector<uint64_t> key = {uint64_t(NV), pk(nd->arc_load), pk(t->arc_ts), pk(t->argmax), pk(sl->drv_slack),
+    std::vector<uint64_t> key = {pk(g->dev), uint64_t(NV), pk(nd->arc_load), pk(t->arc_ts), pk(t->argmax), pk(sl->drv_slack),
                                  pk(o->g_drv_at), pk(o->g_arc_delay), pk(o->g_net_delay), pk(o->g_load),
                                  pk(kl.tables), uint64_t(kl.n_tables), uint64_t(g->use_spans)};
     for (int i = 0; i < 26; ++i) { uint32_t b; std::memcpy(&b, &kl.ax[i], 4); key.push_back(b); }
@@ -2845,8 +2866,7 @@ sta_status sta_batch_info(const sta_batch* b, int32_t* persistent_units, int32_t
 
 void sta_batch_free(sta_batch* b) {
     if (!b) return;
-    if (b->cache.exec) (void)hipGraphExecDestroy(b->cache.exec);
-    if (b->cache.graph) (void)hipGraphDestroy(b->cache.graph);
+    drop_launches(b->cache);
     delete b;
 }
 

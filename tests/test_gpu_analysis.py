@@ -157,6 +157,35 @@ def test_autograd_tns_gradients():
     np.testing.assert_array_equal(g.arc_to_input(nd.grad.cpu().numpy()), g1.astype(np.float32))
 
 
+def test_autograd_tns_two_forwards_then_backward():
+    """Two forward evaluations at different net delays, then backward of the first only:
+    the gradients are those of the first point (the shared buffers hold the second)."""
+    import torch
+    from paper_2203_08395_amd import adjoint
+    d, lib, pa, ps, late, early, modes = _setup(seed=47, n_pins=12000, n_levels=50)
+    say(f"[gpu case] autograd TNS, two forwards: pins={d.n_pins}")
+    r = _gpu(d, lib, pa, ps, late, early, modes)
+    g = r["g"]
+    td = adjoint.TimedDesign(g, r["L"], r["views"], r["pi"], r["rat"], r["nd"]["net_imp2"])
+    A, D = d.n_arcs, d.n_drivers
+    base_nd = r["nd"]["net_delay"][:A].clone()
+    ld = r["nd"]["load"][:D].clone()
+    x1 = base_nd.clone().requires_grad_(True)
+    # the second point: every net delay 25 ps later, which moves slacks and argmaxes
+    x2 = (base_nd + 25.0).requires_grad_(True)
+    t1 = adjoint.tns(x1, ld, td)
+    t2 = adjoint.tns(x2, ld, td)
+    t1.sum().backward()
+    res = _oracle(d, lib, pa, ps, late, early)
+    assert float(t1[0]) == res["late"]["tns"] and float(t1[1]) == res["early"]["tns"]
+    want = sum(oracle.tns_adjoint(d, res[k], m)[1] for k, m in (("late", LATE), ("early", EARLY)))
+    np.testing.assert_array_equal(g.arc_to_input(x1.grad.cpu().numpy()), want.astype(np.float32))
+    assert x2.grad is None
+    # the second point's gradient is its own (not the first's)
+    t2.sum().backward()
+    assert not torch.equal(x2.grad, x1.grad)
+
+
 @pytest.mark.parametrize("cfg", ["c1", "c2"])
 def test_critical_paths_match_oracle(cfg):
     import torch

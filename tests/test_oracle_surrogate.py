@@ -218,3 +218,55 @@ def test_error_buckets_are_monotone_and_exact_on_edges():
         lo = np.float32(oracle.bucket_bound(kk + 1))
         assert oracle.error_bucket(np.array([lo], np.float32))[0] == kk
         assert oracle.error_bucket(np.array([np.nextafter(lo, np.float32(0))], np.float32))[0] == kk + 1 or kk == 126
+
+
+def test_norm_stats_hand_values():
+    """Hand-computed statistics of log(1 + f): a constant feature (std 0 -> rstd 1), a
+    two-valued feature whose population std is 1/2 (the sample std would be larger), and
+    features whose logs are equally spaced."""
+    n = 6
+    feat = np.zeros((n, 12))
+    feat[:, 0] = 3.0                                   # log 4 everywhere: mean log 4, rstd 1
+    feat[:, 1] = [0.0, np.e - 1.0] * 3                 # logs 0, 1: mean 1/2, population std 1/2
+    feat[:, 2] = [0.0, 1.0, 3.0, 7.0, 0.0, 1.0]        # logs (0, 1, 2, 3, 0, 1) * log 2
+    feat[:, 3] = 0.0                                   # log 0 + 1 = 0: mean 0, rstd 1
+    mu, rstd = oracle.norm_stats(feat)
+    assert mu[0] == pytest.approx(np.log(4.0), rel=1e-15) and rstd[0] == 1.0
+    assert mu[1] == pytest.approx(0.5, rel=1e-15) and rstd[1] == pytest.approx(2.0, rel=1e-14)
+    # logs 0,1,2,3,0,1 (x log 2): mean 7/6, E[k^2] = 15/6, variance 15/6 - 49/36 = 41/36
+    assert mu[2] == pytest.approx(7.0 / 6.0 * np.log(2.0), rel=1e-14)
+    assert rstd[2] == pytest.approx(1.0 / (np.log(2.0) * np.sqrt(41.0 / 36.0)), rel=1e-14)
+    assert mu[3] == 0.0 and rstd[3] == 1.0
+
+
+def test_mlp_input_hand_values():
+    """x = (log(1 + f) - mu) * rstd on the 12 features, zero in the 4 pad columns: a zero
+    feature gives the finite value -mu * rstd (log f would give -inf)."""
+    feat = np.zeros((2, 12))
+    feat[0, 0] = np.e - 1.0        # log(1 + f) = 1
+    feat[1, 5] = 3.0               # log 4
+    mu = np.full(12, 0.25)
+    rstd = np.full(12, 4.0)
+    x = oracle.mlp_input(feat, mu, rstd)
+    assert x.shape == (2, 16)
+    assert x[0, 0] == pytest.approx(3.0, rel=1e-15)                      # (1 - 1/4) * 4
+    assert x[0, 1] == -1.0 and x[1, 0] == -1.0                            # zero feature: -mu * rstd
+    assert x[1, 5] == pytest.approx((np.log(4.0) - 0.25) * 4.0, rel=1e-15)
+    assert np.all(x[:, 12:] == 0.0)
+    assert np.all(np.isfinite(x))
+
+
+def test_error_bin_hand_values():
+    """Bins of (depth, nodes) pairs written out by hand from the rule: depth class
+    clamp(depth, 1, 8) - 1 (so 7 and 8 differ, 8 and 9 share), size class (M - 1) // 8
+    clamped to 0..7 (so M = 8 | 9 and M = 64 | 65 straddle or share the edges)."""
+    cases = [  # (depth, M, bin)
+        (1, 2, 0), (1, 8, 0), (1, 9, 1), (1, 64, 7), (1, 65, 7), (1, 200, 7),
+        (0, 5, 0),                                          # depth below 1 joins class 1
+        (2, 17, 8 + 2), (7, 8, 48), (7, 9, 49), (8, 8, 56), (8, 9, 57), (8, 64, 63),
+        (9, 65, 63), (30, 33, 56 + 4), (3, 1, 16),
+    ]
+    feat = np.zeros((len(cases), 12))
+    feat[:, 3] = [c[0] for c in cases]
+    feat[:, 4] = [c[1] for c in cases]
+    assert list(oracle.error_bin(feat)) == [c[2] for c in cases]
