@@ -3,7 +3,7 @@
  *
  * Background.  Heteroflow's timing workload analyses one design under many timing views
  * (a view is a process corner combined with an analysis mode, Section IV-A), and its
- * runtime balances uneven tasks by work stealing (Section III-D) and reruns a task graph
+ * runtime balances uneven tasks by work stealing (Section III-C) and reruns a task graph
  * many times (Executor::run_n).  Here a batch is a set of uploaded graphs of uneven size
  * that share one NLDM library and one set of views (for instance four corners as four
  * table sets).  sta_batch_propagate runs the forward pass of every (graph, view) unit:
