@@ -231,6 +231,23 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
                      const sta_timing_out* t, const float* ep_rat, const sta_slack_out* out,
                      void* scratch, size_t scratch_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).
+ * sta_slack without the scratch argument: the endpoint partials go to a static device
+ * array of the library (192 KiB, one per device, held until the process ends; its
+ * address is looked up on the first call on each device).  Results are those of
+ * sta_slack bit for bit.  The launches are made directly on the stream (no launch-
+ * sequence capture and replay); no device memory is allocated or freed.  The scratch
+ * sta_slack needs has a fixed size (scratch_bytes, independent of the design), checked
+ * against the static array's size: a larger need is refused with STA_E_ARG.  All calls
+ * on one device share the array: calls that overlap on one device (two streams, or two
+ * host threads) race on it and give undefined TNS/WNS; serialize them.  Its contents on
+ * entry are ignored (every partial is written before it is read).  Errors: those of
+ * sta_slack, and STA_E_HIP if the array's address cannot be obtained. */
+sta_status sta_slack_noalloc(const sta_graph* g, const sta_views* views, const sta_net_out* nd,
+                             const sta_timing_out* t, const float* ep_rat, const sta_slack_out* out,
+                             void* stream);
+
 /* Passage: Section III-B (a task graph run many times, run_n: here the captured launch
  * sequence replayed as a hipGraph).
  * Schedule of sta_propagate and sta_slack on graph g.  The view schedule (one workgroup

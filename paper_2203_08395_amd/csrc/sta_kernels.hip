@@ -452,9 +452,18 @@ constexpr int kK4Blocks = 256;
 constexpr int kK4Threads = 256;
 static_assert(kK4Blocks <= 256, "k_endpoint_final's 256 threads read one partial block each");
 
-size_t scratch_bytes() {
-    return size_t(kK4Blocks) * STA_MAX_VIEWS * kLimbs * 8 + size_t(kK4Blocks) * STA_MAX_VIEWS * 4;
-}
+constexpr size_t kSlackScratchBytes =
+    size_t(kK4Blocks) * STA_MAX_VIEWS * kLimbs * 8 + size_t(kK4Blocks) * STA_MAX_VIEWS * 4;
+
+size_t scratch_bytes() { return kSlackScratchBytes; }
+
+// The endpoint summary's per-block partials for sta_slack_noalloc: one copy of this array
+// per device (the code object's global), held until the process ends, shared by every
+// sta_slack_noalloc call on that device.  Host code never uses its name as an address:
+// the device address comes from hipGetSymbolAddress (slack_scratch_ptr below).
+constexpr size_t kNoAllocScratchBytes = 192 * 1024;
+static_assert(kSlackScratchBytes <= kNoAllocScratchBytes, "the endpoint partials must fit the static scratch");
+static __device__ __align__(256) unsigned char slack_scratch[kNoAllocScratchBytes];
 
 __device__ __forceinline__ void add_neg_slack(unsigned long long (&l)[kLimbs], float s) {
     if (!(s < 0.0f)) return;
@@ -2615,6 +2624,61 @@ sta_status sta_slack(const sta_graph* g, const sta_views* views, const sta_net_o
         if (st != STA_OK) return st;
     }
     return launch_check("sta_slack");
+}
+
+// Device address of slack_scratch on the current device, looked up once per device (with
+// that device current) and kept; later calls read the kept address.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static sta_status slack_scratch_ptr(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(STA_E_HIP, std::string("sta_slack_noalloc: hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(STA_E_ARG, "sta_slack_noalloc: device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(slack_scratch));
+        if (e != hipSuccess || !p)
+            return fail(STA_E_HIP, std::string("sta_slack_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return STA_OK;
+}
+
+sta_status sta_slack_noalloc(const sta_graph* g, const sta_views* views, const sta_net_out* nd,
+                             const sta_timing_out* t, const float* ep_rat, const sta_slack_out* out, void* stream) {
+    if (!g || !nd || !t || !out) return fail(STA_E_ARG, "sta_slack_noalloc: null argument");
+    if (!g->dev) return fail(STA_E_ARG, "sta_slack_noalloc: graph not uploaded");
+    std::string why;
+    if (!views_ok(views, -1, why)) return fail(STA_E_ARG, "sta_slack_noalloc: " + why);
+    if (scratch_bytes() > kNoAllocScratchBytes)
+        return fail(STA_E_ARG, "sta_slack_noalloc: the endpoint partials exceed the static scratch");
+    if (!out->tns || !out->wns) return fail(STA_E_ARG, "sta_slack_noalloc: null tns/wns");
+    if (g->D > 0 && (!out->drv_rat || !out->drv_slack || !t->drv_ts || (g->E > 0 && !ep_rat) ||
+                     (g->A > 0 && (!out->arc_rat || !out->arc_slack || !t->arc_ts || !t->arc_delay || !nd->net_delay))))
+        return fail(STA_E_ARG, "sta_slack_noalloc: null buffer");
+    void* scr = nullptr;
+    sta_status st = slack_scratch_ptr(&scr);
+    if (st != STA_OK) return st;
+    const KViews kv = kviews(views);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    size_t lds = 0;
+    // the same schedule choice as sta_slack, launched directly (no launch-sequence capture)
+    if (use_view_backward(g, views->n_views, &lds)) {
+        run_backward_views(g, lds, views->n_views, kv, nd, t, ep_rat, out, s);
+    } else {
+        switch (views->n_views) {
+            case 1: enqueue_backward_levels<1>(g, kv, nd, t, ep_rat, out, scr, s); break;
+            case 2: enqueue_backward_levels<2>(g, kv, nd, t, ep_rat, out, scr, s); break;
+            case 4: enqueue_backward_levels<4>(g, kv, nd, t, ep_rat, out, scr, s); break;
+            default: enqueue_backward_levels<8>(g, kv, nd, t, ep_rat, out, scr, s); break;
+        }
+    }
+    return launch_check("sta_slack_noalloc");
 }
 
 sta_status sta_profile_begin(void) {

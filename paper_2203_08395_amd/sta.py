@@ -77,7 +77,7 @@ class SlackOut(ctypes.Structure):
 _lib = None
 
 EXPORTS = ("sta_last_error", "sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload",
-           "sta_graph_free", "sta_delay_calc", "sta_propagate", "sta_slack", "sta_set_schedule", "sta_set_level_fusion",
+           "sta_graph_free", "sta_delay_calc", "sta_propagate", "sta_slack", "sta_slack_noalloc", "sta_set_schedule", "sta_set_level_fusion",
            "sta_graph_spans", "sta_graph_span_list", "sta_profile_begin", "sta_profile_end")
 
 
@@ -109,6 +109,8 @@ def load_library():
                                   ctypes.POINTER(NetOut), ctypes.POINTER(TimingOut), _P]
     lib.sta_slack.argtypes = [_P, ctypes.POINTER(ViewsC), ctypes.POINTER(NetOut), ctypes.POINTER(TimingOut), _P,
                               ctypes.POINTER(SlackOut), _P, ctypes.c_size_t, _P]
+    lib.sta_slack_noalloc.argtypes = [_P, ctypes.POINTER(ViewsC), ctypes.POINTER(NetOut), ctypes.POINTER(TimingOut),
+                                      _P, ctypes.POINTER(SlackOut), _P]
     lib.sta_set_schedule.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
     lib.sta_set_level_fusion.argtypes = [_P, ctypes.c_int32]
     lib.sta_graph_spans.argtypes = [_P, ctypes.POINTER(SpanInfo)]
@@ -116,7 +118,8 @@ def load_library():
     lib.sta_profile_begin.argtypes = []
     lib.sta_profile_end.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     for f in ("sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload", "sta_delay_calc",
-              "sta_propagate", "sta_slack", "sta_set_schedule", "sta_set_level_fusion", "sta_graph_spans",
+              "sta_propagate", "sta_slack", "sta_slack_noalloc", "sta_set_schedule", "sta_set_level_fusion",
+              "sta_graph_spans",
               "sta_graph_span_list", "sta_profile_begin", "sta_profile_end"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
@@ -338,6 +341,21 @@ def slack(g: Graph, views: ViewsC, nd, timing, ep_rat, out=None):
     _check(load_library().sta_slack(g.handle, ctypes.byref(views), ctypes.byref(no), ctypes.byref(to),
                                     _ptr(ep_rat), ctypes.byref(so), _ptr(out["scratch"]),
                                     out["scratch"].numel(), _stream(torch, g.device)), "sta_slack")
+    return out
+
+
+def slack_noalloc(g: Graph, views: ViewsC, nd, timing, ep_rat, out):
+    """sta_slack_noalloc: sta_slack with the library's static device scratch (no scratch
+    argument; the caller's outputs ``out`` must exist: this call allocates nothing)."""
+    import torch
+    to = TimingOut(_ptr(timing["drv_ts"]), _ptr(timing["arc_ts"]), _ptr(timing["arc_delay"]),
+                   _ptr(timing["argmax"]))
+    so = SlackOut(_ptr(out["drv_rat"]), _ptr(out["arc_rat"]), _ptr(out["drv_slack"]), _ptr(out["arc_slack"]),
+                  _ptr(out["tns"]), _ptr(out["wns"]))
+    no = _netout(nd)
+    _check(load_library().sta_slack_noalloc(g.handle, ctypes.byref(views), ctypes.byref(no), ctypes.byref(to),
+                                            _ptr(ep_rat), ctypes.byref(so), _stream(torch, g.device)),
+           "sta_slack_noalloc")
     return out
 
 
