@@ -139,9 +139,13 @@ def test_predict_matches_oracle(trees):
     err = np.abs(y - yo)
     scale = 1.0 + np.abs(yo)
     print(f"predict |dy|: median {np.median(err):.2e} p99.9 {np.quantile(err, 0.999):.2e} max {err.max():.2e}")
-    assert np.median(err) <= 1e-5
-    assert np.quantile(err / scale, 0.999) <= 5e-3
-    assert np.all(err <= 0.05 * scale)
+    # measured on MI355X: median 0, p99.9 1.9e-7, max 3.0e-3 (= 1.9e-3 relative to 1 + |y|,
+    # a hidden activation rounded to the other BF16 neighbour after FP32 vs FP64 sums);
+    # bounds about ten times those, every element
+    assert np.median(err) <= 1e-6
+    assert np.quantile(err, 0.999) <= 2e-6
+    assert np.mean(err > 1e-4) <= 1e-3
+    assert np.all(err <= 2e-2 * scale)
 
 
 @pytest.mark.parametrize("batch", [16, 1000, 9000])
@@ -163,9 +167,12 @@ def test_gradient_matches_oracle(trees, batch):
     go = mlp.grads(x, t, quant=True)
     gg = sur.Model.unpack(g[:sur.N_PARAMS])
     for k in go:
-        rel = np.linalg.norm(gg[k] - go[k]) / max(np.linalg.norm(go[k]), 1e-30)
-        print(f"batch {batch} {k}: rel err {rel:.2e}")
-        assert rel <= 2e-3, k
+        # element by element: measured |d| <= 3.6e-5 max|g| over all tensors and batches
+        # (FP32 sums on the GPU vs FP64 in the oracle, the same BF16 roundings on both)
+        d = np.abs(gg[k] - go[k])
+        bound = 1e-4 * np.abs(go[k]) + 1e-4 * np.abs(go[k]).max()
+        print(f"batch {batch} {k}: max |d| {d.max():.2e}, max |d|/bound {np.max(d / bound):.3f}")
+        assert np.all(d <= bound), k
     assert np.all(gg["W1"][:, 12:] == 0)
     assert g[sur.N_PARAMS] == pytest.approx(mlp.loss(x, t), rel=1e-4)
 
@@ -190,9 +197,10 @@ def test_adam_steps_match_oracle(trees):
             p[k], m[k], v[k] = oracle.adam(p[k], go[k], m[k], v[k], step, lr)
     got = sur.Model.unpack(model.params.cpu().numpy())
     for k in p:
+        # measured max |d| 9.2e-7 (W1), at most 1.7e-7 elsewhere; an update of the wrong sign
+        # would be off by about 2 lr = 2e-3
         d = np.abs(got[k] - p[k])
-        assert np.quantile(d, 0.99) <= 1e-5, k
-        assert d.max() <= 3 * 2 * lr, k
+        assert np.all(d <= 1e-5), (k, d.max())
     assert np.all(got["W1"][:, 12:] == 0)
 
 
@@ -231,17 +239,18 @@ def test_training_is_deterministic(trees):
 
 
 def test_surrogate_gain_over_bounds_and_exact_fallback():
-    """Trains on 80% of 40k nets, calibrates on 10%, tests on the last 10%.  Shows what the
-    network gains over the method without it: without the network the only estimate
-    short of the exact moments is the midpoint of the Elmore bounds (for the delay; there
-    is none for the slew).  Also checks that the fallback keeps every trusted sink within
-    the 1 ps tolerance and that fallback nets carry the exact values bit for bit."""
+    """Trains on the first 20% of 1M nets, calibrates on the next 20%, tests on the last
+    60% (enough held-out nets for thousands of trusted sinks).  Shows what the network
+    gains over the method without it: without the network the only estimate short of the
+    exact moments is the midpoint of the Elmore bounds (for the delay; there is none for
+    the slew).  Also checks that the fallback keeps the trusted sinks within the 1 ps
+    tolerance and that fallback nets carry the exact values bit for bit."""
     import torch
     from paper_2203_08395_amd import surrogate as sur
-    T = gen.make_rc_trees(40000, seed=4)
+    T = gen.make_rc_trees(1_000_000, seed=4)
     tr = sur.Trees(T)
     out = sur.dataset(tr)
-    n_tr, n_cal = int(0.8 * T.n_nets), int(0.9 * T.n_nets)
+    n_tr, n_cal = int(0.2 * T.n_nets), int(0.4 * T.n_nets)
     s_tr, s_cal = int(T.sink_ptr[n_tr]), int(T.sink_ptr[n_cal])
     norm = sur.norm_stats(out["feat"][:s_tr])
     model = sur.Model(sur.init_params(0), norm)
@@ -280,5 +289,6 @@ def test_surrogate_gain_over_bounds_and_exact_fallback():
           f"max |slew err| {err_s.max() if err_s.size else 0:.3f} ps")
     assert rms_net <= 0.5 * rms_mid
     assert np.mean(e_net <= 1) >= 3 * np.mean(e_mid <= 1)
-    assert cov_net > 0 and err_d.size > 0
-    assert np.mean(err_d <= 1.0) >= 0.995 and np.mean(err_s <= 1.0) >= 0.995
+    assert cov_net > 0 and err_d.size >= 2000
+    # the calibrated bound is a 99.9th-percentile bound per feature bin
+    assert np.mean(err_d <= 1.0) >= 0.999 and np.mean(err_s <= 1.0) >= 0.999
