@@ -623,11 +623,11 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
-// lane l takes lane l + OFF of its 16-lane row (DPP row shift; lanes past the row end keep
-// their own value, which the callers never take)
+// lane l takes lane l + OFF of its 16-lane row (DPP row shift; lanes past the row end read
+// 0, which the callers never take)
 template <int OFF>
 __device__ __forceinline__ int row_down(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x100 + OFF, 0xf, 0xf, false);
+    return __builtin_amdgcn_mov_dpp(v, 0x100 + OFF, 0xf, 0xf, true);
 }
 
 // one step of the segmented maximum with argmax (and maximum slew) inside 16-lane rows
@@ -641,12 +641,15 @@ __device__ __forceinline__ void span_max_step(float* cand, float* slw, int* best
         s2[w] = __int_as_float(row_down<OFF>(__float_as_int(slw[w])));
         k2[w] = row_down<OFF>(best_k[w]);
     }
+    // bitwise conjunctions (no short circuit), so that the step compiles to compares and
+    // selects under one mask instead of a branch on the segment test
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        const bool tc = take && c2[w] > cand[w];
+        const bool tc = take & (c2[w] > cand[w]);
+        const bool ts = take & (s2[w] > slw[w]);
         cand[w] = tc ? c2[w] : cand[w];
         best_k[w] = tc ? k2[w] : best_k[w];
-        slw[w] = (take && s2[w] > slw[w]) ? s2[w] : slw[w];
+        slw[w] = ts ? s2[w] : slw[w];
     }
 }
 
@@ -657,7 +660,7 @@ __device__ __forceinline__ void span_min_step(float* best, bool take) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) b2[v] = __int_as_float(row_down<OFF>(__float_as_int(best[v])));
 #pragma unroll
-    for (int v = 0; v < NV; ++v) best[v] = (take && b2[v] < best[v]) ? b2[v] : best[v];
+    for (int v = 0; v < NV; ++v) best[v] = (take & (b2[v] < best[v])) ? b2[v] : best[v];
 }
 template <int OFF, int NV>
 __device__ __forceinline__ void span_sum_step(float* acc, bool take) {
@@ -753,9 +756,11 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
 // then the arcs' static data and the arrivals of drivers outside the span), then the
 // levels in order, each reading its in-span inputs from LDS: one table round per level
 // instead of one launch and three rounds per level.
-// (Staging the tables in LDS per block was measured slower than the L2-resident reads.)
 // NV views stored, NW of them computed per wavefront: views v0 .. v0 + NW - 1 with
 // v0 = blockIdx.y * NW (so the views of a tile can run on different compute units).
+// (Copying the view's table set into each workgroup's LDS with direct-to-LDS loads, so that
+// the levels read table corners from LDS, was measured slower: the copy delays the tile's
+// own gathers by more than the levels save.)
 template <int NV, int NW>
 __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
                                                       const float* __restrict__ arc_load,
@@ -1923,12 +1928,11 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                 }
                 const int t0 = g->span_tile_h[sp], t1 = g->span_tile_h[sp + 1];
                 if (t1 <= t0) continue;
+                constexpr int NW = kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV;
+                const dim3 grid((t1 - t0 + kSpanWaves - 1) / kSpanWaves, NV / NW);
                 prof_launch("k_forward_span", s, [&] {
-                    hipLaunchKernelGGL((k_forward_span<NV, kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV>),
-                                       dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves,
-                                            NV / (kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV)),
-                                       dim3(64 * kSpanWaves), 0, s, dg, lib, kv,
-                                       t0, t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts,
+                    hipLaunchKernelGGL((k_forward_span<NV, NW>), grid, dim3(64 * kSpanWaves), 0, s, dg, lib, kv, t0,
+                                       t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts,
                                        o->arc_delay, o->argmax);
                 });
             }
