@@ -308,9 +308,11 @@ def _time_ms(fn, reps=5, warm=2):
 
 
 def batch_bench(dev, n_designs, reps=5):
-    """Uneven designs x 4 corners: looping the plain per-design propagation vs one batched
-    launch sequence (persistent launch for the designs the autotuner assigns to it, level
-    launches for the rest, replayed from a hipGraph)."""
+    """Uneven designs x 4 corners, the whole timing pass (RC delay calculation, forward
+    propagation, required times and slack): the single-design calls looped over the
+    designs vs the batch (span steps for the designs the autotuner plans there, the
+    persistent unit queue for the rest, every design built with its size class's tuned
+    span length), each replayed from captured launch sequences."""
     import torch
     from paper_2203_08395_amd import autotune, gen, sta
     specs = gen.c3_designs(n_designs)
@@ -319,58 +321,110 @@ def batch_bench(dev, n_designs, reps=5):
     V = len(gen.CORNER_KAPPAS)
     views = sta.make_views([sta.STA_LATE] * V, list(range(V)))
     t0 = time.perf_counter()
-    entries = []
-    pins = updates = 0
+    designs, loop_e = [], []
+    pins = updates = nbytes = 0
     for sp in specs:
         d = gen.make_design(**sp)
         g = sta.Graph(d, n_tables=lib.tab.shape[1]).upload(dev)
-        nd = sta.delay_calc(g)
         pa, ps = gen.make_pi(d)
         pi = np.zeros((max(d.n_pi, 1), V, 2), np.float32)
         pi[:d.n_pi, :, 0] = pa[:, None]
         pi[:d.n_pi, :, 1] = ps[:, None]
-        entries.append([g, torch.from_numpy(pi).to(dev), nd, sta.alloc_timing(g, V), sta.BATCH_PERSISTENT])
+        E = g.sizes["n_endpoints"]
+        nd, tm, sl = sta.alloc_net(g), sta.alloc_timing(g, V), sta.alloc_slack(g, V)
+        pi_t = torch.from_numpy(pi).to(dev)
+        # required time: the 90th percentile of the endpoint arrivals of each corner
+        sta.delay_calc(g, out=nd)
+        sta.propagate(g, L_lib, views, pi_t, nd, out=tm)
+        at_ep = tm["drv_ts"][torch.from_numpy(g.ep_driver.astype(np.int64)).to(dev), :, 0]
+        rat = torch.zeros((max(E, 1), V), dtype=torch.float32, device=dev)
+        if E:
+            rat[:E] = torch.quantile(at_ep, 0.9, dim=0)[None, :]
+        designs.append(d)
+        loop_e.append((g, pi_t, nd, tm, sl, rat))
         pins += d.n_pins
         updates += (d.n_pins - d.n_pi) * V
+        s = g.sizes
+        nbytes += dc_bytes(s["n_drivers"], s["n_arcs"], s["n_nodes"]) + \
+            fwd_bytes_per_pass(s["n_gates"], s["n_arcs"], V) + bwd_bytes_per_pass(s["n_drivers"], s["n_arcs"], V)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
 
     def loop():
-        for g, pi, nd, tm, _ in entries:
+        for g, pi, nd, tm, sl, rat in loop_e:
+            sta.delay_calc(g, out=nd)
             sta.propagate(g, L_lib, views, pi, nd, out=tm)
+            sta.slack(g, views, nd, tm, rat, out=sl)
 
     ms_loop = _time_ms(loop, reps=reps)
-    ref = [e[3]["drv_ts"].clone() for e in entries]
+    ref = [(e[3]["drv_ts"].clone(), e[3]["arc_ts"].clone(), e[4]["drv_slack"].clone(), e[4]["arc_slack"].clone(),
+            e[4]["tns"].clone(), e[4]["wns"].clone(), e[2]["net_delay"].clone()) for e in loop_e]
+    # autotuning: span length per size class, then the forward schedule per design
     tuner = autotune.Tuner()
     t0 = time.perf_counter()
-    unit, level = [], []
-    for g, pi, nd, tm, _ in entries:
-        u, l_ = tuner.timings(g, L_lib, views, pi, nd, tm)
-        unit.append(u)
-        level.append(l_)
+    recs = [tuner.tune(e[0], d, L_lib, views, e[1], e[5]) for d, e in zip(designs, loop_e)]
     n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
-    sched, est = autotune.Tuner.plan(unit, level, V, n_cu)
+    _, est = autotune.Tuner.plan([r["span_ms"] for r in recs], [r["unit_ms"] for r in recs], V, n_cu)
+    graphs = []
+    for d, e, r in zip(designs, loop_e, recs):
+        caps = tuple(r["spans"])
+        g = e[0] if caps == (8, 8) else sta.Graph(d, n_tables=lib.tab.shape[1], span_levels=caps).upload(dev)
+        graphs.append((g, e[1], sta.alloc_net(g), sta.alloc_timing(g, V), e[5], sta.alloc_slack(g, V)))
+    for g, pi, nd, *_ in graphs:
+        sta.delay_calc(g, out=nd)
+
+    def make_batch(sched_):
+        return sta.Batch([(x[0], x[1], x[2], x[3], sc, x[4], x[5]) for x, sc in zip(graphs, sched_)], L_lib, views)
+    classes = [autotune.size_class(e[0].sizes["n_pins"], e[0].sizes["n_levels"], V) for e in loop_e]
+    sched, fwd_nw, bwd_nw, plan_ms = tuner.pick_plan(classes, [r["unit_ms"] for r in recs], make_batch, V)
     t_tune = time.perf_counter() - t0
     try:
         tuner.save()
     except OSError:
         pass
-    for e, s_ in zip(entries, sched):
-        e[4] = s_
-    b = sta.Batch([tuple(e) for e in entries], L_lib, views)
-    ms_batch = _time_ms(lambda: b.propagate(use_graph=True), reps=reps)
-    same = all(torch.equal(r, e[3]["drv_ts"]) for r, e in zip(ref, entries))
+    entries = [(x[0], x[1], x[2], x[3], sc, x[4], x[5]) for x, sc in zip(graphs, sched)]
+    b = sta.Batch(entries, L_lib, views).set_tiling(fwd_nw, bwd_nw)
+
+    def batched():
+        b.delay_calc()
+        b.propagate()
+        b.slack()
+
+    ms_batch = _time_ms(batched, reps=reps)
+    ms_dc = _time_ms(b.delay_calc, reps=reps)
+    ms_fwd = _time_ms(b.propagate, reps=reps)
+    ms_bwd = _time_ms(b.slack, reps=reps)
+    same = all(torch.equal(r[0], e[3]["drv_ts"]) and torch.equal(r[1], e[3]["arc_ts"]) and
+               torch.equal(r[2], e[6]["drv_slack"]) and torch.equal(r[3], e[6]["arc_slack"]) and
+               torch.equal(r[4], e[6]["tns"]) and torch.equal(r[5], e[6]["wns"]) and
+               torch.equal(r[6], e[2]["net_delay"]) for r, e in zip(ref, entries))
     info = b.info()
+    # the previous batched design for reference: every design's forward pass as persistent
+    # units (each (design, corner) walked by one workgroup)
+    bp = sta.Batch([(e[0], e[1], e[2], e[3], sta.BATCH_PERSISTENT) for e in entries], L_lib, views)
+    ms_fwd_pers = _time_ms(bp.propagate, reps=reps)
+    caps_used = {}
+    for r in recs:
+        k = f"{r['spans'][0]}x{r['spans'][1]}"
+        caps_used[k] = caps_used.get(k, 0) + 1
+    achieved = nbytes / (ms_batch * 1e-3) / 1e9
     return {
         "workload": f"{len(specs)} seeded designs, pins log-uniform 5k-500k (sum {pins}), levels 30*sqrt(P/5k), "
-                    f"x {V} corners (tables scaled {list(gen.CORNER_KAPPAS)}), late, FP32",
+                    f"x {V} corners (tables scaled {list(gen.CORNER_KAPPAS)}), late; delay calc + propagate + "
+                    f"slack per step, FP32 timing, FP64 moments",
         "pins": pins, "pin_updates": updates,
         "loop_ms": ms_loop, "batched_ms": ms_batch, "speedup_vs_loop": ms_loop / ms_batch,
+        "batched_split_ms": {"delay_calc": ms_dc, "propagate": ms_fwd, "slack": ms_bwd},
+        "propagate_all_persistent_ms": ms_fwd_pers,
         "loop_pin_updates_per_s": updates / (ms_loop * 1e-3),
         "batched_pin_updates_per_s": updates / (ms_batch * 1e-3),
-        "persistent_units": info["persistent_units"], "level_designs": info["level_designs"],
-        "autotune": {"size_classes_measured": tuner.measured, "seconds": t_tune, "estimated_ms": est,
-                     "cache": tuner.path},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "bytes_per_step": nbytes},
+        "plan": info,
+        "autotune": {"measured": tuner.measured, "seconds": t_tune, "span_lengths": caps_used,
+                     "views_per_wavefront": {"forward": fwd_nw, "backward": bwd_nw},
+                     "candidates_ms": plan_ms,
+                     "latency_model_forward_ms": est, "cache": tuner.path},
         "bitwise_equal_to_loop": bool(same),
         "setup_s": t_setup,
     }

@@ -164,6 +164,14 @@ const char* sta_last_error(void);
  * STA_E_CYCLE, STA_E_NONFINITE, STA_E_ALLOC.  *out is set only on STA_OK. */
 sta_status sta_build_graph(const sta_design_desc* d, sta_graph** out);
 
+/* No passage: a tiling choice of this library (the level-tile size an autotuner may pick).
+ * sta_build_graph with the longest fused span capped at fwd_levels gate levels (forward)
+ * and bwd_levels driver levels (backward), each 1..8; sta_build_graph uses 8 and 8.
+ * Shorter spans mean more launches and smaller fan-in cones per tile; results do not
+ * change.  Errors: those of sta_build_graph, STA_E_ARG for a length outside 1..8. */
+sta_status sta_build_graph_spans(const sta_design_desc* d, int32_t fwd_levels, int32_t bwd_levels,
+                                 sta_graph** out);
+
 /* Sizes of a built graph (host, synchronous).  Errors: STA_E_ARG (null argument). */
 sta_status sta_graph_sizes(const sta_graph* g, sta_sizes* out);
 

@@ -84,7 +84,7 @@ static int32_t span_place(int32_t st, int32_t k) {
     return ch * 128 + p;
 }
 
-static sta_status build(const sta_design_desc* d, sta_graph* g) {
+static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, int32_t cap_b) {
     if (!d) return fail(STA_E_ARG, "sta_build_graph: null design");
     if (d->n_pi < 0 || d->n_gates < 0) return fail(STA_E_ARG, "sta_build_graph: negative n_pi or n_gates");
     if (d->n_tables < 1 || d->n_tables > STA_MAX_TABLES)
@@ -378,7 +378,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
 
     // ---- fused backward spans ------------------------------------------------------------
     // Spans of driver levels, processed top down: from the highest level not yet covered,
-    // the longest span [top - n + 1, top] (n <= kSpanB) that can be tiled is taken; a level
+    // the longest span [top - n + 1, top] (n <= cap_b <= kSpanB) that can be tiled is taken; a level
     // that cannot be tiled even alone runs as a level launch.  A tile is a set of drivers
     // closed under in-span sinks: the output driver of every gate a tile driver feeds, when
     // its level lies in the span, is in the tile too.  Roots are taken bottom level first;
@@ -531,7 +531,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
         };
         for (int32_t top = Lmax; top >= 0;) {
             const int32_t t0 = int32_t(bp_tile.size() / 4);
-            int32_t n = std::min<int32_t>(kSpanB, top + 1);
+            int32_t n = std::min<int32_t>(cap_b, top + 1);
             bool ok = try_span(top, top - n + 1);
             while (!ok && n > 1) {
                 --n;
@@ -547,7 +547,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
 
     // ---- fused forward spans -------------------------------------------------------------
     // Spans of gate levels, bottom up: from the lowest level not yet covered, the longest
-    // span [l0, l0 + n - 1] (n <= kSpanF) that can be tiled is taken; a level that cannot
+    // span [l0, l0 + n - 1] (n <= cap_f <= kSpanF) that can be tiled is taken; a level that cannot
     // be tiled even alone runs as a level launch.  A span tile computes, level by level
     // inside one wavefront, a set of gates closed under in-span fanin: every in-span driver
     // of a tile gate is itself in the tile (so it may be computed by several tiles,
@@ -691,7 +691,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g) {
         };
         for (int32_t l0 = 1; l0 <= Lmax;) {
             const int32_t t0 = int32_t(sp_tile.size() / 4);
-            int32_t n = std::min<int32_t>(kSpanF, Lmax - l0 + 1);
+            int32_t n = std::min<int32_t>(cap_f, Lmax - l0 + 1);
             bool ok = try_span(l0, l0 + n - 1);
             while (!ok && n > 1) {
                 --n;
@@ -909,11 +909,17 @@ extern "C" {
 const char* sta_last_error(void) { return sta::g_last_error.c_str(); }
 
 sta_status sta_build_graph(const sta_design_desc* d, sta_graph** out) {
+    return sta_build_graph_spans(d, sta::kSpanF, sta::kSpanB, out);
+}
+
+sta_status sta_build_graph_spans(const sta_design_desc* d, int32_t fwd_levels, int32_t bwd_levels, sta_graph** out) {
     if (!out) return sta::fail(STA_E_ARG, "sta_build_graph: null out");
+    if (fwd_levels < 1 || fwd_levels > sta::kSpanF || bwd_levels < 1 || bwd_levels > sta::kSpanB)
+        return sta::fail(STA_E_ARG, "sta_build_graph_spans: span lengths must be 1..8");
     sta_graph* g = nullptr;
     try {
         g = new sta_graph();
-        sta_status st = sta::build(d, g);
+        sta_status st = sta::build(d, g, fwd_levels, bwd_levels);
         if (st != STA_OK) { delete g; return st; }
     } catch (const std::bad_alloc&) {
         delete g;

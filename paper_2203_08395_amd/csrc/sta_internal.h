@@ -102,7 +102,8 @@ struct DevGraph {
     int32_t n_pi, n_gates, n_drivers, n_arcs;
 };
 
-// One graph of a batched launch: its device layout, chunk count, view count and buffers.
+// One graph of a batched launch: its device layout, chunk count, view count and buffers
+// (the slack buffers are null for a batch without a slack pass).
 struct BatchItem {
     DevGraph G;
     int32_t NC, NV;
@@ -114,6 +115,22 @@ struct BatchItem {
     float* arc_ts;
     float* arc_delay;
     uint8_t* argmax;
+    // delay calculation outputs written by the batched delay calculation
+    float* load_w;
+    float* nd_w;
+    float* ni_w;
+    float* arc_load;
+    // backward pass
+    const float* ep_rat;
+    float* drv_rat;
+    float* arc_rat;
+    float* drv_slack;
+    float* arc_slack;
+    double* tns;
+    float* wns;
+    int32_t E;
+    int32_t ep_blocks;      // endpoint-summary workgroups of this graph
+    int32_t ep_part0;       // its first partial in the batch's endpoint scratch
 };
 
 // Captured launch sequences (hipGraphs) of one call kind, each reused while its arguments

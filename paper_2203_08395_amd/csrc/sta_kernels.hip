@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <memory>
 #include <cmath>
 #include <cstdint>
@@ -185,6 +186,23 @@ __global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict
     if (d >= G.n_drivers) return;
     if constexpr (MAXN == 8) dc_net8<T, NT>(G, d, t, sA, sB, sM, load, net_delay, net_imp2, arc_load);
     else dc_net<T, MAXN, NT>(G, d, t, sA, sB, sM, load, net_delay, net_imp2, arc_load);
+}
+
+// Batched delay calculation: workgroup x takes nets map[map0 + x].y * NT + t of design
+// map[map0 + x].x (the designs of one node-count class in one launch).
+template <typename T, int MAXN, int NT>
+__global__ __launch_bounds__(NT) void k_delay_calc_batch(const BatchItem* __restrict__ items,
+                                                         const int2* __restrict__ map, int map0) {
+    __shared__ T sA[MAXN * NT];
+    __shared__ T sB[MAXN * NT];
+    __shared__ T sM[MAXN * NT];
+    const int2 m = map[map0 + int(blockIdx.x)];
+    const BatchItem& it = items[m.x];
+    const int t = threadIdx.x;
+    const int d = m.y * NT + t;
+    if (d >= it.G.n_drivers) return;
+    if constexpr (MAXN == 8) dc_net8<T, NT>(it.G, d, t, sA, sB, sM, it.load_w, it.nd_w, it.ni_w, it.arc_load);
+    else dc_net<T, MAXN, NT>(it.G, d, t, sA, sB, sM, it.load_w, it.nd_w, it.ni_w, it.arc_load);
 }
 
 // ---------------------------------------------------------------------------------
@@ -761,21 +779,19 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
 // (Copying the view's table set into each workgroup's LDS with direct-to-LDS loads, so that
 // the levels read table corners from LDS, was measured slower: the copy delays the tile's
 // own gathers by more than the levels save.)
+// The body of one forward span tile t of graph G, views v0 .. v0 + NW - 1 (tc: t clamped
+// into the launch's tiles, for the unconditional record loads; a wavefront with !valid
+// returns after them).  res: the wavefront's LDS results, kSpanSlotsF * NW values.
 template <int NV, int NW>
-__global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
-                                                      const float* __restrict__ arc_load,
-                                                      const float* __restrict__ nd, const float* __restrict__ ni,
-                                                      float* __restrict__ drv_ts, float* __restrict__ arc_ts,
-                                                      float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
-    __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NW];
-    const int v0 = int(blockIdx.y) * NW;
+__device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib, const KViews& V, int t, int tc,
+                                              bool valid, int v0, const float* __restrict__ arc_load,
+                                              const float* __restrict__ nd, const float* __restrict__ ni,
+                                              float* __restrict__ drv_ts, float* __restrict__ arc_ts,
+                                              float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
+                                              float2* res) {
     // the table axes in wave-uniform registers
     const Axis6 ax_x = axis6(lib, 0, 14), ax_y = axis6(lib, 7, 20);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = tile0 + blockIdx.x * kSpanWaves + wave;
-    const int tc = t < tile1 ? t : tile1 - 1;
     const int lane = threadIdx.x & 63;
-    float2* res = s_res[wave];
     const float* tab[NW];
     bool early[NW];
 #pragma unroll
@@ -801,7 +817,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         gt[c] = r.z;
         meta[c] = uint32_t(r.w);
     }
-    if (t >= tile1) return;
+    if (!valid) return;
     // round 2: the arcs' net data and the arrivals of drivers outside the span
     float ndv[kSpanF], niv[kSpanF], lov[kSpanF];
     float2 ext[kSpanF][NW];
@@ -864,10 +880,45 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     });
 }
 
+template <int NV, int NW>
+__global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
+                                                      const float* __restrict__ arc_load,
+                                                      const float* __restrict__ nd, const float* __restrict__ ni,
+                                                      float* __restrict__ drv_ts, float* __restrict__ arc_ts,
+                                                      float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
+    __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NW];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = tile0 + blockIdx.x * kSpanWaves + wave;
+    const int tc = t < tile1 ? t : tile1 - 1;
+    fwd_span_tile<NV, NW>(G, lib, V, t, tc, t < tile1, int(blockIdx.y) * NW, arc_load, nd, ni, drv_ts, arc_ts,
+                          arc_delay, argmax, s_res[wave]);
+}
+
+// Batched forward spans: workgroup x of the launch runs tile map[map0 + x].y of design
+// map[map0 + x].x (one span of each of several designs per launch), views blockIdx.y * NW
+// onwards; every design has the batch's views.
+template <int NV, int NW>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_forward_span_batch(
+    const BatchItem* __restrict__ items, const int2* __restrict__ map, int map0, KLib lib, KViews V) {
+    static_assert(kSpanWaves == 1, "one span tile per workgroup");
+    __shared__ float2 s_res[kSpanSlotsF * NW];
+    const int2 m = map[map0 + int(blockIdx.x)];
+    const BatchItem& it = items[m.x];
+    fwd_span_tile<NV, NW>(it.G, lib, V, m.y, m.y, true, int(blockIdx.y) * NW, it.arc_load, it.nd, it.ni, it.drv_ts,
+                          it.arc_ts, it.arc_delay, it.argmax, s_res);
+}
+
 // primary inputs: copy (arrival, slew) of every view
 __global__ void k_copy_pi(const float* __restrict__ pi_ts, float* __restrict__ drv_ts, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) drv_ts[i] = pi_ts[i];
+}
+
+// the same for every design of a batch: design blockIdx.y, n_pi * NV * 2 values each
+__global__ void k_copy_pi_batch(const BatchItem* __restrict__ items, int NV) {
+    const BatchItem& it = items[blockIdx.y];
+    const int n = it.G.n_pi * NV * 2;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) it.drv_ts[i] = it.pi_ts[i];
 }
 
 template <int NV>
@@ -904,21 +955,16 @@ __global__ __launch_bounds__(64 * kLevelWaves) void k_backward(DevGraph G, KView
 // times of sink gates outside the span or the endpoint required times), then the levels
 // top down, in-span required times handed over through LDS.
 // NV views stored, NW computed per wavefront (views v0 = blockIdx.y * NW onwards).
+// The body of one backward span tile t of graph G, views v0 .. v0 + NW - 1; rs: the
+// wavefront's LDS required times, kSpanSlotsB * NW values.
 template <int NV, int NW>
-__global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
-                                                       const float* __restrict__ nd, const float* __restrict__ drv_ts,
-                                                       const float* __restrict__ arc_ts,
-                                                       const float* __restrict__ arc_delay,
-                                                       const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
-                                                       float* __restrict__ arc_rat, float* __restrict__ drv_slack,
-                                                       float* __restrict__ arc_slack) {
-    __shared__ float s_rat[kSpanWaves][kSpanSlotsB * NW];
-    const int v0 = int(blockIdx.y) * NW;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = tile0 + blockIdx.x * kSpanWaves + wave;
-    if (t >= tile1) return;
+__device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V, int t, int v0,
+                                              const float* __restrict__ nd, const float* __restrict__ drv_ts,
+                                              const float* __restrict__ arc_ts, const float* __restrict__ arc_delay,
+                                              const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
+                                              float* __restrict__ arc_rat, float* __restrict__ drv_slack,
+                                              float* __restrict__ arc_slack, float* rs) {
     const int lane = threadIdx.x & 63;
-    float* rs = s_rat[wave];
     bool early[NW];
 #pragma unroll
     for (int v = 0; v < NW; ++v) early[v] = V.mode[v0 + v] == STA_EARLY;
@@ -1066,19 +1112,49 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     }
 }
 
+template <int NV, int NW>
+__global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
+                                                       const float* __restrict__ nd, const float* __restrict__ drv_ts,
+                                                       const float* __restrict__ arc_ts,
+                                                       const float* __restrict__ arc_delay,
+                                                       const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
+                                                       float* __restrict__ arc_rat, float* __restrict__ drv_slack,
+                                                       float* __restrict__ arc_slack) {
+    __shared__ float s_rat[kSpanWaves][kSpanSlotsB * NW];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = tile0 + blockIdx.x * kSpanWaves + wave;
+    if (t >= tile1) return;
+    bwd_span_tile<NV, NW>(G, V, t, int(blockIdx.y) * NW, nd, drv_ts, arc_ts, arc_delay, ep_rat, drv_rat, arc_rat,
+                          drv_slack, arc_slack, s_rat[wave]);
+}
+
+// Batched backward spans: workgroup x runs tile map[map0 + x].y of design map[map0 + x].x.
+template <int NV, int NW>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_backward_span_batch(
+    const BatchItem* __restrict__ items, const int2* __restrict__ map, int map0, KViews V) {
+    static_assert(kSpanWaves == 1, "one span tile per workgroup");
+    __shared__ float s_rat[kSpanSlotsB * NW];
+    const int2 m = map[map0 + int(blockIdx.x)];
+    const BatchItem& it = items[m.x];
+    bwd_span_tile<NV, NW>(it.G, V, m.y, int(blockIdx.y) * NW, it.nd, it.drv_ts, it.arc_ts, it.arc_delay, it.ep_rat,
+                          it.drv_rat, it.arc_rat, it.drv_slack, it.arc_slack, s_rat);
+}
+
+// Endpoint summary, first stage: workgroup blk of nblk takes endpoints blk * 256 + t,
+// striding by nblk * 256, and writes its digits and minimum to partial blk.
 template <int NV>
-__global__ __launch_bounds__(kK4Threads) void k_endpoint_partial(const int32_t* __restrict__ ep_drv, int E,
-                                                                 const float* __restrict__ drv_slack,
-                                                                 unsigned long long* __restrict__ part_limbs,
-                                                                 float* __restrict__ part_wns) {
+__device__ __forceinline__ void endpoint_partial_body(const int32_t* __restrict__ ep_drv, int E,
+                                                      const float* __restrict__ drv_slack, int blk, int nblk,
+                                                      unsigned long long* __restrict__ part_limbs,
+                                                      float* __restrict__ part_wns) {
     __shared__ unsigned long long s_l[NV * kLimbs];
     __shared__ float s_min[NV][kK4Threads / 64];
     for (int i = threadIdx.x; i < NV * kLimbs; i += blockDim.x) s_l[i] = 0ull;
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // the thread's first endpoint: its slacks in every view in one round
-    const int e1 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int stride = gridDim.x * blockDim.x;
+    const int e1 = blk * int(blockDim.x) + int(threadIdx.x);
+    const int stride = nblk * int(blockDim.x);
     float s1[NV];
     {
         const int u = e1 < E ? ep_drv[e1] : 0;
@@ -1108,18 +1184,39 @@ __global__ __launch_bounds__(kK4Threads) void k_endpoint_partial(const int32_t* 
         if (lane == 0) s_min[v][w] = mn;
     }
     __syncthreads();
-    if (threadIdx.x < NV * kLimbs) part_limbs[size_t(blockIdx.x) * NV * kLimbs + threadIdx.x] = s_l[threadIdx.x];
+    if (threadIdx.x < NV * kLimbs) part_limbs[size_t(blk) * NV * kLimbs + threadIdx.x] = s_l[threadIdx.x];
     if (threadIdx.x < NV) {
         float mn = s_min[threadIdx.x][0];
         for (int i = 1; i < kK4Threads / 64; ++i) mn = (s_min[threadIdx.x][i] < mn) ? s_min[threadIdx.x][i] : mn;
-        part_wns[size_t(blockIdx.x) * NV + threadIdx.x] = mn;
+        part_wns[size_t(blk) * NV + threadIdx.x] = mn;
     }
 }
 
 template <int NV>
-__global__ __launch_bounds__(256) void k_endpoint_final(int nblk, const unsigned long long* __restrict__ part_limbs,
-                                                        const float* __restrict__ part_wns, double* __restrict__ tns,
-                                                        float* __restrict__ wns) {
+__global__ __launch_bounds__(kK4Threads) void k_endpoint_partial(const int32_t* __restrict__ ep_drv, int E,
+                                                                 const float* __restrict__ drv_slack,
+                                                                 unsigned long long* __restrict__ part_limbs,
+                                                                 float* __restrict__ part_wns) {
+    endpoint_partial_body<NV>(ep_drv, E, drv_slack, int(blockIdx.x), int(gridDim.x), part_limbs, part_wns);
+}
+
+// Batched first stage: workgroup x is workgroup map[map0 + x].y of design map[map0 + x].x,
+// whose partials start at items[..].ep_part0 in the batch's scratch.
+template <int NV>
+__global__ __launch_bounds__(kK4Threads) void k_endpoint_partial_batch(const BatchItem* __restrict__ items,
+                                                                       const int2* __restrict__ map, int map0,
+                                                                       unsigned long long* __restrict__ part_limbs,
+                                                                       float* __restrict__ part_wns) {
+    const int2 m = map[map0 + int(blockIdx.x)];
+    const BatchItem& it = items[m.x];
+    endpoint_partial_body<NV>(it.G.ep_drv, it.E, it.drv_slack, m.y, it.ep_blocks,
+                              part_limbs + size_t(it.ep_part0) * NV * kLimbs, part_wns + size_t(it.ep_part0) * NV);
+}
+
+template <int NV>
+__device__ __forceinline__ void endpoint_final_body(int nblk, const unsigned long long* __restrict__ part_limbs,
+                                                    const float* __restrict__ part_wns, double* __restrict__ tns,
+                                                    float* __restrict__ wns) {
     __shared__ unsigned long long s_sum[NV * kLimbs];
     __shared__ float s_min[NV][4];
     for (int i = threadIdx.x; i < NV * kLimbs; i += blockDim.x) s_sum[i] = 0ull;
@@ -1162,6 +1259,24 @@ __global__ __launch_bounds__(256) void k_endpoint_final(int nblk, const unsigned
         for (int i = 1; i < 4; ++i) mn = (s_min[v][i] < mn) ? s_min[v][i] : mn;
         wns[v] = mn;
     }
+}
+
+template <int NV>
+__global__ __launch_bounds__(256) void k_endpoint_final(int nblk, const unsigned long long* __restrict__ part_limbs,
+                                                        const float* __restrict__ part_wns, double* __restrict__ tns,
+                                                        float* __restrict__ wns) {
+    endpoint_final_body<NV>(nblk, part_limbs, part_wns, tns, wns);
+}
+
+// Batched second stage: one workgroup per design (blockIdx.x), over its own partials.
+template <int NV>
+__global__ __launch_bounds__(256) void k_endpoint_final_batch(const BatchItem* __restrict__ items,
+                                                              const unsigned long long* __restrict__ part_limbs,
+                                                              const float* __restrict__ part_wns) {
+    const BatchItem& it = items[blockIdx.x];
+    if (it.ep_blocks == 0) return;                  // a design without slack buffers
+    endpoint_final_body<NV>(it.ep_blocks, part_limbs + size_t(it.ep_part0) * NV * kLimbs,
+                            part_wns + size_t(it.ep_part0) * NV, it.tns, it.wns);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1897,6 +2012,21 @@ static sta_status run_sequence(const sta_graph* g, LaunchCache& c, std::vector<u
 
 static uint64_t pk(const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); }
 
+// one level launch of the forward pass (gate level l of g, all views)
+template <int NV>
+static void launch_forward_level(const sta_graph* g, const KLib& lib, const KViews& kv, const sta_net_out* nd,
+                                 const sta_timing_out* o, int64_t l, hipStream_t s) {
+    const int t0 = g->fwd_tile_ptr[l], t1 = g->fwd_tile_ptr[l + 1];
+    if (t1 <= t0) return;
+    const KTiles kt = ktiles(g->ftile_arc_h, g->ftile_gate_h, t0, t1);
+    const DevGraph dg = dev_graph(g);
+    prof_launch("k_forward", s, [&] {
+        hipLaunchKernelGGL((k_forward<NV>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves), dim3(64 * kLevelWaves),
+                           0, s, dg, lib, kv, t0, t1, kt, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts,
+                           o->arc_ts, o->arc_delay, o->argmax);
+    });
+}
+
 template <int NV>
 static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KViews& kv, const float* pi_ts,
                                    const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
@@ -1906,17 +2036,7 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
         prof_launch("k_copy_pi", s, [&] {
             hipLaunchKernelGGL(k_copy_pi, dim3((npi + 255) / 256), dim3(256), 0, s, pi_ts, o->drv_ts, npi);
         });
-    auto level = [&](int64_t l) {
-        const int t0 = g->fwd_tile_ptr[l], t1 = g->fwd_tile_ptr[l + 1];
-        if (t1 <= t0) return;
-        const KTiles kt = ktiles(g->ftile_arc_h, g->ftile_gate_h, t0, t1);
-        prof_launch("k_forward", s, [&] {
-            hipLaunchKernelGGL((k_forward<NV>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves),
-                               dim3(64 * kLevelWaves), 0, s, dg, lib, kv, t0,
-                               t1, kt, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts, o->arc_delay,
-                               o->argmax);
-        });
-    };
+    auto level = [&](int64_t l) { launch_forward_level<NV>(g, lib, kv, nd, o, l, s); };
     if constexpr (NV <= kSpanMaxViews) {
         if (g->use_spans) {
             const int64_t NS = int64_t(g->span_fused_h.size());
@@ -1965,21 +2085,30 @@ static void run_forward_views(const sta_graph* g, size_t lds, int NV, const KLib
     });
 }
 
+// one level launch of the backward pass (driver level l of g, all views)
+template <int NV>
+static void launch_backward_level(const sta_graph* g, const KViews& kv, const float* net_delay, const float* drv_ts,
+                                  const float* arc_ts, const float* arc_delay, const float* ep_rat, float* drv_rat,
+                                  float* arc_rat, float* drv_slack, float* arc_slack, int64_t l, hipStream_t s) {
+    const int t0 = g->bwd_tile_ptr[l], t1 = g->bwd_tile_ptr[l + 1];
+    if (t1 <= t0) return;
+    const KTiles kt = ktiles(g->btile_slot_h, g->btile_drv_h, t0, t1);
+    const DevGraph dg = dev_graph(g);
+    prof_launch("k_backward", s, [&] {
+        hipLaunchKernelGGL((k_backward<NV>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves), dim3(64 * kLevelWaves),
+                           0, s, dg, kv, t0, t1, kt, net_delay, drv_ts, arc_ts, arc_delay, ep_rat, drv_rat, arc_rat,
+                           drv_slack, arc_slack);
+    });
+}
+
 template <int NV>
 static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const sta_net_out* nd,
                                     const sta_timing_out* t, const float* ep_rat, const sta_slack_out* o,
                                     void* scratch, hipStream_t s) {
     const DevGraph dg = dev_graph(g);
     auto level = [&](int64_t l) {
-        const int t0 = g->bwd_tile_ptr[l], t1 = g->bwd_tile_ptr[l + 1];
-        if (t1 <= t0) return;
-        const KTiles kt = ktiles(g->btile_slot_h, g->btile_drv_h, t0, t1);
-        prof_launch("k_backward", s, [&] {
-            hipLaunchKernelGGL((k_backward<NV>), dim3((t1 - t0 + kLevelWaves - 1) / kLevelWaves),
-                               dim3(64 * kLevelWaves), 0, s, dg, kv, t0, t1, kt,
-                               nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat, o->arc_rat,
-                               o->drv_slack, o->arc_slack);
-        });
+        launch_backward_level<NV>(g, kv, nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat,
+                                  o->arc_rat, o->drv_slack, o->arc_slack, l, s);
     };
     bool done = false;
     if constexpr (NV <= kSpanMaxViews) {
@@ -2525,7 +2654,25 @@ struct sta_batch {
         sta_net_out nd;
         sta_timing_out out;
     };
+    // a span step: one batched launch over map[map0, map0 + nblk), plus the level launches
+    // of the designs whose span of this step does not fuse (item, first and last level in
+    // the pass's order)
+    struct Step {
+        int map0 = 0, nblk = 0;
+        std::vector<std::array<int64_t, 3>> levels;
+    };
+    struct DcClass {
+        int maxn = 0, map0 = 0, nblk = 0;
+    };
     std::vector<Lvl> level_designs;
+    std::vector<const sta_graph*> graphs;      // per item
+    std::vector<sta_net_out> nds;              // per item
+    std::vector<sta_timing_out> outs;          // per item
+    std::vector<sta_slack_out> sls;            // per item (zeroed without slack)
+    std::vector<const float*> ep_rats;         // per item
+    std::vector<Step> fsteps, bsteps;
+    std::vector<DcClass> dc;
+    int n_items = 0, n_span_items = 0, ep_map0 = 0, ep_nblk = 0, n_slack_items = 0;
     int n_units = 0;
     int NV = 0;
     sta::KLib kl{};
@@ -2534,11 +2681,172 @@ struct sta_batch {
     sta::BatchItem* d_items = nullptr;
     int2* d_units = nullptr;
     int* d_counter = nullptr;
-    sta::LaunchCache cache;
+    int2* d_map = nullptr;
+    unsigned long long* d_limbs = nullptr;
+    float* d_wns = nullptr;
+    sta::BatchItem* d_span_items = nullptr;    // the span designs' items, first in the table
+    sta_batch_plan plan{};
+    sta::LaunchCache cache, bcache, dcache;
     std::mutex mu;
+    // a second stream (default priority) and two events: the persistent launch runs on it,
+    // forked from and joined back into the caller's stream, beside the span steps
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    // views per span wavefront of the batched span launches (sta_batch_set_tiling)
+    int fwd_nw = 1, bwd_nw = 2;
 };
 
 namespace sta {
+
+// Byte offsets of a batch's workspace regions and the entry counts they were sized for.
+struct BatchLayout {
+    size_t items = 0, units = 0, counter = 0, map = 0, limbs = 0, wns = 0, total = 0;
+    int64_t n_map = 0, n_ep = 0;
+};
+
+// endpoint-summary workgroups of one design in a batch: one per 2048 endpoints, 1 to 64
+static int batch_ep_blocks(int64_t E) {
+    const int64_t nb = (E + 2047) / 2048;
+    return int(nb < 1 ? 1 : (nb > 64 ? 64 : nb));
+}
+
+// node-count class of a graph's delay calculation and the workgroup size of that class
+// (the classes and sizes of sta_delay_calc)
+static int dc_class(const sta_graph* g) {
+    const int m = g->max_net_nodes;
+    return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : m <= 128 ? 128 : 256;
+}
+static int dc_threads(int maxn) { return maxn <= 8 ? 256 : 2048 / maxn; }
+
+static bool batch_layout(const sta_batch_design* designs, int32_t n, int NV, BatchLayout* L) {
+    int64_t items = 0, maps = 0, ep = 0;
+    for (int i = 0; i < n; ++i) {
+        const sta_graph* g = designs[i].g;
+        if (!g) return false;
+        if (g->D == 0) continue;
+        ++items;
+        if (designs[i].schedule != STA_BATCH_LEVELS)     // spans (or the persistent fallback)
+            for (size_t sp = 0; sp < g->span_fused_h.size(); ++sp)
+                if (g->span_fused_h[sp]) maps += g->span_tile_h[sp + 1] - g->span_tile_h[sp];
+        if (designs[i].ep_rat && designs[i].sl) {
+            for (size_t sp = 0; sp < g->bspan_fused_h.size(); ++sp)
+                if (g->bspan_fused_h[sp]) maps += g->bspan_tile_h[sp + 1] - g->bspan_tile_h[sp];
+            const int eb = batch_ep_blocks(g->E);
+            maps += eb;
+            ep += eb;
+        }
+        const int nt = dc_threads(dc_class(g));
+        maps += (g->D + nt - 1) / nt;
+    }
+    L->n_map = maps;
+    L->n_ep = ep;
+    size_t off = 0;
+    L->items = off;
+    off += align256(sizeof(BatchItem) * size_t(std::max<int64_t>(items, 1)));
+    L->units = off;
+    off += align256(sizeof(int2) * size_t(std::max<int64_t>(items * NV, 1)));
+    L->counter = off;
+    off += 256;
+    L->map = off;
+    off += align256(sizeof(int2) * size_t(std::max<int64_t>(maps, 1)));
+    L->limbs = off;
+    off += align256(sizeof(unsigned long long) * size_t(std::max<int64_t>(ep, 1)) * NV * kLimbs);
+    L->wns = off;
+    off += align256(sizeof(float) * size_t(std::max<int64_t>(ep, 1)) * NV);
+    L->total = off;
+    return true;
+}
+
+template <typename T>
+static void launch_dc_batch(const sta_batch* b, int maxn, int map0, int nblk, hipStream_t q) {
+    auto go = [&](auto kern, int nt) {
+        prof_launch("k_delay_calc_batch", q, [&] {
+            hipLaunchKernelGGL(kern, dim3(nblk), dim3(nt), 0, q, b->d_items, b->d_map, map0);
+        });
+    };
+    switch (maxn) {
+        case 8: go(k_delay_calc_batch<T, 8, 256>, 256); break;
+        case 16: go(k_delay_calc_batch<T, 16, 128>, 128); break;
+        case 32: go(k_delay_calc_batch<T, 32, 64>, 64); break;
+        case 64: go(k_delay_calc_batch<T, 64, 32>, 32); break;
+        case 128: go(k_delay_calc_batch<T, 128, 16>, 16); break;
+        default: go(k_delay_calc_batch<T, 256, 8>, 8); break;
+    }
+}
+
+// Forward pass of the span designs: the batched primary-input copy, then per step one
+// batched span launch (every design's s-th fused span, every view) and the level launches
+// of the spans of this step that do not fuse.
+template <int NV>
+static void enqueue_batch_forward(const sta_batch* b, hipStream_t q) {
+    if (b->n_span_items > 0) {
+        int max_pi = 0;
+        for (int k = 0; k < b->n_span_items; ++k) max_pi = std::max(max_pi, int(b->graphs[k]->n_pi));
+        const int n = max_pi * NV * 2;
+        if (n > 0) {
+            const int gx = std::min((n + 255) / 256, 64);
+            prof_launch("k_copy_pi_batch", q, [&] {
+                hipLaunchKernelGGL(k_copy_pi_batch, dim3(gx, b->n_span_items), dim3(256), 0, q, b->d_items, NV);
+            });
+        }
+    }
+    for (const auto& st : b->fsteps) {
+        if (st.nblk > 0)
+            prof_launch("k_forward_span_batch", q, [&] {
+                auto go = [&](auto kern, int nw) {
+                    hipLaunchKernelGGL(kern, dim3(st.nblk, NV / nw), dim3(64), 0, q, b->d_items, b->d_map, st.map0,
+                                       b->kl, b->kv);
+                };
+                const int nw = std::min(b->fwd_nw, NV);
+                if (nw >= 4 && NV >= 4) go(k_forward_span_batch<NV, (NV >= 4 ? 4 : 1)>, 4);
+                else if (nw >= 2 && NV >= 2) go(k_forward_span_batch<NV, (NV >= 2 ? 2 : 1)>, 2);
+                else go(k_forward_span_batch<NV, 1>, 1);
+            });
+        for (const auto& lv : st.levels) {
+            const int k = int(lv[0]);
+            for (int64_t l = lv[1]; l <= lv[2]; ++l)
+                launch_forward_level<NV>(b->graphs[k], b->kl, b->kv, &b->nds[k], &b->outs[k], l, q);
+        }
+    }
+}
+
+// Backward pass of the slack designs: per step one batched backward-span launch and the
+// level launches of unfused spans (top down), then the batched endpoint summary.
+template <int NV>
+static void enqueue_batch_backward(const sta_batch* b, hipStream_t q) {
+    for (const auto& st : b->bsteps) {
+        if (st.nblk > 0)
+            prof_launch("k_backward_span_batch", q, [&] {
+                auto go = [&](auto kern, int nw) {
+                    hipLaunchKernelGGL(kern, dim3(st.nblk, NV / nw), dim3(64), 0, q, b->d_items, b->d_map, st.map0,
+                                       b->kv);
+                };
+                const int nw = std::min(b->bwd_nw, NV);
+                if (nw >= 4 && NV >= 4) go(k_backward_span_batch<NV, (NV >= 4 ? 4 : 1)>, 4);
+                else if (nw >= 2 && NV >= 2) go(k_backward_span_batch<NV, (NV >= 2 ? 2 : 1)>, 2);
+                else go(k_backward_span_batch<NV, 1>, 1);
+            });
+        for (const auto& lv : st.levels) {
+            const int k = int(lv[0]);
+            const sta_slack_out& o = b->sls[k];
+            const sta_timing_out& t = b->outs[k];
+            for (int64_t l = lv[1]; l >= lv[2]; --l)
+                launch_backward_level<NV>(b->graphs[k], b->kv, b->nds[k].net_delay, t.drv_ts, t.arc_ts, t.arc_delay,
+                                          b->ep_rats[k], o.drv_rat, o.arc_rat, o.drv_slack, o.arc_slack, l, q);
+        }
+    }
+    if (b->ep_nblk > 0) {
+        prof_launch("k_endpoint_partial_batch", q, [&] {
+            hipLaunchKernelGGL((k_endpoint_partial_batch<NV>), dim3(b->ep_nblk), dim3(kK4Threads), 0, q, b->d_items,
+                               b->d_map, b->ep_map0, b->d_limbs, b->d_wns);
+        });
+        prof_launch("k_endpoint_final_batch", q, [&] {
+            hipLaunchKernelGGL((k_endpoint_final_batch<NV>), dim3(b->n_items), dim3(256), 0, q, b->d_items,
+                               b->d_limbs, b->d_wns);
+        });
+    }
+}
+
 }  // namespace sta
 
 using namespace sta;
@@ -2818,9 +3126,11 @@ sta_status sta_critical_paths(const sta_graph* g, const sta_views* views, int32_
     return launch_check("sta_critical_paths");
 }
 
-size_t sta_batch_workspace_bytes(int32_t n_designs, int32_t n_views) {
-    if (n_designs < 0 || n_views < 1) return 0;
-    return align256(sizeof(BatchItem) * size_t(n_designs)) + align256(sizeof(int2) * size_t(n_designs) * n_views) + 256;
+size_t sta_batch_workspace_bytes(const sta_batch_design* designs, int32_t n, int32_t n_views) {
+    BatchLayout L;
+    if (n < 0 || (n > 0 && !designs) || n_views < 1 || n_views > STA_MAX_VIEWS || !batch_layout(designs, n, n_views, &L))
+        return 0;
+    return L.total;
 }
 
 sta_status sta_batch_create(const sta_batch_design* designs, int32_t n, const sta_library* lib,
@@ -2832,35 +3142,60 @@ sta_status sta_batch_create(const sta_batch_design* designs, int32_t n, const st
     if (!views_ok(views, lib->n_sets, why)) return fail(STA_E_ARG, "sta_batch_create: " + why);
     if (!lib_axes_ok(lib, 0, why)) return fail(STA_E_ARG, "sta_batch_create: " + why);
     const int NV = views->n_views;
-    if (!workspace || workspace_bytes < sta_batch_workspace_bytes(n, NV))
+    for (int i = 0; i < n; ++i) {
+        const sta_batch_design& d = designs[i];
+        const std::string tag = " (design " + std::to_string(i) + ")";
+        if (!d.g || !d.nd || !d.out) return fail(STA_E_ARG, "sta_batch_create: null design entry" + tag);
+        const sta_graph* g = d.g;
+        if (!g->dev) return fail(STA_E_ARG, "sta_batch_create: graph not uploaded" + tag);
+        if (lib->n_tables < g->n_tables) return fail(STA_E_ARG, "sta_batch_create: library has fewer tables than the graph" + tag);
+        if (d.schedule != STA_BATCH_PERSISTENT && d.schedule != STA_BATCH_LEVELS && d.schedule != STA_BATCH_SPANS)
+            return fail(STA_E_ARG, "sta_batch_create: bad schedule" + tag);
+        if ((d.ep_rat == nullptr) != (d.sl == nullptr))
+            return fail(STA_E_ARG, "sta_batch_create: ep_rat and sl must be given together" + tag);
+        if (g->D == 0) continue;
+        if ((g->n_pi > 0 && !d.pi_ts) || !d.out->drv_ts || !d.nd->load ||
+            (g->A > 0 && (!d.out->arc_ts || !d.out->arc_delay || !d.out->argmax || !d.nd->net_delay ||
+                          !d.nd->net_imp2 || !d.nd->arc_load)))
+            return fail(STA_E_ARG, "sta_batch_create: null buffer" + tag);
+        if (d.sl && (!d.sl->tns || !d.sl->wns || !d.sl->drv_rat || !d.sl->drv_slack || (g->E > 0 && !d.ep_rat) ||
+                     (g->A > 0 && (!d.sl->arc_rat || !d.sl->arc_slack))))
+            return fail(STA_E_ARG, "sta_batch_create: null slack buffer" + tag);
+    }
+    BatchLayout L;
+    if (!batch_layout(designs, n, NV, &L)) return fail(STA_E_ARG, "sta_batch_create: bad design list");
+    if (!workspace || workspace_bytes < L.total)
         return fail(STA_E_ARG, "sta_batch_create: workspace smaller than sta_batch_workspace_bytes");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(STA_E_ARG, "sta_batch_create: workspace not 256-byte aligned");
     std::unique_ptr<sta_batch> b(new (std::nothrow) sta_batch());
     if (!b) return fail(STA_E_ALLOC, "sta_batch_create: out of host memory");
     b->NV = NV;
+    b->bwd_nw = std::min(kBwdViewsPerWave, NV);
     b->kl = make_klib(lib);
     b->kv = kviews(views);
     b->lds = size_t(fwd_lds(lib->n_tables).total) * 4;
     const bool lds_ok = b->lds <= lds_limit();
+    // items: the span designs first (the batched primary-input copy covers items
+    // 0 .. n_span_items - 1), then the others
     std::vector<BatchItem> items;
-    std::vector<std::pair<int64_t, int2>> units;
-    for (int i = 0; i < n; ++i) {
-        const sta_batch_design& d = designs[i];
-        if (!d.g || !d.nd || !d.out) return fail(STA_E_ARG, "sta_batch_create: null design entry " + std::to_string(i));
-        const sta_graph* g = d.g;
-        if (!g->dev) return fail(STA_E_ARG, "sta_batch_create: design " + std::to_string(i) + " not uploaded");
-        if (lib->n_tables < g->n_tables) return fail(STA_E_ARG, "sta_batch_create: library has fewer tables than design " + std::to_string(i));
-        if (d.schedule != STA_BATCH_PERSISTENT && d.schedule != STA_BATCH_LEVELS)
-            return fail(STA_E_ARG, "sta_batch_create: bad schedule");
-        if (g->D == 0) continue;
-        if ((g->n_pi > 0 && !d.pi_ts) || !d.out->drv_ts ||
-            (g->A > 0 && (!d.out->arc_ts || !d.out->arc_delay || !d.out->argmax || !d.nd->net_delay ||
-                          !d.nd->net_imp2 || !d.nd->arc_load)) || !d.nd->load)
-            return fail(STA_E_ARG, "sta_batch_create: null buffer in design " + std::to_string(i));
-        const bool pers = d.schedule == STA_BATCH_PERSISTENT && lds_ok && g->L > 0 && g->n_fchunks > 0;
-        if (!pers) {
-            b->level_designs.push_back({g, d.pi_ts, *d.nd, *d.out});
-            continue;
+    std::vector<int> order;                   // design index of each item
+    std::vector<uint8_t> is_span;
+    auto persistent_ok = [&](const sta_graph* g) { return lds_ok && g->L > 0 && g->n_fchunks > 0; };
+    for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < n; ++i) {
+            const sta_batch_design& d = designs[i];
+            if (d.g->D == 0) continue;
+            const bool span = d.schedule == STA_BATCH_SPANS || (d.schedule == STA_BATCH_PERSISTENT && !persistent_ok(d.g));
+            if (span != (pass == 0)) continue;
+            order.push_back(i);
+            is_span.push_back(span ? 1 : 0);
         }
+    b->n_items = int(order.size());
+    int ep_part = 0;
+    std::vector<std::pair<int64_t, int2>> units;
+    for (int k = 0; k < b->n_items; ++k) {
+        const sta_batch_design& d = designs[order[k]];
+        const sta_graph* g = d.g;
         BatchItem it{};
         it.G = dev_graph(g);
         it.NC = g->n_fchunks;
@@ -2873,27 +3208,150 @@ sta_status sta_batch_create(const sta_batch_design* designs, int32_t n, const st
         it.arc_ts = d.out->arc_ts;
         it.arc_delay = d.out->arc_delay;
         it.argmax = d.out->argmax;
-        const int idx = int(items.size());
+        it.load_w = d.nd->load;
+        it.nd_w = d.nd->net_delay;
+        it.ni_w = d.nd->net_imp2;
+        it.arc_load = d.nd->arc_load;
+        it.E = int32_t(g->E);
+        if (d.sl) {
+            it.ep_rat = d.ep_rat;
+            it.drv_rat = d.sl->drv_rat;
+            it.arc_rat = d.sl->arc_rat;
+            it.drv_slack = d.sl->drv_slack;
+            it.arc_slack = d.sl->arc_slack;
+            it.tns = d.sl->tns;
+            it.wns = d.sl->wns;
+            it.ep_blocks = batch_ep_blocks(g->E);
+            it.ep_part0 = ep_part;
+            ep_part += it.ep_blocks;
+            ++b->n_slack_items;
+        }
         items.push_back(it);
-        for (int v = 0; v < NV; ++v) units.push_back({g->A + 64 * g->L, make_int2(idx, v)});
+        b->graphs.push_back(g);
+        b->nds.push_back(*d.nd);
+        b->outs.push_back(*d.out);
+        sta_slack_out so{};
+        if (d.sl) so = *d.sl;
+        b->sls.push_back(so);
+        b->ep_rats.push_back(d.ep_rat);
+        if (is_span[k]) {
+            ++b->n_span_items;
+        } else if (d.schedule == STA_BATCH_PERSISTENT) {
+            for (int v = 0; v < NV; ++v) units.push_back({g->A + 64 * g->L, make_int2(k, v)});
+            ++b->plan.persistent_designs;
+        } else {
+            b->level_designs.push_back({g, d.pi_ts, *d.nd, *d.out});
+        }
     }
     std::stable_sort(units.begin(), units.end(),
                      [](const std::pair<int64_t, int2>& x, const std::pair<int64_t, int2>& y) { return x.first > y.first; });
     std::vector<int2> ulist;
     for (auto& u : units) ulist.push_back(u.second);
-    uint8_t* base = static_cast<uint8_t*>(workspace);
-    b->d_items = reinterpret_cast<BatchItem*>(base);
-    b->d_units = reinterpret_cast<int2*>(base + align256(sizeof(BatchItem) * size_t(n)));
-    b->d_counter = reinterpret_cast<int*>(base + align256(sizeof(BatchItem) * size_t(n)) +
-                                          align256(sizeof(int2) * size_t(n) * NV));
     b->n_units = int(ulist.size());
-    if (!items.empty()) {
-        hipError_t e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(b->d_units, ulist.data(), sizeof(int2) * ulist.size(), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return fail(STA_E_HIP, std::string("sta_batch_create: hipMemcpy: ") + hipGetErrorString(e));
+    // the tile maps: forward span steps, backward span steps, delay-calculation classes,
+    // endpoint workgroups
+    std::vector<int2> map;
+    int64_t max_f = 0, max_b = 0;
+    for (int k = 0; k < b->n_items; ++k) {
+        if (is_span[k]) max_f = std::max<int64_t>(max_f, int64_t(b->graphs[k]->span_fused_h.size()));
+        if (items[k].tns) max_b = std::max<int64_t>(max_b, int64_t(b->graphs[k]->bspan_fused_h.size()));
+    }
+    for (int64_t sp = 0; sp < max_f; ++sp) {
+        sta_batch::Step st;
+        st.map0 = int(map.size());
+        for (int k = 0; k < b->n_items; ++k) {
+            const sta_graph* g = b->graphs[k];
+            if (!is_span[k] || sp >= int64_t(g->span_fused_h.size())) continue;
+            if (g->span_fused_h[sp])
+                for (int t = g->span_tile_h[sp]; t < g->span_tile_h[sp + 1]; ++t) map.push_back(make_int2(k, t));
+            else
+                st.levels.push_back({int64_t(k), int64_t(g->span_lv_h[2 * sp]), int64_t(g->span_lv_h[2 * sp + 1])});
+        }
+        st.nblk = int(map.size()) - st.map0;
+        b->plan.fwd_span_tiles += st.nblk;
+        b->fsteps.push_back(std::move(st));
+    }
+    for (int64_t sp = 0; sp < max_b; ++sp) {
+        sta_batch::Step st;
+        st.map0 = int(map.size());
+        for (int k = 0; k < b->n_items; ++k) {
+            const sta_graph* g = b->graphs[k];
+            if (!items[k].tns || sp >= int64_t(g->bspan_fused_h.size())) continue;
+            if (g->bspan_fused_h[sp])
+                for (int t = g->bspan_tile_h[sp]; t < g->bspan_tile_h[sp + 1]; ++t) map.push_back(make_int2(k, t));
+            else
+                st.levels.push_back({int64_t(k), int64_t(g->bspan_lv_h[2 * sp]), int64_t(g->bspan_lv_h[2 * sp + 1])});
+        }
+        st.nblk = int(map.size()) - st.map0;
+        b->plan.bwd_span_tiles += st.nblk;
+        b->bsteps.push_back(std::move(st));
+    }
+    for (int maxn = 8; maxn <= 256; maxn *= 2) {
+        sta_batch::DcClass dc;
+        dc.maxn = maxn;
+        dc.map0 = int(map.size());
+        const int nt = dc_threads(maxn);
+        for (int k = 0; k < b->n_items; ++k) {
+            if (dc_class(b->graphs[k]) != maxn) continue;
+            const int64_t nb = (b->graphs[k]->D + nt - 1) / nt;
+            for (int64_t x = 0; x < nb; ++x) map.push_back(make_int2(k, int(x)));
+        }
+        dc.nblk = int(map.size()) - dc.map0;
+        if (dc.nblk > 0) b->dc.push_back(dc);
+    }
+    b->ep_map0 = int(map.size());
+    for (int k = 0; k < b->n_items; ++k)
+        for (int x = 0; x < items[k].ep_blocks; ++x) map.push_back(make_int2(k, x));
+    b->ep_nblk = int(map.size()) - b->ep_map0;
+    if (int64_t(map.size()) > L.n_map || ep_part > L.n_ep) return fail(STA_E_ARG, "sta_batch_create: inconsistent layout");
+    uint8_t* base = static_cast<uint8_t*>(workspace);
+    b->d_items = reinterpret_cast<BatchItem*>(base + L.items);
+    b->d_units = reinterpret_cast<int2*>(base + L.units);
+    b->d_counter = reinterpret_cast<int*>(base + L.counter);
+    b->d_map = reinterpret_cast<int2*>(base + L.map);
+    b->d_limbs = reinterpret_cast<unsigned long long*>(base + L.limbs);
+    b->d_wns = reinterpret_cast<float*>(base + L.wns);
+    hipError_t e = hipSuccess;
+    if (!items.empty()) e = hipMemcpy(b->d_items, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !ulist.empty())
+        e = hipMemcpy(b->d_units, ulist.data(), sizeof(int2) * ulist.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !map.empty()) e = hipMemcpy(b->d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(STA_E_HIP, std::string("sta_batch_create: hipMemcpy: ") + hipGetErrorString(e));
+    b->plan.span_designs = b->n_span_items;
+    b->plan.level_designs = int32_t(b->level_designs.size());
+    b->plan.persistent_units = b->n_units;
+    b->plan.fwd_steps = int32_t(b->fsteps.size());
+    b->plan.bwd_steps = int32_t(b->bsteps.size());
+    b->plan.slack_designs = b->n_slack_items;
+    b->plan.dc_launches = int32_t(b->dc.size());
+    if (b->n_units > 0 && b->n_span_items > 0) {
+        e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (b->join) (void)hipEventDestroy(b->join);
+            if (b->fork) (void)hipEventDestroy(b->fork);
+            if (b->side) (void)hipStreamDestroy(b->side);
+            return fail(STA_E_HIP, std::string("sta_batch_create: side stream: ") + hipGetErrorString(e));
+        }
     }
     *out = b.release();
     return STA_OK;
+}
+
+sta_status sta_batch_delay_calc(sta_batch* b, sta_dc_precision prec, int32_t use_graph, void* stream) {
+    if (!b) return fail(STA_E_ARG, "sta_batch_delay_calc: null batch");
+    if (prec != STA_DC_FP64 && prec != STA_DC_FP32) return fail(STA_E_ARG, "sta_batch_delay_calc: unknown precision");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto enqueue = [&](hipStream_t q) {
+        for (const auto& c : b->dc) {
+            if (prec == STA_DC_FP64) launch_dc_batch<double>(b, c.maxn, c.map0, c.nblk, q);
+            else launch_dc_batch<float>(b, c.maxn, c.map0, c.nblk, q);
+        }
+    };
+    const sta_status st = capture_replay(b->dcache, b->mu, use_graph != 0, {uint64_t(prec)}, s, enqueue);
+    if (st != STA_OK) return st;
+    return launch_check("sta_batch_delay_calc");
 }
 
 sta_status sta_batch_propagate(sta_batch* b, int32_t use_graph, int32_t persistent_blocks, void* stream) {
@@ -2908,33 +3366,85 @@ sta_status sta_batch_propagate(sta_batch* b, int32_t use_graph, int32_t persiste
         blocks = cus;
     }
     if (blocks > b->n_units) blocks = b->n_units;
+    // the persistent launch goes to the side stream when span steps run beside it (forked
+    // after, and joined before, everything else of the sequence), else in line
+    const bool fork = b->n_units > 0 && b->n_span_items > 0 && b->side;
     auto enqueue = [&](hipStream_t q) {
+        hipStream_t qp = q;
+        if (fork) {
+            (void)hipEventRecord(b->fork, q);
+            (void)hipStreamWaitEvent(b->side, b->fork, 0);
+            qp = b->side;
+        }
         if (b->n_units > 0) {
-            prof_launch("k_zero_i32", q, [&] { hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, q, b->d_counter); });
+            prof_launch("k_zero_i32", qp, [&] { hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, qp, b->d_counter); });
             set_lds(k_forward_batch, b->lds);
-            prof_launch("k_forward_batch", q, [&] {
-                hipLaunchKernelGGL(k_forward_batch, dim3(blocks), dim3(kViewThreads), b->lds, q, b->d_items,
+            prof_launch("k_forward_batch", qp, [&] {
+                hipLaunchKernelGGL(k_forward_batch, dim3(blocks), dim3(kViewThreads), b->lds, qp, b->d_items,
                                    b->d_units, b->n_units, b->d_counter, b->kl, b->kv);
             });
         }
+        if (fork) (void)hipEventRecord(b->join, b->side);
+        switch (b->NV) {
+            case 1: enqueue_batch_forward<1>(b, q); break;
+            case 2: enqueue_batch_forward<2>(b, q); break;
+            case 4: enqueue_batch_forward<4>(b, q); break;
+            default: enqueue_batch_forward<8>(b, q); break;
+        }
         for (auto& d : b->level_designs) enqueue_levels_nv(b->NV, d.g, b->kl, b->kv, d.pi_ts, &d.nd, &d.out, q);
+        if (fork) (void)hipStreamWaitEvent(q, b->join, 0);
     };
-    std::vector<uint64_t> key = {uint64_t(blocks)};
-    const sta_status st = capture_replay(b->cache, b->mu, use_graph != 0, std::move(key), s, enqueue);
+    const sta_status st = capture_replay(b->cache, b->mu, use_graph != 0, {uint64_t(blocks)}, s, enqueue);
     if (st != STA_OK) return st;
     return launch_check("sta_batch_propagate");
 }
 
-sta_status sta_batch_info(const sta_batch* b, int32_t* persistent_units, int32_t* level_designs) {
-    if (!b) return fail(STA_E_ARG, "sta_batch_info: null batch");
-    if (persistent_units) *persistent_units = b->n_units;
-    if (level_designs) *level_designs = int32_t(b->level_designs.size());
+sta_status sta_batch_slack(sta_batch* b, int32_t use_graph, void* stream) {
+    if (!b) return fail(STA_E_ARG, "sta_batch_slack: null batch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto enqueue = [&](hipStream_t q) {
+        switch (b->NV) {
+            case 1: enqueue_batch_backward<1>(b, q); break;
+            case 2: enqueue_batch_backward<2>(b, q); break;
+            case 4: enqueue_batch_backward<4>(b, q); break;
+            default: enqueue_batch_backward<8>(b, q); break;
+        }
+    };
+    const sta_status st = capture_replay(b->bcache, b->mu, use_graph != 0, {uint64_t(1)}, s, enqueue);
+    if (st != STA_OK) return st;
+    return launch_check("sta_batch_slack");
+}
+
+sta_status sta_batch_set_tiling(sta_batch* b, int32_t fwd_views_per_wave, int32_t bwd_views_per_wave) {
+    if (!b) return fail(STA_E_ARG, "sta_batch_set_tiling: null batch");
+    auto ok = [&](int32_t w) { return (w == 1 || w == 2 || w == 4) && w <= b->NV; };
+    if (!ok(fwd_views_per_wave) || !ok(bwd_views_per_wave))
+        return fail(STA_E_ARG, "sta_batch_set_tiling: views per wavefront must be 1, 2 or 4 and at most the view count");
+    std::lock_guard<std::mutex> lock(b->mu);
+    if (b->fwd_nw != fwd_views_per_wave) drop_launches(b->cache);
+    if (b->bwd_nw != bwd_views_per_wave) drop_launches(b->bcache);
+    b->fwd_nw = fwd_views_per_wave;
+    b->bwd_nw = bwd_views_per_wave;
+    return STA_OK;
+}
+
+sta_status sta_batch_info(const sta_batch* b, sta_batch_plan* out) {
+    if (!b || !out) return fail(STA_E_ARG, "sta_batch_info: null argument");
+    *out = b->plan;
     return STA_OK;
 }
 
 void sta_batch_free(sta_batch* b) {
     if (!b) return;
     drop_launches(b->cache);
+    drop_launches(b->bcache);
+    drop_launches(b->dcache);
+    if (b->side) {
+        (void)hipStreamSynchronize(b->side);
+        (void)hipEventDestroy(b->fork);
+        (void)hipEventDestroy(b->join);
+        (void)hipStreamDestroy(b->side);
+    }
     delete b;
 }
 

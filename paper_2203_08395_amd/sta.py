@@ -76,7 +76,7 @@ class SlackOut(ctypes.Structure):
 
 _lib = None
 
-EXPORTS = ("sta_last_error", "sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload",
+EXPORTS = ("sta_last_error", "sta_build_graph", "sta_build_graph_spans", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload",
            "sta_graph_free", "sta_delay_calc", "sta_propagate", "sta_slack", "sta_slack_noalloc", "sta_set_schedule", "sta_set_level_fusion",
            "sta_graph_spans", "sta_graph_span_list", "sta_profile_begin", "sta_profile_end")
 
@@ -99,6 +99,8 @@ def load_library():
     lib.sta_last_error.restype = ctypes.c_char_p
     lib.sta_last_error.argtypes = []
     lib.sta_build_graph.argtypes = [ctypes.POINTER(DesignDesc), ctypes.POINTER(_P)]
+    lib.sta_build_graph_spans.argtypes = [ctypes.POINTER(DesignDesc), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(_P)]
     lib.sta_graph_sizes.argtypes = [_P, ctypes.POINTER(Sizes)]
     lib.sta_graph_perm.argtypes = [_P, _P, _P, _P, _P, _P]
     lib.sta_graph_upload.argtypes = [_P, _P, ctypes.c_size_t, _P]
@@ -117,7 +119,8 @@ def load_library():
     lib.sta_graph_span_list.argtypes = [_P, _P, _P]
     lib.sta_profile_begin.argtypes = []
     lib.sta_profile_end.argtypes = [ctypes.POINTER(KernelStat), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
-    for f in ("sta_build_graph", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload", "sta_delay_calc",
+    for f in ("sta_build_graph", "sta_build_graph_spans", "sta_graph_sizes", "sta_graph_perm", "sta_graph_upload",
+              "sta_delay_calc",
               "sta_propagate", "sta_slack", "sta_slack_noalloc", "sta_set_schedule", "sta_set_level_fusion",
               "sta_graph_spans",
               "sta_graph_span_list", "sta_profile_begin", "sta_profile_end"):
@@ -147,7 +150,9 @@ def _stream(torch, device):
 class Graph:
     """A levelized design (host side built by sta_build_graph); ``upload`` places it on a GPU."""
 
-    def __init__(self, design, n_tables=None):
+    def __init__(self, design, n_tables=None, span_levels=None):
+        """span_levels: (forward, backward) longest fused span in levels, each 1..8
+        (sta_build_graph_spans); None: the library's (8, 8)."""
         lib = load_library()
         self._keep = [_np(design.gate_arc_ptr, np.int32), _np(design.arc_drv, np.int32),
                       _np(design.arc_tbl, np.int32), _np(design.arc_tap, np.int32),
@@ -159,7 +164,12 @@ class Graph:
         d = DesignDesc(int(design.n_pi), int(design.n_gates), n_tables,
                        *[_P(a.ctypes.data) for a in self._keep])
         h = _P()
-        _check(lib.sta_build_graph(ctypes.byref(d), ctypes.byref(h)), "sta_build_graph")
+        if span_levels is None:
+            _check(lib.sta_build_graph(ctypes.byref(d), ctypes.byref(h)), "sta_build_graph")
+        else:
+            _check(lib.sta_build_graph_spans(ctypes.byref(d), int(span_levels[0]), int(span_levels[1]),
+                                             ctypes.byref(h)), "sta_build_graph_spans")
+        self.span_levels = tuple(span_levels) if span_levels is not None else (8, 8)
         self._h = h
         self._keep = None
         s = Sizes()
@@ -470,14 +480,20 @@ def critical_paths(g: Graph, views: ViewsC, view, k, timing, slack_out):
 
 # ---- batches of designs (include/sta_batch.h) --------------------------------------------
 
-BATCH_PERSISTENT, BATCH_LEVELS = 0, 1
-BATCH_EXPORTS = ("sta_batch_workspace_bytes", "sta_batch_create", "sta_batch_propagate", "sta_batch_info",
-                 "sta_batch_free")
+BATCH_EXPORTS = ("sta_batch_workspace_bytes", "sta_batch_create", "sta_batch_delay_calc", "sta_batch_propagate",
+                 "sta_batch_slack", "sta_batch_set_tiling", "sta_batch_info", "sta_batch_free")
+BATCH_PERSISTENT, BATCH_LEVELS, BATCH_SPANS = 0, 1, 2
 
 
 class BatchDesignC(ctypes.Structure):
     _fields_ = [("g", _P), ("pi_ts", _P), ("nd", ctypes.POINTER(NetOut)), ("out", ctypes.POINTER(TimingOut)),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("ep_rat", _P), ("sl", ctypes.POINTER(SlackOut))]
+
+
+class BatchPlanC(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in ("span_designs", "persistent_designs", "level_designs",
+                                              "persistent_units", "fwd_steps", "fwd_span_tiles", "bwd_steps",
+                                              "bwd_span_tiles", "slack_designs", "dc_launches")]
 
 
 _batch_bound = False
@@ -487,37 +503,49 @@ def _batch_lib():
     global _batch_bound
     lib = load_library()
     if not _batch_bound:
-        lib.sta_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        lib.sta_batch_workspace_bytes.argtypes = [ctypes.POINTER(BatchDesignC), ctypes.c_int32, ctypes.c_int32]
         lib.sta_batch_workspace_bytes.restype = ctypes.c_size_t
         lib.sta_batch_create.argtypes = [ctypes.POINTER(BatchDesignC), ctypes.c_int32, ctypes.POINTER(LibraryC),
                                          ctypes.POINTER(ViewsC), _P, ctypes.c_size_t, ctypes.POINTER(_P)]
+        lib.sta_batch_delay_calc.argtypes = [_P, ctypes.c_int, ctypes.c_int32, _P]
         lib.sta_batch_propagate.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, _P]
-        lib.sta_batch_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        lib.sta_batch_slack.argtypes = [_P, ctypes.c_int32, _P]
+        lib.sta_batch_set_tiling.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
+        lib.sta_batch_info.argtypes = [_P, ctypes.POINTER(BatchPlanC)]
         lib.sta_batch_free.argtypes = [_P]
         lib.sta_batch_free.restype = None
-        for f in ("sta_batch_create", "sta_batch_propagate", "sta_batch_info"):
+        for f in ("sta_batch_create", "sta_batch_delay_calc", "sta_batch_propagate", "sta_batch_slack",
+                  "sta_batch_set_tiling", "sta_batch_info"):
             getattr(lib, f).restype = ctypes.c_int
         _batch_bound = True
     return lib
 
 
 class Batch:
-    """Several uploaded graphs sharing one library and view set, propagated together.
+    """Several uploaded graphs sharing one library and view set, run together.
 
-    entries: list of (graph, pi_ts tensor, net dict, timing dict, schedule)."""
+    entries: list of (graph, pi_ts tensor, net dict, timing dict, schedule) or
+    (graph, pi_ts, net dict, timing dict, schedule, ep_rat tensor, slack dict); the slack
+    dict is the output of ``alloc_slack`` (its scratch is not used)."""
 
     def __init__(self, entries, lib: LibraryC, views: ViewsC):
         import torch
         blib = _batch_lib()
         self._keep = []
         arr = (BatchDesignC * max(len(entries), 1))()
-        for i, (g, pi, nd, tm, sched) in enumerate(entries):
+        for i, e in enumerate(entries):
+            g, pi, nd, tm, sched = e[:5]
+            ep_rat, sl = (e[5], e[6]) if len(e) > 5 else (None, None)
             no, to = _netout(nd), _timingout(tm)
-            self._keep += [g, pi, nd, tm, no, to]
-            arr[i] = BatchDesignC(g.handle, _ptr(pi), ctypes.pointer(no), ctypes.pointer(to), int(sched))
+            so = _slackout(sl) if sl is not None else None
+            self._keep += [g, pi, nd, tm, no, to, ep_rat, sl, so]
+            arr[i] = BatchDesignC(g.handle, _ptr(pi), ctypes.pointer(no), ctypes.pointer(to), int(sched),
+                                  _ptr(ep_rat), ctypes.pointer(so) if so is not None else None)
         self._arr = arr
         self.device = entries[0][0].device if entries else torch.device("cuda")
-        nb = blib.sta_batch_workspace_bytes(len(entries), views.n_views)
+        nb = blib.sta_batch_workspace_bytes(arr, len(entries), views.n_views)
+        if nb == 0:
+            raise StaError(-1, "sta_batch_workspace_bytes: bad design list")
         self.workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
         h = _P()
         self._views, self._lib = views, lib
@@ -525,15 +553,31 @@ class Batch:
                                      _ptr(self.workspace), nb, ctypes.byref(h)), "sta_batch_create")
         self._h = h
 
+    def delay_calc(self, precision=None, use_graph=True):
+        import torch
+        prec = STA_DC_FP64 if precision is None else precision
+        _check(_batch_lib().sta_batch_delay_calc(self._h, int(prec), int(use_graph), _stream(torch, self.device)),
+               "sta_batch_delay_calc")
+
     def propagate(self, use_graph=True, blocks=0):
         import torch
         _check(_batch_lib().sta_batch_propagate(self._h, int(use_graph), int(blocks), _stream(torch, self.device)),
                "sta_batch_propagate")
 
+    def slack(self, use_graph=True):
+        import torch
+        _check(_batch_lib().sta_batch_slack(self._h, int(use_graph), _stream(torch, self.device)),
+               "sta_batch_slack")
+
+    def set_tiling(self, fwd_views_per_wave, bwd_views_per_wave):
+        _check(_batch_lib().sta_batch_set_tiling(self._h, int(fwd_views_per_wave), int(bwd_views_per_wave)),
+               "sta_batch_set_tiling")
+        return self
+
     def info(self):
-        u, l_ = ctypes.c_int32(), ctypes.c_int32()
-        _check(_batch_lib().sta_batch_info(self._h, ctypes.byref(u), ctypes.byref(l_)), "sta_batch_info")
-        return {"persistent_units": u.value, "level_designs": l_.value}
+        p = BatchPlanC()
+        _check(_batch_lib().sta_batch_info(self._h, ctypes.byref(p)), "sta_batch_info")
+        return {f: int(getattr(p, f)) for f, _ in BatchPlanC._fields_}
 
     def __del__(self):
         h = getattr(self, "_h", None)

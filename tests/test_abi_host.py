@@ -180,3 +180,44 @@ def test_pi_only_design():
     d = tiny.design(3, [], [tiny.chain_net([5.0], [1.0, 1.0])] * 3)
     g = sta.Graph(d, n_tables=1)
     assert g.sizes["n_endpoints"] == 3 and g.sizes["n_levels"] == 0
+
+
+def test_library_exports_every_batch_symbol():
+    lib = sta._batch_lib()
+    names = _declared("sta_batch.h")
+    assert len(names) == 8
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sta.BATCH_EXPORTS)
+    # host-side validation, no device memory touched
+    assert lib.sta_batch_workspace_bytes(None, -1, 4) == 0
+    assert lib.sta_batch_workspace_bytes(None, 0, 0) == 0
+    assert lib.sta_batch_delay_calc(None, 0, 1, None) == -1
+    assert lib.sta_batch_propagate(None, 1, 0, None) == -1
+    assert lib.sta_batch_slack(None, 1, None) == -1
+    assert lib.sta_batch_info(None, None) == -1
+    assert lib.sta_batch_set_tiling(None, 1, 1) == -1
+
+
+def test_span_length_caps():
+    """sta_build_graph_spans: lengths outside 1..8 are refused; within, every span is at
+    most that long and the levelization does not change."""
+    d = gen.make_design(n_pins=6000, n_levels=40, fanin="geom", seed=9, n_fanout64=1)
+    for bad in ((0, 8), (8, 0), (9, 8), (8, 9)):
+        with pytest.raises(sta.StaError):
+            sta.Graph(d, n_tables=128, span_levels=bad)
+    ref = sta.Graph(d, n_tables=128)
+    for caps in ((1, 1), (3, 5), (8, 2)):
+        g = sta.Graph(d, n_tables=128, span_levels=caps)
+        f, b = g.span_list()
+        assert np.all(f[:, 1] - f[:, 0] + 1 <= caps[0]) and np.all(b[:, 0] - b[:, 1] + 1 <= caps[1])
+        assert f[0, 0] == 1 and f[-1, 1] == d_levels(ref) and b[0, 0] == d_levels(ref) and b[-1, 1] == 0
+        np.testing.assert_array_equal(g.level, ref.level)
+        np.testing.assert_array_equal(g.drv_input, ref.drv_input)
+        assert g.spans["fwd_span_arcs"] == ref.spans["fwd_span_arcs"] == d.n_arcs
+    g1 = sta.Graph(d, n_tables=128, span_levels=(1, 1))
+    assert g1.spans["fwd_span_launches"] == d_levels(ref)
+
+
+def d_levels(g):
+    return g.sizes["n_levels"]
