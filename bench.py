@@ -462,6 +462,14 @@ def surrogate_bench(dev, n_nets, train_steps, tol_ps=1.0):
     ms_exact = _time_ms(lambda: sur.exact(tr, d_ex, s_ex))
     ms_sur = _time_ms(lambda: sur.evaluate(tr, model, feat, tol_ps, buf))
     ms_net = _time_ms(lambda: sur.predict(model, feat, y))
+    feat2 = torch.empty_like(feat)
+    ms_feat = _time_ms(lambda: sur.features(tr, feat2))
+    same_feat = bool(torch.equal(feat2, feat))
+
+    def end_to_end():
+        sur.features(tr, feat2)
+        sur.evaluate(tr, model, feat2, tol_ps, buf)
+    ms_e2e = _time_ms(end_to_end)
     torch.cuda.synchronize()
     tr.check_status()
     served = 1.0 - int(buf.count.item()) / N
@@ -480,16 +488,27 @@ def surrogate_bench(dev, n_nets, train_steps, tol_ps=1.0):
     exact_bytes = 12 * M + 16 * S + 12 * N
     net_bytes = 56 * S
     net_flops = 9984 * S
+    feat_bytes = 12 * M + 8 * S + 52 * S + 12 * N    # node R/C/parent, sink node/cap, 48 B out, net data
+    net_hbm = net_bytes / (ms_net * 1e-3) / 1e9
+    net_mfma = net_flops / (ms_net * 1e-3) / 1e12
     return {
         "workload": f"{N} random recursive RC trees, 2-64 nodes (R 10-500 ohm, C 0.1-5 fF), {S} sinks "
                     f"(leaves), 12 features per sink -> MLP 12-64-64-2, BF16 operands / FP32 accumulate",
         "nets": N, "sinks": S, "rc_nodes": M, "tol_ps": tol_ps,
-        "exact_ms": ms_exact, "surrogate_ms": ms_sur, "speedup_vs_exact": ms_exact / ms_sur,
+        "exact_ms": ms_exact,
+        "end_to_end_ms": ms_e2e, "end_to_end_speedup_vs_exact": ms_exact / ms_e2e,
+        "end_to_end": "features (k_tree_features, no moment sweeps) + network, decode, error bound and "
+                      "exact fallback of the untrusted nets (sta_surrogate_eval)",
+        "features_ms": ms_feat, "features_bitwise_equal_to_dataset": same_feat,
+        "surrogate_on_resident_features_ms": ms_sur, "speedup_vs_exact_on_resident_features": ms_exact / ms_sur,
         "nets_served_by_network": served,
         "network_only_ms": ms_net, "network_only_speedup_vs_exact": ms_exact / ms_net,
         "exact_GB_s": exact_bytes / (ms_exact * 1e-3) / 1e9,
-        "network_GB_s": net_bytes / (ms_net * 1e-3) / 1e9,
-        "network_TFLOP_s": net_flops / (ms_net * 1e-3) / 1e12,
+        "features_GB_s": feat_bytes / (ms_feat * 1e-3) / 1e9,
+        "network_GB_s": net_hbm, "network_TFLOP_s": net_mfma,
+        "network_roofline": {"bytes_per_sink": 56, "flops_per_sink": 9984,
+                             "hbm_frac": net_hbm / HBM_PEAK_GBS, "mfma_bf16_frac": net_mfma / 2500.0,
+                             "bound": "hbm" if net_bytes / 8e12 > net_flops / 2.5e15 else "mfma"},
         "test_delay_rms_ps": {"network": float(np.sqrt(np.mean(e_net ** 2))),
                               "elmore_bound_midpoint": float(np.sqrt(np.mean(e_mid ** 2)))},
         "test_sinks_within_tol": {"network": float(np.mean(e_net <= tol_ps)),

@@ -4,8 +4,11 @@
  * Background.  Heteroflow's timing workload (Section IV-A) fits a regression model per
  * timing view on the GPU by gradient descent, next to the timer itself.  The learned
  * part here is a small network that predicts the Elmore delay and the PERI slew of every
- * sink of an RC-tree net from 12 cheap features, trained on this library's own exact
- * moments, with the exact computation as fallback and as error judge:
+ * sink of an RC-tree net from 12 features, trained on this library's own exact moments,
+ * with the exact computation as fallback and as error judge.  The features are not free:
+ * the downstream cap and the path sums need one upward sweep and a walk from every sink to
+ * the driver (sta_tree_features), against the four sweeps of the exact moments, so an RC
+ * tree's features cost about half of its exact delay and slew:
  *
  *   exact:      m1, m2 per tree node by the upward/downward sweeps of the RC-tree moments
  *               (the same definition sta_delay_calc uses on the nets of a timing graph),
@@ -97,6 +100,13 @@ typedef struct {
    pointer may be NULL.  One thread per net, FP64 sweeps in the order of the definition. */
 sta_status sta_tree_dataset(const sta_trees* t, float* feat, float* target, float* delay, float* slew,
                             int32_t* status, void* stream);
+
+/* Passage: Section IV-A (the inputs of the regression the correlation layer fits).
+ * The 12 features of every sink only, feat[S][12] (16-byte aligned), bit for bit those of
+ * sta_tree_dataset, without its moment sweeps: node caps, the downstream caps and each
+ * sink's path to the driver.  One wavefront per net.  Errors: STA_E_ARG; a malformed net
+ * sets a bit of *status as in sta_tree_exact. */
+sta_status sta_tree_features(const sta_trees* t, float* feat, int32_t* status, void* stream);
 
 /* Exact delay[S] and slew[S] (FP64 moments).  With net_list == NULL every net is done;
    otherwise only nets net_list[0 .. *net_count - 1] (net_count is a device int32 <= n_nets)

@@ -330,6 +330,116 @@ __global__ __launch_bounds__(256) void k_tree_exact(sta_trees T, const int32_t* 
 }
 
 
+// The 12 features of every sink (those of k_tree_dataset, bit for bit) without the
+// moments: one wavefront per net, lane k = local node k.  Node caps (pin caps added in
+// ascending sink order), downstream caps in rounds of decreasing depth (children in
+// descending index order, as the sequential definition), and each sink's path to the
+// driver walked upward from the sink (path resistance, path capacitance, depth, first-edge
+// resistance), with the net's R and C sums in ascending node order.
+__global__ __launch_bounds__(256) void k_tree_features(sta_trees T, float* __restrict__ feat, int32_t* status) {
+    __shared__ double s_cd[kExactWaves][kMaxN];     // downstream cap
+    __shared__ double s_c[kExactWaves][kMaxN];      // node cap (wire + pin caps)
+    __shared__ float s_r[kExactWaves][kMaxN];
+    __shared__ float s_cw[kExactWaves][kMaxN];      // wire cap
+    __shared__ int s_par[kExactWaves][kMaxN];
+    __shared__ unsigned long long s_ch[kExactWaves][kMaxN];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int n = blockIdx.x * kExactWaves + wv;
+    if (n >= T.n_nets) return;
+    const int n0 = T.net_node_ptr[n];
+    const int nm = T.net_node_ptr[n + 1] - n0;
+    const int s0 = T.sink_ptr[n], s1 = T.sink_ptr[n + 1];
+    if (nm < 1 || nm > kMaxN || s1 < s0) {
+        if (lane == 0) flag_err(status, STA_TREE_ERR_SIZE);
+        return;
+    }
+    const bool act = lane < nm;
+    const int p = (act && lane > 0) ? T.node_parent[n0 + lane] : 0;
+    if (__ballot(act && lane > 0 && (p < 0 || p >= lane))) {
+        if (lane == 0) flag_err(status, STA_TREE_ERR_PARENT);
+        return;
+    }
+    const float Rk = act ? T.node_R[n0 + lane] : 0.0f;
+    const float Cw = act ? T.node_C[n0 + lane] : 0.0f;
+    double Ck = static_cast<double>(Cw);
+    for (int c = s0; c < s1; c += 64) {
+        const bool sv = c + lane < s1;
+        const int k = sv ? T.sink_node[c + lane] : 0;
+        const float cap = sv ? T.sink_pincap[c + lane] : 0.0f;
+        if (__ballot(k < 0 || k >= nm)) {
+            if (lane == 0) flag_err(status, STA_TREE_ERR_SINK);
+            return;
+        }
+        const int ns = min(64, s1 - c);
+        for (int j = 0; j < ns; ++j) {
+            const int kj = __builtin_amdgcn_readlane(k, j);
+            const float cj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cap), j));
+            if (kj == lane) Ck += static_cast<double>(cj);
+        }
+    }
+    s_ch[wv][lane] = 0ull;
+    s_c[wv][lane] = Ck;
+    s_r[wv][lane] = Rk;
+    s_cw[wv][lane] = Cw;
+    s_par[wv][lane] = p;
+    wave_sync();
+    if (act && lane > 0) atomicOr(&s_ch[wv][p], 1ull << lane);
+    int anc = p, dep = (act && lane > 0) ? 1 : 0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        const int da = __shfl(dep, anc);
+        const int aa = __shfl(anc, anc);
+        dep += da;
+        anc = aa;
+    }
+    const int maxd = wave_max_i32(dep);
+    wave_sync();
+    const unsigned long long ch = s_ch[wv][lane];
+    for (int r = maxd; r >= 0; --r) {
+        if (act && dep == r) {
+            double acc = Ck;
+            unsigned long long m = ch;
+            while (m) {
+                const int c = 63 - __clzll(static_cast<long long>(m));
+                acc += s_cd[wv][c];
+                m &= ~(1ull << c);
+            }
+            s_cd[wv][lane] = acc;
+        }
+        wave_sync();
+    }
+    // the net's resistance and wire-cap sums in ascending node order (every lane walks the
+    // same LDS values, so every lane holds them; reading them lane by lane from registers
+    // instead was measured slower)
+    double sumR = 0.0, sumC = 0.0;
+    for (int k = 1; k < nm; ++k) sumR += static_cast<double>(s_r[wv][k]);
+    for (int k = 0; k < nm; ++k) sumC += static_cast<double>(s_cw[wv][k]);
+    const double load = s_cd[wv][0];
+    const float S = T.drv_slew[n];
+    const float meanR = static_cast<float>(nm > 1 ? sumR / static_cast<double>(nm - 1) : 0.0);
+    const float meanC = static_cast<float>(sumC / static_cast<double>(nm));
+    for (int c = s0; c < s1; c += 64) {
+        const int s = c + lane;
+        if (s >= s1) continue;
+        const int k = T.sink_node[s];
+        double rpath = 0.0, cpath = 0.0, rfirst = 0.0;
+        int depth = 0;
+        for (int v = k; v != 0; v = s_par[wv][v]) {
+            rpath += static_cast<double>(s_r[wv][v]);
+            cpath += s_c[wv][v];
+            if (s_par[wv][v] == 0) rfirst = static_cast<double>(s_r[wv][v]);
+            ++depth;
+        }
+        float4* f = reinterpret_cast<float4*>(feat + static_cast<size_t>(s) * 12);
+        f[0] = make_float4(static_cast<float>(rpath), static_cast<float>(load), static_cast<float>(s_cd[wv][k]),
+                           static_cast<float>(depth));
+        f[1] = make_float4(static_cast<float>(nm), static_cast<float>(s1 - s0), static_cast<float>(rfirst),
+                           static_cast<float>(cpath));
+        f[2] = make_float4(meanR, meanC, T.sink_pincap[s], S);
+    }
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t n, int32_t v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -711,23 +821,38 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ P, co
     }
 }
 
-// Sum of the per-wave partials (four interleaved groups of waves per parameter, each in
-// wave order, then the groups in order: a fixed order); optional gradient output;
-// optional Adam.  64 parameters per 256-lane block.
-__global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ P, float* __restrict__ m, float* __restrict__ v,
-                                                  const float* __restrict__ part, int32_t waves,
-                                                  float* __restrict__ grad, int32_t adam, float lr, float b1, float b2,
-                                                  float eps, float bc1, float bc2) {
-    __shared__ float red[4][64];
+// Sum of the per-wave partials in a fixed order (sixteen interleaved groups of waves per
+// parameter, each summed in wave order from loads issued eight at a time, then the groups
+// in order); optional gradient output; optional Adam.  64 parameters per 1024-lane block.
+constexpr int kAdamGroups = 16;
+__global__ __launch_bounds__(64 * kAdamGroups) void k_mlp_adam(float* __restrict__ P, float* __restrict__ m,
+                                                               float* __restrict__ v, const float* __restrict__ part,
+                                                               int32_t waves, float* __restrict__ grad, int32_t adam,
+                                                               float lr, float b1, float b2, float eps, float bc1,
+                                                               float bc2) {
+    __shared__ float red[kAdamGroups][64];
     const int pl = threadIdx.x & 63, grp = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + pl;
     float gs = 0.0f;
-    if (p <= STA_MLP_PARAMS)
-        for (int w = grp; w < waves; w += 4) gs += part[static_cast<size_t>(w) * kPartStride + p];
+    if (p <= STA_MLP_PARAMS) {
+        for (int w0 = grp; w0 < waves; w0 += 8 * kAdamGroups) {
+            float x[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int w = w0 + r * kAdamGroups;
+                x[r] = w < waves ? part[static_cast<size_t>(w) * kPartStride + p] : 0.0f;
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                if (w0 + r * kAdamGroups < waves) gs += x[r];
+        }
+    }
     red[grp][pl] = gs;
     __syncthreads();
     if (grp != 0 || p > STA_MLP_PARAMS) return;
-    gs = ((red[0][pl] + red[1][pl]) + red[2][pl]) + red[3][pl];
+    gs = red[0][pl];
+#pragma unroll
+    for (int q = 1; q < kAdamGroups; ++q) gs += red[q][pl];
     if (grad) grad[p] = gs;
     if (!adam || p == STA_MLP_PARAMS) return;
     const float mm = b1 * m[p] + (1.0f - b1) * gs;
@@ -939,6 +1064,19 @@ sta_status sta_tree_exact(const sta_trees* t, const int32_t* net_list, const int
     return launch_check("sta_tree_exact");
 }
 
+sta_status sta_tree_features(const sta_trees* t, float* feat, int32_t* status, void* stream) {
+    std::string why;
+    if (!trees_ok(t, false, why)) return fail(STA_E_ARG, "sta_tree_features: " + why);
+    if (t->n_sinks > 0 && (!feat || !aligned16(feat))) return fail(STA_E_ARG, "sta_tree_features: null or unaligned feat");
+    if (t->n_nets == 0) return STA_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    prof_launch("k_tree_features", s, [&] {
+        hipLaunchKernelGGL(k_tree_features, dim3((t->n_nets + kExactWaves - 1) / kExactWaves), dim3(256), 0, s, *t,
+                           feat, status);
+    });
+    return launch_check("sta_tree_features");
+}
+
 size_t sta_mlp_norm_scratch_bytes(void) { return sizeof(double) * 24 * kNormBlocks; }
 
 sta_status sta_mlp_norm(const float* feat, int32_t n, float* norm, void* scratch, size_t scratch_bytes,
@@ -990,8 +1128,8 @@ sta_status sta_mlp_train_step(float* params, float* adam_m, float* adam_v, const
         bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(b2), opt->step));
     }
     prof_launch("k_mlp_adam", s, [&] {
-        hipLaunchKernelGGL(k_mlp_adam, dim3((STA_MLP_PARAMS + 1 + 63) / 64), dim3(256), 0, s, params, adam_m,
-                           adam_v, part, waves, grad, opt ? 1 : 0, lr, b1, b2, eps, bc1, bc2);
+        hipLaunchKernelGGL(k_mlp_adam, dim3((STA_MLP_PARAMS + 1 + 63) / 64), dim3(64 * kAdamGroups), 0, s, params,
+                           adam_m, adam_v, part, waves, grad, opt ? 1 : 0, lr, b1, b2, eps, bc1, bc2);
     });
     return launch_check("sta_mlp_train_step");
 }

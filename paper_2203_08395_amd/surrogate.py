@@ -44,6 +44,7 @@ def _lib():
         sz = ctypes.c_size_t
         lib.sta_tree_dataset.argtypes = [T, _P, _P, _P, _P, _P, _P]
         lib.sta_tree_exact.argtypes = [T, _P, _P, _P, _P, _P, _P]
+        lib.sta_tree_features.argtypes = [T, _P, _P, _P]
         lib.sta_mlp_norm_scratch_bytes.argtypes = []
         lib.sta_mlp_norm_scratch_bytes.restype = sz
         lib.sta_mlp_norm.argtypes = [_P, ctypes.c_int32, _P, _P, sz, _P]
@@ -57,14 +58,14 @@ def _lib():
         lib.sta_surrogate_calibrate.argtypes = [_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                                 _P, sz, _P]
         lib.sta_surrogate_eval.argtypes = [T, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P, _P, _P, _P]
-        for f in ("sta_tree_dataset", "sta_tree_exact", "sta_mlp_norm", "sta_mlp_train_step", "sta_mlp_predict",
+        for f in ("sta_tree_dataset", "sta_tree_exact", "sta_tree_features", "sta_mlp_norm", "sta_mlp_train_step", "sta_mlp_predict",
                   "sta_surrogate_calibrate", "sta_surrogate_eval"):
             getattr(lib, f).restype = ctypes.c_int
         _bound = True
     return lib
 
 
-EXPORTS = ("sta_tree_dataset", "sta_tree_exact", "sta_mlp_norm_scratch_bytes", "sta_mlp_norm",
+EXPORTS = ("sta_tree_dataset", "sta_tree_exact", "sta_tree_features", "sta_mlp_norm_scratch_bytes", "sta_mlp_norm",
            "sta_mlp_grad_scratch_bytes", "sta_mlp_train_step", "sta_mlp_predict", "sta_surrogate_cal_scratch_bytes",
            "sta_surrogate_calibrate", "sta_surrogate_eval")
 
@@ -111,6 +112,16 @@ def dataset(tr: Trees):
     _check(_lib().sta_tree_dataset(ctypes.byref(tr.c), _ptr(out["feat"]), _ptr(out["target"]), _ptr(out["delay"]),
                                    _ptr(out["slew"]), _ptr(tr.status), tr.stream()), "sta_tree_dataset")
     return out
+
+
+def features(tr: Trees, feat=None):
+    """Features [S][12] only (sta_tree_features: no moment sweeps)."""
+    import torch
+    if feat is None:
+        feat = torch.empty((tr.n_sinks, 12), dtype=torch.float32, device=tr.device)
+    _check(_lib().sta_tree_features(ctypes.byref(tr.c), _ptr(feat), _ptr(tr.status), tr.stream()),
+           "sta_tree_features")
+    return feat
 
 
 def exact(tr: Trees, delay=None, slew=None, net_list=None, net_count=None):

@@ -63,6 +63,16 @@ def test_tree_dataset_bitwise(trees):
     np.testing.assert_array_equal(out["slew"].cpu().numpy(), exp_t[:, 1])
 
 
+def test_tree_features_bitwise(trees):
+    """The features-only kernel gives the training set's features bit for bit."""
+    from paper_2203_08395_amd import surrogate as sur
+    T, tr = trees
+    f = sur.features(tr)
+    tr.check_status()
+    mom = oracle.tree_moments(T, features=True)
+    np.testing.assert_array_equal(f.cpu().numpy(), mom["feat"].astype(np.float32))
+
+
 def test_tree_exact_all_and_listed(trees):
     import torch
     from paper_2203_08395_amd import surrogate as sur
@@ -99,6 +109,9 @@ def test_tree_data_errors_are_flagged():
         assert int(tr.status.item()) == bit
         with pytest.raises(ValueError):
             tr.check_status()
+        tr.status.zero_()
+        sur.features(tr)
+        assert int(tr.status.item()) == bit
 
 
 def test_norm_stats_match_oracle(trees):
