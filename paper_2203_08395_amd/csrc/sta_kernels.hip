@@ -1009,12 +1009,12 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
         const int sac = sa_[c] >= 0 ? sa_[c] : 0;
-        const float* ts = arc_ts + size_t(sac) * NV * 2;
-        const float* dt = drv_ts + size_t(drv[c]) * NV * 2;
+        const float* ts = arc_ts + (size_t(sac) * NV + v0) * 2;
+        const float* dt = drv_ts + (size_t(drv[c]) * NV + v0) * 2;
 #pragma unroll
         for (int v = 0; v < NW; ++v) {
-            ati[c][v] = ts[2 * (v0 + v)];
-            atd[c][v] = dt[2 * (v0 + v)];
+            ati[c][v] = ts[2 * v];
+            atd[c][v] = dt[2 * v];
         }
     }
     asm volatile("" ::: "memory");             // and these stay here, in flight
