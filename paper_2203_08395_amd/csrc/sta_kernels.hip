@@ -39,11 +39,14 @@ namespace sta {
 // ---------------------------------------------------------------------------------
 
 // Lane t of the block owns net (blockIdx.x*NT + t).  Node temporaries live in LDS,
-// interleaved by lane: slot (k, t) at [k*NT + t].
-// One net's moments (the driver d's lane), node temporaries in the caller's LDS arrays
-// sA, sB, sM of MAXN * NT values interleaved by lane t.
+// interleaved by lane: slot (k, t) at [k*NT + t], two arrays per lane:
+//   X: C (node cap), then W = C m1 (in place), its downstream sums, then m2 (in place);
+//   Y: Cd (downstream cap), then m1 (in place).
+// In place is exact: m1(k) reads m1(parent(k)) (parent < k, already final) and Cd(k)
+// (not yet overwritten) in ascending k, and m2 likewise reads W; the operations and their
+// order are those of the definition, so the results are the same bit for bit.
 template <typename T, int MAXN, int NT>
-__device__ __forceinline__ void dc_net(const DevGraph& G, int d, int t, T* sA, T* sB, T* sM, float* __restrict__ load,
+__device__ __forceinline__ void dc_net(const DevGraph& G, int d, int t, T* sX, T* sY, float* __restrict__ load,
                                        float* __restrict__ net_delay, float* __restrict__ net_imp2,
                                        float* __restrict__ arc_load) {
     const int n0 = G.net_node_ptr[d];
@@ -51,33 +54,32 @@ __device__ __forceinline__ void dc_net(const DevGraph& G, int d, int t, T* sA, T
     const int16_t* par = G.node_parent + n0;
     const float* R = G.node_R + n0;
     const float* Cw = G.node_C + n0;
-    T* A = sA + t;
-    T* B = sB + t;
-    T* Mm = sM + t;
+    T* X = sX + t;
+    T* Y = sY + t;
 #define AT_(arr, k) arr[(k) * NT]
-    for (int k = 0; k < nm; ++k) AT_(A, k) = static_cast<T>(Cw[k]);
+    for (int k = 0; k < nm; ++k) AT_(X, k) = static_cast<T>(Cw[k]);
     const int f0 = G.fo_ptr[d], f1 = G.fo_ptr[d + 1];
-    for (int e = f0; e < f1; ++e) AT_(A, G.fo_tap[e]) += static_cast<T>(G.fo_cap[e]);
-    for (int k = 0; k < nm; ++k) AT_(B, k) = AT_(A, k);
-    for (int k = nm - 1; k >= 1; --k) AT_(B, par[k]) += AT_(B, k);
-    const float ld = static_cast<float>(AT_(B, 0));
+    for (int e = f0; e < f1; ++e) AT_(X, G.fo_tap[e]) += static_cast<T>(G.fo_cap[e]);
+    for (int k = 0; k < nm; ++k) AT_(Y, k) = AT_(X, k);
+    for (int k = nm - 1; k >= 1; --k) AT_(Y, par[k]) += AT_(Y, k);
+    const float ld = static_cast<float>(AT_(Y, 0));
     load[d] = ld;
     if (d >= G.n_pi) {
         const int q = d - G.n_pi;
         for (int a = G.gate_arc_ptr[q]; a < G.gate_arc_ptr[q + 1]; ++a) arc_load[a] = ld;
     }
     const T milli = static_cast<T>(1e-3);
-    AT_(Mm, 0) = T(0);
-    for (int k = 1; k < nm; ++k) AT_(Mm, k) = AT_(Mm, par[k]) + (static_cast<T>(R[k]) * AT_(B, k)) * milli;
-    for (int k = 0; k < nm; ++k) AT_(B, k) = AT_(A, k) * AT_(Mm, k);
-    for (int k = nm - 1; k >= 1; --k) AT_(B, par[k]) += AT_(B, k);
-    AT_(A, 0) = T(0);
-    for (int k = 1; k < nm; ++k) AT_(A, k) = AT_(A, par[k]) + (static_cast<T>(R[k]) * AT_(B, k)) * milli;
+    AT_(Y, 0) = T(0);
+    for (int k = 1; k < nm; ++k) AT_(Y, k) = AT_(Y, par[k]) + (static_cast<T>(R[k]) * AT_(Y, k)) * milli;
+    for (int k = 0; k < nm; ++k) AT_(X, k) = AT_(X, k) * AT_(Y, k);
+    for (int k = nm - 1; k >= 1; --k) AT_(X, par[k]) += AT_(X, k);
+    AT_(X, 0) = T(0);
+    for (int k = 1; k < nm; ++k) AT_(X, k) = AT_(X, par[k]) + (static_cast<T>(R[k]) * AT_(X, k)) * milli;
     for (int e = f0; e < f1; ++e) {
         const int k = G.fo_tap[e];
         const int a = G.fo_arc[e];
-        const T m1 = AT_(Mm, k);
-        T imp2 = T(2) * AT_(A, k) - m1 * m1;
+        const T m1 = AT_(Y, k);
+        T imp2 = T(2) * AT_(X, k) - m1 * m1;
         if (imp2 < T(0)) imp2 = T(0);
         net_delay[a] = static_cast<float>(m1);
         net_imp2[a] = static_cast<float>(imp2);
@@ -90,7 +92,7 @@ __device__ __forceinline__ void dc_net(const DevGraph& G, int d, int t, T* sA, T
 // that use them, so a net costs a few memory round trips instead of one per loop step.
 // The arithmetic and its order are dc_net's.
 template <typename T, int NT>
-__device__ __forceinline__ void dc_net8(const DevGraph& G, int d, int t, T* sA, T* sB, T* sM, float* __restrict__ load,
+__device__ __forceinline__ void dc_net8(const DevGraph& G, int d, int t, T* sX, T* sY, float* __restrict__ load,
                                         float* __restrict__ net_delay, float* __restrict__ net_imp2,
                                         float* __restrict__ arc_load) {
     const int n0 = G.net_node_ptr[d];
@@ -117,54 +119,53 @@ __device__ __forceinline__ void dc_net8(const DevGraph& G, int d, int t, T* sA, 
         }
     };
     if (f1 > f0) load_sinks(f0);
-    T* A = sA + t;
-    T* B = sB + t;
-    T* Mm = sM + t;
+    T* X = sX + t;
+    T* Y = sY + t;
 #define AT_(arr, k) arr[(k) * NT]
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-        if (k < nm) AT_(A, k) = static_cast<T>(Cw[k]);
+        if (k < nm) AT_(X, k) = static_cast<T>(Cw[k]);
     for (int e0 = f0; e0 < f1; e0 += 8) {
         if (e0 != f0) load_sinks(e0);
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-            if (e0 + j < f1) AT_(A, tap[j]) += static_cast<T>(cap[j]);
+            if (e0 + j < f1) AT_(X, tap[j]) += static_cast<T>(cap[j]);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-        if (k < nm) AT_(B, k) = AT_(A, k);
+        if (k < nm) AT_(Y, k) = AT_(X, k);
 #pragma unroll
     for (int k = 7; k >= 1; --k)
-        if (k < nm) AT_(B, par[k]) += AT_(B, k);
-    const float ld = static_cast<float>(AT_(B, 0));
+        if (k < nm) AT_(Y, par[k]) += AT_(Y, k);
+    const float ld = static_cast<float>(AT_(Y, 0));
     load[d] = ld;
     if (d >= G.n_pi) {
         const int q = d - G.n_pi;
         for (int a = G.gate_arc_ptr[q]; a < G.gate_arc_ptr[q + 1]; ++a) arc_load[a] = ld;
     }
     const T milli = static_cast<T>(1e-3);
-    AT_(Mm, 0) = T(0);
+    AT_(Y, 0) = T(0);
 #pragma unroll
     for (int k = 1; k < 8; ++k)
-        if (k < nm) AT_(Mm, k) = AT_(Mm, par[k]) + (static_cast<T>(R[k]) * AT_(B, k)) * milli;
+        if (k < nm) AT_(Y, k) = AT_(Y, par[k]) + (static_cast<T>(R[k]) * AT_(Y, k)) * milli;
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-        if (k < nm) AT_(B, k) = AT_(A, k) * AT_(Mm, k);
+        if (k < nm) AT_(X, k) = AT_(X, k) * AT_(Y, k);
 #pragma unroll
     for (int k = 7; k >= 1; --k)
-        if (k < nm) AT_(B, par[k]) += AT_(B, k);
-    AT_(A, 0) = T(0);
+        if (k < nm) AT_(X, par[k]) += AT_(X, k);
+    AT_(X, 0) = T(0);
 #pragma unroll
     for (int k = 1; k < 8; ++k)
-        if (k < nm) AT_(A, k) = AT_(A, par[k]) + (static_cast<T>(R[k]) * AT_(B, k)) * milli;
+        if (k < nm) AT_(X, k) = AT_(X, par[k]) + (static_cast<T>(R[k]) * AT_(X, k)) * milli;
     for (int e0 = f0; e0 < f1; e0 += 8) {
         if (e0 != f0 || f1 - f0 > 8) load_sinks(e0);    // the first eight are still in registers
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             if (e0 + j >= f1) break;
             const int k = tap[j];
-            const T m1 = AT_(Mm, k);
-            T imp2 = T(2) * AT_(A, k) - m1 * m1;
+            const T m1 = AT_(Y, k);
+            T imp2 = T(2) * AT_(X, k) - m1 * m1;
             if (imp2 < T(0)) imp2 = T(0);
             net_delay[arc[j]] = static_cast<float>(m1);
             net_imp2[arc[j]] = static_cast<float>(imp2);
@@ -178,14 +179,13 @@ __global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict
                                                    float* __restrict__ net_delay,
                                                    float* __restrict__ net_imp2,
                                                    float* __restrict__ arc_load) {
-    __shared__ T sA[MAXN * NT];   // C, later m2
-    __shared__ T sB[MAXN * NT];   // Cd, later W
-    __shared__ T sM[MAXN * NT];   // m1
+    __shared__ T sX[MAXN * NT];   // C, then W, then m2
+    __shared__ T sY[MAXN * NT];   // Cd, then m1
     const int t = threadIdx.x;
     const int d = blockIdx.x * NT + t;
     if (d >= G.n_drivers) return;
-    if constexpr (MAXN == 8) dc_net8<T, NT>(G, d, t, sA, sB, sM, load, net_delay, net_imp2, arc_load);
-    else dc_net<T, MAXN, NT>(G, d, t, sA, sB, sM, load, net_delay, net_imp2, arc_load);
+    if constexpr (MAXN == 8) dc_net8<T, NT>(G, d, t, sX, sY, load, net_delay, net_imp2, arc_load);
+    else dc_net<T, MAXN, NT>(G, d, t, sX, sY, load, net_delay, net_imp2, arc_load);
 }
 
 // Batched delay calculation: workgroup x takes nets map[map0 + x].y * NT + t of design
@@ -193,16 +193,15 @@ __global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict
 template <typename T, int MAXN, int NT>
 __global__ __launch_bounds__(NT) void k_delay_calc_batch(const BatchItem* __restrict__ items,
                                                          const int2* __restrict__ map, int map0) {
-    __shared__ T sA[MAXN * NT];
-    __shared__ T sB[MAXN * NT];
-    __shared__ T sM[MAXN * NT];
+    __shared__ T sX[MAXN * NT];
+    __shared__ T sY[MAXN * NT];
     const int2 m = map[map0 + int(blockIdx.x)];
     const BatchItem& it = items[m.x];
     const int t = threadIdx.x;
     const int d = m.y * NT + t;
     if (d >= it.G.n_drivers) return;
-    if constexpr (MAXN == 8) dc_net8<T, NT>(it.G, d, t, sA, sB, sM, it.load_w, it.nd_w, it.ni_w, it.arc_load);
-    else dc_net<T, MAXN, NT>(it.G, d, t, sA, sB, sM, it.load_w, it.nd_w, it.ni_w, it.arc_load);
+    if constexpr (MAXN == 8) dc_net8<T, NT>(it.G, d, t, sX, sY, it.load_w, it.nd_w, it.ni_w, it.arc_load);
+    else dc_net<T, MAXN, NT>(it.G, d, t, sX, sY, it.load_w, it.nd_w, it.ni_w, it.arc_load);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1859,7 +1858,7 @@ static void launch_dc(const sta_graph* g, const sta_net_out* out, hipStream_t s)
 
 template <typename T>
 static void dispatch_dc(const sta_graph* g, const sta_net_out* out, hipStream_t s) {
-    // node temporaries: 3 * MAXN * NT values of T per block (48 KB for FP64)
+    // node temporaries: 2 * MAXN * NT values of T per block (32 KB for FP64)
     const int m = g->max_net_nodes;
     if (m <= 8) launch_dc<T, 8, 256>(g, out, s);
     else if (m <= 16) launch_dc<T, 16, 128>(g, out, s);
