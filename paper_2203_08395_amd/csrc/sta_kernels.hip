@@ -781,13 +781,13 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
 // The body of one forward span tile t of graph G, views v0 .. v0 + NW - 1 (tc: t clamped
 // into the launch's tiles, for the unconditional record loads; a wavefront with !valid
 // returns after them).  res: the wavefront's LDS results, kSpanSlotsF * NW values.
-template <int NV, int NW>
+template <int NV, int NW, bool PF>
 __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib, const KViews& V, int t, int tc,
                                               bool valid, int v0, const float* __restrict__ arc_load,
                                               const float* __restrict__ nd, const float* __restrict__ ni,
                                               float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                               float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
-                                              float2* res) {
+                                              float2* res, int pf_t = -1) {
     // the table axes in wave-uniform registers
     const Axis6 ax_x = axis6(lib, 0, 14), ax_y = axis6(lib, 7, 20);
     const int lane = threadIdx.x & 63;
@@ -830,6 +830,21 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
         const float2* sp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV + v0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) ext[c][w] = sp[w];
+    }
+    // the records of tile pf_t of the next span, loaded into this compute unit's L2 while
+    // round 2 is in flight (the next launch's workgroup of the same index runs on the same
+    // L2), and consumed only after the last level
+    // (without a next tile the wavefront reloads its own records: no branch, so that the
+    // compiler's waits for round 2 count past these loads)
+    int pfx = 0;
+    int4 pfa[kSpanF], pfc;
+    if constexpr (PF) {
+        const int pft = pf_t >= 0 ? pf_t : tc;
+        __builtin_amdgcn_sched_barrier(0);      // behind every load of round 2
+#pragma unroll
+        for (int c = 0; c < kSpanF; ++c) pfa[c] = G.sp_arec[size_t(pft * kSpanF + c) * 64 + lane];
+        pfc = G.sp_crec[pft * kSpanF + (lane & (kSpanF - 1))];
+        __builtin_amdgcn_sched_barrier(0);
     }
     // all of round 2 is in flight; keep it there (one wait before the first level)
 #pragma unroll
@@ -877,6 +892,12 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     });
+    if constexpr (PF) {
+#pragma unroll
+        for (int c = 0; c < kSpanF; ++c) pfx ^= pfa[c].x ^ pfa[c].y ^ pfa[c].z ^ pfa[c].w;
+        pfx ^= pfc.x ^ pfc.y ^ pfc.z ^ pfc.w;
+        asm volatile("" ::"v"(pfx));
+    }
 }
 
 template <int NV, int NW>
@@ -884,13 +905,16 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
                                                       const float* __restrict__ arc_load,
                                                       const float* __restrict__ nd, const float* __restrict__ ni,
                                                       float* __restrict__ drv_ts, float* __restrict__ arc_ts,
-                                                      float* __restrict__ arc_delay, uint8_t* __restrict__ argmax) {
+                                                      float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
+                                                      int pf0, int pf1) {
     __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NW];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = tile0 + blockIdx.x * kSpanWaves + wave;
     const int tc = t < tile1 ? t : tile1 - 1;
-    fwd_span_tile<NV, NW>(G, lib, V, t, tc, t < tile1, int(blockIdx.y) * NW, arc_load, nd, ni, drv_ts, arc_ts,
-                          arc_delay, argmax, s_res[wave]);
+    // the next span's tile of the same workgroup index (prefetched; -1: none)
+    const int pt = pf0 + (t - tile0);
+    fwd_span_tile<NV, NW, true>(G, lib, V, t, tc, t < tile1, int(blockIdx.y) * NW, arc_load, nd, ni, drv_ts,
+                                arc_ts, arc_delay, argmax, s_res[wave], pt < pf1 ? pt : -1);
 }
 
 // Batched forward spans: workgroup x of the launch runs tile map[map0 + x].y of design
@@ -903,8 +927,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     __shared__ float2 s_res[kSpanSlotsF * NW];
     const int2 m = map[map0 + int(blockIdx.x)];
     const BatchItem& it = items[m.x];
-    fwd_span_tile<NV, NW>(it.G, lib, V, m.y, m.y, true, int(blockIdx.y) * NW, it.arc_load, it.nd, it.ni, it.drv_ts,
-                          it.arc_ts, it.arc_delay, it.argmax, s_res);
+    fwd_span_tile<NV, NW, false>(it.G, lib, V, m.y, m.y, true, int(blockIdx.y) * NW, it.arc_load, it.nd, it.ni,
+                                 it.drv_ts, it.arc_ts, it.arc_delay, it.argmax, s_res);
 }
 
 // primary inputs: copy (arrival, slew) of every view
@@ -2049,10 +2073,16 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                 if (t1 <= t0) continue;
                 constexpr int NW = kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV;
                 const dim3 grid((t1 - t0 + kSpanWaves - 1) / kSpanWaves, NV / NW);
+                // the next fused span's tiles, for the record prefetch
+                int pf0 = 0, pf1 = 0;
+                if (sp + 1 < NS && g->span_fused_h[sp + 1]) {
+                    pf0 = g->span_tile_h[sp + 1];
+                    pf1 = g->span_tile_h[sp + 2];
+                }
                 prof_launch("k_forward_span", s, [&] {
                     hipLaunchKernelGGL((k_forward_span<NV, NW>), grid, dim3(64 * kSpanWaves), 0, s, dg, lib, kv, t0,
                                        t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts,
-                                       o->arc_delay, o->argmax);
+                                       o->arc_delay, o->argmax, pf0, pf1);
                 });
             }
             return;
