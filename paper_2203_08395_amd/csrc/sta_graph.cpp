@@ -54,6 +54,8 @@ DevGraph dev_graph(const sta_graph* g) {
     d.sp_arec = reinterpret_cast<const int4*>(b + L.sp_arec);
     d.bp_crec = reinterpret_cast<const int4*>(b + L.bp_crec);
     d.bp_srec = reinterpret_cast<const int4*>(b + L.bp_srec);
+    d.dc_wide = reinterpret_cast<const int32_t*>(b + L.dc_wide);
+    d.n_dc_wide = g->n_dc_wide;
     d.n_pi = g->n_pi;
     d.n_gates = g->n_gates;
     d.n_drivers = static_cast<int32_t>(g->D);
@@ -281,6 +283,10 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
             fo_cap[fo_ptr[i] + j] = d->arc_pincap[a];
         }
     }
+    std::vector<int32_t> dc_wide;
+    for (int64_t i = 0; i < D; ++i)
+        if (fo_ptr[i + 1] - fo_ptr[i] > kDcLaneSinks) dc_wide.push_back(int32_t(i));
+    g->n_dc_wide = int32_t(dc_wide.size());
     std::vector<int32_t> slot_ptr(D + 1, 0);
     for (int64_t i = 0; i < D; ++i) slot_ptr[i + 1] = slot_ptr[i] + std::max(1, fo_ptr[i + 1] - fo_ptr[i]);
     const int64_t S = slot_ptr[D];
@@ -832,6 +838,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
     lay.sp_arec = place(sp_arec.size() * 4);
     lay.bp_crec = place(bp_crec.size() * 4);
     lay.bp_srec = place(bp_srec.size() * 4);
+    lay.dc_wide = place(dc_wide.size() * 4);
     lay.total = off;
     g->image.assign(off, 0);
     auto put = [&](size_t o, const void* src, size_t bytes) { if (bytes) std::memcpy(g->image.data() + o, src, bytes); };
@@ -853,6 +860,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
     put(lay.bslot_arc, bslot_arc.data(), S * 4);
     put(lay.bslot_out, bslot_out.data(), S * 4);
     put(lay.ep_drv, g->ep_driver.data(), E * 4);
+    put(lay.dc_wide, dc_wide.data(), dc_wide.size() * 4);
     // level tables: forward level l (1..L) owns tiles [f[l].t, f[l+1].t), arcs and gates from
     // f[l].a and f[l].g on; backward level l (0..L) likewise with slots and drivers
     std::vector<int32_t> flvl((Lmax + 2) * 3), blvl((Lmax + 2) * 3);

@@ -48,6 +48,11 @@ constexpr int kBwdViewsPerWave = 2;
 // Largest view count the fused spans serve: all (1, 2, 4, 8; measured faster than the level
 // and view schedules for every count).
 constexpr int kSpanMaxViews = 8;
+// Delay calculation of nets of at most 8 nodes: one lane per net of at most kDcLaneSinks
+// sinks, a wavefront's first kDcWindow sinks staged in LDS; a net with more sinks (listed
+// in dc_wide) gets a wavefront of its own.
+constexpr int kDcLaneSinks = 16;
+constexpr int kDcWindow = 64 * kDcLaneSinks;
 
 // Device arrays of a graph (offsets in bytes into the one device buffer).
 struct DevLayout {
@@ -63,6 +68,7 @@ struct DevLayout {
     size_t bwd_chunk;              // per backward chunk (first tile, first slot, first driver, level)
     size_t sp_crec, sp_arec;       // fused forward spans: level and arc records per tile
     size_t bp_crec, bp_srec;       // fused backward spans: level and slot records per tile
+    size_t dc_wide;                // drivers of more than kDcLaneSinks sinks
     size_t total;
 };
 
@@ -99,7 +105,8 @@ struct DevGraph {
                            //   first LDS driver slot, most slots of a driver, levels of the tile
     const int4* bp_srec;   // [NT][kSpanB][64] per lane: sink arc (-1: endpoint slot), the
                            //   slot's output word (bslot_out), in-tile LDS source or -1, driver
-    int32_t n_pi, n_gates, n_drivers, n_arcs;
+    const int32_t* dc_wide;        // [n_dc_wide] drivers of more than kDcLaneSinks sinks, ascending
+    int32_t n_pi, n_gates, n_drivers, n_arcs, n_dc_wide;
 };
 
 // One graph of a batched launch: its device layout, chunk count, view count and buffers
@@ -160,6 +167,7 @@ struct sta_graph {
     int32_t n_pi = 0, n_gates = 0, n_tables = 0;
     int64_t D = 0, A = 0, M = 0, L = 0, E = 0, S = 0;
     int32_t max_fanin = 0, max_fanout = 0, max_net_nodes = 0;
+    int32_t n_dc_wide = 0;               // drivers of more than sta::kDcLaneSinks sinks
     std::vector<int32_t> drv_input, arc_input, gate_input, level, ep_driver;
     std::vector<int32_t> fwd_tile_ptr;   // [L+2]: tiles of gate level l are [p[l], p[l+1])
     std::vector<int32_t> ftile_arc_h, ftile_gate_h, btile_slot_h, btile_drv_h;   // host copies of the tiles

@@ -87,17 +87,129 @@ __device__ __forceinline__ void dc_net(const DevGraph& G, int d, int t, T* sX, T
 #undef AT_
 }
 
-// dc_net for nets of at most 8 nodes: the node data and the first eight sinks are loaded
-// into registers in one round (clamped, unconditional loads) instead of inside the loops
-// that use them, so a net costs a few memory round trips instead of one per loop step.
-// The arithmetic and its order are dc_net's.
-template <typename T, int NT>
-__device__ __forceinline__ void dc_net8(const DevGraph& G, int d, int t, T* sX, T* sY, float* __restrict__ load,
-                                        float* __restrict__ net_delay, float* __restrict__ net_imp2,
-                                        float* __restrict__ arc_load) {
-    const int n0 = G.net_node_ptr[d];
-    const int nm = G.net_node_ptr[d + 1] - n0;
-    const int f0 = G.fo_ptr[d], f1 = G.fo_ptr[d + 1];
+// Nets of at most 8 nodes keep every node value in registers (no LDS, so the launch's
+// residency is set by registers alone): a step that reads a node's parent, or a sink's tap
+// node, selects among the node registers, and a step that adds into a parent updates the
+// selected register only.  The arithmetic and its order are dc_net's, so the results are
+// the same bit for bit.
+
+// c ? t : f as explicit v_cndmask instructions: written as C++ selects over the node
+// registers, the compiler turns them back into indexed loads from scratch memory
+__device__ __forceinline__ float dc_sel(bool c, float t, float f) {
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(c);
+    float r;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(f), "v"(t), "s"(m));
+    return r;
+}
+__device__ __forceinline__ double dc_sel(bool c, double t, double f) {
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(c);
+    int lo, hi;
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(lo) : "v"(__double2loint(f)), "v"(__double2loint(t)), "s"(m));
+    asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(hi) : "v"(__double2hiint(f)), "v"(__double2hiint(t)), "s"(m));
+    return __hiloint2double(hi, lo);
+}
+
+// a[idx], idx in 0..7: a select tree on the bits of idx
+template <typename T>
+__device__ __forceinline__ T dc_pick(const T (&a)[8], int idx) {
+    const bool b0 = idx & 1, b1 = idx & 2, b2 = idx & 4;
+    const T l0 = dc_sel(b0, a[1], a[0]), l1 = dc_sel(b0, a[3], a[2]);
+    const T l2 = dc_sel(b0, a[5], a[4]), l3 = dc_sel(b0, a[7], a[6]);
+    return dc_sel(b2, dc_sel(b1, l3, l2), dc_sel(b1, l1, l0));
+}
+
+// The tree sweeps of a net of nm <= 8 nodes (parents par[k] < k), X holding each node's
+// capacitance with its pin caps added: Y becomes m1, X becomes m2; returns the total load.
+// chain (uniform): every net of the wavefront is a chain (par[k] = k - 1), so each parent
+// is known without a select.
+template <typename T>
+__device__ __forceinline__ float dc8_sweeps(T (&X)[8], T (&Y)[8], uint32_t pp, const float (&R)[8], int nm,
+                                            bool chain) {
+    // pp: the parents, 3 bits per node
+    auto par = [pp](int k) { return int((pp >> (3 * k)) & 7u); };
+    const T milli = static_cast<T>(1e-3);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) Y[k] = X[k];
+    float ld;
+    if (chain) {
+#pragma unroll
+        for (int k = 7; k >= 1; --k) Y[k - 1] = dc_sel(k < nm, Y[k - 1] + Y[k], Y[k - 1]);
+        ld = static_cast<float>(Y[0]);
+        Y[0] = T(0);
+#pragma unroll
+        for (int k = 1; k < 8; ++k) Y[k] = Y[k - 1] + (static_cast<T>(R[k]) * Y[k]) * milli;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) X[k] = X[k] * Y[k];
+#pragma unroll
+        for (int k = 7; k >= 1; --k) X[k - 1] = dc_sel(k < nm, X[k - 1] + X[k], X[k - 1]);
+        X[0] = T(0);
+#pragma unroll
+        for (int k = 1; k < 8; ++k) X[k] = X[k - 1] + (static_cast<T>(R[k]) * X[k]) * milli;
+        return ld;
+    }
+    // downstream capacitance: children added into their parent, highest node first
+#pragma unroll
+    for (int k = 7; k >= 1; --k)
+#pragma unroll
+        for (int p = 0; p < k; ++p) Y[p] = dc_sel(k < nm && par(k) == p, Y[p] + Y[k], Y[p]);
+    ld = static_cast<float>(Y[0]);
+    Y[0] = T(0);
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+        if (k < nm) Y[k] = dc_pick(Y, par(k)) + (static_cast<T>(R[k]) * Y[k]) * milli;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (k < nm) X[k] = X[k] * Y[k];
+#pragma unroll
+    for (int k = 7; k >= 1; --k)
+#pragma unroll
+        for (int p = 0; p < k; ++p) X[p] = dc_sel(k < nm && par(k) == p, X[p] + X[k], X[p]);
+    X[0] = T(0);
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+        if (k < nm) X[k] = dc_pick(X, par(k)) + (static_cast<T>(R[k]) * X[k]) * milli;
+    return ld;
+}
+
+// lane k's value of v, to every lane
+__device__ __forceinline__ double dc_lane_value(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), k);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), k);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<uint32_t>(lo));
+}
+__device__ __forceinline__ float dc_lane_value(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+template <typename T>
+__device__ __forceinline__ void dc8_store(const T (&X)[8], const T (&Y)[8], int k, int a,
+                                          float* __restrict__ net_delay, float* __restrict__ net_imp2) {
+    const T m1 = dc_pick(Y, k);
+    T imp2 = T(2) * dc_pick(X, k) - m1 * m1;
+    if (imp2 < T(0)) imp2 = T(0);
+    net_delay[a] = static_cast<float>(m1);
+    net_imp2[a] = static_cast<float>(imp2);
+}
+
+// One wavefront of the lane-per-net path: nets dw0 .. dw0 + 63 (those of at most
+// kDcLaneSinks sinks; a wider net is skipped: its own wavefront does it).  The wavefront's
+// sinks are one contiguous range; when it holds at most kDcWindow sinks (always, unless
+// wide nets crowd the wavefront) it is loaded coalesced into LDS (s_cap: pin cap, s_at:
+// arc | tap << 29) in the round that loads the lanes' nodes, and a lane reads its own
+// sinks from LDS; otherwise (STAGED false) each lane reads its sinks from memory.
+template <typename T, bool STAGED>
+__device__ __forceinline__ void dc8_lanes(const DevGraph& G, int dw0, int dwl, int n0, int nm, int f0, int f1,
+                                          int a0, int a1, float* __restrict__ s_cap, int* __restrict__ s_at,
+                                          float* __restrict__ load, float* __restrict__ net_delay,
+                                          float* __restrict__ net_imp2, float* __restrict__ arc_load) {
+    const int lane = threadIdx.x & 63;
+    const int d = dw0 + lane;
+    const bool act = d <= dwl;
+    // the wavefront's sink range, from its first and last lanes
+    const int F0 = __builtin_amdgcn_readfirstlane(f0);
+    const int F1 = __builtin_amdgcn_readlane(f1, dwl - dw0);
+    // the lanes' nodes and (STAGED) the wavefront's sinks, 256 per pass
     int par[8];
     float R[8], Cw[8];
 #pragma unroll
@@ -107,71 +219,159 @@ __device__ __forceinline__ void dc_net8(const DevGraph& G, int d, int t, T* sX, 
         R[k] = G.node_R[kk];
         Cw[k] = G.node_C[kk];
     }
-    int tap[8], arc[8];
-    float cap[8];
-    auto load_sinks = [&](int e0) {
+    if constexpr (STAGED) {
+        for (int c0 = F0; c0 < F1; c0 += 256) {            // uniform
+            int tv[4], av[4];
+            float cv[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int e = e0 + j < f1 ? e0 + j : f0;
-            tap[j] = G.fo_tap[e];
-            cap[j] = G.fo_cap[e];
-            arc[j] = G.fo_arc[e];
+            for (int i = 0; i < 4; ++i) {
+                const int e = c0 + i * 64 + lane;
+                const int ec = e < F1 ? e : F0;
+                tv[i] = G.fo_tap[ec];
+                cv[i] = G.fo_cap[ec];
+                av[i] = G.fo_arc[ec];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int e = c0 + i * 64 + lane;
+                if (e < F1) {
+                    s_cap[e - F0] = cv[i];
+                    s_at[e - F0] = av[i] | (tv[i] << 29);
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    const int ns = f1 - f0;
+    const bool mine = act && ns <= kDcLaneSinks;
+    uint32_t pp = 0;
+    bool chain = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        pp |= uint32_t(par[k] & 7) << (3 * k);
+        if (k >= 1) chain = chain && (k >= nm || par[k] == k - 1);
+    }
+    const bool all_chain = __builtin_amdgcn_ballot_w64(mine && !chain) == 0;
+    if (!mine) return;
+    T X[8], Y[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) X[k] = static_cast<T>(Cw[k]);
+    auto sink = [&](int e, int& tap, int& arc, float& cap) {
+        if constexpr (STAGED) {
+            const int at = s_at[e - F0];
+            tap = int(uint32_t(at) >> 29);
+            arc = at & 0x1fffffff;
+            cap = s_cap[e - F0];
+        } else {
+            tap = G.fo_tap[e];
+            arc = G.fo_arc[e];
+            cap = G.fo_cap[e];
         }
     };
-    if (f1 > f0) load_sinks(f0);
-    T* X = sX + t;
-    T* Y = sY + t;
-#define AT_(arr, k) arr[(k) * NT]
+    // pin caps added to their tap nodes in sink order
+    for (int e = f0; e < f1; ++e) {
+        int tj, aj;
+        float cj;
+        sink(e, tj, aj, cj);
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (k < nm) AT_(X, k) = static_cast<T>(Cw[k]);
-    for (int e0 = f0; e0 < f1; e0 += 8) {
-        if (e0 != f0) load_sinks(e0);
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (e0 + j < f1) AT_(X, tap[j]) += static_cast<T>(cap[j]);
+        for (int k = 0; k < 8; ++k) X[k] = dc_sel(tj == k, X[k] + static_cast<T>(cj), X[k]);
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (k < nm) AT_(Y, k) = AT_(X, k);
-#pragma unroll
-    for (int k = 7; k >= 1; --k)
-        if (k < nm) AT_(Y, par[k]) += AT_(Y, k);
-    const float ld = static_cast<float>(AT_(Y, 0));
+    const float ld = dc8_sweeps<T>(X, Y, pp, R, nm, all_chain);
     load[d] = ld;
-    if (d >= G.n_pi) {
-        const int q = d - G.n_pi;
-        for (int a = G.gate_arc_ptr[q]; a < G.gate_arc_ptr[q + 1]; ++a) arc_load[a] = ld;
+    for (int a = a0; a < a1; ++a) arc_load[a] = ld;
+    for (int e = f0; e < f1; ++e) {
+        int tj, aj;
+        float cj;
+        sink(e, tj, aj, cj);
+        dc8_store<T>(X, Y, tj, aj, net_delay, net_imp2);
     }
-    const T milli = static_cast<T>(1e-3);
-    AT_(Y, 0) = T(0);
+}
+
+// One wavefront: net d of more than kDcLaneSinks sinks (d uniform).  The lanes load 64
+// sinks at a time; the pin caps are added in sink order from broadcast lane values, every
+// lane running the same node arithmetic, and each lane then writes its own sinks.
+template <typename T>
+__device__ __forceinline__ void dc8_wave(const DevGraph& G, int d, float* __restrict__ load,
+                                         float* __restrict__ net_delay, float* __restrict__ net_imp2,
+                                         float* __restrict__ arc_load) {
+    const int lane = threadIdx.x & 63;
+    const int n0 = G.net_node_ptr[d];
+    const int nm = G.net_node_ptr[d + 1] - n0;
+    const int f0 = G.fo_ptr[d], f1 = G.fo_ptr[d + 1];
+    uint32_t pp = 0;
+    bool chain = true;
+    float R[8];
 #pragma unroll
-    for (int k = 1; k < 8; ++k)
-        if (k < nm) AT_(Y, k) = AT_(Y, par[k]) + (static_cast<T>(R[k]) * AT_(Y, k)) * milli;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (k < nm) AT_(X, k) = AT_(X, k) * AT_(Y, k);
-#pragma unroll
-    for (int k = 7; k >= 1; --k)
-        if (k < nm) AT_(X, par[k]) += AT_(X, k);
-    AT_(X, 0) = T(0);
-#pragma unroll
-    for (int k = 1; k < 8; ++k)
-        if (k < nm) AT_(X, k) = AT_(X, par[k]) + (static_cast<T>(R[k]) * AT_(X, k)) * milli;
-    for (int e0 = f0; e0 < f1; e0 += 8) {
-        if (e0 != f0 || f1 - f0 > 8) load_sinks(e0);    // the first eight are still in registers
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (e0 + j >= f1) break;
-            const int k = tap[j];
-            const T m1 = AT_(Y, k);
-            T imp2 = T(2) * AT_(X, k) - m1 * m1;
-            if (imp2 < T(0)) imp2 = T(0);
-            net_delay[arc[j]] = static_cast<float>(m1);
-            net_imp2[arc[j]] = static_cast<float>(imp2);
+    for (int k = 0; k < 8; ++k) {
+        const int kk = n0 + (k < nm ? k : 0);
+        const int pk = G.node_parent[kk];
+        pp |= uint32_t(pk & 7) << (3 * k);
+        if (k >= 1) chain = chain && (k >= nm || pk == k - 1);
+        R[k] = G.node_R[kk];
+    }
+    // lane k < 8 adds the pin caps of node k, in sink order, from the broadcast sink values
+    T acc = static_cast<T>(G.node_C[n0 + (lane < nm ? lane : 0)]);
+    for (int e0 = f0; e0 < f1; e0 += 64) {
+        const int e = e0 + lane < f1 ? e0 + lane : f0;
+        const int tv = G.fo_tap[e];
+        const float cv = G.fo_cap[e];
+        const int n = min(64, f1 - e0);
+        for (int j = 0; j < n; ++j) {
+            const int tj = __builtin_amdgcn_readlane(tv, j);
+            const T cj = static_cast<T>(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(cv), j)));
+            acc = dc_sel(tj == lane, acc + cj, acc);
         }
     }
-#undef AT_
+    T X[8], Y[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) X[k] = dc_lane_value(acc, k);
+    const float ld = dc8_sweeps<T>(X, Y, pp, R, nm, __builtin_amdgcn_ballot_w64(!chain) == 0);
+    if (lane == 0) load[d] = ld;
+    if (d >= G.n_pi) {
+        const int q = d - G.n_pi;
+        for (int a = G.gate_arc_ptr[q] + lane; a < G.gate_arc_ptr[q + 1]; a += 64) arc_load[a] = ld;
+    }
+    for (int e = f0 + lane; e < f1; e += 64) dc8_store<T>(X, Y, G.fo_tap[e], G.fo_arc[e], net_delay, net_imp2);
+}
+
+// Workgroup x (256 lanes) of the delay calculation of a graph whose nets have at most 8
+// nodes: the first ceil(n_dc_wide / 4) workgroups give each wide net a wavefront (first,
+// so that the longest nets start first), the rest one lane per net.
+template <typename T>
+__device__ __forceinline__ void dc8_block(const DevGraph& G, int x, float* __restrict__ load,
+                                          float* __restrict__ net_delay, float* __restrict__ net_imp2,
+                                          float* __restrict__ arc_load) {
+    __shared__ float s_cap[4][kDcWindow];
+    __shared__ int s_at[4][kDcWindow];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wb = (G.n_dc_wide + 3) >> 2;
+    if (x < wb) {
+        const int i = x * 4 + wave;
+        if (i < G.n_dc_wide) dc8_wave<T>(G, __builtin_amdgcn_readfirstlane(G.dc_wide[i]), load, net_delay, net_imp2, arc_load);
+        return;
+    }
+    const int dw0 = (x - wb) * 256 + wave * 64;
+    if (dw0 >= G.n_drivers) return;
+    // one round of loads: each lane's net pointers and gate (clamped to the last net)
+    const int dwl = min(dw0 + 63, G.n_drivers - 1);
+    const int dd = min(dw0 + int(threadIdx.x & 63), dwl);
+    const int n0 = G.net_node_ptr[dd];
+    const int nm = G.net_node_ptr[dd + 1] - n0;
+    const int f0 = G.fo_ptr[dd], f1 = G.fo_ptr[dd + 1];
+    const int q = dd >= G.n_pi ? dd - G.n_pi : -1;
+    const int a0 = q >= 0 ? G.gate_arc_ptr[q] : 0, a1 = q >= 0 ? G.gate_arc_ptr[q + 1] : 0;
+    const int span = __builtin_amdgcn_readlane(f1, dwl - dw0) - __builtin_amdgcn_readfirstlane(f0);
+    if (span <= kDcWindow && G.n_arcs <= (1 << 29))        // (arc | tap << 29 must fit)
+        dc8_lanes<T, true>(G, dw0, dwl, n0, nm, f0, f1, a0, a1, s_cap[wave], s_at[wave], load, net_delay, net_imp2, arc_load);
+    else
+        dc8_lanes<T, false>(G, dw0, dwl, n0, nm, f0, f1, a0, a1, nullptr, nullptr, load, net_delay, net_imp2, arc_load);
+}
+
+// workgroups of the delay calculation of g in node-count class maxn with nt lanes each
+static inline int dc_blocks_of(int64_t D, int32_t n_wide, int maxn, int nt) {
+    return int((D + nt - 1) / nt) + (maxn == 8 ? (n_wide + 3) / 4 : 0);
 }
 
 template <typename T, int MAXN, int NT>
@@ -184,8 +384,15 @@ __global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict
     const int t = threadIdx.x;
     const int d = blockIdx.x * NT + t;
     if (d >= G.n_drivers) return;
-    if constexpr (MAXN == 8) dc_net8<T, NT>(G, d, t, sX, sY, load, net_delay, net_imp2, arc_load);
-    else dc_net<T, MAXN, NT>(G, d, t, sX, sY, load, net_delay, net_imp2, arc_load);
+    dc_net<T, MAXN, NT>(G, d, t, sX, sY, load, net_delay, net_imp2, arc_load);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_delay_calc8(DevGraph G, float* __restrict__ load,
+                                                     float* __restrict__ net_delay,
+                                                     float* __restrict__ net_imp2,
+                                                     float* __restrict__ arc_load) {
+    dc8_block<T>(G, int(blockIdx.x), load, net_delay, net_imp2, arc_load);
 }
 
 // Batched delay calculation: workgroup x takes nets map[map0 + x].y * NT + t of design
@@ -200,8 +407,15 @@ __global__ __launch_bounds__(NT) void k_delay_calc_batch(const BatchItem* __rest
     const int t = threadIdx.x;
     const int d = m.y * NT + t;
     if (d >= it.G.n_drivers) return;
-    if constexpr (MAXN == 8) dc_net8<T, NT>(it.G, d, t, sX, sY, it.load_w, it.nd_w, it.ni_w, it.arc_load);
-    else dc_net<T, MAXN, NT>(it.G, d, t, sX, sY, it.load_w, it.nd_w, it.ni_w, it.arc_load);
+    dc_net<T, MAXN, NT>(it.G, d, t, sX, sY, it.load_w, it.nd_w, it.ni_w, it.arc_load);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_delay_calc8_batch(const BatchItem* __restrict__ items,
+                                                           const int2* __restrict__ map, int map0) {
+    const int2 m = map[map0 + int(blockIdx.x)];
+    const BatchItem& it = items[m.x];
+    dc8_block<T>(it.G, m.y, it.load_w, it.nd_w, it.ni_w, it.arc_load);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1873,16 +2087,21 @@ sta_status launch_check(const char* what) {
 
 template <typename T, int MAXN, int NT>
 static void launch_dc(const sta_graph* g, const sta_net_out* out, hipStream_t s) {
-    const int blocks = int((g->D + NT - 1) / NT);
+    const int blocks = dc_blocks_of(g->D, g->n_dc_wide, MAXN, NT);
     prof_launch("k_delay_calc", s, [&] {
-        hipLaunchKernelGGL((k_delay_calc<T, MAXN, NT>), dim3(blocks), dim3(NT), 0, s, dev_graph(g), out->load,
-                           out->net_delay, out->net_imp2, out->arc_load);
+        if constexpr (MAXN == 8)
+            hipLaunchKernelGGL((k_delay_calc8<T>), dim3(blocks), dim3(NT), 0, s, dev_graph(g), out->load,
+                               out->net_delay, out->net_imp2, out->arc_load);
+        else
+            hipLaunchKernelGGL((k_delay_calc<T, MAXN, NT>), dim3(blocks), dim3(NT), 0, s, dev_graph(g), out->load,
+                               out->net_delay, out->net_imp2, out->arc_load);
     });
 }
 
 template <typename T>
 static void dispatch_dc(const sta_graph* g, const sta_net_out* out, hipStream_t s) {
-    // node temporaries: 2 * MAXN * NT values of T per block (32 KB for FP64)
+    // nets of <= 8 nodes: registers only; larger: node temporaries in LDS, 2 * MAXN * NT
+    // values of T per block (32 KB for FP64)
     const int m = g->max_net_nodes;
     if (m <= 8) launch_dc<T, 8, 256>(g, out, s);
     else if (m <= 16) launch_dc<T, 16, 128>(g, out, s);
@@ -2764,8 +2983,8 @@ static bool batch_layout(const sta_batch_design* designs, int32_t n, int NV, Bat
             maps += eb;
             ep += eb;
         }
-        const int nt = dc_threads(dc_class(g));
-        maps += (g->D + nt - 1) / nt;
+        const int mc = dc_class(g);
+        maps += dc_blocks_of(g->D, g->n_dc_wide, mc, dc_threads(mc));
     }
     L->n_map = maps;
     L->n_ep = ep;
@@ -2794,7 +3013,7 @@ static void launch_dc_batch(const sta_batch* b, int maxn, int map0, int nblk, hi
         });
     };
     switch (maxn) {
-        case 8: go(k_delay_calc_batch<T, 8, 256>, 256); break;
+        case 8: go(k_delay_calc8_batch<T>, 256); break;
         case 16: go(k_delay_calc_batch<T, 16, 128>, 128); break;
         case 32: go(k_delay_calc_batch<T, 32, 64>, 64); break;
         case 64: go(k_delay_calc_batch<T, 64, 32>, 32); break;
@@ -3322,7 +3541,7 @@ sta_status sta_batch_create(const sta_batch_design* designs, int32_t n, const st
         const int nt = dc_threads(maxn);
         for (int k = 0; k < b->n_items; ++k) {
             if (dc_class(b->graphs[k]) != maxn) continue;
-            const int64_t nb = (b->graphs[k]->D + nt - 1) / nt;
+            const int64_t nb = dc_blocks_of(b->graphs[k]->D, b->graphs[k]->n_dc_wide, maxn, nt);
             for (int64_t x = 0; x < nb; ++x) map.push_back(make_int2(k, int(x)));
         }
         dc.nblk = int(map.size()) - dc.map0;

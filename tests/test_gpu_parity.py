@@ -92,6 +92,43 @@ def test_drivers_wider_than_a_tile(seed, n_tables, schedule):
     compare_all(d, lib, pa, ps, rat, [LATE, EARLY], label=f"wide drivers seed {seed}", schedule=schedule)
 
 
+def test_delay_calc_crowded_wavefront():
+    # nets of at most 8 nodes: a lane per net of up to 16 sinks, a wavefront per wider net.
+    # The first 64 drivers (one wavefront of the lane path) include 20 nets of 60 sinks, so
+    # the wavefront's sink range is longer than the lane path stages in LDS and its narrow
+    # nets read their sinks from memory; nets of exactly 16 and 17 sinks sit on either side
+    # of the lane path's limit, and a later wavefront with nets of 9..16 sinks is staged.
+    rng = np.random.default_rng(17)
+    n_pi = 200
+    fo = np.zeros(n_pi, np.int64)
+    fo[:20] = 60
+    fo[20:40] = rng.integers(9, 17, 20)
+    fo[40], fo[41] = 16, 17
+    fo[42:64] = rng.integers(0, 4, 22)
+    fo[64:128] = rng.integers(9, 17, 64)
+    fo[128:] = rng.integers(0, 5, n_pi - 128)
+    pins = np.repeat(np.arange(n_pi), fo)
+    rng.shuffle(pins)
+    gates = [list(map(int, pins[i:i + 8])) for i in range(0, pins.size, 8)]
+    D = n_pi + len(gates)
+    nets, sizes = [], []
+    for u in range(D):
+        m = int(rng.integers(1, 9))
+        parent = [-1] + [int(rng.integers(0, k)) if rng.random() < 0.5 else k - 1 for k in range(1, m)]
+        nets.append((parent, [0.0] + list(rng.uniform(10, 400, m - 1)), list(rng.uniform(0.1, 4, m))))
+        sizes.append(m)
+    A = sum(len(x) for x in gates)
+    taps = [int(rng.integers(0, sizes[u])) for ins in gates for u in ins]
+    d = tiny.design(n_pi, gates, nets, pincaps=list(rng.uniform(0.5, 4, A)), tables=list(rng.integers(0, 128, A)),
+                    taps=taps)
+    lib = gen.make_library()
+    pa = rng.uniform(0, 50, n_pi).astype(np.float32)
+    ps = rng.uniform(5, 50, n_pi).astype(np.float32)
+    ep = oracle.endpoints(d)
+    rat = [rng.uniform(100, 900, ep.size).astype(np.float32) for _ in range(2)]
+    compare_all(d, lib, pa, ps, rat, [LATE, EARLY], label="crowded delay-calculation wavefront")
+
+
 @SCHED
 def test_ties_on_gpu(schedule):
     same = tiny.chain_net([100.0, 50.0], [0.5, 0.5, 0.5])
