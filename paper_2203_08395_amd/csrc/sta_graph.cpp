@@ -118,11 +118,13 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
     }
     const int64_t M = d->net_node_ptr[D];
     if (M > 0 && (!d->node_parent || !d->node_R || !d->node_C)) return fail(STA_E_ARG, "sta_build_graph: null node array");
+    bool chains = true;   // every net an RC chain (node k's parent k - 1)
     for (int64_t u = 0; u < D; ++u) {
         int64_t n0 = d->net_node_ptr[u], m = d->net_node_ptr[u + 1] - n0;
         if (d->node_parent[n0] != -1) return fail(STA_E_RANGE, "sta_build_graph: node 0 of net " + std::to_string(u) + " has a parent");
         for (int64_t k = 1; k < m; ++k) {
             int32_t p = d->node_parent[n0 + k];
+            chains = chains && p == k - 1;
             if (p < 0 || p >= k)
                 return fail(STA_E_RANGE, "sta_build_graph: net " + std::to_string(u) + " node " + std::to_string(k) +
                                              " has parent " + std::to_string(p) + " (must be in 0..node-1)");
@@ -901,6 +903,7 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
     g->max_fanin = max_fanin;
     g->max_fanout = max_fanout;
     g->max_net_nodes = max_nodes;
+    g->chain_nets = chains;
     g->n_ftiles = NF;
     g->n_btiles = NB;
     g->ftile_arc_h = ftile_arc;

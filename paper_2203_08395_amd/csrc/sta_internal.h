@@ -168,6 +168,7 @@ struct sta_graph {
     int64_t D = 0, A = 0, M = 0, L = 0, E = 0, S = 0;
     int32_t max_fanin = 0, max_fanout = 0, max_net_nodes = 0;
     int32_t n_dc_wide = 0;               // drivers of more than sta::kDcLaneSinks sinks
+    bool chain_nets = false;             // every net an RC chain (node k's parent k - 1)
     std::vector<int32_t> drv_input, arc_input, gate_input, level, ep_driver;
     std::vector<int32_t> fwd_tile_ptr;   // [L+2]: tiles of gate level l are [p[l], p[l+1])
     std::vector<int32_t> ftile_arc_h, ftile_gate_h, btile_slot_h, btile_drv_h;   // host copies of the tiles

@@ -198,7 +198,7 @@ __device__ __forceinline__ void dc8_store(const T (&X)[8], const T (&Y)[8], int 
 // wide nets crowd the wavefront) it is loaded coalesced into LDS (s_cap: pin cap, s_at:
 // arc | tap << 29) in the round that loads the lanes' nodes, and a lane reads its own
 // sinks from LDS; otherwise (STAGED false) each lane reads its sinks from memory.
-template <typename T, bool STAGED>
+template <typename T, bool CHAINS, bool STAGED>
 __device__ __forceinline__ void dc8_lanes(const DevGraph& G, int dw0, int dwl, int n0, int nm, int f0, int f1,
                                           int a0, int a1, float* __restrict__ s_cap, int* __restrict__ s_at,
                                           float* __restrict__ load, float* __restrict__ net_delay,
@@ -278,7 +278,7 @@ __device__ __forceinline__ void dc8_lanes(const DevGraph& G, int dw0, int dwl, i
 #pragma unroll
         for (int k = 0; k < 8; ++k) X[k] = dc_sel(tj == k, X[k] + static_cast<T>(cj), X[k]);
     }
-    const float ld = dc8_sweeps<T>(X, Y, pp, R, nm, all_chain);
+    const float ld = dc8_sweeps<T>(X, Y, pp, R, nm, CHAINS || all_chain);
     load[d] = ld;
     for (int a = a0; a < a1; ++a) arc_load[a] = ld;
     for (int e = f0; e < f1; ++e) {
@@ -292,7 +292,7 @@ __device__ __forceinline__ void dc8_lanes(const DevGraph& G, int dw0, int dwl, i
 // One wavefront: net d of more than kDcLaneSinks sinks (d uniform).  The lanes load 64
 // sinks at a time; the pin caps are added in sink order from broadcast lane values, every
 // lane running the same node arithmetic, and each lane then writes its own sinks.
-template <typename T>
+template <typename T, bool CHAINS>
 __device__ __forceinline__ void dc8_wave(const DevGraph& G, int d, float* __restrict__ load,
                                          float* __restrict__ net_delay, float* __restrict__ net_imp2,
                                          float* __restrict__ arc_load) {
@@ -327,7 +327,7 @@ __device__ __forceinline__ void dc8_wave(const DevGraph& G, int d, float* __rest
     T X[8], Y[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) X[k] = dc_lane_value(acc, k);
-    const float ld = dc8_sweeps<T>(X, Y, pp, R, nm, __builtin_amdgcn_ballot_w64(!chain) == 0);
+    const float ld = dc8_sweeps<T>(X, Y, pp, R, nm, CHAINS || __builtin_amdgcn_ballot_w64(!chain) == 0);
     if (lane == 0) load[d] = ld;
     if (d >= G.n_pi) {
         const int q = d - G.n_pi;
@@ -339,7 +339,7 @@ __device__ __forceinline__ void dc8_wave(const DevGraph& G, int d, float* __rest
 // Workgroup x (256 lanes) of the delay calculation of a graph whose nets have at most 8
 // nodes: the first ceil(n_dc_wide / 4) workgroups give each wide net a wavefront (first,
 // so that the longest nets start first), the rest one lane per net.
-template <typename T>
+template <typename T, bool CHAINS>
 __device__ __forceinline__ void dc8_block(const DevGraph& G, int x, float* __restrict__ load,
                                           float* __restrict__ net_delay, float* __restrict__ net_imp2,
                                           float* __restrict__ arc_load) {
@@ -349,7 +349,7 @@ __device__ __forceinline__ void dc8_block(const DevGraph& G, int x, float* __res
     const int wb = (G.n_dc_wide + 3) >> 2;
     if (x < wb) {
         const int i = x * 4 + wave;
-        if (i < G.n_dc_wide) dc8_wave<T>(G, __builtin_amdgcn_readfirstlane(G.dc_wide[i]), load, net_delay, net_imp2, arc_load);
+        if (i < G.n_dc_wide) dc8_wave<T, CHAINS>(G, __builtin_amdgcn_readfirstlane(G.dc_wide[i]), load, net_delay, net_imp2, arc_load);
         return;
     }
     const int dw0 = (x - wb) * 256 + wave * 64;
@@ -364,9 +364,9 @@ __device__ __forceinline__ void dc8_block(const DevGraph& G, int x, float* __res
     const int a0 = q >= 0 ? G.gate_arc_ptr[q] : 0, a1 = q >= 0 ? G.gate_arc_ptr[q + 1] : 0;
     const int span = __builtin_amdgcn_readlane(f1, dwl - dw0) - __builtin_amdgcn_readfirstlane(f0);
     if (span <= kDcWindow && G.n_arcs <= (1 << 29))        // (arc | tap << 29 must fit)
-        dc8_lanes<T, true>(G, dw0, dwl, n0, nm, f0, f1, a0, a1, s_cap[wave], s_at[wave], load, net_delay, net_imp2, arc_load);
+        dc8_lanes<T, CHAINS, true>(G, dw0, dwl, n0, nm, f0, f1, a0, a1, s_cap[wave], s_at[wave], load, net_delay, net_imp2, arc_load);
     else
-        dc8_lanes<T, false>(G, dw0, dwl, n0, nm, f0, f1, a0, a1, nullptr, nullptr, load, net_delay, net_imp2, arc_load);
+        dc8_lanes<T, CHAINS, false>(G, dw0, dwl, n0, nm, f0, f1, a0, a1, nullptr, nullptr, load, net_delay, net_imp2, arc_load);
 }
 
 // workgroups of the delay calculation of g in node-count class maxn with nt lanes each
@@ -387,12 +387,14 @@ __global__ __launch_bounds__(NT) void k_delay_calc(DevGraph G, float* __restrict
     dc_net<T, MAXN, NT>(G, d, t, sX, sY, load, net_delay, net_imp2, arc_load);
 }
 
-template <typename T>
+// CHAINS: every net of the graph is a chain (known at graph build), so the kernel has no
+// select form of the sweeps and needs far fewer registers (63 against 116 VGPRs for FP64)
+template <typename T, bool CHAINS>
 __global__ __launch_bounds__(256) void k_delay_calc8(DevGraph G, float* __restrict__ load,
                                                      float* __restrict__ net_delay,
                                                      float* __restrict__ net_imp2,
                                                      float* __restrict__ arc_load) {
-    dc8_block<T>(G, int(blockIdx.x), load, net_delay, net_imp2, arc_load);
+    dc8_block<T, CHAINS>(G, int(blockIdx.x), load, net_delay, net_imp2, arc_load);
 }
 
 // Batched delay calculation: workgroup x takes nets map[map0 + x].y * NT + t of design
@@ -410,12 +412,12 @@ __global__ __launch_bounds__(NT) void k_delay_calc_batch(const BatchItem* __rest
     dc_net<T, MAXN, NT>(it.G, d, t, sX, sY, it.load_w, it.nd_w, it.ni_w, it.arc_load);
 }
 
-template <typename T>
+template <typename T, bool CHAINS>
 __global__ __launch_bounds__(256) void k_delay_calc8_batch(const BatchItem* __restrict__ items,
                                                            const int2* __restrict__ map, int map0) {
     const int2 m = map[map0 + int(blockIdx.x)];
     const BatchItem& it = items[m.x];
-    dc8_block<T>(it.G, m.y, it.load_w, it.nd_w, it.ni_w, it.arc_load);
+    dc8_block<T, CHAINS>(it.G, m.y, it.load_w, it.nd_w, it.ni_w, it.arc_load);
 }
 
 // ---------------------------------------------------------------------------------
@@ -2089,12 +2091,17 @@ template <typename T, int MAXN, int NT>
 static void launch_dc(const sta_graph* g, const sta_net_out* out, hipStream_t s) {
     const int blocks = dc_blocks_of(g->D, g->n_dc_wide, MAXN, NT);
     prof_launch("k_delay_calc", s, [&] {
-        if constexpr (MAXN == 8)
-            hipLaunchKernelGGL((k_delay_calc8<T>), dim3(blocks), dim3(NT), 0, s, dev_graph(g), out->load,
-                               out->net_delay, out->net_imp2, out->arc_load);
-        else
+        if constexpr (MAXN == 8) {
+            if (g->chain_nets)
+                hipLaunchKernelGGL((k_delay_calc8<T, true>), dim3(blocks), dim3(NT), 0, s, dev_graph(g), out->load,
+                                   out->net_delay, out->net_imp2, out->arc_load);
+            else
+                hipLaunchKernelGGL((k_delay_calc8<T, false>), dim3(blocks), dim3(NT), 0, s, dev_graph(g), out->load,
+                                   out->net_delay, out->net_imp2, out->arc_load);
+        } else {
             hipLaunchKernelGGL((k_delay_calc<T, MAXN, NT>), dim3(blocks), dim3(NT), 0, s, dev_graph(g), out->load,
                                out->net_delay, out->net_imp2, out->arc_load);
+        }
     });
 }
 
@@ -2911,6 +2918,7 @@ struct sta_batch {
     };
     struct DcClass {
         int maxn = 0, map0 = 0, nblk = 0;
+        bool chains = true;        // every design of the class has only chain nets
     };
     std::vector<Lvl> level_designs;
     std::vector<const sta_graph*> graphs;      // per item
@@ -3006,14 +3014,17 @@ static bool batch_layout(const sta_batch_design* designs, int32_t n, int NV, Bat
 }
 
 template <typename T>
-static void launch_dc_batch(const sta_batch* b, int maxn, int map0, int nblk, hipStream_t q) {
+static void launch_dc_batch(const sta_batch* b, int maxn, bool chains, int map0, int nblk, hipStream_t q) {
     auto go = [&](auto kern, int nt) {
         prof_launch("k_delay_calc_batch", q, [&] {
             hipLaunchKernelGGL(kern, dim3(nblk), dim3(nt), 0, q, b->d_items, b->d_map, map0);
         });
     };
     switch (maxn) {
-        case 8: go(k_delay_calc8_batch<T>, 256); break;
+        case 8:
+            if (chains) go(k_delay_calc8_batch<T, true>, 256);
+            else go(k_delay_calc8_batch<T, false>, 256);
+            break;
         case 16: go(k_delay_calc_batch<T, 16, 128>, 128); break;
         case 32: go(k_delay_calc_batch<T, 32, 64>, 64); break;
         case 64: go(k_delay_calc_batch<T, 64, 32>, 32); break;
@@ -3541,6 +3552,7 @@ sta_status sta_batch_create(const sta_batch_design* designs, int32_t n, const st
         const int nt = dc_threads(maxn);
         for (int k = 0; k < b->n_items; ++k) {
             if (dc_class(b->graphs[k]) != maxn) continue;
+            dc.chains = dc.chains && b->graphs[k]->chain_nets;
             const int64_t nb = dc_blocks_of(b->graphs[k]->D, b->graphs[k]->n_dc_wide, maxn, nt);
             for (int64_t x = 0; x < nb; ++x) map.push_back(make_int2(k, int(x)));
         }
@@ -3593,8 +3605,8 @@ sta_status sta_batch_delay_calc(sta_batch* b, sta_dc_precision prec, int32_t use
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto enqueue = [&](hipStream_t q) {
         for (const auto& c : b->dc) {
-            if (prec == STA_DC_FP64) launch_dc_batch<double>(b, c.maxn, c.map0, c.nblk, q);
-            else launch_dc_batch<float>(b, c.maxn, c.map0, c.nblk, q);
+            if (prec == STA_DC_FP64) launch_dc_batch<double>(b, c.maxn, c.chains, c.map0, c.nblk, q);
+            else launch_dc_batch<float>(b, c.maxn, c.chains, c.map0, c.nblk, q);
         }
     };
     const sta_status st = capture_replay(b->dcache, b->mu, use_graph != 0, {uint64_t(prec)}, s, enqueue);
