@@ -575,6 +575,10 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
         int32_t tile_id = 0;                      // unique per filled tile (never reused)
         int32_t stamp = 0;                        // unique per cone search (never reused)
         auto try_span = [&](int32_t l0, int32_t l1) -> bool {
+            // the forward span kernel addresses per-arc and per-driver arrays of up to 8
+            // views by 32-bit byte offsets: larger graphs run their forward levels as level
+            // launches
+            if (A > kSpanMaxIndex || D > kSpanMaxIndex) return false;
             const int32_t q0 = lvl_gate_ptr[l0 - 1], q1 = lvl_gate_ptr[l1];
             auto in_span = [&](int32_t u) { return u >= P && (u - P) >= q0 && (u - P) < q1; };
             const int32_t nl = l1 - l0 + 1;

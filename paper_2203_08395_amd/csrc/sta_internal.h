@@ -48,6 +48,10 @@ constexpr int kBwdViewsPerWave = 2;
 // Largest view count the fused spans serve: all (1, 2, 4, 8; measured faster than the level
 // and view schedules for every count).
 constexpr int kSpanMaxViews = 8;
+// Largest arc and driver count of a graph with fused forward spans: the forward span tiles
+// address per-arc and per-driver arrays of up to kSpanMaxViews views (8 bytes per view) by
+// 32-bit byte offsets.
+constexpr int64_t kSpanMaxIndex = int64_t(1) << 26;
 // Delay calculation of nets of at most 8 nodes: one lane per net of at most kDcLaneSinks
 // sinks, a wavefront's first kDcWindow sinks staged in LDS; a net with more sinks (listed
 // in dc_wide) gets a wavefront of its own.

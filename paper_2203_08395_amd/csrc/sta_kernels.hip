@@ -454,6 +454,26 @@ __device__ __forceinline__ float bilerp(const float* T, int i, int j, float tx, 
     return bilerp4(T[i * 7 + j], T[i * 7 + j + 1], T[(i + 1) * 7 + j], T[(i + 1) * 7 + j + 1], tx, ty);
 }
 
+// base + off bytes, off a 32-bit offset: with a wave-uniform base the access takes the
+// scalar-base form (a 32-bit vector offset, no 64-bit address arithmetic per lane)
+template <typename T>
+__device__ __forceinline__ T* at32(T* base, uint32_t off) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + off);
+}
+
+// the delay and slew lookups of table tb of a set: the corners addressed by a 32-bit byte
+// offset from the set's wave-uniform base, so that the loads take the scalar-base form (no
+// 64-bit address arithmetic per lane); a set is at most 65,536 tables of 392 bytes
+__device__ __forceinline__ void bilerp_pair(const float* set, int tb, int i, int j, float tx, float ty,
+                                            float& dl, float& sl) {
+    const char* b = reinterpret_cast<const char*>(set);
+    const uint32_t o = uint32_t(tb) * 392u + uint32_t(i * 7 + j) * 4u;
+    auto at = [&](uint32_t k) { return *reinterpret_cast<const float*>(b + (o + k)); };
+    dl = bilerp4(at(0), at(4), at(28), at(32), tx, ty);
+    sl = bilerp4(at(196), at(200), at(224), at(228), tx, ty);
+}
+
 __device__ __forceinline__ uint64_t lanes_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }
@@ -507,6 +527,22 @@ __device__ __forceinline__ Axis6 axis6(const KLib& lib, int base, int wbase) {
                  lib.ax[wbase + 4], lib.ax[wbase + 5]};
 }
 
+// a copy of a wave-uniform value in a vector register
+__device__ __forceinline__ float in_vgpr(float x) {
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+// the axis in vector registers: a select between two axis points then needs no copy of
+// each scalar operand into a vector register first (one scalar operand per instruction),
+// which halves the segment searches of a level
+__device__ __forceinline__ Axis6 axis6_v(const KLib& lib, int base, int wbase) {
+    const Axis6 a = axis6(lib, base, wbase);
+    return Axis6{in_vgpr(a.p0), in_vgpr(a.p1), in_vgpr(a.p2), in_vgpr(a.p3), in_vgpr(a.p4), in_vgpr(a.p5),
+                 in_vgpr(a.w0), in_vgpr(a.w1), in_vgpr(a.w2), in_vgpr(a.w3), in_vgpr(a.w4), in_vgpr(a.w5)};
+}
+
 // seg6 by compares and selects, also returning the segment's origin and width.  The axes
 // strictly increase, so the compares are true for a prefix of the points: the count of
 // true compares and the last true one are the same index.
@@ -547,9 +583,8 @@ __device__ __forceinline__ void fwd_finish(const FwdLane& x, const float2* ts, i
             const float si = sqrtf(su2 + x.ni);
             const int i = seg6(X, si);
             const float tx = (si - X[i]) / DX[i];
-            const float* T = tab[w] + size_t(x.tb) * 98;
-            const float dl = bilerp(T, i, j, tx, ty);
-            const float sl = bilerp(T + 49, i, j, tx, ty);
+            float dl, sl;
+            bilerp_pair(tab[w], x.tb, i, j, tx, ty, dl, sl);
             dst[w] = make_float2(ai, si);
             arc_delay[size_t(x.a) * NV + v0 + w] = dl;
             cand[w] = ai + dl;
@@ -916,7 +951,7 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
     float cand[NW], slw[NW];
     int best_k[NW];
     if (x.active) {
-        float2* dst = reinterpret_cast<float2*>(arc_ts) + size_t(x.a) * NV + v0;
+        float2* dst = at32(reinterpret_cast<float2*>(arc_ts), (uint32_t(x.a) * NV + v0) * 8u);
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             const float ai = ts[w].x + x.nd;
@@ -925,11 +960,10 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
             float x0, dx;
             const int i = seg6_sel(ax_x, si, x0, dx);
             const float tx = (si - x0) / dx;
-            const float* T = tab[w] + size_t(x.tb) * 98;
-            const float dl = bilerp(T, i, j, tx, ty);
-            const float sl = bilerp(T + 49, i, j, tx, ty);
+            float dl, sl;
+            bilerp_pair(tab[w], x.tb, i, j, tx, ty, dl, sl);
             dst[w] = make_float2(ai, si);
-            arc_delay[size_t(x.a) * NV + v0 + w] = dl;
+            *at32(arc_delay, (uint32_t(x.a) * NV + v0 + w) * 4u) = dl;
             // early views negated, so that every view takes a maximum (negation is exact)
             cand[w] = early[w] ? -(ai + dl) : ai + dl;
             slw[w] = early[w] ? -sl : sl;
@@ -973,13 +1007,13 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
         }
     }
     if (x.head) {
-        float2* out = reinterpret_cast<float2*>(drv_ts) + size_t(n_pi + x.g) * NV + v0;
+        float2* out = at32(reinterpret_cast<float2*>(drv_ts), (uint32_t(n_pi + x.g) * NV + v0) * 8u);
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             cand[w] = early[w] ? -cand[w] : cand[w];
             slw[w] = early[w] ? -slw[w] : slw[w];
             out[w] = make_float2(cand[w], slw[w]);
-            argmax[size_t(x.g) * NV + v0 + w] = uint8_t(best_k[w]);
+            *at32(argmax, uint32_t(x.g) * NV + v0 + w) = uint8_t(best_k[w]);
             lds_res[slot * NW + w] = make_float2(cand[w], slw[w]);
         }
     }
@@ -1005,7 +1039,7 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
                                               float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
                                               float2* res, int pf_t = -1) {
     // the table axes in wave-uniform registers
-    const Axis6 ax_x = axis6(lib, 0, 14), ax_y = axis6(lib, 7, 20);
+    const Axis6 ax_x = axis6_v(lib, 0, 14), ax_y = axis6_v(lib, 7, 20);
     const int lane = threadIdx.x & 63;
     const float* tab[NW];
     bool early[NW];
@@ -1038,12 +1072,12 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
     float2 ext[kSpanF][NW];
 #pragma unroll
     for (int c = 0; c < kSpanF; ++c) {
-        const int a = ar[c];
-        ndv[c] = nd[a];
-        niv[c] = ni[a];
-        lov[c] = arc_load[a];
+        const uint32_t a4 = uint32_t(ar[c]) * 4u;
+        ndv[c] = *at32(nd, a4);
+        niv[c] = *at32(ni, a4);
+        lov[c] = *at32(arc_load, a4);
         const int u = sc[c] >= 0 ? sc[c] : 0;
-        const float2* sp = reinterpret_cast<const float2*>(drv_ts) + size_t(u) * NV + v0;
+        const float2* sp = at32(reinterpret_cast<const float2*>(drv_ts), (uint32_t(u) * NV + v0) * 8u);
 #pragma unroll
         for (int w = 0; w < NW; ++w) ext[c][w] = sp[w];
     }
@@ -1093,14 +1127,18 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
             j = seg6_sel(ax_y, x.Lo, y0, dy);
             ty = (x.Lo - y0) / dy;
         }
+        // the source: an in-tile gate's result from LDS (read by every lane, from slot 0
+        // when the source is outside the tile, so that there is no branch) or the gathered one
         float2 ts[NW];
-        if (act && sc[c] < 0) {
-            const int src = -1 - sc[c];
+        {
+            const bool lds_src = sc[c] < 0;
+            const int src = lds_src ? -1 - sc[c] : 0;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) ts[w] = res[src * NW + w];
-        } else {
-#pragma unroll
-            for (int w = 0; w < NW; ++w) ts[w] = act ? ext[c][w] : make_float2(0.0f, 0.0f);
+            for (int w = 0; w < NW; ++w) {
+                const float2 r = res[src * NW + w];
+                const float2 e = act ? ext[c][w] : make_float2(0.0f, 0.0f);
+                ts[w] = (act && lds_src) ? r : e;
+            }
         }
         fwd_finish_span<NW>(x, ts, j, ty, mk[c], ax_x, tab, early, NV, v0, G.n_pi, drv_ts, arc_ts, arc_delay,
                             argmax, res, sl0[c] + x.gi);
