@@ -781,10 +781,15 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
             if (c >= nch) continue;
             const int32_t ch = c0 + c, ta0 = sp_chunk[ch * 4], na = sp_chunk[ch * 4 + 1];
             cr[0] = na; cr[1] = sp_chunk[ch * 4 + 2]; cr[2] = sp_chunk[ch * 4 + 3];
-            for (int32_t k = 0; k < na; ++k) {
+            // bits 24..30 of the lane's meta word: the lane of the next gate head of the
+            // level after this lane (na if none), where its gate's segmented maximum ends
+            int32_t next = na;
+            for (int32_t k = na - 1; k >= 0; --k) {
                 int32_t* ar = &sp_arec[(size_t(t * kSpanF + c) * 64 + k) * 4];
                 const int32_t a = sp_ta_arc[ta0 + k];
-                ar[0] = a; ar[1] = sp_ta_src[ta0 + k]; ar[2] = sp_ta_gate[ta0 + k]; ar[3] = int32_t(arc_meta[a]);
+                ar[0] = a; ar[1] = sp_ta_src[ta0 + k]; ar[2] = sp_ta_gate[ta0 + k];
+                ar[3] = int32_t(arc_meta[a] | (uint32_t(next) << 24));
+                if (sp_ta_gate[ta0 + k] >= 0 && ((arc_meta[a] >> 16) & 0xffu) == 0u) next = k;
             }
         }
     }
@@ -801,14 +806,21 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
             if (c >= nch) continue;
             const int32_t ch = c0 + c, ts0 = bp_chunk[ch * 4], ns = bp_chunk[ch * 4 + 1];
             cr[0] = ns; cr[1] = bp_chunk[ch * 4 + 2]; cr[2] = bp_chunk[ch * 4 + 3];
-            for (int32_t k = 0; k < ns; ++k) {
+            // the source word: the in-tile source (16 bits, signed) | the lane of the next
+            // driver head of the level after this lane (ns if none) << 16, where its driver's
+            // segmented minimum ends
+            int32_t next = ns;
+            for (int32_t k = ns - 1; k >= 0; --k) {
                 int32_t* sr = &bp_srec[(size_t(t * kSpanB + c) * 64 + k) * 4];
                 const int32_t sl = bp_slot[ts0 + k];
+                const int32_t src = sl < 0 ? -2 : bp_src[ts0 + k];
+                sr[2] = int32_t((uint32_t(src) & 0xffffu) | (uint32_t(next) << 16));
                 if (sl < 0) {            // padding lane: source -2, loads from endpoint rank 0 and driver 0
-                    sr[0] = -1; sr[1] = 0; sr[2] = -2; sr[3] = 0;
+                    sr[0] = -1; sr[1] = 0; sr[3] = 0;
                     continue;
                 }
-                sr[0] = bslot_arc[sl]; sr[1] = bslot_out[sl]; sr[2] = bp_src[ts0 + k]; sr[3] = bp_drv[ts0 + k];
+                sr[0] = bslot_arc[sl]; sr[1] = bslot_out[sl]; sr[3] = bp_drv[ts0 + k];
+                if (uint32_t(bslot_out[sl]) & kHeadBit) next = k;
             }
         }
     }

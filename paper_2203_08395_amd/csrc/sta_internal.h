@@ -105,10 +105,13 @@ struct DevGraph {
                            //   widest gate's arc count, levels of the tile
     const int4* sp_arec;   // [NT][kSpanF][64] per lane: cell arc, source (driver >= 0 or
                            //   -1 - LDS slot of an in-tile gate), gate, arc_meta of the arc
+                           //   | the lane's gate end lane (next head of the level) << 24
     const int4* bp_crec;   // [NT][kSpanB] backward level c of tile t (top first): slots,
                            //   first LDS driver slot, most slots of a driver, levels of the tile
     const int4* bp_srec;   // [NT][kSpanB][64] per lane: sink arc (-1: endpoint slot), the
-                           //   slot's output word (bslot_out), in-tile LDS source or -1, driver
+                           //   slot's output word (bslot_out), in-tile LDS source or -1 (-2:
+                           //   padding; low 16 bits, signed) | the lane's driver end lane
+                           //   (next head of the level) << 16, driver
     const int32_t* dc_wide;        // [n_dc_wide] drivers of more than kDcLaneSinks sinks, ascending
     int32_t n_pi, n_gates, n_drivers, n_arcs, n_dc_wide;
 };

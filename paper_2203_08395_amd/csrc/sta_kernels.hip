@@ -493,6 +493,19 @@ struct FwdLane {
     float nd, ni, Lo;
 };
 
+// fwd_lane_setup for a span record: the end lane of the lane's gate comes with the record
+// (bits 24..30 of its meta word, raw: also for idle and padding lanes)
+__device__ __forceinline__ void fwd_lane_setup_span(FwdLane& x, bool act, uint32_t raw, int lane) {
+    const uint32_t meta = act ? raw : 0u;
+    x.active = act;
+    x.kpos = int((meta >> 16) & 0xffu);
+    x.tb = int(meta & 0xffffu);
+    x.head = act && x.kpos == 0;
+    const uint64_t heads = __ballot(x.head);
+    x.gi = __popcll(heads & lanes_le(lane)) - 1;
+    x.seg_end = int((raw >> 24) & 0x7fu);
+}
+
 // gate heads, the lane's gate within the tile and its gate's end lane (wave-uniform call)
 __device__ __forceinline__ void fwd_lane_setup(FwdLane& x, bool act, uint32_t meta, int n, int lane) {
     x.active = act;
@@ -1114,7 +1127,7 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
         if (c >= nch) return;                   // uniform
         const bool act = lane < na[c] && gt[c] >= 0;   // gate -1: padding lane
         FwdLane x;
-        fwd_lane_setup(x, act, act ? meta[c] : 0u, na[c], lane);
+        fwd_lane_setup_span(x, act, meta[c], lane);
         x.a = ar[c];
         x.g = gt[c];
         x.nd = act ? ndv[c] : 0.0f;
@@ -1247,7 +1260,7 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
     for (int v = 0; v < NW; ++v) early[v] = V.mode[v0 + v] == STA_EARLY;
     // round 1: the tile's level and slot records, all indexed by (tile, level, lane)
     int ns[kSpanB], ds0[kSpanB], ms[kSpanB];
-    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB];
+    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB], sge[kSpanB];
     bool hd[kSpanB];
     int nch = 0;
 #pragma unroll
@@ -1262,7 +1275,8 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
         sa_[c] = r.x;
         so_[c] = int(bo & 0x7fffffffu);
         hd[c] = (bo & kHeadBit) != 0u;
-        src[c] = r.z;
+        src[c] = int(int16_t(r.z & 0xffff));
+        sge[c] = (r.z >> 16) & 0x7f;
         drv[c] = r.w;
     }
     // round 2: the slot data the required times need (net delay, arc delay, required
@@ -1312,10 +1326,8 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
         const bool act = lane < n && src[c] != -2;   // source -2: padding lane
         const bool head = act && hd[c];
         const uint64_t heads = __ballot(head);
-        const uint64_t le = lanes_le(lane);
-        const int gi = __popcll(heads & le) - 1;
-        const uint64_t after = heads & ~le;
-        const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : n;
+        const int gi = __popcll(heads & lanes_le(lane)) - 1;
+        const int seg_end = sge[c];            // from the record
         const bool on_arc = act && sa_[c] >= 0;
         // the required times at the sinks' gate outputs: from LDS (in-tile) or prefetched
         const int si = src[c] >= 0 ? src[c] : 0;
@@ -2584,7 +2596,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     for (int v = 0; v < NW; ++v) early[v] = V.mode[v0 + v] == STA_EARLY;
     // round 1: the tile's level and slot records
     int ns[kSpanB], ds0[kSpanB], ms[kSpanB];
-    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB];
+    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB], sge[kSpanB];
     bool hd[kSpanB];
     int nch = 0;
 #pragma unroll
@@ -2599,7 +2611,8 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         sa_[c] = r.x;
         so_[c] = int(bo & 0x7fffffffu);
         hd[c] = (bo & kHeadBit) != 0u;
-        src[c] = r.z;
+        src[c] = int(int16_t(r.z & 0xffff));
+        sge[c] = (r.z >> 16) & 0x7f;
         drv[c] = r.w;
     }
     // round 2
@@ -2635,10 +2648,8 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         const bool act = lane < n && src[c] != -2;   // source -2: padding lane
         const bool head = act && hd[c];
         const uint64_t heads = __ballot(head);
-        const uint64_t le = lanes_le(lane);
-        const int gi = __popcll(heads & le) - 1;
-        const uint64_t after = heads & ~le;
-        const int seg_end = after ? (__ffsll(static_cast<unsigned long long>(after)) - 1) : n;
+        const int gi = __popcll(heads & lanes_le(lane)) - 1;
+        const int seg_end = sge[c];            // from the record
         const bool on_arc = act && sa_[c] >= 0;
         const int si = src[c] >= 0 ? src[c] : 0;
         float gin[NW];
