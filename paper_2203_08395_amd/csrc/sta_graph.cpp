@@ -781,16 +781,20 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
             if (c >= nch) continue;
             const int32_t ch = c0 + c, ta0 = sp_chunk[ch * 4], na = sp_chunk[ch * 4 + 1];
             cr[0] = na; cr[1] = sp_chunk[ch * 4 + 2]; cr[2] = sp_chunk[ch * 4 + 3];
-            // bits 24..30 of the lane's meta word: the lane of the next gate head of the
-            // level after this lane (na if none), where its gate's segmented maximum ends
+            // the lane's meta word: arc_meta | the lane of the next gate head of the level
+            // after this lane (na if none: where its gate's segmented maximum ends) << 24 |
+            // head bit 31 (the gate's first arc); lanes past the level's last are idle
+            // (gate -1), like padding lanes
             int32_t next = na;
             for (int32_t k = na - 1; k >= 0; --k) {
                 int32_t* ar = &sp_arec[(size_t(t * kSpanF + c) * 64 + k) * 4];
                 const int32_t a = sp_ta_arc[ta0 + k];
+                const bool head = sp_ta_gate[ta0 + k] >= 0 && ((arc_meta[a] >> 16) & 0xffu) == 0u;
                 ar[0] = a; ar[1] = sp_ta_src[ta0 + k]; ar[2] = sp_ta_gate[ta0 + k];
-                ar[3] = int32_t(arc_meta[a] | (uint32_t(next) << 24));
-                if (sp_ta_gate[ta0 + k] >= 0 && ((arc_meta[a] >> 16) & 0xffu) == 0u) next = k;
+                ar[3] = int32_t(arc_meta[a] | (uint32_t(next) << 24) | (head ? 0x80000000u : 0u));
+                if (head) next = k;
             }
+            for (int32_t k = na; k < 64; ++k) sp_arec[(size_t(t * kSpanF + c) * 64 + k) * 4 + 2] = -1;
         }
     }
     std::vector<int32_t> bp_crec(size_t(NTB) * kSpanB * 4, 0), bp_srec(size_t(NTB) * kSpanB * 64 * 4, 0);

@@ -493,17 +493,17 @@ struct FwdLane {
     float nd, ni, Lo;
 };
 
-// fwd_lane_setup for a span record: the end lane of the lane's gate comes with the record
-// (bits 24..30 of its meta word, raw: also for idle and padding lanes)
-__device__ __forceinline__ void fwd_lane_setup_span(FwdLane& x, bool act, uint32_t raw, int lane) {
-    const uint32_t meta = act ? raw : 0u;
+// fwd_lane_setup for a span record: the end lane of the lane's gate and its head bit come
+// with the record (bits 24..30 and 31 of its meta word; an idle or padding lane has a
+// valid table id and is never a head)
+__device__ __forceinline__ void fwd_lane_setup_span(FwdLane& x, bool act, uint32_t meta, int lane) {
     x.active = act;
     x.kpos = int((meta >> 16) & 0xffu);
     x.tb = int(meta & 0xffffu);
-    x.head = act && x.kpos == 0;
+    x.head = int32_t(meta) < 0;
     const uint64_t heads = __ballot(x.head);
     x.gi = __popcll(heads & lanes_le(lane)) - 1;
-    x.seg_end = int((raw >> 24) & 0x7fu);
+    x.seg_end = int((meta >> 24) & 0x7fu);
 }
 
 // gate heads, the lane's gate within the tile and its gate's end lane (wave-uniform call)
@@ -1125,7 +1125,7 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
     static_for<0, kSpanF>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         if (c >= nch) return;                   // uniform
-        const bool act = lane < na[c] && gt[c] >= 0;   // gate -1: padding lane
+        const bool act = gt[c] >= 0;            // gate -1: padding or idle lane
         FwdLane x;
         fwd_lane_setup_span(x, act, meta[c], lane);
         x.a = ar[c];
