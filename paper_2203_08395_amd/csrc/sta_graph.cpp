@@ -826,6 +826,8 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
                 sr[0] = bslot_arc[sl]; sr[1] = bslot_out[sl]; sr[3] = bp_drv[ts0 + k];
                 if (uint32_t(bslot_out[sl]) & kHeadBit) next = k;
             }
+            for (int32_t k = ns; k < 64; ++k)     // idle lanes: padding (source -2)
+                bp_srec[(size_t(t * kSpanB + c) * 64 + k) * 4 + 2] = 0xfffe;
         }
     }
 

@@ -111,7 +111,7 @@ struct DevGraph {
                            //   first LDS driver slot, most slots of a driver, levels of the tile
     const int4* bp_srec;   // [NT][kSpanB][64] per lane: sink arc (-1: endpoint slot), the
                            //   slot's output word (bslot_out), in-tile LDS source or -1 (-2:
-                           //   padding; low 16 bits, signed) | the lane's driver end lane
+                           //   padding or idle; low 16 bits, signed) | the lane's driver end lane
                            //   (next head of the level) << 16, driver
     const int32_t* dc_wide;        // [n_dc_wide] drivers of more than kDcLaneSinks sinks, ascending
     int32_t n_pi, n_gates, n_drivers, n_arcs, n_dc_wide;

@@ -1322,8 +1322,7 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
         if (c >= nch) break;                    // uniform
-        const int n = ns[c];
-        const bool act = lane < n && src[c] != -2;   // source -2: padding lane
+        const bool act = src[c] != -2;          // source -2: padding or idle lane
         const bool head = act && hd[c];
         const uint64_t heads = __ballot(head);
         const int gi = __popcll(heads & lanes_le(lane)) - 1;
@@ -1343,9 +1342,12 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
         for (int v = 0; v < NW; ++v) {
             const float rin = ro[v] - dl[c][v];
             rin_[c][v] = rin;
-            if (on_arc) arc_rat[size_t(sa_[c]) * NV + v0 + v] = rin;
             const float val = on_arc ? rin - ndv[c] : ext[c][v];
             best[v] = act ? (early[v] ? -val : val) : __builtin_inff();   // idle lanes never win
+        }
+        if (on_arc) {
+#pragma unroll
+            for (int v = 0; v < NW; ++v) arc_rat[size_t(sa_[c]) * NV + v0 + v] = rin_[c][v];
         }
         // segmented minimum over a driver's slots: ceil(log2(most slots)) steps; drivers of
         // <= 16 slots lie inside 16-lane rows (DPP row shifts), wider ones use permutes
@@ -1386,7 +1388,7 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
 #pragma unroll
     for (int c = 0; c < kSpanB; ++c) {
         if (c >= nch) break;                    // uniform
-        const bool act = lane < ns[c] && src[c] != -2;
+        const bool act = src[c] != -2;
         if (act && sa_[c] >= 0) {
 #pragma unroll
             for (int v = 0; v < NW; ++v)
