@@ -785,12 +785,23 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
             // after this lane (na if none: where its gate's segmented maximum ends) << 24 |
             // head bit 31 (the gate's first arc); lanes past the level's last are idle
             // (gate -1), like padding lanes
+            // The gate word: the gate (26 bits: graphs with fused spans have fewer than
+            // 2^26 drivers) | its rank among the level's gates in the tile (its LDS slot
+            // past the level's first) << 26, or -1 for a padding or idle lane.
+            int32_t heads_before = 0;
+            for (int32_t k = 0; k < na; ++k) {
+                const int32_t a = sp_ta_arc[ta0 + k];
+                if (sp_ta_gate[ta0 + k] >= 0 && ((arc_meta[a] >> 16) & 0xffu) == 0u) ++heads_before;
+                int32_t* ar = &sp_arec[(size_t(t * kSpanF + c) * 64 + k) * 4];
+                ar[2] = sp_ta_gate[ta0 + k] < 0 ? -1
+                                                : int32_t(uint32_t(sp_ta_gate[ta0 + k]) | (uint32_t(heads_before - 1) << 26));
+            }
             int32_t next = na;
             for (int32_t k = na - 1; k >= 0; --k) {
                 int32_t* ar = &sp_arec[(size_t(t * kSpanF + c) * 64 + k) * 4];
                 const int32_t a = sp_ta_arc[ta0 + k];
                 const bool head = sp_ta_gate[ta0 + k] >= 0 && ((arc_meta[a] >> 16) & 0xffu) == 0u;
-                ar[0] = a; ar[1] = sp_ta_src[ta0 + k]; ar[2] = sp_ta_gate[ta0 + k];
+                ar[0] = a; ar[1] = sp_ta_src[ta0 + k];
                 ar[3] = int32_t(arc_meta[a] | (uint32_t(next) << 24) | (head ? 0x80000000u : 0u));
                 if (head) next = k;
             }

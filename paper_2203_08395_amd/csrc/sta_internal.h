@@ -104,9 +104,10 @@ struct DevGraph {
     const int4* sp_crec;   // [NT][kSpanF] forward level c of tile t: arcs, first LDS slot,
                            //   widest gate's arc count, levels of the tile
     const int4* sp_arec;   // [NT][kSpanF][64] per lane: cell arc, source (driver >= 0 or
-                           //   -1 - LDS slot of an in-tile gate), gate (-1: padding or
-                           //   idle lane), arc_meta of the arc | the lane's gate end lane
-                           //   (next head of the level) << 24 | head (first arc) << 31
+                           //   -1 - LDS slot of an in-tile gate), gate | its rank among
+                           //   the level's gates << 26 (-1: padding or idle lane), arc_meta
+                           //   of the arc | the lane's gate end lane (next head of the
+                           //   level) << 24 | head (first arc) << 31
     const int4* bp_crec;   // [NT][kSpanB] backward level c of tile t (top first): slots,
                            //   first LDS driver slot, most slots of a driver, levels of the tile
     const int4* bp_srec;   // [NT][kSpanB][64] per lane: sink arc (-1: endpoint slot), the

@@ -495,14 +495,15 @@ struct FwdLane {
 
 // fwd_lane_setup for a span record: the end lane of the lane's gate and its head bit come
 // with the record (bits 24..30 and 31 of its meta word; an idle or padding lane has a
-// valid table id and is never a head)
-__device__ __forceinline__ void fwd_lane_setup_span(FwdLane& x, bool act, uint32_t meta, int lane) {
+// valid table id and is never a head), and so do the gate and its rank in the level (the
+// gate word: gate | rank << 26)
+__device__ __forceinline__ void fwd_lane_setup_span(FwdLane& x, bool act, uint32_t meta, uint32_t gword) {
     x.active = act;
     x.kpos = int((meta >> 16) & 0xffu);
     x.tb = int(meta & 0xffffu);
     x.head = int32_t(meta) < 0;
-    const uint64_t heads = __ballot(x.head);
-    x.gi = __popcll(heads & lanes_le(lane)) - 1;
+    x.g = int(gword & 0x3ffffffu);
+    x.gi = int(gword >> 26);
     x.seg_end = int((meta >> 24) & 0x7fu);
 }
 
@@ -1125,11 +1126,10 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
     static_for<0, kSpanF>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         if (c >= nch) return;                   // uniform
-        const bool act = gt[c] >= 0;            // gate -1: padding or idle lane
+        const bool act = gt[c] != -1;           // gate word -1: padding or idle lane
         FwdLane x;
-        fwd_lane_setup_span(x, act, meta[c], lane);
+        fwd_lane_setup_span(x, act, meta[c], uint32_t(gt[c]));
         x.a = ar[c];
-        x.g = gt[c];
         x.nd = act ? ndv[c] : 0.0f;
         x.ni = act ? niv[c] : 0.0f;
         x.Lo = act ? lov[c] : 0.0f;
