@@ -408,6 +408,8 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
         auto nslots = [&](int64_t i) { return slot_ptr[i + 1] - slot_ptr[i]; };
         // tiles the span [bot, top]; on failure removes what it appended and returns false
         auto try_span = [&](int32_t top, int32_t bot) -> bool {
+            // (the records pack a driver into 26 bits: larger graphs run level launches)
+            if (A > kSpanMaxIndex || D > kSpanMaxIndex) return false;
             auto in_span = [&](int64_t i) { return lv(i) >= bot && lv(i) <= top; };
             const int32_t nl = top - bot + 1;
             const size_t t0 = bp_tile.size(), c0all = bp_chunk.size(), s0all = bp_slot.size();
@@ -576,8 +578,8 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
         int32_t stamp = 0;                        // unique per cone search (never reused)
         auto try_span = [&](int32_t l0, int32_t l1) -> bool {
             // the forward span kernel addresses per-arc and per-driver arrays of up to 8
-            // views by 32-bit byte offsets: larger graphs run their forward levels as level
-            // launches
+            // views by 32-bit byte offsets, and the records pack a gate into 26 bits: larger
+            // graphs run their forward levels as level launches
             if (A > kSpanMaxIndex || D > kSpanMaxIndex) return false;
             const int32_t q0 = lvl_gate_ptr[l0 - 1], q1 = lvl_gate_ptr[l1];
             auto in_span = [&](int32_t u) { return u >= P && (u - P) >= q0 && (u - P) < q1; };
@@ -824,17 +826,26 @@ static sta_status build(const sta_design_desc* d, sta_graph* g, int32_t cap_f, i
             // the source word: the in-tile source (16 bits, signed) | the lane of the next
             // driver head of the level after this lane (ns if none) << 16, where its driver's
             // segmented minimum ends
-            int32_t next = ns;
+            // and the driver word: the driver (26 bits: graphs with fused spans have at most
+            // 2^26 drivers) | its rank among the level's drivers in the tile (its LDS slot
+            // past the level's first) << 26
+            int32_t next = ns, heads_before = 0;
+            for (int32_t k = 0; k < ns; ++k) {
+                const int32_t sl = bp_slot[ts0 + k];
+                if (sl >= 0 && (uint32_t(bslot_out[sl]) & kHeadBit)) ++heads_before;
+                bp_srec[(size_t(t * kSpanB + c) * 64 + k) * 4 + 3] =
+                    sl < 0 ? 0 : int32_t(uint32_t(bp_drv[ts0 + k]) | (uint32_t(std::max(heads_before - 1, 0)) << 26));
+            }
             for (int32_t k = ns - 1; k >= 0; --k) {
                 int32_t* sr = &bp_srec[(size_t(t * kSpanB + c) * 64 + k) * 4];
                 const int32_t sl = bp_slot[ts0 + k];
                 const int32_t src = sl < 0 ? -2 : bp_src[ts0 + k];
                 sr[2] = int32_t((uint32_t(src) & 0xffffu) | (uint32_t(next) << 16));
                 if (sl < 0) {            // padding lane: source -2, loads from endpoint rank 0 and driver 0
-                    sr[0] = -1; sr[1] = 0; sr[3] = 0;
+                    sr[0] = -1; sr[1] = 0;
                     continue;
                 }
-                sr[0] = bslot_arc[sl]; sr[1] = bslot_out[sl]; sr[3] = bp_drv[ts0 + k];
+                sr[0] = bslot_arc[sl]; sr[1] = bslot_out[sl];
                 if (uint32_t(bslot_out[sl]) & kHeadBit) next = k;
             }
             for (int32_t k = ns; k < 64; ++k)     // idle lanes: padding (source -2)

@@ -48,9 +48,9 @@ constexpr int kBwdViewsPerWave = 2;
 // Largest view count the fused spans serve: all (1, 2, 4, 8; measured faster than the level
 // and view schedules for every count).
 constexpr int kSpanMaxViews = 8;
-// Largest arc and driver count of a graph with fused forward spans: the forward span tiles
-// address per-arc and per-driver arrays of up to kSpanMaxViews views (8 bytes per view) by
-// 32-bit byte offsets.
+// Largest arc and driver count of a graph with fused spans: the forward span tiles address
+// per-arc and per-driver arrays of up to kSpanMaxViews views (8 bytes per view) by 32-bit
+// byte offsets, and the span records pack a gate or driver into 26 bits.
 constexpr int64_t kSpanMaxIndex = int64_t(1) << 26;
 // Delay calculation of nets of at most 8 nodes: one lane per net of at most kDcLaneSinks
 // sinks, a wavefront's first kDcWindow sinks staged in LDS; a net with more sinks (listed
@@ -113,7 +113,8 @@ struct DevGraph {
     const int4* bp_srec;   // [NT][kSpanB][64] per lane: sink arc (-1: endpoint slot), the
                            //   slot's output word (bslot_out), in-tile LDS source or -1 (-2:
                            //   padding or idle; low 16 bits, signed) | the lane's driver end lane
-                           //   (next head of the level) << 16, driver
+                           //   (next head of the level) << 16, driver | its rank among the
+                           //   level's drivers << 26
     const int32_t* dc_wide;        // [n_dc_wide] drivers of more than kDcLaneSinks sinks, ascending
     int32_t n_pi, n_gates, n_drivers, n_arcs, n_dc_wide;
 };

@@ -1260,7 +1260,7 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
     for (int v = 0; v < NW; ++v) early[v] = V.mode[v0 + v] == STA_EARLY;
     // round 1: the tile's level and slot records, all indexed by (tile, level, lane)
     int ns[kSpanB], ds0[kSpanB], ms[kSpanB];
-    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB], sge[kSpanB];
+    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB], sge[kSpanB], grk[kSpanB];
     bool hd[kSpanB];
     int nch = 0;
 #pragma unroll
@@ -1277,7 +1277,8 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
         hd[c] = (bo & kHeadBit) != 0u;
         src[c] = int(int16_t(r.z & 0xffff));
         sge[c] = (r.z >> 16) & 0x7f;
-        drv[c] = r.w;
+        drv[c] = r.w & 0x3ffffff;
+        grk[c] = int(uint32_t(r.w) >> 26);
     }
     // round 2: the slot data the required times need (net delay, arc delay, required
     // times from outside the tile), waited for before the first level; then the arrivals
@@ -1324,8 +1325,7 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
         if (c >= nch) break;                    // uniform
         const bool act = src[c] != -2;          // source -2: padding or idle lane
         const bool head = act && hd[c];
-        const uint64_t heads = __ballot(head);
-        const int gi = __popcll(heads & lanes_le(lane)) - 1;
+        const int gi = grk[c];                 // from the record
         const int seg_end = sge[c];            // from the record
         const bool on_arc = act && sa_[c] >= 0;
         // the required times at the sinks' gate outputs: from LDS (in-tile) or prefetched
@@ -2598,7 +2598,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
     for (int v = 0; v < NW; ++v) early[v] = V.mode[v0 + v] == STA_EARLY;
     // round 1: the tile's level and slot records
     int ns[kSpanB], ds0[kSpanB], ms[kSpanB];
-    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB], sge[kSpanB];
+    int sa_[kSpanB], so_[kSpanB], src[kSpanB], drv[kSpanB], sge[kSpanB], grk[kSpanB];
     bool hd[kSpanB];
     int nch = 0;
 #pragma unroll
@@ -2615,7 +2615,8 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         hd[c] = (bo & kHeadBit) != 0u;
         src[c] = int(int16_t(r.z & 0xffff));
         sge[c] = (r.z >> 16) & 0x7f;
-        drv[c] = r.w;
+        drv[c] = r.w & 0x3ffffff;
+        grk[c] = int(uint32_t(r.w) >> 26);
     }
     // round 2
     int kp[kSpanB], am[kSpanB][NW];
@@ -2649,8 +2650,7 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
         const int n = ns[c];
         const bool act = lane < n && src[c] != -2;   // source -2: padding lane
         const bool head = act && hd[c];
-        const uint64_t heads = __ballot(head);
-        const int gi = __popcll(heads & lanes_le(lane)) - 1;
+        const int gi = grk[c];                 // from the record
         const int seg_end = sge[c];            // from the record
         const bool on_arc = act && sa_[c] >= 0;
         const int si = src[c] >= 0 ? src[c] : 0;
