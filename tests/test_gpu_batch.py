@@ -44,6 +44,10 @@ def _designs():
         out.append((d, sched, caps))
     out.append((_wide_gate_design(7), SP, None))
     out.append((tiny.wide_fanout_design(8), SP, None))      # backward spans that do not fuse
+    # RC trees (not chains): the batched delay calculation then takes its select form for
+    # every design of the node-count class
+    out.append((gen.make_design(n_pins=4000, n_levels=16, fanin="geom", seed=309, m_range=(2, 8), tree=True),
+                SP, None))
     return out
 
 

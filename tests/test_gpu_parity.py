@@ -168,9 +168,13 @@ def test_rc_tree_nets_every_size_class(m_range):
     compare_all(d, lib, pa, ps, [late, early], [LATE, EARLY], label=f"RC trees {m_range}")
 
 
-def test_fp32_delay_calc_within_1e5():
-    d, lib, pa, ps, late, early = workload("c1")
-    say("[gpu case] fp32 delay calc c1")
+@pytest.mark.parametrize("nets", ["c1 chains", "RC trees"])
+def test_fp32_delay_calc_within_1e5(nets):
+    if nets == "RC trees":
+        d = gen.make_design(n_pins=3000, n_levels=12, fanin="geom", seed=33, m_range=(2, 8), tree=True)
+    else:
+        d, lib, pa, ps, late, early = workload("c1")
+    say(f"[gpu case] fp32 delay calc, {nets}")
     import torch
     g = sta.Graph(d, n_tables=128).upload("cuda")
     nd = sta.delay_calc(g, sta.STA_DC_FP32)
