@@ -1045,13 +1045,18 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
 // The body of one forward span tile t of graph G, views v0 .. v0 + NW - 1 (tc: t clamped
 // into the launch's tiles, for the unconditional record loads; a wavefront with !valid
 // returns after them).  res: the wavefront's LDS results, kSpanSlotsF * NW values.
-template <int NV, int NW, bool PF>
+// FIRST (the pass's first launch, when it is a span): drivers that are primary inputs are
+// read from pi_ts, and lane pe >= 0 of the launch copies primary-input element pe (one
+// view's arrival and slew) from pi_ts into drv_ts, loaded with the records and stored
+// after the last level, in place of a separate copy launch.
+template <int NV, int NW, bool PF, bool FIRST = false>
 __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib, const KViews& V, int t, int tc,
                                               bool valid, int v0, const float* __restrict__ arc_load,
                                               const float* __restrict__ nd, const float* __restrict__ ni,
                                               float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                               float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
-                                              float2* res, int pf_t = -1) {
+                                              float2* res, int pf_t = -1, const float* __restrict__ pi_ts = nullptr,
+                                              int pe = -1) {
     // the table axes in wave-uniform registers
     const Axis6 ax_x = axis6_v(lib, 0, 14), ax_y = axis6_v(lib, 7, 20);
     const int lane = threadIdx.x & 63;
@@ -1080,6 +1085,14 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
         gt[c] = r.z;
         meta[c] = uint32_t(r.w);
     }
+    float2 piv = make_float2(0.0f, 0.0f);
+    if constexpr (FIRST) {
+        piv = reinterpret_cast<const float2*>(pi_ts)[pe >= 0 ? pe : 0];
+        if (!valid) {
+            if (pe >= 0) reinterpret_cast<float2*>(drv_ts)[pe] = piv;
+            return;
+        }
+    }
     if (!valid) return;
     // round 2: the arcs' net data and the arrivals of drivers outside the span
     float ndv[kSpanF], niv[kSpanF], lov[kSpanF];
@@ -1091,7 +1104,11 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
         niv[c] = *at32(ni, a4);
         lov[c] = *at32(arc_load, a4);
         const int u = sc[c] >= 0 ? sc[c] : 0;
-        const float2* sp = at32(reinterpret_cast<const float2*>(drv_ts), (uint32_t(u) * NV + v0) * 8u);
+        const float2* sp;
+        if constexpr (FIRST)
+            sp = reinterpret_cast<const float2*>(u < G.n_pi ? pi_ts : drv_ts) + size_t(u) * NV + v0;
+        else
+            sp = at32(reinterpret_cast<const float2*>(drv_ts), (uint32_t(u) * NV + v0) * 8u);
 #pragma unroll
         for (int w = 0; w < NW; ++w) ext[c][w] = sp[w];
     }
@@ -1165,23 +1182,32 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
         pfx ^= pfc.x ^ pfc.y ^ pfc.z ^ pfc.w;
         asm volatile("" ::"v"(pfx));
     }
+    if constexpr (FIRST) {
+        if (pe >= 0) reinterpret_cast<float2*>(drv_ts)[pe] = piv;
+    }
 }
 
-template <int NV, int NW>
+template <int NV, int NW, bool FIRST>
 __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_forward_span(DevGraph G, KLib lib, KViews V, int tile0, int tile1,
                                                       const float* __restrict__ arc_load,
                                                       const float* __restrict__ nd, const float* __restrict__ ni,
                                                       float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                                       float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
-                                                      int pf0, int pf1) {
+                                                      int pf0, int pf1, const float* __restrict__ pi_ts) {
     __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NW];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = tile0 + blockIdx.x * kSpanWaves + wave;
     const int tc = t < tile1 ? t : tile1 - 1;
     // the next span's tile of the same workgroup index (prefetched; -1: none)
     const int pt = pf0 + (t - tile0);
-    fwd_span_tile<NV, NW, true>(G, lib, V, t, tc, t < tile1, int(blockIdx.y) * NW, arc_load, nd, ni, drv_ts,
-                                arc_ts, arc_delay, argmax, s_res[wave], pt < pf1 ? pt : -1);
+    // FIRST: this lane's primary-input element (-1: none)
+    int pe = -1;
+    if constexpr (FIRST) {
+        const int e = ((int(blockIdx.y) * int(gridDim.x) + int(blockIdx.x)) * kSpanWaves + wave) * 64 + int(threadIdx.x & 63);
+        pe = e < G.n_pi * NV ? e : -1;
+    }
+    fwd_span_tile<NV, NW, true, FIRST>(G, lib, V, t, tc, t < tile1, int(blockIdx.y) * NW, arc_load, nd, ni, drv_ts,
+                                       arc_ts, arc_delay, argmax, s_res[wave], pt < pf1 ? pt : -1, pi_ts, pe);
 }
 
 // Batched forward spans: workgroup x of the launch runs tile map[map0 + x].y of design
@@ -2333,7 +2359,14 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                                    const sta_net_out* nd, const sta_timing_out* o, hipStream_t s) {
     const DevGraph dg = dev_graph(g);
     const int npi = int(g->n_pi) * NV * 2;
-    if (npi > 0)
+    // the primary inputs' copy rides on the first span launch when that span is fused and
+    // its lanes cover the copy (one element per lane), else it is a launch of its own
+    constexpr int NWf = kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV;
+    bool copy_in_first = false;
+    if constexpr (NV <= kSpanMaxViews)
+        copy_in_first = npi > 0 && g->use_spans && !g->span_fused_h.empty() && g->span_fused_h[0] &&
+                        int64_t(g->span_tile_h[1] - g->span_tile_h[0]) * (NV / NWf) * 64 >= int64_t(g->n_pi) * NV;
+    if (npi > 0 && !copy_in_first)
         prof_launch("k_copy_pi", s, [&] {
             hipLaunchKernelGGL(k_copy_pi, dim3((npi + 255) / 256), dim3(256), 0, s, pi_ts, o->drv_ts, npi);
         });
@@ -2358,9 +2391,14 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                     pf1 = g->span_tile_h[sp + 2];
                 }
                 prof_launch("k_forward_span", s, [&] {
-                    hipLaunchKernelGGL((k_forward_span<NV, NW>), grid, dim3(64 * kSpanWaves), 0, s, dg, lib, kv, t0,
-                                       t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts, o->arc_ts,
-                                       o->arc_delay, o->argmax, pf0, pf1);
+                    if (sp == 0 && copy_in_first)
+                        hipLaunchKernelGGL((k_forward_span<NV, NW, true>), grid, dim3(64 * kSpanWaves), 0, s, dg, lib,
+                                           kv, t0, t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts,
+                                           o->arc_ts, o->arc_delay, o->argmax, pf0, pf1, pi_ts);
+                    else
+                        hipLaunchKernelGGL((k_forward_span<NV, NW, false>), grid, dim3(64 * kSpanWaves), 0, s, dg, lib,
+                                           kv, t0, t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts,
+                                           o->arc_ts, o->arc_delay, o->argmax, pf0, pf1, pi_ts);
                 });
             }
             return;
