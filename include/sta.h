@@ -284,7 +284,9 @@ sta_status sta_set_schedule(sta_graph* g, int32_t view_max_arcs_per_level, int32
  * slots, at most eight chunks per tile), level by level, with the in-span arrival
  * (required) times kept in LDS.  A gate or driver needed by several
  * tiles is computed in each of them, identically, so results do not change.  A level that
- * cannot be tiled even alone runs as a level launch.  The view schedule is unaffected. */
+ * cannot be tiled even alone runs as a level launch, and so does every level of a graph
+ * of more than 2^26 cell arcs or drivers (the span kernels address by 32-bit offsets and
+ * pack indices into 26 bits).  The view schedule is unaffected. */
 sta_status sta_set_level_fusion(sta_graph* g, int32_t enable);
 
 /* The fusion plan of a built graph (host only; independent of sta_set_level_fusion,
