@@ -11,10 +11,13 @@ LIB = os.path.join(HERE, "libsta.so")
 
 # -ffp-contract=off: no a*b+c contraction; IEEE-rounded FP32 divide/sqrt; FP32 denormals kept.
 # Packed-FP32 instructions are disabled (their generation is left off on purpose).
+# MFMA results in ordinary vector registers (the network kernels then need no copy out of
+# the accumulation registers before each activation).
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-ffp-contract=off", "-fno-fast-math", "-fhip-fp32-correctly-rounded-divide-sqrt",
                "-fno-gpu-flush-denormals-to-zero",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-mllvm", "-amdgpu-mfma-vgpr-form",
                "-Wall", "-Wno-unused-result"]
 
 

@@ -506,10 +506,11 @@ __global__ void k_norm_final(const double* __restrict__ part, int32_t blocks, in
 // the network on the matrix cores
 // ---------------------------------------------------------------------------------
 
-__device__ __forceinline__ short bf16r(float f) {   // round to nearest even (finite f)
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return static_cast<short>(u >> 16);
+// BF16 bits of f rounded to nearest even (the hardware conversion, v_cvt_pk_bf16_f32 on
+// gfx950: for finite f the same bits as adding 0x7fff plus the kept lowest bit and
+// truncating)
+__device__ __forceinline__ short bf16r(float f) {
+    return __builtin_bit_cast(short, static_cast<__bf16>(f));
 }
 
 __device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
@@ -629,13 +630,18 @@ struct Fwd {
 };
 
 __device__ __forceinline__ v8s relu_pair(v4f a, v4f b) {
-    v8s h;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        h[j] = bf16r(fmaxf(a[j], 0.0f));
-        h[4 + j] = bf16r(fmaxf(b[j], 0.0f));
-    }
-    return h;
+    // BF16 of max(z, 0): z rounded to BF16 first, two values per instruction, then a
+    // negative BF16 (sign bit set: a negative 16-bit integer, -0 included) replaced by +0
+    // with a packed integer maximum; the bits are those of rounding max(z, 0)
+    typedef float v2f_ __attribute__((ext_vector_type(2)));
+    typedef __bf16 v2b_ __attribute__((ext_vector_type(2)));
+    typedef short v2s_ __attribute__((ext_vector_type(2)));
+    const v2s_ p0 = __builtin_bit_cast(v2s_, __builtin_convertvector(v2f_{a[0], a[1]}, v2b_));
+    const v2s_ p1 = __builtin_bit_cast(v2s_, __builtin_convertvector(v2f_{a[2], a[3]}, v2b_));
+    const v2s_ p2 = __builtin_bit_cast(v2s_, __builtin_convertvector(v2f_{b[0], b[1]}, v2b_));
+    const v2s_ p3 = __builtin_bit_cast(v2s_, __builtin_convertvector(v2f_{b[2], b[3]}, v2b_));
+    const v8s h = {p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+    return __builtin_elementwise_max(h, v8s(0));
 }
 
 __device__ __forceinline__ void forward(const Wf& W, v4s x, Fwd& F) {
