@@ -24,6 +24,7 @@
 #include <memory>
 #include <cmath>
 #include <cstdint>
+#include <cfloat>
 #include <cstring>
 #include <map>
 #include <string>
@@ -426,6 +427,7 @@ __global__ __launch_bounds__(256) void k_delay_calc8_batch(const BatchItem* __re
 
 struct KLib {
     float ax[26];                // x[7], y[7], dx[6] = fl32(x[i+1]-x[i]), dy[6]
+    float sq[5];                 // sq[k]: the least float a with sqrtf(a) >= x[k+1] (slew thresholds)
     const float* tables;         // [sets][K][2][49]
     int32_t n_tables;
 };
@@ -570,6 +572,31 @@ __device__ __forceinline__ int seg6_sel(const Axis6& a, float v, float& x0, floa
     SEG6_STEP_(a.p3, a.w3)
     SEG6_STEP_(a.p4, a.w4)
     SEG6_STEP_(a.p5, a.w5)
+#undef SEG6_STEP_
+    return i;
+}
+
+// The slew axis's square-root thresholds (KLib::sq) as named wave-uniform scalars.
+struct Sq5 {
+    float t1, t2, t3, t4, t5;
+};
+
+__device__ __forceinline__ Sq5 sq5(const KLib& lib) {
+    return Sq5{lib.sq[0], lib.sq[1], lib.sq[2], lib.sq[3], lib.sq[4]};
+}
+
+// seg6_sel of v = sqrtf(a), found from a itself: a >= sq[k] exactly when sqrtf(a) >= x[k+1]
+// (KLib::sq), so the segment, its origin and its width are known before the root is.
+__device__ __forceinline__ int seg6_sq(const Axis6& ax, const Sq5& q, float a, float& x0, float& dx) {
+    int i = 0;
+    x0 = ax.p0;
+    dx = ax.w0;
+#define SEG6_STEP_(T, P, W) { const bool ge = (T) <= a; i += ge ? 1 : 0; x0 = ge ? (P) : x0; dx = ge ? (W) : dx; }
+    SEG6_STEP_(q.t1, ax.p1, ax.w1)
+    SEG6_STEP_(q.t2, ax.p2, ax.w2)
+    SEG6_STEP_(q.t3, ax.p3, ax.w3)
+    SEG6_STEP_(q.t4, ax.p4, ax.w4)
+    SEG6_STEP_(q.t5, ax.p5, ax.w5)
 #undef SEG6_STEP_
     return i;
 }
@@ -957,7 +984,7 @@ __device__ __forceinline__ void span_sum_step(float* acc, bool take) {
 // in LDS (slot-indexed) for the tile's gates of the levels above
 template <int NW>
 __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* ts, int j, float ty, int span,
-                                                const Axis6& ax_x, const float* const* tab, const bool* early,
+                                                const Axis6& ax_x, const Sq5& sq_x, const float* const* tab, const bool* early,
                                                 int NV, int v0, int n_pi, float* __restrict__ drv_ts,
                                                 float* __restrict__ arc_ts, float* __restrict__ arc_delay,
                                                 uint8_t* __restrict__ argmax, float2* lds_res, int slot) {
@@ -970,9 +997,11 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
         for (int w = 0; w < NW; ++w) {
             const float ai = ts[w].x + x.nd;
             const float su2 = ts[w].y * ts[w].y;
-            const float si = sqrtf(su2 + x.ni);
+            const float a = su2 + x.ni;
+            // the segment from a, so that the table reads need not wait for the root
             float x0, dx;
-            const int i = seg6_sel(ax_x, si, x0, dx);
+            const int i = seg6_sq(ax_x, sq_x, a, x0, dx);
+            const float si = sqrtf(a);
             const float tx = (si - x0) / dx;
             float dl, sl;
             bilerp_pair(tab[w], x.tb, i, j, tx, ty, dl, sl);
@@ -1059,6 +1088,7 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
                                               int pe = -1) {
     // the table axes in wave-uniform registers
     const Axis6 ax_x = axis6_v(lib, 0, 14), ax_y = axis6_v(lib, 7, 20);
+    const Sq5 sq_x = sq5(lib);
     const int lane = threadIdx.x & 63;
     const float* tab[NW];
     bool early[NW];
@@ -1170,7 +1200,7 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
                 ts[w] = (act && lds_src) ? r : e;
             }
         }
-        fwd_finish_span<NW>(x, ts, j, ty, mk[c], ax_x, tab, early, NV, v0, G.n_pi, drv_ts, arc_ts, arc_delay,
+        fwd_finish_span<NW>(x, ts, j, ty, mk[c], ax_x, sq_x, tab, early, NV, v0, G.n_pi, drv_ts, arc_ts, arc_delay,
                             argmax, res, sl0[c] + x.gi);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -2957,10 +2987,26 @@ static bool lib_axes_ok(const sta_library* lib, int n_tables, std::string& why) 
     return true;
 }
 
+// The least float a for which the correctly rounded square root reaches p: sqrtf is
+// nondecreasing, so sqrtf(a) >= p exactly when a >= sqrt_floor_of(p), for every a, NaN
+// included (both sides false).  p <= 0: every a >= -0 qualifies (sqrtf(-0) = -0 >= p), and
+// a negative a has a NaN root, so the threshold is 0; p = +inf: only a = +inf; NaN: none.
+static float sqrt_threshold(float p) {
+    if (std::isnan(p)) return p;
+    if (!(p > 0.0f)) return 0.0f;
+    if (std::isinf(p)) return p;
+    const double d = double(p) * double(p);
+    float t = d >= double(FLT_MAX) ? FLT_MAX : float(d);
+    while (t > 0.0f && std::sqrt(std::nextafter(t, 0.0f)) >= p) t = std::nextafter(t, 0.0f);
+    while (!(std::sqrt(t) >= p)) t = std::nextafter(t, HUGE_VALF);
+    return t;
+}
+
 static KLib make_klib(const sta_library* lib) {
     KLib kl{};
     for (int i = 0; i < 7; ++i) { kl.ax[i] = lib->x[i]; kl.ax[7 + i] = lib->y[i]; }
     for (int i = 0; i < 6; ++i) { kl.ax[14 + i] = lib->x[i + 1] - lib->x[i]; kl.ax[20 + i] = lib->y[i + 1] - lib->y[i]; }
+    for (int k = 0; k < 5; ++k) kl.sq[k] = sqrt_threshold(lib->x[k + 1]);
     kl.tables = lib->tables;
     kl.n_tables = lib->n_tables;
     return kl;
@@ -3234,11 +3280,7 @@ sta_status sta_propagate(const sta_graph* g, const sta_library* lib, const sta_v
                       !nd->arc_load)) ||
         !nd->load)
         return fail(STA_E_ARG, "sta_propagate: null buffer");
-    KLib kl{};
-    for (int i = 0; i < 7; ++i) { kl.ax[i] = lib->x[i]; kl.ax[7 + i] = lib->y[i]; }
-    for (int i = 0; i < 6; ++i) { kl.ax[14 + i] = lib->x[i + 1] - lib->x[i]; kl.ax[20 + i] = lib->y[i + 1] - lib->y[i]; }
-    kl.tables = lib->tables;
-    kl.n_tables = lib->n_tables;
+    const KLib kl = make_klib(lib);
     const KViews kv = kviews(views);
     hipStream_t s = static_cast<hipStream_t>(stream);
     size_t lds = 0;

@@ -143,6 +143,82 @@ def test_ties_on_gpu(schedule):
     assert np.all(h["argmax"][:2] == 0)
 
 
+def _sqrt_threshold(p):
+    """The least float32 a whose float32 square root reaches p (p > 0 finite), by a walk
+    over neighbouring floats from p * p."""
+    f32 = np.float32
+    p = f32(p)
+    t = f32(np.float64(p) * np.float64(p))
+    while t > 0 and np.sqrt(np.nextafter(t, f32(0))) >= p:
+        t = np.nextafter(t, f32(0))
+    while not (np.sqrt(t) >= p):
+        t = np.nextafter(t, f32(np.inf))
+    return t
+
+
+@SCHED
+def test_slews_at_the_axis_square_roots(schedule):
+    """Input slews whose radicand S_u^2 + imp2 lies at, just below and just above the least
+    value whose FP32 square root reaches each inner slew axis point, and input slews at and
+    next to the axis points: the segment taken, hence every output, is the oracle's, bit for
+    bit (the span kernel finds the segment from the radicand before taking the root)."""
+    import torch
+    from tests.gpu_common import SCHEDULES
+    f32 = np.float32
+    lib = gen.make_library(n_tables=2, seed=5)
+    ni_l1, s_pi = [], []
+    for p in lib.x[1:6]:
+        T = _sqrt_threshold(p)
+        assert np.sqrt(T) >= p and np.sqrt(np.nextafter(T, f32(0))) < p
+        for a in (T, np.nextafter(T, f32(0)), np.nextafter(T, f32(np.inf)), f32(p) * f32(p)):
+            ni_l1.append(a)
+            s_pi.append(f32(0))
+        for sv in (f32(p), np.nextafter(f32(p), f32(0)), np.nextafter(f32(p), f32(np.inf))):
+            ni_l1.append(f32(0))
+            s_pi.append(sv)
+    for a in (0.0, 1e-41, 1e-30, 1e12):
+        ni_l1.append(f32(a))
+        s_pi.append(f32(0))
+    rng = np.random.default_rng(17)
+    for _ in range(64):
+        ni_l1.append(f32(rng.uniform(0, float(lib.x[6]) ** 2)))
+        s_pi.append(f32(rng.uniform(0, 1.2 * float(lib.x[6]))))
+    n = len(ni_l1)
+    # one single-arc gate per primary input, then two-input gates over pairs of them
+    gates = [[i] for i in range(n)] + [[n + 2 * k, n + 2 * k + 1] for k in range(n // 2)]
+    nets = [tiny.chain_net([40.0], [0.3, 0.4])] * (n + len(gates))
+    A = n + 2 * (n // 2)
+    d = tiny.design(n, gates, nets, tables=[i % 2 for i in range(A)])
+    load, nd_o, ni_o = oracle.delay_calc(d)
+    ni_in = ni_o.copy()
+    ni_in[:n] = np.array(ni_l1, np.float32)
+    pa = rng.uniform(0, 50, n).astype(np.float32)
+    ps = np.array(s_pi, np.float32)
+    say(f"[gpu case] radicands at the axis thresholds: {n} primary inputs, schedule={schedule}")
+    g = sta.Graph(d, n_tables=2).upload("cuda")
+    thr, graphs, fuse = SCHEDULES[schedule]
+    g.set_schedule(thr, graphs)
+    g.set_level_fusion(fuse)
+    nd = sta.delay_calc(g)
+    nd["net_imp2"][:A].copy_(torch.from_numpy(ni_in[g.arc_input]))
+    L = sta.make_library(lib.x, lib.y, torch.from_numpy(np.ascontiguousarray(lib.tab)).to("cuda"))
+    modes = [LATE, EARLY]
+    pi = np.zeros((n, 2, 2), np.float32)
+    pi[:, :, 0] = pa[:, None]
+    pi[:, :, 1] = ps[:, None]
+    t = sta.propagate(g, L, sta.make_views(modes), torch.from_numpy(pi).to("cuda"), nd)
+    h = {k: v.cpu().numpy() for k, v in t.items()}
+    D, G = d.n_drivers, d.n_gates
+    for v, m in enumerate(modes):
+        o = oracle.propagate(d, lib.x, lib.y, lib.tab, load, nd_o, ni_in, pa, ps, m)
+        tag = f"view{v}"
+        assert_bitwise(tag + " slew_in", g.arc_to_input(h["arc_ts"][:A, v, 1]), o["slew_in"])
+        assert_bitwise(tag + " arc_delay", g.arc_to_input(h["arc_delay"][:A, v]), o["arc_delay"])
+        assert_bitwise(tag + " at_drv", g.drv_to_input(h["drv_ts"][:D, v, 0]), o["at_drv"])
+        assert_bitwise(tag + " slew_drv", g.drv_to_input(h["drv_ts"][:D, v, 1]), o["slew_drv"])
+        assert_bitwise(tag + " argmax", g.gate_to_input(h["argmax"][:G, v].astype(np.int32)), o["argmax"])
+
+
 @SCHED
 def test_pi_only_and_empty_designs(schedule):
     d = tiny.design(3, [], [tiny.chain_net([5.0], [1.0, 1.0])] * 3)
