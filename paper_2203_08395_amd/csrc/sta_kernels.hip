@@ -1459,6 +1459,133 @@ __device__ __forceinline__ void bwd_span_tile(const DevGraph& G, const KViews& V
     }
 }
 
+// The endpoint summary folded into backward span launches (one 64-lane workgroup per
+// partial; workgroups past the launch's tiles, in its first view group).  An endpoint's only
+// slot is its endpoint slot, so the required time the backward pass takes for it is the
+// endpoint's own, and its slack (required - arrival late, arrival - required early) is
+// formed here from the arrivals and the endpoint required times, the same FP32 operation:
+// the summary then does not wait for the backward pass.
+struct EpFold {
+    const float* drv_ts;       // [D][NV][2]
+    const float* ep_rat;       // [E][NV]
+    unsigned long long* limbs; // partials: [nblk][NV][kLimbs]
+    float* pw;                 // [nblk][NV]
+    double* tns;
+    float* wns;
+    int E, nblk;
+    int role;                  // 0: none, 1: the partials, 2: the final sum
+};
+
+constexpr int kEpPerLane = 4;   // endpoints per lane in one round of loads
+
+// first stage: workgroup blk of nblk takes endpoints blk * 256 + r * 64 + lane (r < 4),
+// striding by nblk * 256
+template <int NV>
+__device__ __forceinline__ void endpoint_partial_fold(const DevGraph& G, const KViews& V, const EpFold& f, int blk) {
+    __shared__ unsigned long long s_l[NV * kLimbs];
+    const int lane = threadIdx.x & 63;
+    for (int i = lane; i < NV * kLimbs; i += 64) s_l[i] = 0ull;
+    __syncthreads();
+    bool early[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) early[v] = V.mode[v] == STA_EARLY;
+    const int stride = f.nblk * 64 * kEpPerLane;
+    auto slack_of = [&](int e, float (&sv)[NV]) {
+        const bool in = e < f.E;
+        const int u = in ? G.ep_drv[e] : 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            // (loads only for lanes with an endpoint)
+            const float at = in ? f.drv_ts[(size_t(u) * NV + v) * 2] : 0.0f;
+            const float r = in ? f.ep_rat[size_t(e) * NV + v] : 0.0f;
+            sv[v] = in ? (early[v] ? at - r : r - at) : __builtin_inff();
+        }
+    };
+    float s1[kEpPerLane][NV];
+#pragma unroll
+    for (int r = 0; r < kEpPerLane; ++r) slack_of(blk * 64 * kEpPerLane + r * 64 + lane, s1[r]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        unsigned long long l[kLimbs];
+#pragma unroll
+        for (int i = 0; i < kLimbs; ++i) l[i] = 0ull;
+        float mn = __builtin_inff();
+#pragma unroll
+        for (int r = 0; r < kEpPerLane; ++r) {
+            mn = (s1[r][v] < mn) ? s1[r][v] : mn;
+            add_neg_slack(l, s1[r][v]);
+        }
+        for (int e0 = blk * 64 * kEpPerLane + stride; e0 < f.E; e0 += stride) {
+#pragma unroll
+            for (int r = 0; r < kEpPerLane; ++r) {
+                float sv[NV];
+                slack_of(e0 + r * 64 + lane, sv);
+                mn = (sv[v] < mn) ? sv[v] : mn;
+                add_neg_slack(l, sv[v]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kLimbs; ++i)
+            if (l[i]) atomicAdd(&s_l[v * kLimbs + i], l[i]);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float o2 = __shfl_xor(mn, off, 64);
+            mn = (o2 < mn) ? o2 : mn;
+        }
+        if (lane == 0) f.pw[size_t(blk) * NV + v] = mn;
+    }
+    __syncthreads();
+    for (int i = lane; i < NV * kLimbs; i += 64) f.limbs[size_t(blk) * NV * kLimbs + i] = s_l[i];
+}
+
+// second stage, one 64-lane workgroup over the nblk partials
+template <int NV>
+__device__ __forceinline__ void endpoint_final_fold(const EpFold& f) {
+    __shared__ unsigned long long s_sum[NV * kLimbs];
+    const int lane = threadIdx.x & 63;
+    for (int i = lane; i < NV * kLimbs; i += 64) s_sum[i] = 0ull;
+    __syncthreads();
+    const int n = f.nblk * NV * kLimbs;
+    for (int i0 = lane; i0 < n; i0 += 8 * 64) {
+        unsigned long long x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int i = i0 + r * 64;
+            x[r] = i < n ? f.limbs[i] : 0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (x[r]) atomicAdd(&s_sum[(i0 + r * 64) % (NV * kLimbs)], x[r]);
+    }
+    float mn[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) mn[v] = __builtin_inff();
+    for (int b = lane; b < f.nblk; b += 64) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const float x = f.pw[size_t(b) * NV + v];
+            mn[v] = (x < mn[v]) ? x : mn[v];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float o2 = __shfl_xor(mn[v], off, 64);
+            mn[v] = (o2 < mn[v]) ? o2 : mn[v];
+        }
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double mag = digits_to_double(&s_sum[v * kLimbs]);
+            f.tns[v] = (mag == 0.0) ? 0.0 : -mag;
+            f.wns[v] = mn[v];
+        }
+    }
+}
+
 template <int NV, int NW>
 __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
                                                        const float* __restrict__ nd, const float* __restrict__ drv_ts,
@@ -1466,9 +1593,18 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
                                                        const float* __restrict__ arc_delay,
                                                        const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
                                                        float* __restrict__ arc_rat, float* __restrict__ drv_slack,
-                                                       float* __restrict__ arc_slack) {
+                                                       float* __restrict__ arc_slack, EpFold ep) {
     __shared__ float s_rat[kSpanWaves][kSpanSlotsB * NW];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tb = (tile1 - tile0 + kSpanWaves - 1) / kSpanWaves;   // workgroups of tiles
+    if (int(blockIdx.x) >= tb) {
+        // past the tiles: the endpoint summary's workgroups (first view group only)
+        static_assert(kSpanWaves == 1, "the endpoint summary's workgroups are one wavefront");
+        if (blockIdx.y != 0) return;
+        if (ep.role == 1) endpoint_partial_fold<NV>(G, V, ep, int(blockIdx.x) - tb);
+        else if (ep.role == 2) endpoint_final_fold<NV>(ep);
+        return;
+    }
     const int t = tile0 + blockIdx.x * kSpanWaves + wave;
     if (t >= tile1) return;
     bwd_span_tile<NV, NW>(G, V, t, int(blockIdx.y) * NW, nd, drv_ts, arc_ts, arc_delay, ep_rat, drv_rat, arc_rat,
@@ -2485,10 +2621,24 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
         launch_backward_level<NV>(g, kv, nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat,
                                   o->arc_rat, o->drv_slack, o->arc_slack, l, s);
     };
-    bool done = false;
+    auto* limbs = static_cast<unsigned long long*>(scratch);
+    auto* pw = reinterpret_cast<float*>(static_cast<uint8_t*>(scratch) + size_t(kK4Blocks) * STA_MAX_VIEWS * kLimbs * 8);
+    bool done = false, folded = false;
     if constexpr (NV <= kSpanMaxViews) {
         if (g->use_spans) {
             const int64_t NSB = int64_t(g->bspan_fused_h.size());
+            // with two span launches or more, the endpoint summary rides along: its partials
+            // in the first launch's spare workgroups, its final sum in the second's
+            int n_launch = 0;
+            for (int64_t b = 0; b < NSB; ++b)
+                n_launch += g->bspan_fused_h[b] && g->bspan_tile_h[b + 1] > g->bspan_tile_h[b];
+            folded = n_launch >= 2;
+            EpFold ep{t->drv_ts, ep_rat, limbs, pw, o->tns, o->wns, int(g->E), 1, 0};
+            {
+                int nb = int((g->E + 64 * kEpPerLane - 1) / (64 * kEpPerLane));
+                ep.nblk = nb < 1 ? 1 : (nb > kK4Blocks ? kK4Blocks : nb);
+            }
+            int k = 0;
             for (int64_t b = 0; b < NSB; ++b) {
                 const int64_t top = g->bspan_lv_h[2 * b], bot = g->bspan_lv_h[2 * b + 1];
                 if (!g->bspan_fused_h[b]) {
@@ -2497,13 +2647,16 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
                 }
                 const int t0 = g->bspan_tile_h[b], t1 = g->bspan_tile_h[b + 1];
                 if (t1 <= t0) continue;
+                ep.role = folded && k < 2 ? k + 1 : 0;
+                const int extra = ep.role == 1 ? ep.nblk : ep.role == 2 ? 1 : 0;
+                ++k;
                 prof_launch("k_backward_span", s, [&] {
                     hipLaunchKernelGGL((k_backward_span<NV, kBwdViewsPerWave < NV ? kBwdViewsPerWave : NV>),
-                                       dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves,
+                                       dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves + extra,
                                             NV / (kBwdViewsPerWave < NV ? kBwdViewsPerWave : NV)),
                                        dim3(64 * kSpanWaves), 0, s, dg, kv, t0,
                                        t1, nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat,
-                                       o->arc_rat, o->drv_slack, o->arc_slack);
+                                       o->arc_rat, o->drv_slack, o->arc_slack, ep);
                 });
             }
             done = true;
@@ -2511,10 +2664,9 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
     }
     if (!done)
         for (int64_t l = g->L; l >= 0; --l) level(l);
+    if (folded) return;
     int nblk = int((g->E + kK4Threads - 1) / kK4Threads);
     nblk = nblk < 1 ? 1 : (nblk > kK4Blocks ? kK4Blocks : nblk);
-    auto* limbs = static_cast<unsigned long long*>(scratch);
-    auto* pw = reinterpret_cast<float*>(static_cast<uint8_t*>(scratch) + size_t(kK4Blocks) * STA_MAX_VIEWS * kLimbs * 8);
     prof_launch("k_endpoint_partial", s, [&] {
         hipLaunchKernelGGL((k_endpoint_partial<NV>), dim3(nblk), dim3(kK4Threads), 0, s, dg.ep_drv, int(g->E),
                            o->drv_slack, limbs, pw);
