@@ -1078,14 +1078,13 @@ __device__ __forceinline__ void fwd_finish_span(const FwdLane& x, const float2* 
 // read from pi_ts, and lane pe >= 0 of the launch copies primary-input element pe (one
 // view's arrival and slew) from pi_ts into drv_ts, loaded with the records and stored
 // after the last level, in place of a separate copy launch.
-template <int NV, int NW, bool PF, bool FIRST = false>
+template <int NV, int NW, bool FIRST = false>
 __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib, const KViews& V, int t, int tc,
                                               bool valid, int v0, const float* __restrict__ arc_load,
                                               const float* __restrict__ nd, const float* __restrict__ ni,
                                               float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                               float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
-                                              float2* res, int pf_t = -1, const float* __restrict__ pi_ts = nullptr,
-                                              int pe = -1) {
+                                              float2* res, const float* __restrict__ pi_ts = nullptr, int pe = -1) {
     // the table axes in wave-uniform registers
     const Axis6 ax_x = axis6_v(lib, 0, 14), ax_y = axis6_v(lib, 7, 20);
     const Sq5 sq_x = sq5(lib);
@@ -1142,21 +1141,6 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
 #pragma unroll
         for (int w = 0; w < NW; ++w) ext[c][w] = sp[w];
     }
-    // the records of tile pf_t of the next span, loaded into this compute unit's L2 while
-    // round 2 is in flight (the next launch's workgroup of the same index runs on the same
-    // L2), and consumed only after the last level
-    // (without a next tile the wavefront reloads its own records: no branch, so that the
-    // compiler's waits for round 2 count past these loads)
-    int pfx = 0;
-    int4 pfa[kSpanF], pfc;
-    if constexpr (PF) {
-        const int pft = pf_t >= 0 ? pf_t : tc;
-        __builtin_amdgcn_sched_barrier(0);      // behind every load of round 2
-#pragma unroll
-        for (int c = 0; c < kSpanF; ++c) pfa[c] = G.sp_arec[size_t(pft * kSpanF + c) * 64 + lane];
-        pfc = G.sp_crec[pft * kSpanF + (lane & (kSpanF - 1))];
-        __builtin_amdgcn_sched_barrier(0);
-    }
     // all of round 2 is in flight; keep it there (one wait before the first level)
 #pragma unroll
     for (int c = 0; c < kSpanF; ++c) {
@@ -1206,15 +1190,45 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     });
-    if constexpr (PF) {
-#pragma unroll
-        for (int c = 0; c < kSpanF; ++c) pfx ^= pfa[c].x ^ pfa[c].y ^ pfa[c].z ^ pfa[c].w;
-        pfx ^= pfc.x ^ pfc.y ^ pfc.z ^ pfc.w;
-        asm volatile("" ::"v"(pfx));
-    }
     if constexpr (FIRST) {
         if (pe >= 0) reinterpret_cast<float2*>(drv_ts)[pe] = piv;
     }
+}
+
+// Spare workgroups of a span launch load the records of the next launch's tiles into L2
+// before that launch reads them.  Workgroups go to the XCDs (each with its own L2)
+// round-robin by linear index, and every span launch's grid has a multiple of eight
+// workgroups per view group, so the next launch's tile r runs on XCD r mod 8 in every view
+// group; spare workgroup q (counted from a multiple of eight) serves the next tiles r with
+// r = q (mod 8), kSpanPfTiles of them.
+constexpr int kSpanPfTiles = 2;
+
+__host__ __device__ __forceinline__ int span_round8(int n) { return (n + 7) & ~7; }
+__host__ __device__ __forceinline__ int span_pf_blocks(int n_next) {
+    return n_next > 0 ? 8 * ((((n_next + 7) / 8) + kSpanPfTiles - 1) / kSpanPfTiles) : 0;
+}
+
+// the records of the next launch's tiles served by spare workgroup q: LPT int4 lane records
+// per tile level (recs: [NT][LV][64]) and the level records (crec: [NT][LV])
+template <int LV>
+__device__ __forceinline__ void span_prefetch_records(const int4* __restrict__ recs, const int4* __restrict__ crec,
+                                                      int pf0, int pf1, int q) {
+    const int lane = threadIdx.x & 63;
+    const int rho = q & 7, kappa = q >> 3;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kSpanPfTiles; ++i) {
+        const int t = pf0 + rho + 8 * (kappa * kSpanPfTiles + i);
+        if (t >= pf1) break;                    // uniform
+        int4 r[LV];
+#pragma unroll
+        for (int c = 0; c < LV; ++c) r[c] = recs[size_t(t * LV + c) * 64 + lane];
+        const int4 cr = crec[t * LV + (lane & (LV - 1))];
+#pragma unroll
+        for (int c = 0; c < LV; ++c) acc ^= uint32_t(r[c].x ^ r[c].y ^ r[c].z ^ r[c].w);
+        acc ^= uint32_t(cr.x ^ cr.y ^ cr.z ^ cr.w);
+    }
+    asm volatile("" ::"v"(acc));               // the loads complete before the wavefront ends
 }
 
 template <int NV, int NW, bool FIRST>
@@ -1225,19 +1239,23 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
                                                       float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
                                                       int pf0, int pf1, const float* __restrict__ pi_ts) {
     __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NW];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = tile0 + blockIdx.x * kSpanWaves + wave;
-    const int tc = t < tile1 ? t : tile1 - 1;
-    // the next span's tile of the same workgroup index (prefetched; -1: none)
-    const int pt = pf0 + (t - tile0);
+    static_assert(kSpanWaves == 1, "one span tile per workgroup");
+    const int tb = tile1 - tile0;               // workgroups of tiles
+    if (int(blockIdx.x) >= tb) {
+        // spare workgroups: the next launch's records (first view group only)
+        const int q = int(blockIdx.x) - span_round8(tb);
+        if (blockIdx.y == 0 && q >= 0 && pf1 > pf0) span_prefetch_records<kSpanF>(G.sp_arec, G.sp_crec, pf0, pf1, q);
+        return;
+    }
+    const int t = tile0 + int(blockIdx.x);
     // FIRST: this lane's primary-input element (-1: none)
     int pe = -1;
     if constexpr (FIRST) {
-        const int e = ((int(blockIdx.y) * int(gridDim.x) + int(blockIdx.x)) * kSpanWaves + wave) * 64 + int(threadIdx.x & 63);
+        const int e = (int(blockIdx.y) * tb + int(blockIdx.x)) * 64 + int(threadIdx.x & 63);
         pe = e < G.n_pi * NV ? e : -1;
     }
-    fwd_span_tile<NV, NW, true, FIRST>(G, lib, V, t, tc, t < tile1, int(blockIdx.y) * NW, arc_load, nd, ni, drv_ts,
-                                       arc_ts, arc_delay, argmax, s_res[wave], pt < pf1 ? pt : -1, pi_ts, pe);
+    fwd_span_tile<NV, NW, FIRST>(G, lib, V, t, t, true, int(blockIdx.y) * NW, arc_load, nd, ni, drv_ts, arc_ts,
+                                 arc_delay, argmax, s_res[0], pi_ts, pe);
 }
 
 // Batched forward spans: workgroup x of the launch runs tile map[map0 + x].y of design
@@ -1250,7 +1268,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
     __shared__ float2 s_res[kSpanSlotsF * NW];
     const int2 m = map[map0 + int(blockIdx.x)];
     const BatchItem& it = items[m.x];
-    fwd_span_tile<NV, NW, false>(it.G, lib, V, m.y, m.y, true, int(blockIdx.y) * NW, it.arc_load, it.nd, it.ni,
+    fwd_span_tile<NV, NW>(it.G, lib, V, m.y, m.y, true, int(blockIdx.y) * NW, it.arc_load, it.nd, it.ni,
                                  it.drv_ts, it.arc_ts, it.arc_delay, it.argmax, s_res);
 }
 
@@ -1586,6 +1604,43 @@ __device__ __forceinline__ void endpoint_final_fold(const EpFold& f) {
     }
 }
 
+// Spare workgroup q of a backward span launch (as span_prefetch_records, for the next
+// launch's tiles): the tiles' records, then the data their slots gather that is final before
+// this launch starts (net and arc delays, arrivals of the sink pins and of the drivers), into
+// L2; required times from outside a tile can still change in this launch and are not loaded.
+template <int NV>
+__device__ __forceinline__ void bwd_prefetch_gathers(const DevGraph& G, const float* __restrict__ nd,
+                                                     const float* __restrict__ drv_ts, const float* __restrict__ arc_ts,
+                                                     const float* __restrict__ arc_delay, int pf0, int pf1, int q) {
+    const int lane = threadIdx.x & 63;
+    const int rho = q & 7, kappa = q >> 3;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kSpanPfTiles; ++i) {
+        const int t = pf0 + rho + 8 * (kappa * kSpanPfTiles + i);
+        if (t >= pf1) break;                    // uniform
+        int4 r[kSpanB];
+#pragma unroll
+        for (int c = 0; c < kSpanB; ++c) r[c] = G.bp_srec[size_t(t * kSpanB + c) * 64 + lane];
+        const int4 cr = G.bp_crec[t * kSpanB + (lane & (kSpanB - 1))];
+        acc ^= uint32_t(cr.x ^ cr.y ^ cr.z ^ cr.w);
+        float f[kSpanB][4];
+#pragma unroll
+        for (int c = 0; c < kSpanB; ++c) {
+            const int sac = r[c].x >= 0 ? r[c].x : 0;
+            const int u = r[c].w & 0x3ffffff;
+            f[c][0] = nd[sac];
+            f[c][1] = arc_delay[size_t(sac) * NV];
+            f[c][2] = arc_ts[size_t(sac) * NV * 2];
+            f[c][3] = drv_ts[size_t(u) * NV * 2];
+        }
+#pragma unroll
+        for (int c = 0; c < kSpanB; ++c)
+            acc ^= __float_as_uint(f[c][0]) ^ __float_as_uint(f[c][1]) ^ __float_as_uint(f[c][2]) ^ __float_as_uint(f[c][3]);
+    }
+    asm volatile("" ::"v"(acc));
+}
+
 template <int NV, int NW>
 __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_backward_span(DevGraph G, KViews V, int tile0, int tile1,
                                                        const float* __restrict__ nd, const float* __restrict__ drv_ts,
@@ -1593,16 +1648,24 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
                                                        const float* __restrict__ arc_delay,
                                                        const float* __restrict__ ep_rat, float* __restrict__ drv_rat,
                                                        float* __restrict__ arc_rat, float* __restrict__ drv_slack,
-                                                       float* __restrict__ arc_slack, EpFold ep) {
+                                                       float* __restrict__ arc_slack, EpFold ep, int pf0, int pf1) {
     __shared__ float s_rat[kSpanWaves][kSpanSlotsB * NW];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tb = (tile1 - tile0 + kSpanWaves - 1) / kSpanWaves;   // workgroups of tiles
     if (int(blockIdx.x) >= tb) {
-        // past the tiles: the endpoint summary's workgroups (first view group only)
-        static_assert(kSpanWaves == 1, "the endpoint summary's workgroups are one wavefront");
+        // past the tiles: the endpoint summary's workgroups, then the prefetch's
+        // (first view group only)
+        static_assert(kSpanWaves == 1, "the spare workgroups are one wavefront");
         if (blockIdx.y != 0) return;
-        if (ep.role == 1) endpoint_partial_fold<NV>(G, V, ep, int(blockIdx.x) - tb);
-        else if (ep.role == 2) endpoint_final_fold<NV>(ep);
+        const int x = int(blockIdx.x) - tb;
+        const int ne = ep.role == 1 ? ep.nblk : ep.role == 2 ? 1 : 0;
+        if (x < ne) {
+            if (ep.role == 1) endpoint_partial_fold<NV>(G, V, ep, x);
+            else endpoint_final_fold<NV>(ep);
+            return;
+        }
+        const int q = int(blockIdx.x) - span_round8(tb + ne);
+        if (q >= 0 && pf1 > pf0) bwd_prefetch_gathers<NV>(G, nd, drv_ts, arc_ts, arc_delay, pf0, pf1, q);
         return;
     }
     const int t = tile0 + blockIdx.x * kSpanWaves + wave;
@@ -2549,13 +2612,14 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                 const int t0 = g->span_tile_h[sp], t1 = g->span_tile_h[sp + 1];
                 if (t1 <= t0) continue;
                 constexpr int NW = kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV;
-                const dim3 grid((t1 - t0 + kSpanWaves - 1) / kSpanWaves, NV / NW);
-                // the next fused span's tiles, for the record prefetch
+                // the next fused span's tiles, for the record prefetch of the spare workgroups;
+                // a multiple of eight workgroups per view group
                 int pf0 = 0, pf1 = 0;
                 if (sp + 1 < NS && g->span_fused_h[sp + 1]) {
                     pf0 = g->span_tile_h[sp + 1];
                     pf1 = g->span_tile_h[sp + 2];
                 }
+                const dim3 grid(span_round8(t1 - t0) + span_pf_blocks(pf1 - pf0), NV / NW);
                 prof_launch("k_forward_span", s, [&] {
                     if (sp == 0 && copy_in_first)
                         hipLaunchKernelGGL((k_forward_span<NV, NW, true>), grid, dim3(64 * kSpanWaves), 0, s, dg, lib,
@@ -2648,15 +2712,24 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
                 const int t0 = g->bspan_tile_h[b], t1 = g->bspan_tile_h[b + 1];
                 if (t1 <= t0) continue;
                 ep.role = folded && k < 2 ? k + 1 : 0;
-                const int extra = ep.role == 1 ? ep.nblk : ep.role == 2 ? 1 : 0;
+                const int ne = ep.role == 1 ? ep.nblk : ep.role == 2 ? 1 : 0;
                 ++k;
+                // the next launch's tiles (a fused span directly after this one), for the
+                // prefetch of their records and gathers
+                int pf0 = 0, pf1 = 0;
+                if (b + 1 < NSB && g->bspan_fused_h[b + 1]) {
+                    pf0 = g->bspan_tile_h[b + 1];
+                    pf1 = g->bspan_tile_h[b + 2];
+                }
+                // spare workgroups: the endpoint summary's, then the prefetch's; a multiple
+                // of eight workgroups per view group
+                const int nx = span_round8(t1 - t0 + ne) + span_pf_blocks(pf1 - pf0);
                 prof_launch("k_backward_span", s, [&] {
                     hipLaunchKernelGGL((k_backward_span<NV, kBwdViewsPerWave < NV ? kBwdViewsPerWave : NV>),
-                                       dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves + extra,
-                                            NV / (kBwdViewsPerWave < NV ? kBwdViewsPerWave : NV)),
+                                       dim3(nx, NV / (kBwdViewsPerWave < NV ? kBwdViewsPerWave : NV)),
                                        dim3(64 * kSpanWaves), 0, s, dg, kv, t0,
                                        t1, nd->net_delay, t->drv_ts, t->arc_ts, t->arc_delay, ep_rat, o->drv_rat,
-                                       o->arc_rat, o->drv_slack, o->arc_slack, ep);
+                                       o->arc_rat, o->drv_slack, o->arc_slack, ep, pf0, pf1);
                 });
             }
             done = true;
