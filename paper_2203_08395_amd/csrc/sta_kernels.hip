@@ -1195,10 +1195,10 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
     }
 }
 
-// Spare workgroups of a span launch load the records of the next launch's tiles into L2
-// before that launch reads them.  Workgroups go to the XCDs (each with its own L2)
-// round-robin by linear index, and every span launch's grid has a multiple of eight
-// workgroups per view group, so the next launch's tile r runs on XCD r mod 8 in every view
+// Spare workgroups of a span launch load the records of the next launch's tiles, and data
+// they gather, into L2 before that launch reads them.  Workgroups go to the XCDs (each with
+// its own L2) round-robin by linear index, and every span launch's grid has a multiple of
+// eight workgroups per view group, so the next launch's tile r runs on XCD r mod 8 in every view
 // group; spare workgroup q (counted from a multiple of eight) serves the next tiles r with
 // r = q (mod 8), kSpanPfTiles of them.
 constexpr int kSpanPfTiles = 2;
@@ -1208,11 +1208,15 @@ __host__ __device__ __forceinline__ int span_pf_blocks(int n_next) {
     return n_next > 0 ? 8 * ((((n_next + 7) / 8) + kSpanPfTiles - 1) / kSpanPfTiles) : 0;
 }
 
-// the records of the next launch's tiles served by spare workgroup q: LPT int4 lane records
-// per tile level (recs: [NT][LV][64]) and the level records (crec: [NT][LV])
-template <int LV>
-__device__ __forceinline__ void span_prefetch_records(const int4* __restrict__ recs, const int4* __restrict__ crec,
-                                                      int pf0, int pf1, int q) {
+// Spare workgroup q of a forward span launch: the next launch's tile records, then the data
+// their arcs gather that is final before this launch starts (net delay and spread, arc load,
+// and the arrivals of source drivers numbered below fin: drivers are numbered level by level,
+// and fin is the first driver of this launch's span, 0 in the launch that copies the primary
+// inputs), into L2.
+template <int NV>
+__device__ __forceinline__ void fwd_prefetch_gathers(const DevGraph& G, const float* __restrict__ arc_load,
+                                                      const float* __restrict__ nd, const float* __restrict__ ni,
+                                                      const float* __restrict__ drv_ts, int pf0, int pf1, int q, int fin) {
     const int lane = threadIdx.x & 63;
     const int rho = q & 7, kappa = q >> 3;
     uint32_t acc = 0;
@@ -1220,15 +1224,26 @@ __device__ __forceinline__ void span_prefetch_records(const int4* __restrict__ r
     for (int i = 0; i < kSpanPfTiles; ++i) {
         const int t = pf0 + rho + 8 * (kappa * kSpanPfTiles + i);
         if (t >= pf1) break;                    // uniform
-        int4 r[LV];
+        int4 r[kSpanF];
 #pragma unroll
-        for (int c = 0; c < LV; ++c) r[c] = recs[size_t(t * LV + c) * 64 + lane];
-        const int4 cr = crec[t * LV + (lane & (LV - 1))];
-#pragma unroll
-        for (int c = 0; c < LV; ++c) acc ^= uint32_t(r[c].x ^ r[c].y ^ r[c].z ^ r[c].w);
+        for (int c = 0; c < kSpanF; ++c) r[c] = G.sp_arec[size_t(t * kSpanF + c) * 64 + lane];
+        const int4 cr = G.sp_crec[t * kSpanF + (lane & (kSpanF - 1))];
         acc ^= uint32_t(cr.x ^ cr.y ^ cr.z ^ cr.w);
+        float f[kSpanF][4];
+#pragma unroll
+        for (int c = 0; c < kSpanF; ++c) {
+            const uint32_t a4 = uint32_t(r[c].x) * 4u;
+            f[c][0] = *at32(nd, a4);
+            f[c][1] = *at32(ni, a4);
+            f[c][2] = *at32(arc_load, a4);
+            const int u = r[c].y;
+            f[c][3] = (u >= 0 && u < fin) ? drv_ts[size_t(u) * NV * 2] : 0.0f;
+        }
+#pragma unroll
+        for (int c = 0; c < kSpanF; ++c)
+            acc ^= __float_as_uint(f[c][0]) ^ __float_as_uint(f[c][1]) ^ __float_as_uint(f[c][2]) ^ __float_as_uint(f[c][3]);
     }
-    asm volatile("" ::"v"(acc));               // the loads complete before the wavefront ends
+    asm volatile("" ::"v"(acc));
 }
 
 template <int NV, int NW, bool FIRST>
@@ -1237,14 +1252,14 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
                                                       const float* __restrict__ nd, const float* __restrict__ ni,
                                                       float* __restrict__ drv_ts, float* __restrict__ arc_ts,
                                                       float* __restrict__ arc_delay, uint8_t* __restrict__ argmax,
-                                                      int pf0, int pf1, const float* __restrict__ pi_ts) {
+                                                      int pf0, int pf1, const float* __restrict__ pi_ts, int pf_fin) {
     __shared__ float2 s_res[kSpanWaves][kSpanSlotsF * NW];
     static_assert(kSpanWaves == 1, "one span tile per workgroup");
     const int tb = tile1 - tile0;               // workgroups of tiles
     if (int(blockIdx.x) >= tb) {
-        // spare workgroups: the next launch's records (first view group only)
+        // spare workgroups: the next launch's records and gathers (first view group only)
         const int q = int(blockIdx.x) - span_round8(tb);
-        if (blockIdx.y == 0 && q >= 0 && pf1 > pf0) span_prefetch_records<kSpanF>(G.sp_arec, G.sp_crec, pf0, pf1, q);
+        if (blockIdx.y == 0 && q >= 0 && pf1 > pf0) fwd_prefetch_gathers<NV>(G, arc_load, nd, ni, drv_ts, pf0, pf1, q, pf_fin);
         return;
     }
     const int t = tile0 + int(blockIdx.x);
@@ -1604,7 +1619,7 @@ __device__ __forceinline__ void endpoint_final_fold(const EpFold& f) {
     }
 }
 
-// Spare workgroup q of a backward span launch (as span_prefetch_records, for the next
+// Spare workgroup q of a backward span launch (as fwd_prefetch_gathers, for the next
 // launch's tiles): the tiles' records, then the data their slots gather that is final before
 // this launch starts (net and arc delays, arrivals of the sink pins and of the drivers), into
 // L2; required times from outside a tile can still change in this launch and are not loaded.
@@ -2620,15 +2635,18 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                     pf1 = g->span_tile_h[sp + 2];
                 }
                 const dim3 grid(span_round8(t1 - t0) + span_pf_blocks(pf1 - pf0), NV / NW);
+                // drivers below pf_fin (those of lower levels) hold final arrivals
+                const int pf_fin = (sp == 0 && copy_in_first) ? 0 :
+                    int(std::lower_bound(g->level.begin(), g->level.end(), int32_t(l0)) - g->level.begin());
                 prof_launch("k_forward_span", s, [&] {
                     if (sp == 0 && copy_in_first)
                         hipLaunchKernelGGL((k_forward_span<NV, NW, true>), grid, dim3(64 * kSpanWaves), 0, s, dg, lib,
                                            kv, t0, t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts,
-                                           o->arc_ts, o->arc_delay, o->argmax, pf0, pf1, pi_ts);
+                                           o->arc_ts, o->arc_delay, o->argmax, pf0, pf1, pi_ts, pf_fin);
                     else
                         hipLaunchKernelGGL((k_forward_span<NV, NW, false>), grid, dim3(64 * kSpanWaves), 0, s, dg, lib,
                                            kv, t0, t1, nd->arc_load, nd->net_delay, nd->net_imp2, o->drv_ts,
-                                           o->arc_ts, o->arc_delay, o->argmax, pf0, pf1, pi_ts);
+                                           o->arc_ts, o->arc_delay, o->argmax, pf0, pf1, pi_ts, pf_fin);
                 });
             }
             return;
