@@ -522,15 +522,23 @@ def surrogate_bench(dev, n_nets, train_steps, tol_ps=1.0):
     }
 
 
+def kernel_source_sha256():
+    """sha256 over the span and delay-calculation kernels' source and the header that holds
+    their tiling constants, in that order."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("sta_kernels.hip", "sta_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2203_08395_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter runs (FETCH_SIZE and
     WRITE_SIZE scaled by a known-size copy), or None when the kernel source changed since."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "pmc_traffic_c2.json")
-    src = os.path.join(ROOT, "paper_2203_08395_amd", "csrc", "sta_kernels.hip")
     try:
         rec = json.load(open(path))
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        if kernel_source_sha256() != rec["source_sha256"]:
             return None
         return rec["kernels"][kernel]["bytes_per_dispatch"]
     except (OSError, KeyError, ValueError):

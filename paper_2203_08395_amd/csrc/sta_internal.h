@@ -41,10 +41,11 @@ constexpr int kSpanWaves = 1;
 // Level-kernel tiles per workgroup (the same reasoning: a level has a few hundred tiles).
 constexpr int kLevelWaves = 1;
 // Views a span wavefront computes (the others run as separate workgroups of the same
-// launch): one for the forward and adjoint spans, whose levels are long chains; both for
-// the backward span, whose levels are short and whose slot records serve both views.
+// launch): one for the forward, backward and adjoint spans.  Two views per backward
+// wavefront (its slot records serve both) lost once the next launch's gathers were warmed
+// into L2: the level chain, not the record round, then sets the launch time.
 constexpr int kSpanViewsPerWave = 1;
-constexpr int kBwdViewsPerWave = 2;
+constexpr int kBwdViewsPerWave = 1;
 // Largest view count the fused spans serve: all (1, 2, 4, 8; measured faster than the level
 // and view schedules for every count).
 constexpr int kSpanMaxViews = 8;
