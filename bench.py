@@ -368,7 +368,7 @@ def batch_bench(dev, n_designs, reps=5):
     graphs = []
     for d, e, r in zip(designs, loop_e, recs):
         caps = tuple(r["spans"])
-        g = e[0] if caps == (8, 8) else sta.Graph(d, n_tables=lib.tab.shape[1], span_levels=caps).upload(dev)
+        g = e[0] if caps == tuple(e[0].span_levels) else sta.Graph(d, n_tables=lib.tab.shape[1], span_levels=caps).upload(dev)
         graphs.append((g, e[1], sta.alloc_net(g), sta.alloc_timing(g, V), e[5], sta.alloc_slack(g, V)))
     for g, pi, nd, *_ in graphs:
         sta.delay_calc(g, out=nd)
