@@ -92,7 +92,7 @@ sta_status sta_batch_slack(sta_batch* b, int32_t use_graph, void* stream);
  * count); the other views of a tile run in other workgroups of the same launch.  More
  * views per wavefront read a tile's records and gathers once for all of them (less
  * traffic, the batch being bound by throughput), fewer give shorter chains.  Defaults:
- * 1 forward, 2 backward.  Captured sequences are dropped when a value changes; results
+ * 1 forward, 1 backward.  Captured sequences are dropped when a value changes; results
  * do not change.  Errors: STA_E_ARG. */
 sta_status sta_batch_set_tiling(sta_batch* b, int32_t fwd_views_per_wave, int32_t bwd_views_per_wave);
 
