@@ -1200,12 +1200,15 @@ __device__ __forceinline__ void fwd_span_tile(const DevGraph& G, const KLib& lib
 // its own L2) round-robin by linear index, and every span launch's grid has a multiple of
 // eight workgroups per view group, so the next launch's tile r runs on XCD r mod 8 in every view
 // group; spare workgroup q (counted from a multiple of eight) serves the next tiles r with
-// r = q (mod 8), kSpanPfTiles of them.
-constexpr int kSpanPfTiles = 2;
+// r = q (mod 8), kSpanPfTilesF (forward) or kSpanPfTilesB (backward) of them.  One tile per
+// spare wavefront measured best forward, two backward (c2 propagate 0.3023 -> 0.3010 ms;
+// slack 0.2978 -> 0.3038 ms with one).
+constexpr int kSpanPfTilesF = 1;
+constexpr int kSpanPfTilesB = 2;
 
 __host__ __device__ __forceinline__ int span_round8(int n) { return (n + 7) & ~7; }
-__host__ __device__ __forceinline__ int span_pf_blocks(int n_next) {
-    return n_next > 0 ? 8 * ((((n_next + 7) / 8) + kSpanPfTiles - 1) / kSpanPfTiles) : 0;
+__host__ __device__ __forceinline__ int span_pf_blocks(int n_next, int per) {
+    return n_next > 0 ? 8 * ((((n_next + 7) / 8) + per - 1) / per) : 0;
 }
 
 // Spare workgroup q of a forward span launch: the next launch's tile records, then the data
@@ -1221,8 +1224,8 @@ __device__ __forceinline__ void fwd_prefetch_gathers(const DevGraph& G, const fl
     const int rho = q & 7, kappa = q >> 3;
     uint32_t acc = 0;
 #pragma unroll
-    for (int i = 0; i < kSpanPfTiles; ++i) {
-        const int t = pf0 + rho + 8 * (kappa * kSpanPfTiles + i);
+    for (int i = 0; i < kSpanPfTilesF; ++i) {
+        const int t = pf0 + rho + 8 * (kappa * kSpanPfTilesF + i);
         if (t >= pf1) break;                    // uniform
         int4 r[kSpanF];
 #pragma unroll
@@ -1631,8 +1634,8 @@ __device__ __forceinline__ void bwd_prefetch_gathers(const DevGraph& G, const fl
     const int rho = q & 7, kappa = q >> 3;
     uint32_t acc = 0;
 #pragma unroll
-    for (int i = 0; i < kSpanPfTiles; ++i) {
-        const int t = pf0 + rho + 8 * (kappa * kSpanPfTiles + i);
+    for (int i = 0; i < kSpanPfTilesB; ++i) {
+        const int t = pf0 + rho + 8 * (kappa * kSpanPfTilesB + i);
         if (t >= pf1) break;                    // uniform
         int4 r[kSpanB];
 #pragma unroll
@@ -2634,7 +2637,7 @@ static void enqueue_forward_levels(const sta_graph* g, const KLib& lib, const KV
                     pf0 = g->span_tile_h[sp + 1];
                     pf1 = g->span_tile_h[sp + 2];
                 }
-                const dim3 grid(span_round8(t1 - t0) + span_pf_blocks(pf1 - pf0), NV / NW);
+                const dim3 grid(span_round8(t1 - t0) + span_pf_blocks(pf1 - pf0, kSpanPfTilesF), NV / NW);
                 // drivers below pf_fin (those of lower levels) hold final arrivals
                 const int pf_fin = (sp == 0 && copy_in_first) ? 0 :
                     int(std::lower_bound(g->level.begin(), g->level.end(), int32_t(l0)) - g->level.begin());
@@ -2741,7 +2744,7 @@ static void enqueue_backward_levels(const sta_graph* g, const KViews& kv, const 
                 }
                 // spare workgroups: the endpoint summary's, then the prefetch's; a multiple
                 // of eight workgroups per view group
-                const int nx = span_round8(t1 - t0 + ne) + span_pf_blocks(pf1 - pf0);
+                const int nx = span_round8(t1 - t0 + ne) + span_pf_blocks(pf1 - pf0, kSpanPfTilesB);
                 prof_launch("k_backward_span", s, [&] {
                     hipLaunchKernelGGL((k_backward_span<NV, kBwdViewsPerWave < NV ? kBwdViewsPerWave : NV>),
                                        dim3(nx, NV / (kBwdViewsPerWave < NV ? kBwdViewsPerWave : NV)),
