@@ -2899,10 +2899,45 @@ __global__ __launch_bounds__(64 * kSpanWaves) __attribute__((amdgpu_waves_per_eu
                                                                   const uint8_t* __restrict__ argmax,
                                                                   const float* __restrict__ drv_slack,
                                                                   float* __restrict__ g_at, float* __restrict__ g_arc,
-                                                                  float* __restrict__ g_nd) {
+                                                                  float* __restrict__ g_nd, int pf0, int pf1) {
     __shared__ float s_g[kSpanWaves][kSpanSlotsB * NW];
+    static_assert(kSpanWaves == 1, "one span tile per workgroup");
     const int v0 = int(blockIdx.y) * NW;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tb = tile1 - tile0;
+    if (int(blockIdx.x) >= tb) {
+        // spare workgroups (first view group): the next launch's tile records and the data
+        // its slots gather that is final (arc metadata, argmax, driver slacks), into L2, as
+        // the backward span launches do; out-of-tile gradients can still change
+        const int q = int(blockIdx.x) - span_round8(tb);
+        if (blockIdx.y == 0 && q >= 0 && pf1 > pf0) {
+            const int rho = q & 7, kappa = q >> 3;
+            const int ln = threadIdx.x & 63;
+            uint32_t acc = 0;
+#pragma unroll
+            for (int i = 0; i < kSpanPfTilesB; ++i) {
+                const int tt = pf0 + rho + 8 * (kappa * kSpanPfTilesB + i);
+                if (tt >= pf1) break;           // uniform
+                int4 r[kSpanB];
+#pragma unroll
+                for (int c = 0; c < kSpanB; ++c) r[c] = G.bp_srec[size_t(tt * kSpanB + c) * 64 + ln];
+                const int4 cr = G.bp_crec[tt * kSpanB + (ln & (kSpanB - 1))];
+                acc ^= uint32_t(cr.x ^ cr.y ^ cr.z ^ cr.w);
+#pragma unroll
+                for (int c = 0; c < kSpanB; ++c) {
+                    const int sa = r[c].x;
+                    const int sac = sa >= 0 ? sa : 0;
+                    const int so = int(uint32_t(r[c].y) & 0x7fffffffu);
+                    const int gq = sa >= 0 ? so - G.n_pi : 0;
+                    const int u = r[c].w & 0x3ffffff;
+                    acc ^= uint32_t(G.arc_meta[sac]) ^ uint32_t(argmax[size_t(gq) * NV]) ^
+                           __float_as_uint(drv_slack[size_t(u) * NV]);
+                }
+            }
+            asm volatile("" ::"v"(acc));
+        }
+        return;
+    }
     const int t = tile0 + blockIdx.x * kSpanWaves + wave;
     if (t >= tile1) return;
     const int lane = threadIdx.x & 63;
@@ -3190,12 +3225,18 @@ static void enqueue_adjoint_levels(const sta_graph* g, const KLib& kl, const KVi
                 }
                 const int t0 = g->bspan_tile_h[b], t1 = g->bspan_tile_h[b + 1];
                 if (t1 <= t0) continue;
+                // the next fused span's tiles, for the spare workgroups' L2 prefetch
+                int pf0 = 0, pf1 = 0;
+                if (b + 1 < int64_t(g->bspan_fused_h.size()) && g->bspan_fused_h[b + 1]) {
+                    pf0 = g->bspan_tile_h[b + 1];
+                    pf1 = g->bspan_tile_h[b + 2];
+                }
+                const int gx = pf1 > pf0 ? span_round8(t1 - t0) + span_pf_blocks(pf1 - pf0, kSpanPfTilesB) : t1 - t0;
                 prof_launch("k_adjoint_span", s, [&] {
                     hipLaunchKernelGGL((k_adjoint_span<NV, kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV>),
-                                       dim3((t1 - t0 + kSpanWaves - 1) / kSpanWaves,
-                                            NV / (kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV)),
+                                       dim3(gx, NV / (kSpanViewsPerWave < NV ? kSpanViewsPerWave : NV)),
                                        dim3(64 * kSpanWaves), 0, s, dg, kv, t0, t1, t->argmax, sl->drv_slack,
-                                       o->g_drv_at, o->g_arc_delay, o->g_net_delay);
+                                       o->g_drv_at, o->g_arc_delay, o->g_net_delay, pf0, pf1);
                 });
             }
             done = true;
